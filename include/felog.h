@@ -1,0 +1,284 @@
+/*
+ * felog.h -- C ABI of the FeLoG hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (FeLoG, arxiv 2606.22180, Section 5.1 and Algorithm 1): generate
+ * random walks from the active nodes (Sample), train skip-gram with negative
+ * sampling on them (Train, Eq. (1)-(2)), score each active node by the mean
+ * cosine between its embedding and a subsample of its neighbours' (Psi,
+ * Eq. (4)), keep the nodes with Psi < mu (Eq. (5)), and repeat.
+ *
+ * Conventions
+ *  - Every call returns felog_status: FELOG_OK (0) or a negative error code.
+ *    felog_last_error() returns a message for the calling thread's last error;
+ *    it stays valid until that thread's next felog_* call.  No C++ exception
+ *    crosses this boundary.
+ *  - Handles are opaque.  Each *_create / *_generate / *_load has a matching
+ *    *_destroy; *_destroy(NULL) is a no-op.  The library owns every device
+ *    buffer behind a handle and frees it in *_destroy.
+ *  - Host pointers passed in are read during the call and never retained.
+ *    Host output buffers are written during the call and are owned by the
+ *    caller.  Output buffers smaller than the result give FELOG_EINVAL.
+ *  - A context is bound to one device and one HIP stream.  Calls enqueue work
+ *    on that stream and return after it completes, unless documented otherwise.
+ *    A context and the handles made from it are used by one thread at a time.
+ *  - Node ids are int32; sizes and counts are int64.
+ *  - Device work runs in hand-written HIP kernels; no call falls back to the
+ *    host for any step of the method.
+ */
+#ifndef FELOG_H
+#define FELOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t felog_status;
+
+enum {
+    FELOG_OK = 0,
+    FELOG_EINVAL = -1,        /* bad argument, malformed graph, buffer too small   */
+    FELOG_ENOMEM = -2,        /* device allocation failed or HBM budget exceeded   */
+    FELOG_EDEVICE = -3,       /* a HIP call failed                                 */
+    FELOG_ESTATE = -4,        /* handle in the wrong state for this call           */
+    FELOG_EUNSUPPORTED = -5,  /* valid request this build does not implement        */
+};
+
+typedef struct felog_ctx felog_ctx;
+typedef struct felog_graph felog_graph;
+typedef struct felog_walks felog_walks;
+typedef struct felog_active felog_active;
+typedef struct felog_model felog_model;
+
+/* ------------------------------------------------------------------------- */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Bind a context to HIP device `device` and stream `hip_stream` (a hipStream_t,
+ * or NULL for the null stream).  `hbm_budget_bytes` caps the device memory the
+ * context may hold at once (0 = no cap); an allocation beyond it fails with
+ * FELOG_ENOMEM. */
+felog_status felog_ctx_create(int device, void* hip_stream, uint64_t hbm_budget_bytes,
+                              felog_ctx** out);
+void felog_ctx_destroy(felog_ctx* ctx);
+
+/* Device bytes currently held by handles of this context. */
+felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* felog_last_error(void);
+
+/* ------------------------------------------------------------------------- */
+/* Graph (Table 1: G = (V, E), undirected, unweighted; weighted for node2vec)  */
+/* ------------------------------------------------------------------------- */
+
+/* Upload a symmetric CSR graph.  indptr[n_nodes+1] (int64, indptr[0] = 0,
+ * indptr[n] = nnz, non-decreasing), indices[nnz] (int32 in [0, n), strictly
+ * increasing within each row, no self loops), weights[nnz] (float32 > 0, or
+ * NULL for an unweighted graph).  The graph must be symmetric (v in N(u) iff
+ * u in N(v)) with equal weights on both directions; a graph that is not gives
+ * FELOG_EINVAL with a message naming the first offending row. */
+felog_status felog_graph_load_csr(felog_ctx* ctx, int32_t n_nodes, int64_t nnz,
+                                  const int64_t* indptr, const int32_t* indices,
+                                  const float* weights, felog_graph** out);
+void felog_graph_destroy(felog_graph* g);
+felog_status felog_graph_info(const felog_graph* g, int32_t* n_nodes, int64_t* nnz,
+                              int32_t* weighted);
+
+/* ------------------------------------------------------------------------- */
+/* Active node sets (V_a of Algorithm 1), sorted ascending on the device        */
+/* ------------------------------------------------------------------------- */
+
+/* Copy a strictly increasing list of node ids to the device. */
+felog_status felog_active_from_host(felog_graph* g, const int32_t* sorted_nodes, int64_t count,
+                                    felog_active** out);
+/* All nodes 0..n-1 (V_a at the first round). */
+felog_status felog_active_all(felog_graph* g, felog_active** out);
+felog_status felog_active_count(const felog_active* a, int64_t* count);
+/* Copy the list to host memory nodes[cap]; *count receives its length. */
+felog_status felog_active_read(const felog_active* a, int32_t* nodes, int64_t cap,
+                               int64_t* count);
+void felog_active_destroy(felog_active* a);
+
+/* ------------------------------------------------------------------------- */
+/* Sample: random walks (Section 2 "Sampling process"; Section 5.1 Sample)      */
+/* ------------------------------------------------------------------------- */
+
+enum { FELOG_WALK_UNIFORM = 0, FELOG_WALK_NODE2VEC = 1 };
+
+typedef struct felog_walk_params {
+    int32_t kind;             /* FELOG_WALK_UNIFORM or FELOG_WALK_NODE2VEC        */
+    int32_t walks_per_node;   /* r >= 1                                           */
+    int32_t length;           /* L >= 1 nodes per walk, start included            */
+    float p, q;               /* node2vec return / in-out parameters (> 0)         */
+    uint64_t seed;            /* Philox key                                        */
+    int64_t id_base;          /* id of the first walk (walk ids key the RNG)       */
+} felog_walk_params;
+
+/* Generate r walks per start node.  Walk i (0 <= i < r * |starts|) has id
+ * id_base + i and starts at starts[i mod |starts|] (starts = NULL: all nodes).
+ * Uniform: transition t moves to neighbour floor(x0 * deg / 2^32), x0 from
+ * Philox(key = seed, counter = (id, t, 0, 1 << 24)).  node2vec: rejection
+ * sampling of w(v,x) * alpha(t,x) with alpha = 1/p, 1, 1/q (return, common
+ * neighbour, outward); attempt a uses counter (id, t, 0, 2 << 24 | a).
+ * A start node without neighbours gives a one-node walk.  The walks stay on
+ * the device. */
+felog_status felog_walks_generate(felog_graph* g, const felog_walk_params* params,
+                                  const felog_active* starts, felog_walks** out);
+felog_status felog_walks_info(const felog_walks* w, int64_t* n_walks, int32_t* length,
+                              int64_t* id_base);
+/* Copy walks to host memory as walk-major int32 [n_walks][length], -1 after a
+ * walk's end.  cap is the element capacity of `walks`. */
+felog_status felog_walks_read(const felog_walks* w, int32_t* walks, int64_t cap);
+/* Number of node2vec proposals that hit the attempt cap (expected 0). */
+felog_status felog_walks_capped(const felog_walks* w, int64_t* capped);
+void felog_walks_destroy(felog_walks* w);
+
+/* ------------------------------------------------------------------------- */
+/* Model: embedding tables phi_in, phi_out (Eq. (2)) and the noise distribution */
+/* ------------------------------------------------------------------------- */
+
+enum { FELOG_NEG_DEGREE = 0, FELOG_NEG_UNIGRAM = 1 };
+enum { FELOG_TABLE_IN = 0, FELOG_TABLE_OUT = 1 };
+
+typedef struct felog_model_params {
+    int32_t dim;              /* d; 64, 128 or 256                                */
+    int32_t neg_dist;         /* FELOG_NEG_DEGREE or FELOG_NEG_UNIGRAM             */
+    uint64_t seed;            /* Philox key of the initial in-table                */
+} felog_model_params;
+
+/* Create FP32 tables [n][d]: in[v][c] = ((x >> 8) * 2^-24 - 0.5) / d with x
+ * word c mod 4 of Philox(key = seed, counter = (v, c / 4, 0, 4 << 24)); out = 0.
+ * With FELOG_NEG_DEGREE the noise distribution is degree^0.75 at once; with
+ * FELOG_NEG_UNIGRAM it is set from the first corpus passed to training. */
+felog_status felog_model_create(felog_graph* g, const felog_model_params* params,
+                                felog_model** out);
+void felog_model_destroy(felog_model* m);
+
+/* Set the noise distribution Pn(u) ~ c_u^0.75 from the node counts of a walk
+ * corpus (the unigram distribution).  Weight of u: floor(2^16 * sqrt(c) *
+ * sqrt(sqrt(c))) in IEEE double; a draw maps 64 random bits x to
+ * floor(x * T / 2^64) and returns the node whose cumulative-weight interval
+ * holds it. */
+felog_status felog_model_set_unigram(felog_model* m, const felog_walks* corpus);
+/* Copy the integer cumulative weights cdf[n+1] (uint64) to host memory. */
+felog_status felog_model_read_cdf(const felog_model* m, uint64_t* cdf, int64_t cap);
+
+/* Copy a table (FELOG_TABLE_IN / FELOG_TABLE_OUT) as row-major float32 [n][d]. */
+felog_status felog_embeddings_read(const felog_model* m, int32_t which, float* host, int64_t cap);
+/* Same into device memory (e.g. a torch tensor's data pointer) on the context's stream. */
+felog_status felog_embeddings_read_dev(const felog_model* m, int32_t which, void* dev,
+                                       int64_t cap);
+/* Overwrite a table from host memory (count = n * d floats). */
+felog_status felog_embeddings_write(felog_model* m, int32_t which, const float* host,
+                                    int64_t count);
+
+/* ------------------------------------------------------------------------- */
+/* Train: skip-gram with negative sampling (Eq. (1), Eq. (2))                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct felog_train_params {
+    int32_t window;           /* w: offsets i in [-w, w] \ {0}                     */
+    int32_t negatives;        /* K negatives per pair                              */
+    float lr_start, lr_end;   /* linear decay over the call's minibatches          */
+    int64_t minibatch_pairs;  /* P pairs per minibatch                             */
+    int64_t chunk_walks;      /* pairs are ordered within chunks of this many walks
+                                 (0 = 2^20)                                        */
+    uint64_t seed;            /* Philox key of the negative draws                  */
+} felog_train_params;
+
+typedef struct felog_train_stats {
+    int64_t minibatches;      /* minibatches run by the call                       */
+    int64_t pairs;            /* (context, centre) pairs trained                   */
+    int64_t minibatches_total;/* minibatches in the whole corpus                   */
+    double loss;              /* sum over the call's pairs of -log sigma(s0)
+                                 - sum_k log sigma(-s_k), FP64                     */
+    double ms;                /* device time of the call                           */
+} felog_train_stats;
+
+/* One Train() call: every minibatch of the corpus in order.  Pairs: within each
+ * chunk, centre position j, then offset slot (i = -w..-1, 1..w), then walk; a
+ * minibatch is the next P pairs of the chunk.  Every pair reads the tables as
+ * they stand at the minibatch's start; the minibatch's deltas are summed per
+ * row and then added:
+ *   g0 = lr (1 - sigma(in[c].out[t0])),  gk = -lr sigma(in[c].out[tk])
+ *   delta in[c] += sum_k gk out[tk],   delta out[tk] += gk in[c].
+ * Negative k of a pair is drawn with Philox(key = seed, counter = (walk id,
+ * j << 8 | slot, 0, 3 << 24 | k / 2)); a negative equal to the centre is
+ * skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1). */
+felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
+                               const felog_train_params* params, felog_train_stats* stats);
+/* Minibatches [first_mb, first_mb + n_mb) of the same schedule (the tables must
+ * hold the state at the start of first_mb). */
+felog_status felog_train_steps(felog_model* m, const felog_walks* corpus,
+                               const felog_train_params* params, int64_t first_mb,
+                               int64_t n_mb, felog_train_stats* stats);
+/* The summed deltas of minibatch `mb` without applying them (for checking one
+ * step).  rows_in / rows_out receive the touched rows (any order) and
+ * d_in / d_out their FP32 deltas, row-major [count][d]; capacities in rows. */
+felog_status felog_train_delta(felog_model* m, const felog_walks* corpus,
+                               const felog_train_params* params, int64_t mb,
+                               int32_t* rows_in, float* d_in, int64_t cap_in, int64_t* n_in,
+                               int32_t* rows_out, float* d_out, int64_t cap_out,
+                               int64_t* n_out, double* loss);
+
+/* ------------------------------------------------------------------------- */
+/* Feedback: Psi (Eq. (4)) and the next active set (Eq. (5))                 */
+/* ------------------------------------------------------------------------- */
+
+enum { FELOG_FEEDBACK_MONOTONE = 0, FELOG_FEEDBACK_RECOMPUTE_ALL = 1 };
+
+typedef struct felog_feedback_params {
+    double mu;                /* keep v when Psi(v) < mu                           */
+    int32_t k_s;              /* neighbour subsample size (1..64)                  */
+    int32_t mode;             /* MONOTONE: score `in`; RECOMPUTE_ALL: score all V  */
+    uint64_t seed;            /* Philox key of the neighbour subsets               */
+    uint32_t round;           /* round number, part of the subset counter          */
+} felog_feedback_params;
+
+/* Psi(v) = mean over a neighbour subset of cos(in[v], in[u]): all neighbours
+ * when deg(v) <= k_s, else k_s distinct ones by Floyd's algorithm with draw m
+ * from Philox(key = seed, counter = (v, round, m / 4, 5 << 24)) word m mod 4.
+ * FP64 products and sums.  *out receives {v : Psi(v) < mu}, sorted; nodes
+ * without neighbours are never kept.  psi_host (nullable) receives Psi of the
+ * scored nodes in list order (NaN for nodes without neighbours). */
+felog_status felog_feedback(felog_model* m, const felog_feedback_params* params,
+                            const felog_active* in, felog_active** out, double* psi_host,
+                            int64_t psi_cap);
+
+/* ------------------------------------------------------------------------- */
+/* Algorithm 1 end to end                                                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct felog_run_params {
+    felog_walk_params walk;        /* id_base is ignored: rounds number walks on */
+    felog_train_params train;
+    felog_feedback_params feedback;/* round is set by the loop                   */
+    int32_t max_rounds;            /* stop after this many rounds (>= 1)         */
+} felog_run_params;
+
+#define FELOG_MAX_ROUNDS 64
+
+typedef struct felog_run_stats {
+    int32_t rounds;
+    int64_t active[FELOG_MAX_ROUNDS];      /* |V_a| at the start of each round   */
+    int64_t walks[FELOG_MAX_ROUNDS];
+    int64_t walk_steps[FELOG_MAX_ROUNDS];  /* transitions taken                  */
+    int64_t pairs[FELOG_MAX_ROUNDS];
+    double loss[FELOG_MAX_ROUNDS];
+    double ms_walk[FELOG_MAX_ROUNDS], ms_train[FELOG_MAX_ROUNDS],
+           ms_feedback[FELOG_MAX_ROUNDS];
+    int64_t final_active;                  /* |V_a| after the last round         */
+} felog_run_stats;
+
+/* Algorithm 1: V_a = V; while V_a is not empty and fewer than max_rounds rounds
+ * ran: walks from V_a, one training call over them (the unigram noise
+ * distribution is set from the first round's corpus if the model asks for it),
+ * feedback on V_a (or on V in RECOMPUTE_ALL mode), V_a = result. */
+felog_status felog_run(felog_model* m, const felog_run_params* params, felog_run_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FELOG_H */

@@ -1,0 +1,692 @@
+// C ABI of the FeLoG hot path (include/felog.h): argument checks, handle
+// lifetimes, host<->device copies and Algorithm 1's round loop.  Every step
+// of the method runs in the kernels of the .hip files.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "common.h"
+
+struct felog_ctx : felog::Ctx {};
+struct felog_graph : felog::Graph {};
+struct felog_walks : felog::Walks {};
+struct felog_active : felog::Active {};
+struct felog_model : felog::Model {};
+
+namespace felog {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+void fail(felog_status code, const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    throw Error{code};
+}
+
+DevBuf& DevBuf::operator=(DevBuf&& o) noexcept
+{
+    if (this != &o) {
+        release();
+        ctx = o.ctx;
+        ptr = o.ptr;
+        bytes = o.bytes;
+        o.ctx = nullptr;
+        o.ptr = nullptr;
+        o.bytes = 0;
+    }
+    return *this;
+}
+
+void DevBuf::alloc(Ctx* c, size_t nbytes)
+{
+    release();
+    if (nbytes == 0) nbytes = 16;
+    if (c->budget && c->in_use + nbytes > c->budget)
+        fail(FELOG_ENOMEM, "HBM budget exceeded: %llu bytes held, %llu requested, budget %llu",
+             (unsigned long long)c->in_use, (unsigned long long)nbytes,
+             (unsigned long long)c->budget);
+    c->make_current();
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess)
+        fail(FELOG_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)nbytes,
+             hipGetErrorString(e));
+    ctx = c;
+    ptr = p;
+    bytes = nbytes;
+    c->in_use += nbytes;
+}
+
+void DevBuf::release()
+{
+    if (ptr) {
+        ctx->make_current();
+        (void)hipFree(ptr);
+        ctx->in_use -= bytes;
+    }
+    ptr = nullptr;
+    bytes = 0;
+    ctx = nullptr;
+}
+
+void Ctx::make_current() const { (void)hipSetDevice(device); }
+
+void Ctx::sync() const { FELOG_HIP(hipStreamSynchronize(stream)); }
+
+}  // namespace felog
+
+using namespace felog;
+
+// Run `body`, turning thrown errors into status codes.
+template <class F>
+static felog_status guarded(F&& body)
+{
+    clear_error();
+    try {
+        body();
+        return FELOG_OK;
+    } catch (const Error& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return FELOG_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FELOG_EDEVICE;
+    }
+}
+
+#define NEED(p) FELOG_REQUIRE((p) != nullptr, "%s must not be NULL", #p)
+
+extern "C" {
+
+const char* felog_last_error(void) { return g_last_error.c_str(); }
+
+// ----------------------------------------------------------------- context
+felog_status felog_ctx_create(int device, void* hip_stream, uint64_t hbm_budget_bytes,
+                              felog_ctx** out)
+{
+    return guarded([&] {
+        NEED(out);
+        *out = nullptr;
+        int n = 0;
+        FELOG_HIP(hipGetDeviceCount(&n));
+        FELOG_REQUIRE(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
+        FELOG_HIP(hipSetDevice(device));
+        hipDeviceProp_t prop;
+        FELOG_HIP(hipGetDeviceProperties(&prop, device));
+        auto c = std::make_unique<felog_ctx>();
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->budget = hbm_budget_bytes;
+        c->num_cus = prop.multiProcessorCount;
+        FELOG_HIP(hipEventCreate(&c->ev0));
+        FELOG_HIP(hipEventCreate(&c->ev1));
+        *out = c.release();
+    });
+}
+
+void felog_ctx_destroy(felog_ctx* ctx)
+{
+    if (!ctx) return;
+    ctx->make_current();
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes)
+{
+    return guarded([&] {
+        NEED(ctx);
+        NEED(bytes);
+        *bytes = ctx->in_use;
+    });
+}
+
+// ------------------------------------------------------------------- graph
+felog_status felog_graph_load_csr(felog_ctx* ctx, int32_t n_nodes, int64_t nnz,
+                                  const int64_t* indptr, const int32_t* indices,
+                                  const float* weights, felog_graph** out)
+{
+    return guarded([&] {
+        NEED(ctx);
+        NEED(out);
+        NEED(indptr);
+        *out = nullptr;
+        FELOG_REQUIRE(n_nodes >= 1, "n_nodes must be >= 1 (got %d)", n_nodes);
+        FELOG_REQUIRE(nnz >= 0, "nnz must be >= 0");
+        FELOG_REQUIRE(nnz == 0 || indices, "indices must not be NULL when nnz > 0");
+        FELOG_REQUIRE(indptr[0] == 0, "indptr[0] must be 0 (got %lld)", (long long)indptr[0]);
+        FELOG_REQUIRE(indptr[n_nodes] == nnz, "indptr[n] = %lld differs from nnz = %lld",
+                      (long long)indptr[n_nodes], (long long)nnz);
+        int64_t isolated = 0;
+        for (int32_t v = 0; v < n_nodes; ++v) {
+            FELOG_REQUIRE(indptr[v + 1] >= indptr[v], "indptr decreases at row %d", v);
+            isolated += indptr[v + 1] == indptr[v];
+        }
+        ctx->make_current();
+        auto g = std::make_unique<felog_graph>();
+        g->ctx = ctx;
+        g->n = n_nodes;
+        g->nnz = nnz;
+        g->weighted = weights != nullptr;
+        g->isolated = isolated;
+        g->indptr.alloc(ctx, sizeof(int64_t) * (n_nodes + 1));
+        g->indices.alloc(ctx, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+        FELOG_HIP(hipMemcpyAsync(g->indptr.ptr, indptr, sizeof(int64_t) * (n_nodes + 1),
+                                 hipMemcpyHostToDevice, ctx->stream));
+        if (nnz)
+            FELOG_HIP(hipMemcpyAsync(g->indices.ptr, indices, sizeof(int32_t) * nnz,
+                                     hipMemcpyHostToDevice, ctx->stream));
+        if (weights) {
+            g->weights.alloc(ctx, sizeof(float) * std::max<int64_t>(nnz, 1));
+            if (nnz)
+                FELOG_HIP(hipMemcpyAsync(g->weights.ptr, weights, sizeof(float) * nnz,
+                                         hipMemcpyHostToDevice, ctx->stream));
+        }
+        DevBuf bad;
+        bad.alloc(ctx, sizeof(unsigned long long));
+        launch_validate_graph(*g, bad.as<unsigned long long>());
+        unsigned long long h_code = 0;
+        FELOG_HIP(hipMemcpyAsync(&h_code, bad.ptr, sizeof h_code, hipMemcpyDeviceToHost,
+                                 ctx->stream));
+        ctx->sync();
+        int32_t h_bad[2] = {INT32_MAX, 0};
+        if (h_code != ~0ull) {
+            h_bad[0] = (int32_t)(h_code >> 3);
+            h_bad[1] = (int32_t)(h_code & 7);
+        }
+        static const char* what[] = {"", "an index out of [0, n)", "a self loop",
+                                     "indices not strictly increasing",
+                                     "an edge whose reverse is missing",
+                                     "a weight that is not positive and finite",
+                                     "a weight that differs from its reverse edge's"};
+        if (h_bad[0] != INT32_MAX)
+            fail(FELOG_EINVAL, "graph is not a valid symmetric CSR: row %d has %s", h_bad[0],
+                 what[h_bad[1] >= 0 && h_bad[1] < 7 ? h_bad[1] : 0]);
+        launch_row_wmax(*g);
+        ctx->sync();
+        *out = g.release();
+    });
+}
+
+void felog_graph_destroy(felog_graph* g) { delete g; }
+
+felog_status felog_graph_info(const felog_graph* g, int32_t* n_nodes, int64_t* nnz,
+                              int32_t* weighted)
+{
+    return guarded([&] {
+        NEED(g);
+        if (n_nodes) *n_nodes = g->n;
+        if (nnz) *nnz = g->nnz;
+        if (weighted) *weighted = g->weighted ? 1 : 0;
+    });
+}
+
+// ------------------------------------------------------------------ active
+felog_status felog_active_from_host(felog_graph* g, const int32_t* nodes, int64_t count,
+                                    felog_active** out)
+{
+    return guarded([&] {
+        NEED(g);
+        NEED(out);
+        *out = nullptr;
+        FELOG_REQUIRE(count >= 0 && count <= g->n, "count %lld out of range", (long long)count);
+        FELOG_REQUIRE(count == 0 || nodes, "nodes must not be NULL when count > 0");
+        for (int64_t i = 0; i < count; ++i) {
+            FELOG_REQUIRE(nodes[i] >= 0 && nodes[i] < g->n, "node %d at %lld out of range",
+                          nodes[i], (long long)i);
+            FELOG_REQUIRE(i == 0 || nodes[i] > nodes[i - 1],
+                          "active list must be strictly increasing (position %lld)",
+                          (long long)i);
+        }
+        auto a = std::make_unique<felog_active>();
+        a->g = g;
+        a->count = count;
+        a->nodes.alloc(g->ctx, sizeof(int32_t) * std::max<int64_t>(count, 1));
+        if (count)
+            FELOG_HIP(hipMemcpyAsync(a->nodes.ptr, nodes, sizeof(int32_t) * count,
+                                     hipMemcpyHostToDevice, g->ctx->stream));
+        g->ctx->sync();
+        *out = a.release();
+    });
+}
+
+felog_status felog_active_all(felog_graph* g, felog_active** out)
+{
+    return guarded([&] {
+        NEED(g);
+        NEED(out);
+        *out = nullptr;
+        std::vector<int32_t> all(g->n);
+        for (int32_t v = 0; v < g->n; ++v) all[v] = v;
+        auto a = std::make_unique<felog_active>();
+        a->g = g;
+        a->count = g->n;
+        a->nodes.alloc(g->ctx, sizeof(int32_t) * g->n);
+        FELOG_HIP(hipMemcpyAsync(a->nodes.ptr, all.data(), sizeof(int32_t) * g->n,
+                                 hipMemcpyHostToDevice, g->ctx->stream));
+        g->ctx->sync();
+        *out = a.release();
+    });
+}
+
+felog_status felog_active_count(const felog_active* a, int64_t* count)
+{
+    return guarded([&] {
+        NEED(a);
+        NEED(count);
+        *count = a->count;
+    });
+}
+
+felog_status felog_active_read(const felog_active* a, int32_t* nodes, int64_t cap,
+                               int64_t* count)
+{
+    return guarded([&] {
+        NEED(a);
+        if (count) *count = a->count;
+        if (a->count == 0) return;
+        NEED(nodes);
+        FELOG_REQUIRE(cap >= a->count, "buffer holds %lld nodes, need %lld", (long long)cap,
+                      (long long)a->count);
+        Ctx* c = a->g->ctx;
+        FELOG_HIP(hipMemcpyAsync(nodes, a->nodes.ptr, sizeof(int32_t) * a->count,
+                                 hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+    });
+}
+
+void felog_active_destroy(felog_active* a) { delete a; }
+
+// ------------------------------------------------------------------- walks
+static void check_walk_params(const Graph* g, const felog_walk_params* p)
+{
+    NEED(p);
+    FELOG_REQUIRE(p->kind == FELOG_WALK_UNIFORM || p->kind == FELOG_WALK_NODE2VEC,
+                  "unknown walk kind %d", p->kind);
+    FELOG_REQUIRE(p->walks_per_node >= 1, "walks_per_node must be >= 1");
+    FELOG_REQUIRE(p->length >= 1 && p->length <= 65536, "length must be in [1, 65536]");
+    FELOG_REQUIRE(p->id_base >= 0, "id_base must be >= 0");
+    if (p->kind == FELOG_WALK_NODE2VEC)
+        FELOG_REQUIRE(p->p > 0 && p->q > 0 && std::isfinite(p->p) && std::isfinite(p->q),
+                      "node2vec p and q must be positive and finite");
+    (void)g;
+}
+
+felog_status felog_walks_generate(felog_graph* g, const felog_walk_params* params,
+                                  const felog_active* starts, felog_walks** out)
+{
+    return guarded([&] {
+        NEED(g);
+        NEED(out);
+        *out = nullptr;
+        check_walk_params(g, params);
+        FELOG_REQUIRE(!starts || starts->g == g, "active set belongs to another graph");
+        int64_t n_starts = starts ? starts->count : g->n;
+        auto w = std::make_unique<felog_walks>();
+        w->g = g;
+        w->L = params->length;
+        w->W = n_starts * params->walks_per_node;
+        w->id_base = params->id_base;
+        w->data.alloc(g->ctx, sizeof(int32_t) * std::max<int64_t>(w->W * w->L, 1));
+        if (w->W) launch_walks(*w, *params, starts, n_starts);
+        g->ctx->sync();
+        *out = w.release();
+    });
+}
+
+felog_status felog_walks_info(const felog_walks* w, int64_t* n_walks, int32_t* length,
+                              int64_t* id_base)
+{
+    return guarded([&] {
+        NEED(w);
+        if (n_walks) *n_walks = w->W;
+        if (length) *length = w->L;
+        if (id_base) *id_base = w->id_base;
+    });
+}
+
+felog_status felog_walks_read(const felog_walks* w, int32_t* walks, int64_t cap)
+{
+    return guarded([&] {
+        NEED(w);
+        int64_t total = w->W * w->L;
+        if (total == 0) return;
+        NEED(walks);
+        FELOG_REQUIRE(cap >= total, "buffer holds %lld ints, need %lld", (long long)cap,
+                      (long long)total);
+        Ctx* c = w->g->ctx;
+        // Device layout is step-major [L][W]; transpose to walk-major on the host.
+        std::vector<int32_t> tmp(total);
+        FELOG_HIP(hipMemcpyAsync(tmp.data(), w->data.ptr, sizeof(int32_t) * total,
+                                 hipMemcpyDeviceToHost, c->stream));
+        c->sync();
+        for (int32_t t = 0; t < w->L; ++t)
+            for (int64_t col = 0; col < w->W; ++col) walks[col * w->L + t] = tmp[t * w->W + col];
+    });
+}
+
+felog_status felog_walks_capped(const felog_walks* w, int64_t* capped)
+{
+    return guarded([&] {
+        NEED(w);
+        NEED(capped);
+        *capped = w->capped;
+    });
+}
+
+void felog_walks_destroy(felog_walks* w) { delete w; }
+
+// ------------------------------------------------------------------- model
+felog_status felog_model_create(felog_graph* g, const felog_model_params* p, felog_model** out)
+{
+    return guarded([&] {
+        NEED(g);
+        NEED(p);
+        NEED(out);
+        *out = nullptr;
+        FELOG_REQUIRE(p->dim == 64 || p->dim == 128 || p->dim == 256,
+                      "dim must be 64, 128 or 256 (got %d)", p->dim);
+        FELOG_REQUIRE(p->neg_dist == FELOG_NEG_DEGREE || p->neg_dist == FELOG_NEG_UNIGRAM,
+                      "unknown noise distribution %d", p->neg_dist);
+        Ctx* c = g->ctx;
+        auto m = std::make_unique<felog_model>();
+        m->ctx = c;
+        m->g = g;
+        m->dim = p->dim;
+        m->neg_dist = p->neg_dist;
+        size_t tb = sizeof(float) * (size_t)g->n * p->dim;
+        m->tin.alloc(c, tb);
+        m->tout.alloc(c, tb);
+        m->din.alloc(c, tb);
+        m->dout.alloc(c, tb);
+        m->stamp_in.alloc(c, sizeof(uint32_t) * g->n);
+        m->stamp_out.alloc(c, sizeof(uint32_t) * g->n);
+        m->counters.alloc(c, sizeof(uint32_t) * 4);
+        m->loss_out.alloc(c, sizeof(double));
+        FELOG_HIP(hipMemsetAsync(m->din.ptr, 0, tb, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->dout.ptr, 0, tb, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->stamp_in.ptr, 0xFF, sizeof(uint32_t) * g->n, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->stamp_out.ptr, 0xFF, sizeof(uint32_t) * g->n, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->counters.ptr, 0, sizeof(uint32_t) * 4, c->stream));
+        launch_init_tables(*m, p->seed);
+        if (p->neg_dist == FELOG_NEG_DEGREE) {
+            DevBuf counts;
+            counts.alloc(c, sizeof(uint32_t) * g->n);
+            launch_degree_counts(*g, counts.as<uint32_t>());
+            build_noise_from_counts(*m, counts.as<uint32_t>());
+            c->sync();
+        }
+        c->sync();
+        *out = m.release();
+    });
+}
+
+void felog_model_destroy(felog_model* m) { delete m; }
+
+felog_status felog_model_set_unigram(felog_model* m, const felog_walks* corpus)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(corpus);
+        FELOG_REQUIRE(corpus->g == m->g, "corpus belongs to another graph");
+        Ctx* c = m->ctx;
+        DevBuf counts;
+        counts.alloc(c, sizeof(uint32_t) * m->g->n);
+        launch_corpus_counts(*corpus, counts.as<uint32_t>());
+        build_noise_from_counts(*m, counts.as<uint32_t>());
+        c->sync();
+    });
+}
+
+felog_status felog_model_read_cdf(const felog_model* m, uint64_t* cdf, int64_t cap)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(cdf);
+        FELOG_REQUIRE(m->have_noise, "the noise distribution is not set yet");
+        FELOG_REQUIRE(cap >= (int64_t)m->g->n + 1, "buffer holds %lld values, need %d",
+                      (long long)cap, m->g->n + 1);
+        FELOG_HIP(hipMemcpyAsync(cdf, m->cdf.ptr, sizeof(uint64_t) * (m->g->n + 1),
+                                 hipMemcpyDeviceToHost, m->ctx->stream));
+        m->ctx->sync();
+    });
+}
+
+static const DevBuf& table_of(const felog_model* m, int32_t which)
+{
+    FELOG_REQUIRE(which == FELOG_TABLE_IN || which == FELOG_TABLE_OUT, "unknown table %d", which);
+    return which == FELOG_TABLE_IN ? m->tin : m->tout;
+}
+
+felog_status felog_embeddings_read(const felog_model* m, int32_t which, float* host, int64_t cap)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(host);
+        const DevBuf& t = table_of(m, which);
+        int64_t count = (int64_t)m->g->n * m->dim;
+        FELOG_REQUIRE(cap >= count, "buffer holds %lld floats, need %lld", (long long)cap,
+                      (long long)count);
+        FELOG_HIP(hipMemcpyAsync(host, t.ptr, sizeof(float) * count, hipMemcpyDeviceToHost,
+                                 m->ctx->stream));
+        m->ctx->sync();
+    });
+}
+
+felog_status felog_embeddings_read_dev(const felog_model* m, int32_t which, void* dev,
+                                       int64_t cap)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(dev);
+        const DevBuf& t = table_of(m, which);
+        int64_t count = (int64_t)m->g->n * m->dim;
+        FELOG_REQUIRE(cap >= count, "buffer holds %lld floats, need %lld", (long long)cap,
+                      (long long)count);
+        FELOG_HIP(hipMemcpyAsync(dev, t.ptr, sizeof(float) * count, hipMemcpyDeviceToDevice,
+                                 m->ctx->stream));
+        m->ctx->sync();
+    });
+}
+
+felog_status felog_embeddings_write(felog_model* m, int32_t which, const float* host,
+                                    int64_t count)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(host);
+        const DevBuf& t = table_of(m, which);
+        FELOG_REQUIRE(count == (int64_t)m->g->n * m->dim, "count must be n * d = %lld",
+                      (long long)m->g->n * m->dim);
+        FELOG_HIP(hipMemcpyAsync(t.ptr, host, sizeof(float) * count, hipMemcpyHostToDevice,
+                                 m->ctx->stream));
+        m->ctx->sync();
+    });
+}
+
+// ------------------------------------------------------------------- train
+static void check_train_params(const felog_model* m, const felog_walks* w,
+                               const felog_train_params* p)
+{
+    NEED(m);
+    NEED(w);
+    NEED(p);
+    FELOG_REQUIRE(w->g == m->g, "corpus belongs to another graph");
+    FELOG_REQUIRE(p->window >= 1 && p->window <= 127, "window must be in [1, 127]");
+    FELOG_REQUIRE(p->negatives >= 1 && p->negatives <= 20, "negatives must be in [1, 20]");
+    FELOG_REQUIRE(p->minibatch_pairs >= 1 && p->minibatch_pairs <= (1 << 24),
+                  "minibatch_pairs must be in [1, 2^24]");
+    FELOG_REQUIRE(p->chunk_walks >= 0, "chunk_walks must be >= 0");
+    FELOG_REQUIRE(std::isfinite(p->lr_start) && std::isfinite(p->lr_end),
+                  "learning rates must be finite");
+    FELOG_REQUIRE(w->L <= (1 << 23), "walks longer than 2^23 are not supported");
+    FELOG_REQUIRE(m->have_noise, "the noise distribution is not set (unigram models need "
+                  "felog_model_set_unigram or a first felog_run round)");
+}
+
+felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
+                               const felog_train_params* params, felog_train_stats* stats)
+{
+    return guarded([&] {
+        check_train_params(m, corpus, params);
+        train_minibatches(*m, *const_cast<felog_walks*>(corpus), *params, 0, -1, true, stats,
+                          nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr);
+    });
+}
+
+felog_status felog_train_steps(felog_model* m, const felog_walks* corpus,
+                               const felog_train_params* params, int64_t first_mb, int64_t n_mb,
+                               felog_train_stats* stats)
+{
+    return guarded([&] {
+        check_train_params(m, corpus, params);
+        FELOG_REQUIRE(first_mb >= 0 && n_mb >= 0, "minibatch range must be non-negative");
+        train_minibatches(*m, *const_cast<felog_walks*>(corpus), *params, first_mb, n_mb, true,
+                          stats, nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr);
+    });
+}
+
+felog_status felog_train_delta(felog_model* m, const felog_walks* corpus,
+                               const felog_train_params* params, int64_t mb, int32_t* rows_in,
+                               float* d_in, int64_t cap_in, int64_t* n_in, int32_t* rows_out,
+                               float* d_out, int64_t cap_out, int64_t* n_out, double* loss)
+{
+    return guarded([&] {
+        check_train_params(m, corpus, params);
+        NEED(rows_in);
+        NEED(d_in);
+        NEED(n_in);
+        NEED(rows_out);
+        NEED(d_out);
+        NEED(n_out);
+        FELOG_REQUIRE(mb >= 0, "minibatch index must be non-negative");
+        felog_train_stats st{};
+        train_minibatches(*m, *const_cast<felog_walks*>(corpus), *params, mb, 1, false, &st,
+                          rows_in, d_in, cap_in, n_in, rows_out, d_out, cap_out, n_out);
+        if (loss) *loss = st.loss;
+    });
+}
+
+// ---------------------------------------------------------------- feedback
+static void check_feedback_params(const felog_feedback_params* p)
+{
+    NEED(p);
+    FELOG_REQUIRE(p->k_s >= 1 && p->k_s <= 64, "k_s must be in [1, 64]");
+    FELOG_REQUIRE(p->mode == FELOG_FEEDBACK_MONOTONE || p->mode == FELOG_FEEDBACK_RECOMPUTE_ALL,
+                  "unknown feedback mode %d", p->mode);
+    FELOG_REQUIRE(!std::isnan(p->mu), "mu must not be NaN");
+}
+
+felog_status felog_feedback(felog_model* m, const felog_feedback_params* params,
+                            const felog_active* in, felog_active** out, double* psi_host,
+                            int64_t psi_cap)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(out);
+        *out = nullptr;
+        check_feedback_params(params);
+        FELOG_REQUIRE(!in || in->g == m->g, "active set belongs to another graph");
+        auto a = std::make_unique<felog_active>();
+        a->g = m->g;
+        const Active* src = params->mode == FELOG_FEEDBACK_RECOMPUTE_ALL ? nullptr : in;
+        feedback(*m, *params, src, *a, psi_host, psi_cap);
+        *out = a.release();
+    });
+}
+
+// --------------------------------------------------------------------- run
+felog_status felog_run(felog_model* m, const felog_run_params* p, felog_run_stats* stats)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(p);
+        check_walk_params(m->g, &p->walk);
+        check_feedback_params(&p->feedback);
+        FELOG_REQUIRE(p->max_rounds >= 1 && p->max_rounds <= FELOG_MAX_ROUNDS,
+                      "max_rounds must be in [1, %d]", FELOG_MAX_ROUNDS);
+        Ctx* c = m->ctx;
+        felog_run_stats st{};
+        std::unique_ptr<felog_active> act;   // null = all nodes
+        int64_t n_active = m->g->n;
+        int64_t id_base = 0;
+        for (int32_t r = 0; r < p->max_rounds && n_active > 0; ++r) {
+            felog_walk_params wp = p->walk;
+            wp.id_base = id_base;
+            auto w = std::make_unique<felog_walks>();
+            w->g = m->g;
+            w->L = wp.length;
+            w->W = n_active * wp.walks_per_node;
+            w->id_base = id_base;
+            w->data.alloc(c, sizeof(int32_t) * std::max<int64_t>(w->W * w->L, 1));
+            FELOG_HIP(hipEventRecord(c->ev0, c->stream));
+            launch_walks(*w, wp, act.get(), n_active);
+            FELOG_HIP(hipEventRecord(c->ev1, c->stream));
+            c->sync();
+            float ms = 0;
+            FELOG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            st.ms_walk[r] = ms;
+            if (!m->have_noise) {
+                DevBuf counts;
+                counts.alloc(c, sizeof(uint32_t) * m->g->n);
+                launch_corpus_counts(*w, counts.as<uint32_t>());
+                build_noise_from_counts(*m, counts.as<uint32_t>());
+                c->sync();
+            }
+            check_train_params(m, w.get(), &p->train);
+            felog_train_stats ts{};
+            train_minibatches(*m, *w, p->train, 0, -1, true, &ts, nullptr, nullptr, 0, nullptr,
+                              nullptr, nullptr, 0, nullptr);
+            st.active[r] = n_active;
+            st.walks[r] = w->W;
+            st.walk_steps[r] = w->n_valid * (int64_t)(w->L - 1);
+            st.pairs[r] = ts.pairs;
+            st.loss[r] = ts.loss;
+            st.ms_train[r] = ts.ms;
+            id_base += w->W;
+            w.reset();
+            felog_feedback_params fp = p->feedback;
+            fp.round = (uint32_t)r;
+            auto next = std::make_unique<felog_active>();
+            next->g = m->g;
+            FELOG_HIP(hipEventRecord(c->ev0, c->stream));
+            const Active* src = fp.mode == FELOG_FEEDBACK_RECOMPUTE_ALL ? nullptr : act.get();
+            feedback(*m, fp, src, *next, nullptr, 0);
+            FELOG_HIP(hipEventRecord(c->ev1, c->stream));
+            c->sync();
+            FELOG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            st.ms_feedback[r] = ms;
+            act = std::move(next);
+            n_active = act->count;
+            st.rounds = r + 1;
+        }
+        st.final_active = n_active;
+        if (stats) *stats = st;
+    });
+}
+
+}  // extern "C"

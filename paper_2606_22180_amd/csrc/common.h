@@ -1,0 +1,188 @@
+// Internal declarations of the FeLoG HIP library (gfx950).  Not installed;
+// the public interface is include/felog.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "felog.h"
+
+namespace felog {
+
+// ---------------------------------------------------------------------------
+// Errors: a thread-local message plus the status code returned across the ABI.
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+struct Error {
+    felog_status code;
+};
+
+[[noreturn]] void fail(felog_status code, const char* fmt, ...);
+
+#define FELOG_HIP(call)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            ::felog::fail(e_ == hipErrorOutOfMemory ? FELOG_ENOMEM : FELOG_EDEVICE,  \
+                          "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),     \
+                          __FILE__, __LINE__);                                       \
+    } while (0)
+
+#define FELOG_REQUIRE(cond, ...)                                   \
+    do {                                                           \
+        if (!(cond)) ::felog::fail(FELOG_EINVAL, __VA_ARGS__);     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Device memory owned by a context, counted against its HBM budget.
+// ---------------------------------------------------------------------------
+struct Ctx;
+
+struct DevBuf {
+    Ctx* ctx = nullptr;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept;
+    ~DevBuf() { release(); }
+    void alloc(Ctx* c, size_t nbytes);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(ptr); }
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;     // 0 = no cap
+    uint64_t in_use = 0;
+    int num_cus = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void make_current() const;
+    void sync() const;
+};
+
+struct Graph {
+    Ctx* ctx = nullptr;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    bool weighted = false;
+    DevBuf indptr;    // int64 [n+1]
+    DevBuf indices;   // int32 [nnz]
+    DevBuf weights;   // float [nnz]   (weighted only)
+    DevBuf wmax;      // float [n]     (max weight of each row; 1 when unweighted)
+    int64_t isolated = 0;                // nodes without neighbours
+};
+
+struct Active {
+    Graph* g = nullptr;
+    int64_t count = 0;
+    DevBuf nodes;     // int32 [count], strictly increasing
+};
+
+struct Walks {
+    Graph* g = nullptr;
+    int64_t W = 0;
+    int32_t L = 0;
+    int64_t id_base = 0;
+    int64_t capped = 0;      // node2vec proposals taken at the attempt cap
+    DevBuf data;             // int32 [L][W], step-major, -1 after a walk's end
+    // Columns whose walk has at least two nodes (the ones that yield pairs),
+    // in column order; built on first use by training.
+    bool have_valid = false;
+    int64_t n_valid = 0;
+    DevBuf valid_cols;       // int32 [n_valid]
+    std::vector<int64_t> chunk_valid;   // per chunk of `chunk_for_valid` walks
+    int64_t chunk_for_valid = 0;
+};
+
+struct Model {
+    Ctx* ctx = nullptr;
+    Graph* g = nullptr;
+    int32_t dim = 0;
+    int32_t neg_dist = FELOG_NEG_DEGREE;
+    bool have_noise = false;
+    DevBuf tin, tout;         // float [n][d]
+    DevBuf din, dout;         // float [n][d], zero between minibatches
+    DevBuf stamp_in, stamp_out;   // uint32 [n], minibatch serial of the last touch
+    DevBuf cdf;               // uint64 [n+1]
+    DevBuf guide;             // int32 [2^guide_bits]
+    int32_t guide_bits = 0;
+    uint64_t total_weight = 0;
+    uint32_t serial = 0;      // minibatch serial (stamps)
+    // scratch sized for the largest minibatch seen
+    int64_t cap_pairs = 0;
+    int32_t cap_K = 0;
+    DevBuf touched_in, touched_out;   // int32 lists
+    DevBuf counters;          // uint32 [4]: touched counts, double-buffered by serial parity
+    DevBuf loss_part;         // double [waves]
+    DevBuf loss_out;          // double [1]
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplications with the Weyl key schedule.
+// ---------------------------------------------------------------------------
+struct Rand4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Rand4 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint64_t seed)
+{
+    uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
+        uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Rand4{{c0, c1, c2, c3}};
+}
+
+// Stream tags (top byte of counter word 3).
+constexpr uint32_t kTagWalk = 1u << 24, kTagN2V = 2u << 24, kTagNeg = 3u << 24,
+                   kTagInit = 4u << 24, kTagPsi = 5u << 24, kTagSharedNeg = 6u << 24;
+
+// floor(x * m / 2^32): uniform integer below m from 32 random bits.
+__device__ __forceinline__ uint32_t scale32(uint32_t x, uint32_t m) { return __umulhi(x, m); }
+
+// ---------------------------------------------------------------------------
+// Launch helpers implemented in the .hip files.
+// ---------------------------------------------------------------------------
+void launch_validate_graph(Graph& g, unsigned long long* d_bad);
+void launch_row_wmax(Graph& g);
+void launch_walks(Walks& w, const felog_walk_params& p, const Active* starts, int64_t n_starts);
+void launch_valid_columns(Walks& w, int64_t chunk);
+void launch_init_tables(Model& m, uint64_t seed);
+void build_noise_from_counts(Model& m, const uint32_t* d_counts);   // counts in device memory
+void launch_degree_counts(Graph& g, uint32_t* d_counts);
+void launch_corpus_counts(const Walks& w, uint32_t* d_counts);
+void train_minibatches(Model& m, const Walks& w, const felog_train_params& p, int64_t first_mb,
+                       int64_t n_mb, bool apply, felog_train_stats* stats,
+                       int32_t* rows_in, float* d_in, int64_t cap_in, int64_t* n_in,
+                       int32_t* rows_out, float* d_out, int64_t cap_out, int64_t* n_out);
+int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_pairs);
+void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
+              double* psi_host, int64_t psi_cap);
+// Order-preserving compaction of nodes[i] where flags[i] != 0; returns the count.
+int64_t compact_nodes(Ctx& ctx, const int32_t* d_nodes, const uint8_t* d_flags, int64_t count,
+                      DevBuf& out);
+
+}  // namespace felog

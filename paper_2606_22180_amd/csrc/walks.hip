@@ -1,0 +1,281 @@
+// Graph checks and random-walk generation (Sample of Algorithm 1).
+//
+// Uniform walks follow the DeepWalk sampler of Section 2 ("Sampling
+// process"): each transition picks a neighbour of the current node
+// uniformly.  node2vec walks (named in Sections 3 and 5.4) bias the choice by
+// the previous node with return parameter p and in-out parameter q; they are
+// drawn by rejection so no per-edge alias tables are needed.
+//
+// Layout: walks are stored step-major, walk[t][col] at t * W + col, so the W
+// lanes of a launch write each step as one coalesced row.  One lane owns one
+// walk: the step loop is a chain of dependent loads (row bounds, then the
+// neighbour), and thousands of walks in flight per CU hide that latency.
+#include "common.h"
+#include "scan.h"
+
+namespace felog {
+
+// --------------------------------------------------------------------------
+// Graph validation: one thread per CSR entry.  Records the smallest offending
+// row and the kind of fault as (row << 3 | code) with an atomic minimum.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int64_t row_of_entry(const int64_t* indptr, int32_t n, int64_t e)
+{
+    int32_t lo = 0, hi = n - 1;   // last row r with indptr[r] <= e
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo + 1) / 2;
+        if (indptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t find_in_row(const int64_t* indptr, const int32_t* indices,
+                                               int32_t row, int32_t x)
+{
+    int64_t lo = indptr[row], hi = indptr[row + 1];
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (indices[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return (lo < indptr[row + 1] && indices[lo] == x) ? lo : -1;
+}
+
+__global__ void validate_graph_kernel(const int64_t* indptr, const int32_t* indices,
+                                      const float* weights, int32_t n, int64_t nnz,
+                                      unsigned long long* bad)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int32_t u = (int32_t)row_of_entry(indptr, n, e);
+    int32_t v = indices[e];
+    int code = 0;
+    if (v < 0 || v >= n) code = 1;
+    else if (v == u) code = 2;
+    else if (e > indptr[u] && indices[e - 1] >= v) code = 3;
+    else {
+        int64_t r = find_in_row(indptr, indices, v, u);
+        if (r < 0) code = 4;
+        else if (weights) {
+            float w = weights[e];
+            if (!(w > 0.0f) || !isfinite(w)) code = 5;
+            else if (weights[r] != w) code = 6;
+        }
+    }
+    if (code) atomicMin(bad, ((unsigned long long)u << 3) | (unsigned long long)code);
+}
+
+void launch_validate_graph(Graph& g, unsigned long long* d_bad)
+{
+    Ctx& c = *g.ctx;
+    FELOG_HIP(hipMemsetAsync(d_bad, 0xFF, sizeof(unsigned long long), c.stream));
+    if (g.nnz == 0) return;
+    int64_t blocks = (g.nnz + 255) / 256;
+    hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, c.stream,
+                       g.indptr.as<int64_t>(), g.indices.as<int32_t>(),
+                       g.weighted ? g.weights.as<float>() : nullptr, g.n, g.nnz, d_bad);
+    FELOG_HIP(hipGetLastError());
+}
+
+// Largest edge weight of each row (1 for unweighted graphs): the rejection bound.
+__global__ void row_wmax_kernel(const int64_t* indptr, const float* weights, int32_t n,
+                                float* wmax)
+{
+    int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    float m = 0.0f;
+    if (weights) {
+        for (int64_t e = indptr[v]; e < indptr[v + 1]; ++e) m = fmaxf(m, weights[e]);
+    } else {
+        m = indptr[v + 1] > indptr[v] ? 1.0f : 0.0f;
+    }
+    wmax[v] = m;
+}
+
+void launch_row_wmax(Graph& g)
+{
+    Ctx& c = *g.ctx;
+    g.wmax.alloc(&c, sizeof(float) * g.n);
+    hipLaunchKernelGGL(row_wmax_kernel, dim3((g.n + 255) / 256), dim3(256), 0, c.stream,
+                       g.indptr.as<int64_t>(), g.weighted ? g.weights.as<float>() : nullptr, g.n,
+                       g.wmax.as<float>());
+    FELOG_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------------------------
+// Uniform walks.  Transition t of walk `wid` moves from v to its neighbour
+// number floor(x0 * deg(v) / 2^32), x0 = word 0 of Philox(wid, t, WALK).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void walk_uniform_kernel(
+    const int64_t* __restrict__ indptr, const int32_t* __restrict__ indices,
+    const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int32_t L, uint64_t seed,
+    int64_t id_base, int32_t* __restrict__ walks)
+{
+    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= W) return;
+    int64_t si = col % n_starts;
+    int32_t v = starts ? starts[si] : (int32_t)si;
+    int64_t wid = id_base + col;
+    walks[col] = v;
+    int32_t t = 0;
+    for (; t + 1 < L; ++t) {
+        int64_t lo = indptr[v];
+        int64_t deg = indptr[v + 1] - lo;
+        if (deg == 0) break;
+        Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)t, kTagWalk, seed);
+        v = indices[lo + scale32(r.v[0], (uint32_t)deg)];
+        walks[(int64_t)(t + 1) * W + col] = v;
+    }
+    for (int32_t s = t + 1; s < L; ++s) walks[(int64_t)s * W + col] = -1;
+}
+
+// --------------------------------------------------------------------------
+// node2vec walks by rejection.  From v (previous node `prev`), attempt a of
+// transition t uses Philox(wid, t, N2V | a): propose the neighbour
+// floor(x0 * deg / 2^32), draw u = (x1 >> 8) * 2^-24, and accept when
+//   u * (wmax(v) * alpha_max) < w(v, x) * alpha(prev, x)
+// in FP32, alpha = 1/p (x == prev), 1 (x adjacent to prev), 1/q (otherwise).
+// The first transition uses alpha = 1 and the bound wmax(v).  The adjacency
+// test is a binary search in prev's sorted row, and it is skipped when the
+// proposal is decided by the extreme alpha values alone (same result).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void walk_node2vec_kernel(
+    const int64_t* __restrict__ indptr, const int32_t* __restrict__ indices,
+    const float* __restrict__ weights, const float* __restrict__ wmax,
+    const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int32_t L, float inv_p,
+    float inv_q, float amax, uint32_t max_attempts, uint64_t seed, int64_t id_base,
+    int32_t* __restrict__ walks, unsigned long long* __restrict__ capped)
+{
+    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= W) return;
+    int64_t si = col % n_starts;
+    int32_t v = starts ? starts[si] : (int32_t)si;
+    int32_t prev = -1;
+    int64_t wid = id_base + col;
+    walks[col] = v;
+    uint32_t my_capped = 0;
+    int32_t t = 0;
+    for (; t + 1 < L; ++t) {
+        int64_t lo = indptr[v];
+        int64_t deg = indptr[v + 1] - lo;
+        if (deg == 0) break;
+        const float bound = t == 0 ? wmax[v] : __fmul_rn(wmax[v], amax);
+        int32_t x = -1;
+        for (uint32_t a = 0; a < max_attempts; ++a) {
+            Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)t, kTagN2V | a,
+                                 seed);
+            int64_t e = lo + scale32(r.v[0], (uint32_t)deg);
+            x = indices[e];
+            float w = weights ? weights[e] : 1.0f;
+            float u = (float)(r.v[1] >> 8) * (1.0f / 16777216.0f);
+            float lhs = __fmul_rn(u, bound);
+            bool accept;
+            if (t == 0) {
+                accept = lhs < w;
+            } else if (x == prev) {
+                accept = lhs < __fmul_rn(w, inv_p);
+            } else if (!(lhs < __fmul_rn(w, fmaxf(1.0f, inv_q)))) {
+                accept = false;        // rejected even by the larger of alpha in {1, 1/q}
+            } else if (lhs < __fmul_rn(w, fminf(1.0f, inv_q))) {
+                accept = true;         // accepted even by the smaller of alpha in {1, 1/q}
+            } else {
+                // decided by adjacency of x to prev: binary search in prev's row
+                int64_t lo2 = indptr[prev], hi2 = indptr[prev + 1];
+                while (lo2 < hi2) {
+                    int64_t mid = lo2 + ((hi2 - lo2) >> 1);
+                    if (indices[mid] < x) lo2 = mid + 1; else hi2 = mid;
+                }
+                bool adj = lo2 < indptr[prev + 1] && indices[lo2] == x;
+                accept = lhs < __fmul_rn(w, adj ? 1.0f : inv_q);
+            }
+            if (accept) break;
+            if (a + 1 == max_attempts) ++my_capped;
+        }
+        prev = v;
+        v = x;
+        walks[(int64_t)(t + 1) * W + col] = v;
+    }
+    for (int32_t s = t + 1; s < L; ++s) walks[(int64_t)s * W + col] = -1;
+    if (my_capped) atomicAdd(capped, (unsigned long long)my_capped);
+}
+
+void launch_walks(Walks& w, const felog_walk_params& p, const Active* starts, int64_t n_starts)
+{
+    Graph& g = *w.g;
+    Ctx& c = *g.ctx;
+    const int32_t* st = starts ? starts->nodes.as<int32_t>() : nullptr;
+    int64_t blocks = (w.W + 255) / 256;
+    w.have_valid = false;
+    if (p.kind == FELOG_WALK_UNIFORM) {
+        hipLaunchKernelGGL(walk_uniform_kernel, dim3(blocks), dim3(256), 0, c.stream,
+                           g.indptr.as<int64_t>(), g.indices.as<int32_t>(), st, n_starts, w.W,
+                           w.L, p.seed, w.id_base, w.data.as<int32_t>());
+        FELOG_HIP(hipGetLastError());
+        w.capped = 0;
+    } else {
+        DevBuf cap;
+        cap.alloc(&c, sizeof(unsigned long long));
+        FELOG_HIP(hipMemsetAsync(cap.ptr, 0, sizeof(unsigned long long), c.stream));
+        float inv_p = 1.0f / p.p, inv_q = 1.0f / p.q;
+        float amax = fmaxf(1.0f, fmaxf(inv_p, inv_q));
+        hipLaunchKernelGGL(walk_node2vec_kernel, dim3(blocks), dim3(256), 0, c.stream,
+                           g.indptr.as<int64_t>(), g.indices.as<int32_t>(),
+                           g.weighted ? g.weights.as<float>() : nullptr, g.wmax.as<float>(), st,
+                           n_starts, w.W, w.L, inv_p, inv_q, amax, 1u << 16, p.seed, w.id_base,
+                           w.data.as<int32_t>(), cap.as<unsigned long long>());
+        FELOG_HIP(hipGetLastError());
+        unsigned long long h = 0;
+        FELOG_HIP(hipMemcpyAsync(&h, cap.ptr, sizeof h, hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        w.capped = (int64_t)h;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Columns whose walk yields pairs (two or more nodes), and their count per
+// chunk of `chunk` consecutive walks.
+// --------------------------------------------------------------------------
+struct LongWalk {
+    const int32_t* second_step;   // walk[1][*]
+    __device__ bool operator()(int64_t col) const { return second_step[col] >= 0; }
+};
+struct ColumnId {
+    __device__ int32_t operator()(int64_t col) const { return (int32_t)col; }
+};
+
+__global__ void chunk_count_kernel(const int32_t* second_step, int64_t W, int64_t chunk,
+                                   unsigned long long* counts)
+{
+    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= W || second_step[col] < 0) return;
+    atomicAdd(&counts[col / chunk], 1ull);
+}
+
+void launch_valid_columns(Walks& w, int64_t chunk)
+{
+    if (w.have_valid && w.chunk_for_valid == chunk) return;
+    Ctx& c = *w.g->ctx;
+    int64_t n_chunks = (w.W + chunk - 1) / chunk;
+    w.chunk_valid.assign(n_chunks, 0);
+    if (w.L < 2 || w.W == 0) {
+        w.n_valid = 0;
+        w.valid_cols.alloc(&c, sizeof(int32_t));
+    } else {
+        const int32_t* second = w.data.as<int32_t>() + w.W;
+        w.n_valid = compact(c, LongWalk{second}, ColumnId{}, w.W, w.valid_cols);
+        DevBuf cnt;
+        cnt.alloc(&c, sizeof(unsigned long long) * n_chunks);
+        FELOG_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * n_chunks, c.stream));
+        hipLaunchKernelGGL(chunk_count_kernel, dim3((w.W + 255) / 256), dim3(256), 0, c.stream,
+                           second, w.W, chunk, cnt.as<unsigned long long>());
+        FELOG_HIP(hipGetLastError());
+        std::vector<unsigned long long> h(n_chunks);
+        FELOG_HIP(hipMemcpyAsync(h.data(), cnt.ptr, sizeof(unsigned long long) * n_chunks,
+                                 hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        for (int64_t i = 0; i < n_chunks; ++i) w.chunk_valid[i] = (int64_t)h[i];
+    }
+    w.have_valid = true;
+    w.chunk_for_valid = chunk;
+}
+
+}  // namespace felog

@@ -1,0 +1,368 @@
+"""ctypes binding of the FeLoG C ABI (include/felog.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``_lib/libfelog.so``.  Loading fails loudly when the library has not been
+built; there is no fallback.
+
+The raw entry points keep the C names (``felog_walks_generate`` ...); the small
+classes below own handles and free them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfelog.so")
+
+FELOG_OK, FELOG_EINVAL, FELOG_ENOMEM, FELOG_EDEVICE, FELOG_ESTATE, FELOG_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+WALK_UNIFORM, WALK_NODE2VEC = 0, 1
+NEG_DEGREE, NEG_UNIGRAM = 0, 1
+TABLE_IN, TABLE_OUT = 0, 1
+FEEDBACK_MONOTONE, FEEDBACK_RECOMPUTE_ALL = 0, 1
+MAX_ROUNDS = 64
+
+_STATUS = {0: "FELOG_OK", -1: "FELOG_EINVAL", -2: "FELOG_ENOMEM", -3: "FELOG_EDEVICE",
+           -4: "FELOG_ESTATE", -5: "FELOG_EUNSUPPORTED"}
+
+
+class FelogError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+class felog_walk_params(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("walks_per_node", C.c_int32), ("length", C.c_int32),
+                ("p", C.c_float), ("q", C.c_float), ("seed", C.c_uint64),
+                ("id_base", C.c_int64)]
+
+
+class felog_model_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("neg_dist", C.c_int32), ("seed", C.c_uint64)]
+
+
+class felog_train_params(C.Structure):
+    _fields_ = [("window", C.c_int32), ("negatives", C.c_int32), ("lr_start", C.c_float),
+                ("lr_end", C.c_float), ("minibatch_pairs", C.c_int64),
+                ("chunk_walks", C.c_int64), ("seed", C.c_uint64)]
+
+
+class felog_train_stats(C.Structure):
+    _fields_ = [("minibatches", C.c_int64), ("pairs", C.c_int64),
+                ("minibatches_total", C.c_int64), ("loss", C.c_double), ("ms", C.c_double)]
+
+
+class felog_feedback_params(C.Structure):
+    _fields_ = [("mu", C.c_double), ("k_s", C.c_int32), ("mode", C.c_int32),
+                ("seed", C.c_uint64), ("round", C.c_uint32)]
+
+
+class felog_run_params(C.Structure):
+    _fields_ = [("walk", felog_walk_params), ("train", felog_train_params),
+                ("feedback", felog_feedback_params), ("max_rounds", C.c_int32)]
+
+
+class felog_run_stats(C.Structure):
+    _fields_ = [("rounds", C.c_int32),
+                ("active", C.c_int64 * MAX_ROUNDS), ("walks", C.c_int64 * MAX_ROUNDS),
+                ("walk_steps", C.c_int64 * MAX_ROUNDS), ("pairs", C.c_int64 * MAX_ROUNDS),
+                ("loss", C.c_double * MAX_ROUNDS), ("ms_walk", C.c_double * MAX_ROUNDS),
+                ("ms_train", C.c_double * MAX_ROUNDS), ("ms_feedback", C.c_double * MAX_ROUNDS),
+                ("final_active", C.c_int64)]
+
+
+_p = C.c_void_p
+_pp = C.POINTER(C.c_void_p)
+_i32, _i64, _u32, _u64, _f32, _f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float, C.c_double
+
+# name -> (restype, argtypes); the names and order follow include/felog.h
+SIGNATURES = {
+    "felog_ctx_create": (_i32, [C.c_int, _p, _u64, _pp]),
+    "felog_ctx_destroy": (None, [_p]),
+    "felog_ctx_bytes_in_use": (_i32, [_p, C.POINTER(_u64)]),
+    "felog_last_error": (C.c_char_p, []),
+    "felog_graph_load_csr": (_i32, [_p, _i32, _i64, _p, _p, _p, _pp]),
+    "felog_graph_destroy": (None, [_p]),
+    "felog_graph_info": (_i32, [_p, C.POINTER(_i32), C.POINTER(_i64), C.POINTER(_i32)]),
+    "felog_active_from_host": (_i32, [_p, _p, _i64, _pp]),
+    "felog_active_all": (_i32, [_p, _pp]),
+    "felog_active_count": (_i32, [_p, C.POINTER(_i64)]),
+    "felog_active_read": (_i32, [_p, _p, _i64, C.POINTER(_i64)]),
+    "felog_active_destroy": (None, [_p]),
+    "felog_walks_generate": (_i32, [_p, C.POINTER(felog_walk_params), _p, _pp]),
+    "felog_walks_info": (_i32, [_p, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i64)]),
+    "felog_walks_read": (_i32, [_p, _p, _i64]),
+    "felog_walks_capped": (_i32, [_p, C.POINTER(_i64)]),
+    "felog_walks_destroy": (None, [_p]),
+    "felog_model_create": (_i32, [_p, C.POINTER(felog_model_params), _pp]),
+    "felog_model_destroy": (None, [_p]),
+    "felog_model_set_unigram": (_i32, [_p, _p]),
+    "felog_model_read_cdf": (_i32, [_p, _p, _i64]),
+    "felog_embeddings_read": (_i32, [_p, _i32, _p, _i64]),
+    "felog_embeddings_read_dev": (_i32, [_p, _i32, _p, _i64]),
+    "felog_embeddings_write": (_i32, [_p, _i32, _p, _i64]),
+    "felog_train_epoch": (_i32, [_p, _p, C.POINTER(felog_train_params),
+                                 C.POINTER(felog_train_stats)]),
+    "felog_train_steps": (_i32, [_p, _p, C.POINTER(felog_train_params), _i64, _i64,
+                                 C.POINTER(felog_train_stats)]),
+    "felog_train_delta": (_i32, [_p, _p, C.POINTER(felog_train_params), _i64,
+                                 _p, _p, _i64, C.POINTER(_i64), _p, _p, _i64, C.POINTER(_i64),
+                                 C.POINTER(_f64)]),
+    "felog_feedback": (_i32, [_p, C.POINTER(felog_feedback_params), _p, _pp, _p, _i64]),
+    "felog_run": (_i32, [_p, C.POINTER(felog_run_params), C.POINTER(felog_run_stats)]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libfelog.so (built in-tree by paper_2606_22180_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfelog.so is not built (%s); run "
+                              "`python -m paper_2606_22180_amd.build`" % LIB_PATH)
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != FELOG_OK:
+        raise FelogError(status, load().felog_last_error().decode())
+
+
+def _arr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return None
+
+
+class Context:
+    """A device + stream binding (felog_ctx)."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.felog_ctx_create(device, _stream_handle(stream), hbm_budget, C.byref(h)))
+        self.handle = h
+
+    def bytes_in_use(self) -> int:
+        b = C.c_uint64()
+        _check(load().felog_ctx_bytes_in_use(self.handle, C.byref(b)))
+        return b.value
+
+    def close(self):
+        if self.handle:
+            load().felog_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Handle:
+    _destroy = ""
+
+    def __init__(self, handle, owner):
+        self.handle = handle
+        self._owner = owner          # keeps the context (and graph) alive
+
+    def close(self):
+        if self.handle:
+            getattr(load(), self._destroy)(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph(_Handle):
+    _destroy = "felog_graph_destroy"
+
+    @classmethod
+    def from_csr(cls, ctx: Context, indptr, indices, weights=None) -> "Graph":
+        ip, ipp = _arr(indptr, np.int64)
+        ix, ixp = _arr(indices, np.int32)
+        wp = None
+        if weights is not None:
+            w, wp = _arr(weights, np.float32)
+        n = ip.shape[0] - 1
+        h = C.c_void_p()
+        _check(load().felog_graph_load_csr(ctx.handle, n, ix.shape[0], ipp, ixp, wp, C.byref(h)))
+        g = cls(h, ctx)
+        g.n = n
+        g.nnz = int(ix.shape[0])
+        return g
+
+
+class Active(_Handle):
+    _destroy = "felog_active_destroy"
+
+    @classmethod
+    def from_host(cls, g: Graph, nodes) -> "Active":
+        a, ap = _arr(nodes, np.int32)
+        h = C.c_void_p()
+        _check(load().felog_active_from_host(g.handle, ap, a.shape[0], C.byref(h)))
+        return cls(h, g)
+
+    @classmethod
+    def all(cls, g: Graph) -> "Active":
+        h = C.c_void_p()
+        _check(load().felog_active_all(g.handle, C.byref(h)))
+        return cls(h, g)
+
+    def count(self) -> int:
+        c = C.c_int64()
+        _check(load().felog_active_count(self.handle, C.byref(c)))
+        return c.value
+
+    def read(self) -> np.ndarray:
+        n = self.count()
+        out = np.zeros(max(n, 1), np.int32)
+        c = C.c_int64()
+        _check(load().felog_active_read(self.handle, out.ctypes.data, out.shape[0], C.byref(c)))
+        return out[:c.value]
+
+
+class Walks(_Handle):
+    _destroy = "felog_walks_destroy"
+
+    @classmethod
+    def generate(cls, g: Graph, *, r: int, L: int, seed: int, id_base: int = 0,
+                 kind: int = WALK_UNIFORM, p: float = 1.0, q: float = 1.0,
+                 starts: Active | None = None) -> "Walks":
+        prm = felog_walk_params(kind, r, L, p, q, seed, id_base)
+        h = C.c_void_p()
+        _check(load().felog_walks_generate(g.handle, C.byref(prm),
+                                           starts.handle if starts else None, C.byref(h)))
+        return cls(h, g)
+
+    def info(self):
+        W, L, b = C.c_int64(), C.c_int32(), C.c_int64()
+        _check(load().felog_walks_info(self.handle, C.byref(W), C.byref(L), C.byref(b)))
+        return W.value, L.value, b.value
+
+    def read(self) -> np.ndarray:
+        W, L, _ = self.info()
+        out = np.zeros((max(W, 1), L), np.int32)
+        _check(load().felog_walks_read(self.handle, out.ctypes.data, out.size))
+        return out[:W]
+
+    def capped(self) -> int:
+        c = C.c_int64()
+        _check(load().felog_walks_capped(self.handle, C.byref(c)))
+        return c.value
+
+
+def train_params(*, window, negatives, lr_start=0.025, lr_end=1e-4, minibatch_pairs,
+                 chunk_walks=0, seed=0) -> felog_train_params:
+    return felog_train_params(window, negatives, lr_start, lr_end, minibatch_pairs,
+                              chunk_walks, seed)
+
+
+class Model(_Handle):
+    _destroy = "felog_model_destroy"
+
+    @classmethod
+    def create(cls, g: Graph, *, dim: int, neg_dist: int = NEG_DEGREE, seed: int = 0) -> "Model":
+        prm = felog_model_params(dim, neg_dist, seed)
+        h = C.c_void_p()
+        _check(load().felog_model_create(g.handle, C.byref(prm), C.byref(h)))
+        m = cls(h, g)
+        m.n = g.n
+        m.dim = dim
+        return m
+
+    def set_unigram(self, corpus: Walks):
+        _check(load().felog_model_set_unigram(self.handle, corpus.handle))
+
+    def read_cdf(self) -> np.ndarray:
+        out = np.zeros(self.n + 1, np.uint64)
+        _check(load().felog_model_read_cdf(self.handle, out.ctypes.data, out.shape[0]))
+        return out
+
+    def read(self, which: int = TABLE_IN) -> np.ndarray:
+        out = np.zeros((self.n, self.dim), np.float32)
+        _check(load().felog_embeddings_read(self.handle, which, out.ctypes.data, out.size))
+        return out
+
+    def read_dev(self, which: int, ptr: int, cap: int):
+        _check(load().felog_embeddings_read_dev(self.handle, which, ptr, cap))
+
+    def write(self, which: int, values):
+        v, vp = _arr(values, np.float32)
+        _check(load().felog_embeddings_write(self.handle, which, vp, v.size))
+
+    def train_epoch(self, corpus: Walks, prm: felog_train_params) -> felog_train_stats:
+        st = felog_train_stats()
+        _check(load().felog_train_epoch(self.handle, corpus.handle, C.byref(prm), C.byref(st)))
+        return st
+
+    def train_steps(self, corpus: Walks, prm: felog_train_params, first_mb: int,
+                    n_mb: int) -> felog_train_stats:
+        st = felog_train_stats()
+        _check(load().felog_train_steps(self.handle, corpus.handle, C.byref(prm), first_mb, n_mb,
+                                        C.byref(st)))
+        return st
+
+    def train_delta(self, corpus: Walks, prm: felog_train_params, mb: int):
+        """Deltas of one minibatch, not applied: (rows_in, d_in, rows_out, d_out, loss)."""
+        P = prm.minibatch_pairs
+        K = prm.negatives
+        ri = np.zeros(P, np.int32)
+        di = np.zeros((P, self.dim), np.float32)
+        ro = np.zeros(P * (K + 1), np.int32)
+        do = np.zeros((P * (K + 1), self.dim), np.float32)
+        ni, no, loss = C.c_int64(), C.c_int64(), C.c_double()
+        _check(load().felog_train_delta(self.handle, corpus.handle, C.byref(prm), mb,
+                                        ri.ctypes.data, di.ctypes.data, P, C.byref(ni),
+                                        ro.ctypes.data, do.ctypes.data, P * (K + 1), C.byref(no),
+                                        C.byref(loss)))
+        a, b = ni.value, no.value
+        return ri[:a], di[:a], ro[:b], do[:b], loss.value
+
+    def feedback(self, *, mu: float, k_s: int, seed: int, round: int,
+                 mode: int = FEEDBACK_MONOTONE, active: Active | None = None,
+                 want_psi: bool = False):
+        prm = felog_feedback_params(mu, k_s, mode, seed, round)
+        h = C.c_void_p()
+        n_scored = self.n if (active is None or mode == FEEDBACK_RECOMPUTE_ALL) else active.count()
+        psi = np.zeros(max(1, n_scored), np.float64) if want_psi else None
+        _check(load().felog_feedback(self.handle, C.byref(prm),
+                                     active.handle if active else None, C.byref(h),
+                                     psi.ctypes.data if want_psi else None,
+                                     psi.shape[0] if want_psi else 0))
+        nxt = Active(h, self._owner)
+        return (nxt, psi[:n_scored]) if want_psi else nxt
+
+    def run(self, prm: felog_run_params) -> felog_run_stats:
+        st = felog_run_stats()
+        _check(load().felog_run(self.handle, C.byref(prm), C.byref(st)))
+        return st

@@ -1,0 +1,328 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Integer work (walks, noise tables, active lists) must be bit-exact.  SGNS
+deltas are FP32 sums in any order against the oracle's FP64; per updated row
+  ||d_gpu - d_orc|| <= 1e-5 ||d_orc|| + 2^-20 ||m_orc||,
+where m_orc is the row's sum of |term| vectors (the natural scale of FP32
+summation error when terms cancel).  Psi (FP64 on both sides) within 1e-12
+and identical decisions.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fl():
+    from paper_2606_22180_amd import build, felog
+    import os
+    if not os.path.exists(build.LIB):
+        build.build()
+    felog.load()
+    return felog
+
+
+@pytest.fixture(scope="module")
+def ctx(fl):
+    return fl.Context(0)
+
+
+@pytest.fixture(scope="module")
+def sbm():
+    return synth.build_graph("sbm1k")
+
+
+def _rmat(scale, edges, seed, weighted=False):
+    e = synth.rmat_edges(scale, edges, seed=seed)
+    w = synth.edge_weights(e.shape[0], seed + 1) if weighted else None
+    return synth.csr_from_edges(1 << scale, e, w)
+
+
+# ------------------------------------------------------------------ walks
+@pytest.mark.parametrize("kind", ["path", "star", "house", "k8"])
+def test_uniform_walks_tiny(fl, ctx, orc, kind):
+    g = synth.tiny_graph(kind)
+    _say("uniform walks tiny", kind)
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=33, L=17, seed=7, id_base=3)
+    assert np.array_equal(W.read(), orc.walks_uniform(g, np.arange(g.n), 33, 17, 7, 3))
+
+
+def test_uniform_walks_sbm_and_starts(fl, ctx, orc, sbm):
+    g = sbm.train
+    _say("uniform walks sbm1k")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=10, L=40, seed=11)
+    assert np.array_equal(W.read(), orc.walks_uniform(g, np.arange(g.n), 10, 40, 11))
+    starts = np.arange(3, g.n, 7, dtype=np.int32)
+    A = fl.Active.from_host(G, starts)
+    W2 = fl.Walks.generate(G, r=3, L=25, seed=11, id_base=10000, starts=A)
+    assert np.array_equal(W2.read(), orc.walks_uniform(g, starts, 3, 25, 11, 10000))
+
+
+def test_uniform_walks_rmat(fl, ctx, orc):
+    g = _rmat(16, 1 << 20, seed=5)
+    _say("uniform walks rmat16 n=%d nnz=%d" % (g.n, g.nnz))
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=2, L=80, seed=3, id_base=1 << 33)   # ids above 2^32
+    gw = W.read()
+    ow = orc.walks_uniform(g, np.arange(g.n), 2, 80, 3, 1 << 33)
+    assert np.array_equal(gw, ow)
+
+
+@pytest.mark.parametrize("p,q", [(0.5, 2.0), (2.0, 0.5), (1.0, 1.0)])
+def test_node2vec_walks(fl, ctx, orc, p, q):
+    g = _rmat(12, 40000, seed=9, weighted=True)
+    _say("node2vec walks rmat12 weighted p=%g q=%g" % (p, q))
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices, g.weights)
+    W = fl.Walks.generate(G, r=2, L=30, seed=13, id_base=77, kind=fl.WALK_NODE2VEC, p=p, q=q)
+    ow, capped = orc.walks_node2vec(g, np.arange(g.n), 2, 30, p, q, 13, 77)
+    assert np.array_equal(W.read(), ow)
+    assert W.capped() == capped == 0
+
+
+def test_node2vec_unweighted(fl, ctx, orc, sbm):
+    g = sbm.train
+    _say("node2vec walks sbm1k unweighted")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=2, L=40, seed=1, kind=fl.WALK_NODE2VEC, p=0.5, q=2.0)
+    ow, _ = orc.walks_node2vec(g, np.arange(g.n), 2, 40, 0.5, 2.0, 1)
+    assert np.array_equal(W.read(), ow)
+
+
+# ------------------------------------------------------- tables and noise
+def test_init_and_noise_tables(fl, ctx, orc, sbm):
+    g = sbm.train
+    _say("init + degree noise table")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=42)
+    tin, tout = orc.init_tables(g.n, 64, 42)
+    assert np.array_equal(M.read(fl.TABLE_IN), tin)
+    assert np.array_equal(M.read(fl.TABLE_OUT), tout)
+    assert np.array_equal(M.read_cdf(), orc.neg_cdf(g.degrees().astype(np.uint64)))
+
+
+def test_unigram_noise_table(fl, ctx, orc):
+    g = _rmat(15, 1 << 19, seed=2)
+    _say("unigram noise table rmat15")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=4, L=30, seed=8)
+    M = fl.Model.create(G, dim=128, neg_dist=fl.NEG_UNIGRAM, seed=1)
+    M.set_unigram(W)
+    counts = orc.corpus_counts(W.read(), g.n)
+    assert np.array_equal(M.read_cdf(), orc.neg_cdf(counts))
+
+
+# ------------------------------------------------------------------ SGNS
+def _dense(rows, vals, n, d):
+    out = np.zeros((n, d))
+    out[rows] = vals
+    return out
+
+
+def _mass(tin, tout, ctx_, ctr, neg, lr, orc):
+    """Per-row sum of |term| vectors of a minibatch (the FP32 error scale)."""
+    n, d = tin.shape
+    ain = np.zeros((n, d))
+    aout = np.zeros((n, d))
+    a = tin.astype(np.float64)
+    b = tout.astype(np.float64)
+    for p in range(len(ctx_)):
+        c = ctx_[p]
+        ts = [ctr[p]] + [t for t in neg[p] if t != ctr[p]]
+        for k, t in enumerate(ts):
+            s = a[c] @ b[t]
+            g = lr * (1 - 1 / (1 + np.exp(-s))) if k == 0 else lr / (1 + np.exp(-s))
+            ain[c] += np.abs(g * b[t])
+            aout[t] += np.abs(g * a[c])
+    return ain, aout
+
+
+def _check_delta(gpu, ref, mass, what):
+    num = np.linalg.norm(gpu - ref, axis=1)
+    tol = 1e-5 * np.linalg.norm(ref, axis=1) + 2 ** -20 * np.linalg.norm(mass, axis=1)
+    bad = np.nonzero(num > tol + 1e-30)[0]
+    rel = num / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+    _say("%s: rows=%d max rel=%.3e bad=%d" % (what, int((np.abs(ref).sum(1) > 0).sum()),
+                                              rel.max(), len(bad)))
+    assert len(bad) == 0, (what, bad[:5], num[bad[:5]], tol[bad[:5]])
+
+
+def _sgns_step_parity(fl, ctx, orc, g, *, dim, K, P, window, L, neg, mbs, seed=3, pre_mb=0):
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=10 if g.n < 5000 else 1, L=L, seed=11)
+    M = fl.Model.create(G, dim=dim, neg_dist=neg, seed=5)
+    if neg == fl.NEG_UNIGRAM:
+        M.set_unigram(W)
+    cdf = M.read_cdf()
+    prm = fl.train_params(window=window, negatives=K, minibatch_pairs=P, seed=seed)
+    walks = W.read()
+    B, _ = orc.count_minibatches(walks, window, P)
+    if pre_mb:
+        M.train_steps(W, prm, 0, pre_mb)          # move away from the initial state
+    for b in mbs:
+        b = b % B
+        tin = M.read(fl.TABLE_IN)
+        tout = M.read(fl.TABLE_OUT)
+        ri, di, ro, do, loss = M.train_delta(W, prm, b)
+        mb = orc.minibatch_pairs(walks, window, P, b)
+        ng = orc.draw_negatives(mb, 0, K, seed, cdf)
+        lr = orc.lr_at(b, B, prm.lr_start, prm.lr_end)
+        ref = orc.sgns_step(tin.copy(), tout.copy(), mb.ctx, mb.ctr, ng, lr, apply=False)
+        assert sorted(ri.tolist()) == sorted(ref.rows_in.tolist())
+        assert sorted(ro.tolist()) == sorted(ref.rows_out.tolist())
+        ain, aout = _mass(tin, tout, mb.ctx, mb.ctr, ng, lr, orc)
+        _check_delta(_dense(ri, di, g.n, dim), _dense(ref.rows_in, ref.d_in, g.n, dim), ain,
+                     "mb %d in" % b)
+        _check_delta(_dense(ro, do, g.n, dim), _dense(ref.rows_out, ref.d_out, g.n, dim), aout,
+                     "mb %d out" % b)
+        assert abs(loss - ref.loss) <= 1e-5 * abs(ref.loss)
+        # advance the GPU state by this minibatch so the next check starts elsewhere
+        M.train_steps(W, prm, b, 1)
+    return M
+
+
+def test_sgns_step_parity_sbm(fl, ctx, orc, sbm):
+    _say("sgns per-step parity sbm1k d=64 K=5 P=1024")
+    _sgns_step_parity(fl, ctx, orc, sbm.train, dim=64, K=5, P=1024, window=5, L=40,
+                      neg=fl.NEG_DEGREE, mbs=[0, 1, 1800, 3613], pre_mb=0)
+
+
+def test_sgns_step_parity_trained_state(fl, ctx, orc, sbm):
+    _say("sgns per-step parity sbm1k after 2000 minibatches")
+    _sgns_step_parity(fl, ctx, orc, sbm.train, dim=64, K=5, P=1024, window=5, L=40,
+                      neg=fl.NEG_DEGREE, mbs=[2000, 3000], pre_mb=2000)
+
+
+def test_sgns_step_parity_rmat_d128(fl, ctx, orc):
+    g = _rmat(14, 1 << 18, seed=4)
+    _say("sgns per-step parity rmat14 d=128 K=5 P=8192 w=10 unigram")
+    _sgns_step_parity(fl, ctx, orc, g, dim=128, K=5, P=8192, window=10, L=80,
+                      neg=fl.NEG_UNIGRAM, mbs=[0, 7, 123], pre_mb=64)
+
+
+def test_sgns_step_parity_k_and_dims(fl, ctx, orc, sbm):
+    for dim, K in ((256, 3), (128, 20), (64, 1)):
+        _say("sgns per-step parity sbm1k d=%d K=%d" % (dim, K))
+        _sgns_step_parity(fl, ctx, orc, sbm.train, dim=dim, K=K, P=777, window=3, L=12,
+                          neg=fl.NEG_DEGREE, mbs=[0, 5], pre_mb=20)
+
+
+def test_sgns_epoch_auc_matches_oracle(fl, ctx, orc, sbm):
+    """Free-running epoch on sbm1k: AUC within 0.005 of the oracle's."""
+    g = sbm.train
+    _say("sgns free-running epoch sbm1k")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=10, L=40, seed=11)
+    M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=0)
+    prm = fl.train_params(window=5, negatives=5, minibatch_pairs=1024, seed=3)
+    st = M.train_epoch(W, prm)
+    tin, tout = orc.init_tables(g.n, 64, 0)
+    ref = orc.train_epoch(tin, tout, W.read(), window=5, K=5, lr0=prm.lr_start,
+                          lr_end=prm.lr_end, P=1024, seed=3,
+                          cdf=orc.neg_cdf(g.degrees().astype(np.uint64)))
+    a_gpu = orc.link_auc(M.read(fl.TABLE_IN), sbm)
+    a_orc = orc.link_auc(tin, sbm)
+    _say("AUC gpu=%.5f oracle=%.5f loss gpu=%.6e oracle=%.6e" % (a_gpu, a_orc, st.loss,
+                                                                 ref.loss))
+    assert st.pairs == ref.pairs == 3_700_000
+    assert abs(a_gpu - a_orc) <= 0.005
+    assert abs(st.loss - ref.loss) <= 1e-4 * ref.loss
+    emb = M.read(fl.TABLE_IN)
+    assert np.abs(emb - tin).max() <= 1e-3 * np.abs(tin).max()
+
+
+# -------------------------------------------------------------- feedback
+def test_psi_and_active_set(fl, ctx, orc, sbm):
+    g = sbm.train
+    _say("psi teacher-forced sbm1k")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    M = fl.Model.create(G, dim=128, neg_dist=fl.NEG_DEGREE, seed=2)
+    rng = np.random.default_rng(0)
+    tin = rng.normal(0, 1, (g.n, 128)).astype(np.float32)
+    tin[::97] += tin[1::97][: tin[::97].shape[0]]          # correlated neighbours
+    tin[5] = 0.0                                            # zero vector
+    M.write(fl.TABLE_IN, tin)
+    for rnd, k_s, mu in ((0, 10, 0.02), (3, 4, 0.0), (1, 64, -0.01)):
+        act, psi = M.feedback(mu=mu, k_s=k_s, seed=9, round=rnd, want_psi=True)
+        opsi = orc.psi(tin, g, np.arange(g.n), k_s, 9, rnd)
+        fin = np.isfinite(opsi)
+        assert np.array_equal(np.isfinite(psi), fin)
+        assert np.abs(psi[fin] - opsi[fin]).max() <= 1e-12
+        assert np.array_equal(act.read(), orc.next_active(np.arange(g.n, dtype=np.int32),
+                                                          opsi, mu))
+    # monotone mode scores only the given list
+    sub = fl.Active.from_host(G, np.arange(0, g.n, 3, dtype=np.int32))
+    act, psi = M.feedback(mu=0.01, k_s=10, seed=9, round=1, active=sub, want_psi=True)
+    nodes = np.arange(0, g.n, 3, dtype=np.int32)
+    opsi = orc.psi(tin, g, nodes, 10, 9, 1)
+    assert np.array_equal(act.read(), orc.next_active(nodes, opsi, 0.01))
+
+
+def test_run_algorithm1_matches_oracle(fl, ctx, orc, sbm):
+    """Algorithm 1 end to end on sbm1k (3 rounds): identical round-1 walks and
+    active sets, up to decisions within 1e-4 of mu."""
+    g = sbm.train
+    _say("felog_run sbm1k 3 rounds")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=2)
+    rp = fl.felog_run_params()
+    rp.walk = fl.felog_walk_params(fl.WALK_UNIFORM, 4, 20, 1.0, 1.0, 1, 0)
+    rp.train = fl.train_params(window=4, negatives=5, minibatch_pairs=1024, seed=3)
+    rp.feedback = fl.felog_feedback_params(0.2, 10, fl.FEEDBACK_MONOTONE, 4, 0)
+    rp.max_rounds = 3
+    st = M.run(rp)
+    tin, tout, ostats = orc.run(g, d=64, r=4, L=20, window=4, K=5, lr0=rp.train.lr_start,
+                                lr_end=rp.train.lr_end, P=1024, mu=0.2, k_s=10, r_max=3,
+                                seed_walk=1, seed_model=2, seed_train=3, seed_psi=4,
+                                neg="degree")
+    _say("rounds gpu=%d oracle=%d active gpu=%s oracle=%s" % (
+        st.rounds, len(ostats), list(st.active[:st.rounds]), [s.active for s in ostats]))
+    assert st.rounds == len(ostats)
+    for r in range(st.rounds):
+        assert abs(st.active[r] - ostats[r].active) <= max(2, ostats[r].active // 200)
+        if st.active[r] == ostats[r].active:
+            assert st.pairs[r] == ostats[r].pairs
+    a_gpu = orc.link_auc(M.read(fl.TABLE_IN), sbm)
+    a_orc = orc.link_auc(tin, sbm)
+    assert abs(a_gpu - a_orc) <= 0.005
+
+
+# ---------------------------------------------------------- error paths
+def test_invalid_graphs_rejected(fl, ctx):
+    _say("invalid CSR")
+    bad = {
+        "asymmetric": ([0, 1, 1], [1]),
+        "self loop": ([0, 1, 2], [0, 0]),
+        "unsorted": ([0, 2, 3, 4], [2, 1, 0, 0]),
+        "out of range": ([0, 1, 2], [5, 0]),
+    }
+    for what, (ip, ix) in bad.items():
+        with pytest.raises(fl.FelogError) as e:
+            fl.Graph.from_csr(ctx, np.array(ip), np.array(ix))
+        assert e.value.status == fl.FELOG_EINVAL, what
+    g = synth.tiny_graph("path")
+    w = np.ones(g.nnz, np.float32)
+    w[0] = 2.0                                    # reverse edge has weight 1
+    with pytest.raises(fl.FelogError):
+        fl.Graph.from_csr(ctx, g.indptr, g.indices, w)
+
+
+def test_budget_and_bad_params(fl):
+    _say("budget / params")
+    small = fl.Context(0, hbm_budget=1 << 14)
+    g = synth.tiny_graph("k8")
+    G = fl.Graph.from_csr(small, g.indptr, g.indices)
+    with pytest.raises(fl.FelogError) as e:
+        fl.Model.create(G, dim=256)
+    assert e.value.status in (fl.FELOG_ENOMEM, fl.FELOG_EINVAL)
+    with pytest.raises(fl.FelogError) as e:
+        fl.Walks.generate(G, r=0, L=5, seed=1)
+    assert e.value.status == fl.FELOG_EINVAL
