@@ -146,25 +146,18 @@ def _arr(a, dtype):
     return a, a.ctypes.data
 
 
-def _stream_handle(stream):
-    if stream is not None:
-        return stream
-    try:
-        import torch
-        if torch.cuda.is_available():
-            return torch.cuda.current_stream().cuda_stream
-    except ImportError:
-        pass
-    return None
-
-
 class Context:
-    """A device + stream binding (felog_ctx)."""
+    """A device + stream binding (felog_ctx).
+
+    ``stream`` is a hipStream_t handle as an int (e.g. torch's
+    ``torch.cuda.current_stream().cuda_stream``) or None for the null stream.
+    A process that also uses torch on the GPU must import torch before this
+    module loads the library, so that both share torch's HIP runtime."""
 
     def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
         lib = load()
         h = C.c_void_p()
-        _check(lib.felog_ctx_create(device, _stream_handle(stream), hbm_budget, C.byref(h)))
+        _check(lib.felog_ctx_create(device, stream, hbm_budget, C.byref(h)))
         self.handle = h
 
     def bytes_in_use(self) -> int:
