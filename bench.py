@@ -1,0 +1,215 @@
+"""Benchmark of the FeLoG hot path on one MI355X.
+
+One step = Algorithm 1 end to end on the R-MAT 2^20 workload: walks from the
+active set, one SGNS training call per round, the Psi feedback and the
+active-set compaction, until the active set is empty or 4 rounds ran.  The
+graph is resident in HBM before the timed region; each step re-initialises the
+embedding tables so that every step does the same work.
+
+Prints one JSON line (see the keys below).  `--gpus N` with N > 1 is refused:
+this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SGNS pair-updates/s + walk steps/s at matched link-pred AUC; p99 job latency"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "sgns_forward_rmat20_counters.json")
+FORWARD_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def auc_score(emb: np.ndarray, pos: np.ndarray, neg: np.ndarray) -> float:
+    """Link-prediction AUC (Section 6.4): score phi(u).phi(v), Mann-Whitney."""
+    from sklearn.metrics import roc_auc_score
+    e = emb.astype(np.float64)
+    sp = np.einsum("ij,ij->i", e[pos[:, 0]], e[pos[:, 1]])
+    sn = np.einsum("ij,ij->i", e[neg[:, 0]], e[neg[:, 1]])
+    y = np.r_[np.ones(sp.shape[0]), np.zeros(sn.shape[0])]
+    return float(roc_auc_score(y, np.r_[sp, sn]))
+
+
+def forward_traffic():
+    """HBM bytes per forward launch from the committed rocprofv3 counters, if
+    they were taken on the current kernel source; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    rec = json.load(open(COUNTERS))
+    src = hashlib.sha256(open(FORWARD_SRC, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != src:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(g, cfg, n_walks: int, n_mb: int):
+    """The CPU oracle as it stands, on a bounded sample of the same workload:
+    the first n_walks walks of round 1 and the first n_mb minibatches of SGNS
+    over that sub-corpus.  Single-threaded C."""
+    import oracle
+    t0 = time.perf_counter()
+    walks = oracle.walks_uniform(g, np.arange(n_walks, dtype=np.int32), 1, cfg["L"], cfg["seed_walk"])
+    t_walk = time.perf_counter() - t0
+    steps = int((walks[:, 1:] >= 0).sum())
+    cdf = oracle.neg_cdf(oracle.corpus_counts(walks, g.n))
+    tin, tout = oracle.init_tables(g.n, cfg["dim"], cfg["seed_model"])
+    t1 = time.perf_counter()
+    tr = oracle.train_epoch(tin, tout, walks, window=cfg["window"], K=cfg["K"],
+                            lr0=float(np.float32(cfg["lr0"])), lr_end=float(np.float32(cfg["lr_end"])),
+                            P=cfg["minibatch"], seed=cfg["seed_train"], cdf=cdf, mb_end=n_mb)
+    t_train = time.perf_counter() - t1
+    return {
+        "value": tr.pairs / t_train, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
+        "walk_steps_per_s": steps / t_walk,
+        "sample": "first %d round-1 walks (%d steps, %.1f s) and the first %d minibatches "
+                  "of %d pairs over that sub-corpus (%d pairs, %.1f s), single thread"
+                  % (n_walks, steps, t_walk, n_mb, cfg["minibatch"], tr.pairs, t_train),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--max-rounds", type=int, default=4)
+    ap.add_argument("--timing-every", type=int, default=16,
+                    help="time every n-th forward/apply launch with HIP events")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-walks", type=int, default=1 << 17)
+    ap.add_argument("--cpu-minibatches", type=int, default=30)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    from paper_2606_22180_amd import build as hipbuild
+    from paper_2606_22180_amd import felog
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build()
+
+    preset = synth.CONFIGS["rmat20"]
+    cfg = dict(L=preset["L"], r=preset["r"], window=preset["window"], K=preset["K"],
+               dim=preset["dim"], minibatch=preset["minibatch"], lr0=preset["lr0"],
+               lr_end=preset["lr_end"], mu=preset["mu"], k_s=preset["k_s"],
+               r_max=args.max_rounds, seed_walk=1, seed_model=2, seed_train=3, seed_psi=4)
+    t = time.perf_counter()
+    split = synth.build_graph("rmat20")
+    g = split.train
+    log("graph n=%d nnz=%d isolated=%d (%.1f s)" % (g.n, g.nnz, int((g.degrees() == 0).sum()),
+                                                   time.perf_counter() - t))
+
+    ctx = felog.Context(0)
+    G = felog.Graph.from_csr(ctx, g.indptr, g.indices)
+    M = felog.Model.create(G, dim=cfg["dim"], neg_dist=felog.NEG_UNIGRAM, seed=cfg["seed_model"])
+    rp = felog.felog_run_params()
+    rp.walk = felog.felog_walk_params(felog.WALK_UNIFORM, cfg["r"], cfg["L"], 1.0, 1.0,
+                                      cfg["seed_walk"], 0)
+    rp.train = felog.train_params(window=cfg["window"], negatives=cfg["K"], lr_start=cfg["lr0"],
+                                  lr_end=cfg["lr_end"], minibatch_pairs=cfg["minibatch"],
+                                  seed=cfg["seed_train"])
+    rp.feedback = felog.felog_feedback_params(cfg["mu"], cfg["k_s"], felog.FEEDBACK_MONOTONE,
+                                              cfg["seed_psi"], 0)
+    rp.max_rounds = cfg["r_max"]
+
+    def step():
+        M.reset(cfg["seed_model"])
+        t0 = time.perf_counter()
+        st = M.run(rp)
+        return st, time.perf_counter() - t0
+
+    for i in range(args.warmup):
+        st, dt = step()
+        log("warmup %d: %.2f s, rounds=%d" % (i, dt, st.rounds))
+
+    ctx.set_timing(args.timing_every)
+    times = []
+    st = None
+    for i in range(args.steps):
+        st, dt = step()
+        times.append(dt)
+        log("step %d: %.2f s, rounds=%d active=%s" % (i, dt, st.rounds,
+                                                       list(st.active[:st.rounds])))
+    ctx.set_timing(0)
+    total = float(np.sum(times))
+    R = st.rounds
+    rounds = []
+    pairs = walk_steps = 0
+    fwd_ms = apply_ms = 0.0
+    timed = 0
+    mbs = rows = 0
+    ms_walk = 0.0
+    for r in range(R):
+        tr = st.train[r]
+        pairs += tr.pairs
+        walk_steps += st.walk_steps[r]
+        fwd_ms += tr.ms_forward
+        apply_ms += tr.ms_apply
+        timed += tr.timed_launches
+        mbs += tr.minibatches
+        rows += tr.rows_in + tr.rows_out
+        ms_walk += st.ms_walk[r]
+        rounds.append(dict(active=int(st.active[r]), walks=int(st.walks[r]),
+                           walk_steps=int(st.walk_steps[r]), pairs=int(tr.pairs),
+                           loss_per_pair=tr.loss / max(1, tr.pairs), ms_walk=st.ms_walk[r],
+                           ms_train=tr.ms, ms_feedback=st.ms_feedback[r],
+                           minibatches=int(tr.minibatches)))
+    pairs_per_step = pairs
+    value = pairs_per_step * len(times) / total
+    emb = M.read(felog.TABLE_IN)
+    auc = auc_score(emb, split.test_pos, split.test_neg)
+    log("pairs/step=%d walk_steps/step=%d value=%.4g pairs/s auc=%.4f" % (
+        pairs_per_step, walk_steps, value, auc))
+
+    # roofline of the dominant kernel (SGNS forward): algorithmic bytes per launch =
+    # each distinct touched row read once (d*4 B) and its delta written once (d*4 B),
+    # plus the pair's node ids (2*4 B) and one 8 B cumulative-weight read per negative.
+    d = cfg["dim"]
+    alg_bytes = rows * d * 8 + pairs * (8 + 8 * cfg["K"])
+    per_launch = alg_bytes / max(1, mbs)
+    avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
+    achieved = per_launch / avg_fwd_s / 1e9 if timed else None
+    traffic = forward_traffic()
+    roof = {"bound": "hbm", "kernel": "sgns_forward_kernel<2,5>", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_fwd_s * 1e6,
+            "timed_launches": timed, "avg_apply_us": apply_ms / 1e3 / max(1, timed) * 1e6}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "pair-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / len(times) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rmat20: R-MAT scale 20 (a,b,c = .57,.19,.19), 2^24 undirected "
+                               "edges with 10% held out, uniform walks r=10 L=80, SGNS d=128 "
+                               "w=10 K=5 unigram^0.75 minibatch 65536, FeeST mu=0.65 k_s=10 "
+                               "monotone, at most %d rounds" % cfg["r_max"],
+                   "nodes": g.n, "csr_entries": g.nnz},
+        "walk_steps_per_s": walk_steps * len(times) / (ms_walk / 1e3 * len(times)),
+        "walk_steps_per_step": int(walk_steps), "pairs_per_step": int(pairs_per_step),
+        "link_pred_auc": auc, "rounds": rounds, "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, cfg, args.cpu_walks, args.cpu_minibatches)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

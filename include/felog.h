@@ -66,6 +66,11 @@ void felog_ctx_destroy(felog_ctx* ctx);
 /* Device bytes currently held by handles of this context. */
 felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes);
 
+/* Kernel timing: with every > 0, training brackets every `every`-th forward
+ * and apply launch with HIP events on the context's stream and reports their
+ * summed durations in felog_train_stats (0 = off, the default). */
+felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every);
+
 /* Message for the calling thread's last failed call ("" if none). */
 const char* felog_last_error(void);
 
@@ -119,9 +124,10 @@ typedef struct felog_walk_params {
 /* Generate r walks per start node.  Walk i (0 <= i < r * |starts|) has id
  * id_base + i and starts at starts[i mod |starts|] (starts = NULL: all nodes).
  * Uniform: transition t moves to neighbour floor(x0 * deg / 2^32), x0 from
- * Philox(key = seed, counter = (id, t, 0, 1 << 24)).  node2vec: rejection
- * sampling of w(v,x) * alpha(t,x) with alpha = 1/p, 1, 1/q (return, common
- * neighbour, outward); attempt a uses counter (id, t, 0, 2 << 24 | a).
+ * Philox(key = seed, counter = (id low, id high, t, 1 << 24)).  node2vec:
+ * rejection sampling of w(v,x) * alpha(t,x) with alpha = 1/p, 1, 1/q (return,
+ * common neighbour, outward); attempt a uses counter (id low, id high, t,
+ * 2 << 24 | a).
  * A start node without neighbours gives a one-node walk.  The walks stay on
  * the device. */
 felog_status felog_walks_generate(felog_graph* g, const felog_walk_params* params,
@@ -149,7 +155,8 @@ typedef struct felog_model_params {
 } felog_model_params;
 
 /* Create FP32 tables [n][d]: in[v][c] = ((x >> 8) * 2^-24 - 0.5) / d with x
- * word c mod 4 of Philox(key = seed, counter = (v, c / 4, 0, 4 << 24)); out = 0.
+ * word c mod 4 of Philox(key = seed, counter = (v low, v high, c / 4, 4 << 24));
+ * out = 0.
  * With FELOG_NEG_DEGREE the noise distribution is degree^0.75 at once; with
  * FELOG_NEG_UNIGRAM it is set from the first corpus passed to training. */
 felog_status felog_model_create(felog_graph* g, const felog_model_params* params,
@@ -170,6 +177,10 @@ felog_status felog_embeddings_read(const felog_model* m, int32_t which, float* h
 /* Same into device memory (e.g. a torch tensor's data pointer) on the context's stream. */
 felog_status felog_embeddings_read_dev(const felog_model* m, int32_t which, void* dev,
                                        int64_t cap);
+/* Re-initialise the tables as felog_model_create does (in from `seed`,
+ * out = 0); a unigram noise distribution is cleared so that the next
+ * felog_run sets it again from its first round. */
+felog_status felog_model_reset(felog_model* m, uint64_t seed);
 /* Overwrite a table from host memory (count = n * d floats). */
 felog_status felog_embeddings_write(felog_model* m, int32_t which, const float* host,
                                     int64_t count);
@@ -195,6 +206,11 @@ typedef struct felog_train_stats {
     double loss;              /* sum over the call's pairs of -log sigma(s0)
                                  - sum_k log sigma(-s_k), FP64                     */
     double ms;                /* device time of the call                           */
+    int64_t rows_in;          /* sum over minibatches of distinct in-rows updated  */
+    int64_t rows_out;         /* sum over minibatches of distinct out-rows updated */
+    int64_t timed_launches;   /* forward (and apply) launches timed with events    */
+    double ms_forward;        /* summed duration of the timed forward launches     */
+    double ms_apply;          /* summed duration of the timed apply launches       */
 } felog_train_stats;
 
 /* One Train() call: every minibatch of the corpus in order.  Pairs: within each
@@ -204,9 +220,9 @@ typedef struct felog_train_stats {
  * row and then added:
  *   g0 = lr (1 - sigma(in[c].out[t0])),  gk = -lr sigma(in[c].out[tk])
  *   delta in[c] += sum_k gk out[tk],   delta out[tk] += gk in[c].
- * Negative k of a pair is drawn with Philox(key = seed, counter = (walk id,
- * j << 8 | slot, 0, 3 << 24 | k / 2)); a negative equal to the centre is
- * skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1). */
+ * Negative k of a pair uses words 2(k mod 2), 2(k mod 2)+1 (low, high) of
+ * Philox(key = seed, counter = (walk id low, walk id high, j << 8 | slot,
+ * 3 << 24 | k / 2)); a negative equal to the centre is skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1). */
 felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
                                const felog_train_params* params, felog_train_stats* stats);
 /* Minibatches [first_mb, first_mb + n_mb) of the same schedule (the tables must
@@ -265,10 +281,9 @@ typedef struct felog_run_stats {
     int64_t active[FELOG_MAX_ROUNDS];      /* |V_a| at the start of each round   */
     int64_t walks[FELOG_MAX_ROUNDS];
     int64_t walk_steps[FELOG_MAX_ROUNDS];  /* transitions taken                  */
-    int64_t pairs[FELOG_MAX_ROUNDS];
-    double loss[FELOG_MAX_ROUNDS];
-    double ms_walk[FELOG_MAX_ROUNDS], ms_train[FELOG_MAX_ROUNDS],
-           ms_feedback[FELOG_MAX_ROUNDS];
+    double ms_walk[FELOG_MAX_ROUNDS];
+    double ms_feedback[FELOG_MAX_ROUNDS];
+    felog_train_stats train[FELOG_MAX_ROUNDS];
     int64_t final_active;                  /* |V_a| after the last round         */
 } felog_run_stats;
 

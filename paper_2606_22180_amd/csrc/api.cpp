@@ -153,7 +153,22 @@ void felog_ctx_destroy(felog_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (hipEvent_t e : ctx->timing_pool) (void)hipEventDestroy(e);
     delete ctx;
+}
+
+felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every)
+{
+    return guarded([&] {
+        NEED(ctx);
+        FELOG_REQUIRE(every >= 0, "every must be >= 0");
+        ctx->make_current();
+        if (every > 0 && ctx->timing_pool.empty()) {
+            ctx->timing_pool.resize(3 * 256);
+            for (hipEvent_t& e : ctx->timing_pool) FELOG_HIP(hipEventCreate(&e));
+        }
+        ctx->timing_every = every;
+    });
 }
 
 felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes)
@@ -426,6 +441,7 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
         m->stamp_in.alloc(c, sizeof(uint32_t) * g->n);
         m->stamp_out.alloc(c, sizeof(uint32_t) * g->n);
         m->counters.alloc(c, sizeof(uint32_t) * 4);
+        m->row_totals.alloc(c, sizeof(uint64_t) * 2);
         m->loss_out.alloc(c, sizeof(double));
         FELOG_HIP(hipMemsetAsync(m->din.ptr, 0, tb, c->stream));
         FELOG_HIP(hipMemsetAsync(m->dout.ptr, 0, tb, c->stream));
@@ -446,6 +462,16 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
 }
 
 void felog_model_destroy(felog_model* m) { delete m; }
+
+felog_status felog_model_reset(felog_model* m, uint64_t seed)
+{
+    return guarded([&] {
+        NEED(m);
+        launch_init_tables(*m, seed);
+        if (m->neg_dist == FELOG_NEG_UNIGRAM) m->have_noise = false;
+        m->ctx->sync();
+    });
+}
 
 felog_status felog_model_set_unigram(felog_model* m, const felog_walks* corpus)
 {
@@ -658,15 +684,12 @@ felog_status felog_run(felog_model* m, const felog_run_params* p, felog_run_stat
                 c->sync();
             }
             check_train_params(m, w.get(), &p->train);
-            felog_train_stats ts{};
+            felog_train_stats& ts = st.train[r];
             train_minibatches(*m, *w, p->train, 0, -1, true, &ts, nullptr, nullptr, 0, nullptr,
                               nullptr, nullptr, 0, nullptr);
             st.active[r] = n_active;
             st.walks[r] = w->W;
             st.walk_steps[r] = w->n_valid * (int64_t)(w->L - 1);
-            st.pairs[r] = ts.pairs;
-            st.loss[r] = ts.loss;
-            st.ms_train[r] = ts.ms;
             id_base += w->W;
             w.reset();
             felog_feedback_params fp = p->feedback;

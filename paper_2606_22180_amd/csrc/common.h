@@ -66,6 +66,8 @@ struct Ctx {
     uint64_t in_use = 0;
     int num_cus = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int32_t timing_every = 0;             // time every n-th training launch (0 = off)
+    std::vector<hipEvent_t> timing_pool;  // 3 events per timed minibatch
     void make_current() const;
     void sync() const;
 };
@@ -123,8 +125,8 @@ struct Model {
     int32_t cap_K = 0;
     DevBuf touched_in, touched_out;   // int32 lists
     DevBuf counters;          // uint32 [4]: touched counts, double-buffered by serial parity
-    DevBuf loss_part;         // double [waves]
     DevBuf loss_out;          // double [1]
+    DevBuf row_totals;        // uint64 [2]: summed touched-list lengths (in, out)
 };
 
 // ---------------------------------------------------------------------------

@@ -262,7 +262,8 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(float* __restrict__ tin
                                                          float* __restrict__ dout,
                                                          const int32_t* __restrict__ list_in,
                                                          const int32_t* __restrict__ list_out,
-                                                         const uint32_t* cnt, uint32_t* cnt_next)
+                                                         const uint32_t* cnt, uint32_t* cnt_next,
+                                                         unsigned long long* row_totals)
 {
     constexpr int D = 64 * VPL;
     const int lane = threadIdx.x & 63;
@@ -284,6 +285,8 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(float* __restrict__ tin
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         cnt_next[0] = 0;
         cnt_next[1] = 0;
+        row_totals[0] += n_in;
+        row_totals[1] += n_out;
     }
 }
 
@@ -435,6 +438,24 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     loss_part.alloc(&c, sizeof(double) * blocks * 4);
     FELOG_HIP(hipMemsetAsync(loss_part.ptr, 0, sizeof(double) * blocks * 4, c.stream));
     FELOG_HIP(hipMemsetAsync(m.counters.ptr, 0, sizeof(uint32_t) * 4, c.stream));
+    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
+
+    // sampled kernel timing: events before forward, between forward and apply, after apply
+    const int every = apply ? c.timing_every : 0;
+    const size_t pool = c.timing_pool.size() / 3;
+    size_t next_slot = 0, used_slots = 0;
+    int64_t timed = 0;
+    double ms_fwd = 0.0, ms_apply = 0.0;
+    auto harvest = [&](size_t slot) {
+        hipEvent_t* e = &c.timing_pool[3 * slot];
+        FELOG_HIP(hipEventSynchronize(e[2]));
+        float f = 0.0f, ap = 0.0f;
+        FELOG_HIP(hipEventElapsedTime(&f, e[0], e[1]));
+        FELOG_HIP(hipEventElapsedTime(&ap, e[1], e[2]));
+        ms_fwd += f;
+        ms_apply += ap;
+        ++timed;
+    };
 
     std::vector<int32_t> sl = make_slices(w.L, p.window);
     DevBuf slices;
@@ -482,22 +503,36 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         a.serial = m.serial;
         a.cnt = m.counters.as<uint32_t>() + 2 * parity;
         int64_t nwaves = (np + ppw - 1) / ppw;
+        const bool timed_mb = every > 0 && pool > 0 && (b - first_mb) % every == 0;
+        hipEvent_t* ev = nullptr;
+        if (timed_mb) {
+            if (used_slots == pool) harvest(next_slot);   // reuse the oldest slot
+            else ++used_slots;
+            ev = &c.timing_pool[3 * next_slot];
+            next_slot = (next_slot + 1) % pool;
+            FELOG_HIP(hipEventRecord(ev[0], c.stream));
+        }
         launch_forward(m.dim, K, dim3((uint32_t)((nwaves + 3) / 4)), c.stream, a);
+        if (timed_mb) FELOG_HIP(hipEventRecord(ev[1], c.stream));
         if (apply) {
             uint32_t* next = m.counters.as<uint32_t>() + 2 * (1 - parity);
             if (m.dim == 64)
                 hipLaunchKernelGGL(sgns_apply_kernel<1>, dim3(apply_blocks), dim3(256), 0,
                                    c.stream, m.tin.as<float>(), m.tout.as<float>(), a.din,
-                                   a.dout, a.list_in, a.list_out, a.cnt, next);
+                                   a.dout, a.list_in, a.list_out, a.cnt, next,
+                                   m.row_totals.as<unsigned long long>());
             else if (m.dim == 128)
                 hipLaunchKernelGGL(sgns_apply_kernel<2>, dim3(apply_blocks), dim3(256), 0,
                                    c.stream, m.tin.as<float>(), m.tout.as<float>(), a.din,
-                                   a.dout, a.list_in, a.list_out, a.cnt, next);
+                                   a.dout, a.list_in, a.list_out, a.cnt, next,
+                                   m.row_totals.as<unsigned long long>());
             else
                 hipLaunchKernelGGL(sgns_apply_kernel<4>, dim3(apply_blocks), dim3(256), 0,
                                    c.stream, m.tin.as<float>(), m.tout.as<float>(), a.din,
-                                   a.dout, a.list_in, a.list_out, a.cnt, next);
+                                   a.dout, a.list_in, a.list_out, a.cnt, next,
+                                   m.row_totals.as<unsigned long long>());
             FELOG_HIP(hipGetLastError());
+            if (timed_mb) FELOG_HIP(hipEventRecord(ev[2], c.stream));
         } else {
             uint32_t h_cnt[2];
             FELOG_HIP(hipMemcpyAsync(h_cnt, a.cnt, sizeof h_cnt, hipMemcpyDeviceToHost,
@@ -551,8 +586,14 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     FELOG_HIP(hipGetLastError());
     FELOG_HIP(hipEventRecord(c.ev1, c.stream));
     double loss = 0.0;
+    unsigned long long rows[2] = {0, 0};
     FELOG_HIP(hipMemcpyAsync(&loss, m.loss_out.ptr, sizeof loss, hipMemcpyDeviceToHost, c.stream));
+    FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost,
+                             c.stream));
     c.sync();
+    // harvest the slots still pending, oldest first
+    for (size_t k = 0; k < used_slots; ++k)
+        harvest((next_slot + pool - used_slots + k) % pool);
     float ms = 0.0f;
     FELOG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
     if (stats) {
@@ -561,6 +602,11 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         stats->minibatches_total = sch.B;
         stats->loss = loss;
         stats->ms = ms;
+        stats->rows_in = (int64_t)rows[0];
+        stats->rows_out = (int64_t)rows[1];
+        stats->timed_launches = timed;
+        stats->ms_forward = ms_fwd;
+        stats->ms_apply = ms_apply;
     }
 }
 

@@ -54,7 +54,10 @@ class felog_train_params(C.Structure):
 
 class felog_train_stats(C.Structure):
     _fields_ = [("minibatches", C.c_int64), ("pairs", C.c_int64),
-                ("minibatches_total", C.c_int64), ("loss", C.c_double), ("ms", C.c_double)]
+                ("minibatches_total", C.c_int64), ("loss", C.c_double), ("ms", C.c_double),
+                ("rows_in", C.c_int64), ("rows_out", C.c_int64),
+                ("timed_launches", C.c_int64), ("ms_forward", C.c_double),
+                ("ms_apply", C.c_double)]
 
 
 class felog_feedback_params(C.Structure):
@@ -70,10 +73,9 @@ class felog_run_params(C.Structure):
 class felog_run_stats(C.Structure):
     _fields_ = [("rounds", C.c_int32),
                 ("active", C.c_int64 * MAX_ROUNDS), ("walks", C.c_int64 * MAX_ROUNDS),
-                ("walk_steps", C.c_int64 * MAX_ROUNDS), ("pairs", C.c_int64 * MAX_ROUNDS),
-                ("loss", C.c_double * MAX_ROUNDS), ("ms_walk", C.c_double * MAX_ROUNDS),
-                ("ms_train", C.c_double * MAX_ROUNDS), ("ms_feedback", C.c_double * MAX_ROUNDS),
-                ("final_active", C.c_int64)]
+                ("walk_steps", C.c_int64 * MAX_ROUNDS), ("ms_walk", C.c_double * MAX_ROUNDS),
+                ("ms_feedback", C.c_double * MAX_ROUNDS),
+                ("train", felog_train_stats * MAX_ROUNDS), ("final_active", C.c_int64)]
 
 
 _p = C.c_void_p
@@ -85,6 +87,7 @@ SIGNATURES = {
     "felog_ctx_create": (_i32, [C.c_int, _p, _u64, _pp]),
     "felog_ctx_destroy": (None, [_p]),
     "felog_ctx_bytes_in_use": (_i32, [_p, C.POINTER(_u64)]),
+    "felog_ctx_set_timing": (_i32, [_p, _i32]),
     "felog_last_error": (C.c_char_p, []),
     "felog_graph_load_csr": (_i32, [_p, _i32, _i64, _p, _p, _p, _pp]),
     "felog_graph_destroy": (None, [_p]),
@@ -103,6 +106,7 @@ SIGNATURES = {
     "felog_model_destroy": (None, [_p]),
     "felog_model_set_unigram": (_i32, [_p, _p]),
     "felog_model_read_cdf": (_i32, [_p, _p, _i64]),
+    "felog_model_reset": (_i32, [_p, _u64]),
     "felog_embeddings_read": (_i32, [_p, _i32, _p, _i64]),
     "felog_embeddings_read_dev": (_i32, [_p, _i32, _p, _i64]),
     "felog_embeddings_write": (_i32, [_p, _i32, _p, _i64]),
@@ -159,6 +163,9 @@ class Context:
         h = C.c_void_p()
         _check(lib.felog_ctx_create(device, stream, hbm_budget, C.byref(h)))
         self.handle = h
+
+    def set_timing(self, every: int):
+        _check(load().felog_ctx_set_timing(self.handle, every))
 
     def bytes_in_use(self) -> int:
         b = C.c_uint64()
@@ -295,6 +302,9 @@ class Model(_Handle):
 
     def set_unigram(self, corpus: Walks):
         _check(load().felog_model_set_unigram(self.handle, corpus.handle))
+
+    def reset(self, seed: int):
+        _check(load().felog_model_reset(self.handle, seed))
 
     def read_cdf(self) -> np.ndarray:
         out = np.zeros(self.n + 1, np.uint64)
