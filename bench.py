@@ -198,7 +198,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "rmat20: R-MAT scale 20 (a,b,c = .57,.19,.19), 2^24 undirected "
-                               "edges with 10% held out, uniform walks r=10 L=80, SGNS d=128 "
+                               "edges with 10%% held out, uniform walks r=10 L=80, SGNS d=128 "
                                "w=10 K=5 unigram^0.75 minibatch 65536, FeeST mu=0.65 k_s=10 "
                                "monotone, at most %d rounds" % cfg["r_max"],
                    "nodes": g.n, "csr_entries": g.nnz},

@@ -436,18 +436,16 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
         size_t tb = sizeof(float) * (size_t)g->n * p->dim;
         m->tin.alloc(c, tb);
         m->tout.alloc(c, tb);
-        m->din.alloc(c, tb);
-        m->dout.alloc(c, tb);
-        m->stamp_in.alloc(c, sizeof(uint32_t) * g->n);
-        m->stamp_out.alloc(c, sizeof(uint32_t) * g->n);
-        m->counters.alloc(c, sizeof(uint32_t) * 4);
+        m->cnt_in.alloc(c, sizeof(uint32_t) * g->n);
+        m->cnt_out.alloc(c, sizeof(uint32_t) * g->n);
+        m->off_in.alloc(c, sizeof(int32_t) * g->n);
+        m->off_out.alloc(c, sizeof(int32_t) * g->n);
+        m->meta.alloc(c, sizeof(uint32_t) * 8);
         m->row_totals.alloc(c, sizeof(uint64_t) * 2);
         m->loss_out.alloc(c, sizeof(double));
-        FELOG_HIP(hipMemsetAsync(m->din.ptr, 0, tb, c->stream));
-        FELOG_HIP(hipMemsetAsync(m->dout.ptr, 0, tb, c->stream));
-        FELOG_HIP(hipMemsetAsync(m->stamp_in.ptr, 0xFF, sizeof(uint32_t) * g->n, c->stream));
-        FELOG_HIP(hipMemsetAsync(m->stamp_out.ptr, 0xFF, sizeof(uint32_t) * g->n, c->stream));
-        FELOG_HIP(hipMemsetAsync(m->counters.ptr, 0, sizeof(uint32_t) * 4, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->cnt_in.ptr, 0, sizeof(uint32_t) * g->n, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->cnt_out.ptr, 0, sizeof(uint32_t) * g->n, c->stream));
+        FELOG_HIP(hipMemsetAsync(m->meta.ptr, 0, sizeof(uint32_t) * 8, c->stream));
         launch_init_tables(*m, p->seed);
         if (p->neg_dist == FELOG_NEG_DEGREE) {
             DevBuf counts;

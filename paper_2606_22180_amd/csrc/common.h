@@ -112,21 +112,29 @@ struct Model {
     int32_t dim = 0;
     int32_t neg_dist = FELOG_NEG_DEGREE;
     bool have_noise = false;
-    DevBuf tin, tout;         // float [n][d]
-    DevBuf din, dout;         // float [n][d], zero between minibatches
-    DevBuf stamp_in, stamp_out;   // uint32 [n], minibatch serial of the last touch
-    DevBuf cdf;               // uint64 [n+1]
-    DevBuf guide;             // int32 [2^guide_bits]
+    DevBuf tin, tout;             // float [n][d]
+    DevBuf cnt_in, cnt_out;       // uint32 [n]: touches of each row in this minibatch (0 between)
+    DevBuf off_in, off_out;       // int32 [n]: first entry of each touched row's segment
+    DevBuf cdf;                   // uint64 [n+1]
+    DevBuf guide;                 // int32 [2^guide_bits]
     int32_t guide_bits = 0;
     uint64_t total_weight = 0;
-    uint32_t serial = 0;      // minibatch serial (stamps)
-    // scratch sized for the largest minibatch seen
+    // minibatch scratch, sized for the largest (pairs, negatives) seen
     int64_t cap_pairs = 0;
     int32_t cap_K = 0;
-    DevBuf touched_in, touched_out;   // int32 lists
-    DevBuf counters;          // uint32 [4]: touched counts, double-buffered by serial parity
-    DevBuf loss_out;          // double [1]
-    DevBuf row_totals;        // uint64 [2]: summed touched-list lengths (in, out)
+    DevBuf pair_ctx;              // int32 [P]
+    DevBuf pair_t;                // int32 [P][K+1]: centre, negatives (-1 = skipped)
+    DevBuf pair_g;                // float [P][K+1]: coefficients g_k
+    DevBuf rank_in, rank_out;     // uint32 [P], [P][K+1]: order of the touch within its row
+    DevBuf dinp;                  // float [P][d]: sum_k g_k out[t_k] of each pair
+    DevBuf list_in, list_out;     // int32: touched rows, in order of first touch
+    DevBuf entries_in;            // int32 [P]: in-touches (pair ids) grouped by row
+    DevBuf entries_out;           // int32 [P(K+1)]: out-touches (touch ids) grouped by row
+    DevBuf chunks_in, chunks_out; // int32 [4 per chunk]: row, list slot, first entry, length|flags
+    DevBuf partials;              // per scan block: uint64 (entries | chunks << 32), uint32 rows
+    DevBuf meta;                  // uint32 [8]: list lengths (in, out), chunk counts (in, out)
+    DevBuf loss_out;              // double [1]
+    DevBuf row_totals;            // uint64 [2]: summed touched-list lengths (in, out)
 };
 
 // ---------------------------------------------------------------------------

@@ -8,18 +8,24 @@
 // and the one-node walks are left out of valid_cols, so this closed form is
 // exactly the order "next P pairs whose positions both hold a node".
 //
-// Per minibatch two kernels run:
-//   forward: per pair, gather in[ctx], out[ctr] and K noise rows, K+1 dot
-//            products, sigma, coefficients g, and scatter-add the row deltas
-//            into zeroed delta tables with FP32 atomics; first touches of a
-//            row in this minibatch append it to a touched list (stamps).
-//   apply:   for each touched row, table += delta, delta = 0.
-// The tables are only read during forward, so every pair sees the state at
-// the start of the minibatch, and the sum of a row's deltas is added once.
-//
-// A wave owns up to 64/(K+2) pairs: pair metadata, noise draws and stamps are
-// computed for all of them at once in parallel lanes, then rows are processed
-// pair by pair with 64 lanes spanning d (lane owns elements lane + 64 v).
+// Every pair reads the tables as they stand at the minibatch's start; each
+// row's deltas are summed and added once.  FP32 atomics on table rows are
+// slow on this part (an L2 atomic unit handles a few dwords per clock, and
+// hot rows serialise), so the update is a sort by destination instead:
+//   forward   per pair: gather in[ctx], out[ctr], out[neg_1..K]; K+1 dots,
+//             sigma, coefficients g; store g and sum_k g_k out[t_k] per pair;
+//             count each touched row with an integer atomic whose result is
+//             the touch's rank within its row (rank 0 lists the row).
+//   scan      two passes over the touched rows: segment offsets and work
+//             items (chunks of at most kChunk touches per row).
+//   fill      each touch writes its id at its row's offset + rank.
+//   reduce    one wave per chunk: out rows sum g * in[ctx] over their
+//             touches, in rows sum the per-pair deltas; plain read-modify-
+//             write of the row (atomic only for rows split over chunks),
+//             and the row's counter is cleared.  Out rows run first, since
+//             they read the in-table as of the minibatch start.
+// Lanes own elements lane + 64 v of a row, so each row access is one
+// coalesced 256-byte transaction per v.
 #include <algorithm>
 
 #include "common.h"
@@ -27,11 +33,14 @@
 
 namespace felog {
 
+constexpr int kChunk = 16;                 // touches per reduction work item (one per lane of a group)
+constexpr uint32_t kFirstChunk = 1u << 31; // flags in chunk_len
+constexpr uint32_t kMultiChunk = 1u << 30;
+constexpr uint32_t kLenMask = (1u << 30) - 1;
+
 struct SgnsArgs {
     const float* __restrict__ tin;
     const float* __restrict__ tout;
-    float* din;
-    float* dout;
     const int32_t* __restrict__ walks;   // step-major [L][W]
     int64_t W;
     const int32_t* __restrict__ vcols;   // valid columns of this chunk
@@ -45,12 +54,14 @@ struct SgnsArgs {
     uint64_t seed;
     NoiseTable noise;
     float lr;
-    uint32_t serial;
-    uint32_t* stamp_in;
-    uint32_t* stamp_out;
-    int32_t* list_in;
-    int32_t* list_out;
-    uint32_t* cnt;                        // [0] in-list length, [1] out-list length
+    uint32_t* cnt_in;
+    uint32_t* cnt_out;
+    int32_t* pair_ctx;
+    int32_t* pair_t;
+    float* pair_g;
+    uint32_t* rank_in;
+    uint32_t* rank_out;
+    float* dinp;
     double* loss_part;                    // one slot per wave
 };
 
@@ -102,11 +113,38 @@ __device__ __forceinline__ double neg_log_sigmoid(double x)
     return fmax(-x, 0.0) + log1p(exp(-fabs(x)));
 }
 
-template <int VPL, int K>
+// ----------------------------------------------------------------- forward
+// A row is handled by a group of 16 lanes (lane j of a group owns the float4s
+// j + 16 i of the row), so one wave works on 4 pairs at a time.
+template <int D>
+__device__ __forceinline__ const float4* row4(const float* base, int64_t row)
+{
+    return reinterpret_cast<const float4*>(base + row * D);
+}
+
+__device__ __forceinline__ float dot4(float4 a, float4 b, float acc)
+{
+    acc = fmaf(a.x, b.x, acc);
+    acc = fmaf(a.y, b.y, acc);
+    acc = fmaf(a.z, b.z, acc);
+    return fmaf(a.w, b.w, acc);
+}
+
+__device__ __forceinline__ float group16_sum(float x)
+{
+    x += __shfl_xor(x, 8);
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 2);
+    x += __shfl_xor(x, 1);
+    return x;
+}
+
+template <int D, int K>
 __global__ __launch_bounds__(256) void sgns_forward_kernel(SgnsArgs a)
 {
-    constexpr int D = 64 * VPL;
+    constexpr int V4 = D / 64;   // float4s per lane
     const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, gl = lane & 15;
     const uint32_t gwave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t q0 = gwave * (uint32_t)a.ppw;
     if (q0 >= a.npairs) return;
@@ -143,9 +181,84 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(SgnsArgs a)
         }
     }
 
-    // ---- first-touch stamps and touched lists: lane l < np*(K+2) handles
-    //      row r = l % (K+2) of pair l / (K+2): r = 0 centre, 1..K negatives
-    //      (out table), K+1 context (in table).
+    // ---- rows, dots, coefficients, per-pair in-row delta: 4 pairs at a time
+    double lacc = 0.0;
+    for (int base = 0; base < np; base += 4) {
+        const int p = base + grp;
+        const bool live = p < np;
+        const int ps = live ? p : 0;
+        const uint32_t q = q0 + ps;
+        const int32_t ctx = __shfl(m_ctx, ps);
+        int32_t t[K + 1];
+        t[0] = __shfl(m_ctr, ps);
+#pragma unroll
+        for (int k = 0; k < K; ++k) t[k + 1] = __shfl(m_neg, ps * K + k);
+
+        float4 vin[V4];
+        float4 vo[K + 1][V4];
+        const float4* ri = row4<D>(a.tin, ctx);
+#pragma unroll
+        for (int i = 0; i < V4; ++i) vin[i] = ri[i * 16 + gl];
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            const float4* ro = row4<D>(a.tout, t[k]);
+#pragma unroll
+            for (int i = 0; i < V4; ++i) vo[k][i] = ro[i * 16 + gl];
+        }
+        float dot[K + 1];
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int i = 0; i < V4; ++i) acc = dot4(vin[i], vo[k][i], acc);
+            dot[k] = group16_sum(acc);
+        }
+        float g[K + 1];
+        g[0] = a.lr * (1.0f - sigmoidf_(dot[0]));
+#pragma unroll
+        for (int k = 1; k <= K; ++k) g[k] = t[k] != t[0] ? -a.lr * sigmoidf_(dot[k]) : 0.0f;
+
+        // lane j of the group stores g_k and takes loss term k for k = j and
+        // k = j + 16 (K + 1 may exceed the 16 lanes of a group)
+        float s_lo = 0.0f, s_hi = 0.0f;
+        bool v_lo = false, v_hi = false;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            if ((k & 15) == gl) {
+                if (live) a.pair_g[q * (K + 1) + k] = g[k];
+                const float sk = k == 0 ? dot[0] : -dot[k];   // -log sigma(sk) is the term
+                const bool vk = live && (k == 0 || t[k] != t[0]);
+                if (k < 16) {
+                    s_lo = sk;
+                    v_lo = vk;
+                } else {
+                    s_hi = sk;
+                    v_hi = vk;
+                }
+            }
+        }
+        if (v_lo) lacc += neg_log_sigmoid((double)s_lo);
+        if (K >= 16 && v_hi) lacc += neg_log_sigmoid((double)s_hi);
+        if (live) {
+            float4* dp = reinterpret_cast<float4*>(a.dinp + (int64_t)q * D);
+#pragma unroll
+            for (int i = 0; i < V4; ++i) {
+                float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                for (int k = 0; k <= K; ++k) {
+                    acc.x = fmaf(g[k], vo[k][i].x, acc.x);
+                    acc.y = fmaf(g[k], vo[k][i].y, acc.y);
+                    acc.z = fmaf(g[k], vo[k][i].z, acc.z);
+                    acc.w = fmaf(g[k], vo[k][i].w, acc.w);
+                }
+                dp[i * 16 + gl] = acc;
+            }
+        }
+    }
+
+    // ---- touches: lane l < np*(K+2) handles touch r = l % (K+2) of pair l / (K+2):
+    //      r = 0 centre, 1..K negatives (out table), K+1 context (in table).  The
+    //      count's old value is the touch's rank within its row.
     {
         const int p = lane / (K + 2);
         const int r = lane - p * (K + 2);
@@ -153,161 +266,330 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(SgnsArgs a)
         int32_t ctr = __shfl(m_ctr, ps);
         int32_t ctx = __shfl(m_ctx, ps);
         int32_t neg = __shfl(m_neg, ps * K + (r >= 1 && r <= K ? r - 1 : 0));
-        int which = -1;   // 1 = out table, 0 = in table
-        int32_t row = 0;
         if (lane < np * (K + 2)) {
-            if (r == 0) { which = 1; row = ctr; }
-            else if (r <= K) { which = neg != ctr ? 1 : -1; row = neg; }
-            else { which = 0; row = ctx; }
-        }
-        uint32_t old = a.serial;
-        if (which == 1) old = atomicExch(&a.stamp_out[row], a.serial);
-        else if (which == 0) old = atomicExch(&a.stamp_in[row], a.serial);
-        const bool fresh = which >= 0 && old != a.serial;
-        const uint64_t bout = __ballot(fresh && which == 1);
-        const uint64_t bin = __ballot(fresh && which == 0);
-        uint32_t base_out = 0, base_in = 0;
-        if (lane == 0) {
-            if (bout) base_out = atomicAdd(&a.cnt[1], (uint32_t)__popcll(bout));
-            if (bin) base_in = atomicAdd(&a.cnt[0], (uint32_t)__popcll(bin));
-        }
-        base_out = __shfl(base_out, 0);
-        base_in = __shfl(base_in, 0);
-        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-        if (fresh && which == 1) a.list_out[base_out + __popcll(bout & below)] = row;
-        if (fresh && which == 0) a.list_in[base_in + __popcll(bin & below)] = row;
-    }
-
-    // ---- rows, dots, coefficients and scatter-add, one pair at a time
-    float s_term = 0.0f;
-    bool s_valid = false;
-    for (int p = 0; p < np; ++p) {
-        const int32_t ctx = __builtin_amdgcn_readlane(m_ctx, p);
-        int32_t t[K + 1];
-        t[0] = __builtin_amdgcn_readlane(m_ctr, p);
-#pragma unroll
-        for (int k = 0; k < K; ++k) t[k + 1] = __builtin_amdgcn_readlane(m_neg, p * K + k);
-
-        float vin[VPL];
-        float vo[K + 1][VPL];
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) vin[v] = a.tin[(int64_t)ctx * D + v * 64 + lane];
-#pragma unroll
-        for (int k = 0; k <= K; ++k)
-#pragma unroll
-            for (int v = 0; v < VPL; ++v) vo[k][v] = a.tout[(int64_t)t[k] * D + v * 64 + lane];
-
-        float dot[K + 1];
-#pragma unroll
-        for (int k0 = 0; k0 <= K; k0 += 8) {
-            float part[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                part[i] = 0.0f;
-                if (k0 + i <= K) {
-#pragma unroll
-                    for (int v = 0; v < VPL; ++v) part[i] = fmaf(vin[v], vo[k0 + i][v], part[i]);
-                }
+            const uint32_t q = q0 + p;
+            if (r == 0) {
+                a.rank_out[q * (K + 1)] = atomicAdd(&a.cnt_out[ctr], 1u);
+                a.pair_t[q * (K + 1)] = ctr;
+            } else if (r <= K) {
+                const bool keep = neg != ctr;
+                a.rank_out[q * (K + 1) + r] = keep ? atomicAdd(&a.cnt_out[neg], 1u) : 0u;
+                a.pair_t[q * (K + 1) + r] = keep ? neg : -1;
+            } else {
+                a.rank_in[q] = atomicAdd(&a.cnt_in[ctx], 1u);
+                a.pair_ctx[q] = ctx;
             }
-            float red = reduce8(part, lane);
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (k0 + i <= K) dot[k0 + i] = __shfl(red, 8 * i);
-        }
-
-        float g[K + 1];
-        g[0] = a.lr * (1.0f - sigmoidf_(dot[0]));
-#pragma unroll
-        for (int k = 1; k <= K; ++k) g[k] = t[k] != t[0] ? -a.lr * sigmoidf_(dot[k]) : 0.0f;
-
-        // loss terms for this pair go to lanes p*(K+1) .. p*(K+1)+K
-#pragma unroll
-        for (int k = 0; k <= K; ++k) {
-            if (lane == p * (K + 1) + k) {
-                s_term = k == 0 ? -dot[0] : dot[k];
-                s_valid = k == 0 || t[k] != t[0];
-            }
-        }
-
-        float dctx[VPL];
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int k = 0; k <= K; ++k) acc = fmaf(g[k], vo[k][v], acc);
-            dctx[v] = acc;
-        }
-#pragma unroll
-        for (int v = 0; v < VPL; ++v)
-            unsafeAtomicAdd(&a.din[(int64_t)ctx * D + v * 64 + lane], dctx[v]);
-#pragma unroll
-        for (int k = 0; k <= K; ++k) {
-            if (k > 0 && t[k] == t[0]) continue;
-#pragma unroll
-            for (int v = 0; v < VPL; ++v)
-                unsafeAtomicAdd(&a.dout[(int64_t)t[k] * D + v * 64 + lane], g[k] * vin[v]);
         }
     }
 
     // ---- loss: -log sigma(s0) - sum_k log sigma(-s_k) = softplus(-s0) + sum_k softplus(s_k)
-    double term = s_valid ? neg_log_sigmoid(-(double)s_term) : 0.0;
-    term = wave_sum_f64(term);
-    if (lane == 0) a.loss_part[gwave] += term;
+    lacc = wave_sum_f64(lacc);
+    if (lane == 0) a.loss_part[gwave] += lacc;
 }
 
-template <int VPL>
-__global__ __launch_bounds__(256) void sgns_apply_kernel(float* __restrict__ tin,
-                                                         float* __restrict__ tout,
-                                                         float* __restrict__ din,
-                                                         float* __restrict__ dout,
-                                                         const int32_t* __restrict__ list_in,
-                                                         const int32_t* __restrict__ list_out,
-                                                         const uint32_t* cnt, uint32_t* cnt_next,
-                                                         unsigned long long* row_totals)
+// ------------------------------------------------------------------ scan
+// Touched rows are the touches of rank 0, listed in touch order: for the in
+// table the touches are the pairs (p = 0..P-1), for the out table the
+// (pair, slot) ids e = p (K+1) + k.  Scan blocks [0, nb_in) cover the in
+// table, the rest the out table; per item the scanned values are
+// (rank 0 ? 1 : 0) and (rank 0 ? c : 0 | chunks << 32), c = the row's count.
+constexpr int kScanT = 256, kScanI = 8, kScanSpanS = kScanT * kScanI;
+
+struct TouchView {
+    const int32_t* pair_ctx;
+    const int32_t* pair_t;
+    const uint32_t* rank_in;
+    const uint32_t* rank_out;
+    const uint32_t* cnt_in;
+    const uint32_t* cnt_out;
+    // row of item i (-1 = not a first touch) and its count
+    __device__ void item(bool out, uint32_t i, int32_t& row, uint32_t& c) const
+    {
+        int32_t r;
+        uint32_t rk;
+        if (out) {
+            r = pair_t[i];
+            rk = r >= 0 ? rank_out[i] : 1u;
+        } else {
+            r = pair_ctx[i];
+            rk = rank_in[i];
+        }
+        row = rk == 0 ? r : -1;
+        c = rk == 0 ? (out ? cnt_out[r] : cnt_in[r]) : 0u;
+    }
+};
+
+__device__ __forceinline__ unsigned long long pack_ec(uint32_t c)
 {
-    constexpr int D = 64 * VPL;
-    const int lane = threadIdx.x & 63;
-    const uint32_t n_in = cnt[0], n_out = cnt[1];
-    const uint32_t total = n_in + n_out;
-    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < total; i += nw) {
-        const bool is_in = i < n_in;
-        const int32_t row = is_in ? list_in[i] : list_out[i - n_in];
-        float* T = is_in ? tin : tout;
-        float* Dl = is_in ? din : dout;
+    return (unsigned long long)c | ((unsigned long long)((c + kChunk - 1) / kChunk) << 32);
+}
+
+__global__ __launch_bounds__(256) void sgns_scan_partials(TouchView tv, uint32_t n_in,
+                                                          uint32_t n_out, uint32_t nb_in,
+                                                          unsigned long long* part_ec,
+                                                          uint32_t* part_rows)
+{
+    __shared__ unsigned long long lds[kScanT];
+    __shared__ uint32_t lds_r[kScanT];
+    const bool out = blockIdx.x >= nb_in;
+    const uint32_t nb = out ? blockIdx.x - nb_in : blockIdx.x;
+    const uint32_t n = out ? n_out : n_in;
+    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
+    unsigned long long acc = 0;
+    uint32_t rows = 0;
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-            int64_t idx = (int64_t)row * D + v * 64 + lane;
-            T[idx] += Dl[idx];
-            Dl[idx] = 0.0f;
+    for (int k = 0; k < kScanI; ++k) {
+        if (base + k < n) {
+            int32_t row;
+            uint32_t c;
+            tv.item(out, base + k, row, c);
+            if (row >= 0) {
+                acc += pack_ec(c);
+                ++rows;
+            }
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        cnt_next[0] = 0;
-        cnt_next[1] = 0;
-        row_totals[0] += n_in;
-        row_totals[1] += n_out;
+    lds[threadIdx.x] = acc;
+    lds_r[threadIdx.x] = rows;
+    __syncthreads();
+    for (int s = kScanT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            lds[threadIdx.x] += lds[threadIdx.x + s];
+            lds_r[threadIdx.x] += lds_r[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_ec[blockIdx.x] = lds[0];
+        part_rows[blockIdx.x] = lds_r[0];
     }
 }
 
-// Copy the deltas of the touched rows out (row-major [count][D]) and clear them.
-template <int VPL>
-__global__ void sgns_capture_kernel(float* __restrict__ delta, const int32_t* __restrict__ list,
-                                    uint32_t count, float* __restrict__ out,
-                                    int32_t* __restrict__ rows)
+struct ScanOut {
+    int32_t* list;      // touched rows
+    int32_t* off;       // [n] first entry of each row's segment
+    int32_t* chunks;    // 4 ints per chunk
+};
+
+// meta[0 + out] = rows listed, meta[2 + out] = chunks.
+__global__ __launch_bounds__(256) void sgns_scan_write(TouchView tv, uint32_t n_in, uint32_t n_out,
+                                                       uint32_t nb_in,
+                                                       const unsigned long long* part_ec,
+                                                       const uint32_t* part_rows, ScanOut so_in,
+                                                       ScanOut so_out, uint32_t* meta)
 {
-    constexpr int D = 64 * VPL;
-    const int lane = threadIdx.x & 63;
-    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < count; i += nw) {
-        int32_t row = list[i];
-        if (lane == 0) rows[i] = row;
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-            int64_t idx = (int64_t)row * D + v * 64 + lane;
-            out[(int64_t)i * D + v * 64 + lane] = delta[idx];
-            delta[idx] = 0.0f;
+    __shared__ unsigned long long lds[kScanT];
+    __shared__ uint32_t lds_r[kScanT];
+    const bool out = blockIdx.x >= nb_in;
+    const uint32_t b0 = out ? nb_in : 0u;          // first block of this table
+    const uint32_t n = out ? n_out : n_in;
+    const uint32_t nb = blockIdx.x - b0;
+    const ScanOut so = out ? so_out : so_in;
+    // offset of this block: partials of the earlier blocks of the same table
+    unsigned long long pre = 0;
+    uint32_t pre_r = 0;
+    for (uint32_t b = b0 + threadIdx.x; b < blockIdx.x; b += kScanT) {
+        pre += part_ec[b];
+        pre_r += part_rows[b];
+    }
+    lds[threadIdx.x] = pre;
+    lds_r[threadIdx.x] = pre_r;
+    __syncthreads();
+    for (int s = kScanT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            lds[threadIdx.x] += lds[threadIdx.x + s];
+            lds_r[threadIdx.x] += lds_r[threadIdx.x + s];
         }
+        __syncthreads();
+    }
+    const unsigned long long block_ec = lds[0];
+    const uint32_t block_r = lds_r[0];
+    __syncthreads();
+
+    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
+    int32_t rows[kScanI];
+    uint32_t cs[kScanI];
+    unsigned long long mine = 0;
+    uint32_t mine_r = 0;
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) {
+        rows[k] = -1;
+        cs[k] = 0;
+        if (base + k < n) tv.item(out, base + k, rows[k], cs[k]);
+        if (rows[k] >= 0) {
+            mine += pack_ec(cs[k]);
+            ++mine_r;
+        }
+    }
+    // block exclusive scans
+    lds[threadIdx.x] = mine;
+    lds_r[threadIdx.x] = mine_r;
+    __syncthreads();
+    for (int off = 1; off < kScanT; off <<= 1) {
+        unsigned long long add = threadIdx.x >= off ? lds[threadIdx.x - off] : 0ull;
+        uint32_t add_r = threadIdx.x >= off ? lds_r[threadIdx.x - off] : 0u;
+        __syncthreads();
+        lds[threadIdx.x] += add;
+        lds_r[threadIdx.x] += add_r;
+        __syncthreads();
+    }
+    unsigned long long run = block_ec + lds[threadIdx.x] - mine;
+    uint32_t slot = block_r + lds_r[threadIdx.x] - mine_r;
+    uint32_t entry = (uint32_t)run, chunk = (uint32_t)(run >> 32);
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) {
+        const uint32_t i = base + k;
+        if (rows[k] >= 0) {
+            so.list[slot] = rows[k];
+            so.off[rows[k]] = (int32_t)entry;
+            const uint32_t nch = (cs[k] + kChunk - 1) / kChunk;
+            for (uint32_t j = 0; j < nch; ++j) {
+                const uint32_t len = min((uint32_t)kChunk, cs[k] - j * kChunk);
+                int32_t* d = so.chunks + 4 * (int64_t)(chunk + j);
+                d[0] = rows[k];
+                d[1] = (int32_t)slot;
+                d[2] = (int32_t)(entry + j * kChunk);
+                d[3] = (int32_t)(len | (j == 0 ? kFirstChunk : 0u) | (nch > 1 ? kMultiChunk : 0u));
+            }
+            entry += cs[k];
+            chunk += nch;
+            ++slot;
+        }
+        if (i + 1 == n) {       // last item of the table: totals
+            meta[out ? 1 : 0] = slot;
+            meta[out ? 3 : 2] = chunk;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ fill
+template <int K>
+__global__ __launch_bounds__(256) void sgns_fill_kernel(uint32_t npairs, const int32_t* pair_ctx,
+                                                        const int32_t* pair_t,
+                                                        const uint32_t* rank_in,
+                                                        const uint32_t* rank_out,
+                                                        const int32_t* off_in,
+                                                        const int32_t* off_out,
+                                                        int32_t* entries_in, int32_t* entries_out)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < npairs * (K + 1)) {
+        const int32_t row = pair_t[t];
+        if (row >= 0) entries_out[off_out[row] + rank_out[t]] = (int32_t)t;
+    } else if (t < npairs * (K + 2)) {
+        const uint32_t p = t - npairs * (K + 1);
+        entries_in[off_in[pair_ctx[p]] + rank_in[p]] = (int32_t)p;
+    }
+}
+
+// ---------------------------------------------------------------- reduce
+// Out rows: delta out[t] = sum over touches (p, k) of g_pk * in[ctx_p].
+// In rows:  delta in[c]  = sum over touches p of dinp[p].
+// Groups of 16 lanes take one chunk each, 4 chunks per wave.  capture !=
+// NULL: write the deltas to capture[slot][d] (zeroed) instead of the table.
+template <int D, int K, bool OUT>
+__global__ __launch_bounds__(256) void sgns_reduce_kernel(
+    float* __restrict__ table, const float* __restrict__ tin, const float* __restrict__ dinp,
+    const float* __restrict__ pair_g, const int32_t* __restrict__ pair_ctx,
+    const int32_t* __restrict__ entries, const int32_t* __restrict__ chunks,
+    uint32_t* __restrict__ cnt, const uint32_t* meta, float* __restrict__ capture,
+    unsigned long long* row_totals)
+{
+    constexpr int V4 = D / 64;
+    const int lane = threadIdx.x & 63;
+    const int grp = lane >> 4, gl = lane & 15;
+    const uint32_t n_chunks = meta[OUT ? 3 : 2];
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    const float* src = OUT ? tin : dinp;
+    for (uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4u;
+         base < n_chunks; base += nw * 4u) {
+        const uint32_t c = base + grp;
+        const bool live = c < n_chunks;
+        int32_t row = 0, slot = 0, start = 0, len = 0;
+        uint32_t lf = 0;
+        if (live) {
+            const int4 d = reinterpret_cast<const int4*>(chunks)[c];
+            row = d.x;
+            slot = d.y;
+            start = d.z;
+            lf = (uint32_t)d.w;
+            len = (int32_t)(lf & kLenMask);
+        }
+        float my_g = 0.0f;
+        int32_t my_src = 0;
+        if (gl < len) {
+            const int32_t e = entries[start + gl];
+            if (OUT) {
+                my_g = pair_g[e];
+                my_src = pair_ctx[e / (K + 1)];
+            } else {
+                my_g = 1.0f;
+                my_src = e;
+            }
+        }
+        // longest chunk among the wave's four groups
+        int32_t mlen = max(len, __shfl_xor(len, 16));
+        mlen = max(mlen, __shfl_xor(mlen, 32));
+        float4 acc[V4];
+#pragma unroll
+        for (int i = 0; i < V4; ++i) acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int32_t i0 = 0; i0 < mlen; i0 += 4) {
+            float gg[4];
+            float4 x[4][V4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t idx = min(i0 + u, kChunk - 1);
+                gg[u] = __shfl(my_g, (grp << 4) + idx);
+                const int32_t rr = __shfl(my_src, (grp << 4) + idx);
+                if (i0 + u < len) {
+                    const float4* rp = row4<D>(src, rr);
+#pragma unroll
+                    for (int i = 0; i < V4; ++i) x[u][i] = rp[i * 16 + gl];
+                } else {
+                    gg[u] = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < V4; ++i) x[u][i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int i = 0; i < V4; ++i) {
+                    acc[i].x = fmaf(gg[u], x[u][i].x, acc[i].x);
+                    acc[i].y = fmaf(gg[u], x[u][i].y, acc[i].y);
+                    acc[i].z = fmaf(gg[u], x[u][i].z, acc[i].z);
+                    acc[i].w = fmaf(gg[u], x[u][i].w, acc[i].w);
+                }
+        }
+        if (live) {
+            float* dst = capture ? capture + (int64_t)slot * D : table + (int64_t)row * D;
+            float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+            for (int i = 0; i < V4; ++i) {
+                if (lf & kMultiChunk) {
+                    float* f = dst + (i * 16 + gl) * 4;
+                    unsafeAtomicAdd(f + 0, acc[i].x);
+                    unsafeAtomicAdd(f + 1, acc[i].y);
+                    unsafeAtomicAdd(f + 2, acc[i].z);
+                    unsafeAtomicAdd(f + 3, acc[i].w);
+                } else if (capture) {
+                    d4[i * 16 + gl] = acc[i];
+                } else {
+                    float4 v = d4[i * 16 + gl];
+                    v.x += acc[i].x;
+                    v.y += acc[i].y;
+                    v.z += acc[i].z;
+                    v.w += acc[i].w;
+                    d4[i * 16 + gl] = v;
+                }
+            }
+            if ((lf & kFirstChunk) && gl == 0) cnt[row] = 0;
+        }
+    }
+    // the in-row reduction is the minibatch's last kernel: count the touched rows
+    if (!OUT && blockIdx.x == 0 && threadIdx.x == 0) {
+        row_totals[0] += meta[0];
+        row_totals[1] += meta[1];
     }
 }
 
@@ -330,33 +612,6 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const double* part, in
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-template <int VPL, int K>
-static void launch_forward_t(dim3 grid, hipStream_t s, const SgnsArgs& a)
-{
-    hipLaunchKernelGGL((sgns_forward_kernel<VPL, K>), grid, dim3(256), 0, s, a);
-}
-
-template <int VPL>
-static void launch_forward_k(int K, dim3 grid, hipStream_t s, const SgnsArgs& a)
-{
-    switch (K) {
-#define FELOG_K(k) case k: launch_forward_t<VPL, k>(grid, s, a); break;
-        FELOG_K(1) FELOG_K(2) FELOG_K(3) FELOG_K(4) FELOG_K(5) FELOG_K(6) FELOG_K(7)
-        FELOG_K(8) FELOG_K(9) FELOG_K(10) FELOG_K(11) FELOG_K(12) FELOG_K(13) FELOG_K(14)
-        FELOG_K(15) FELOG_K(16) FELOG_K(17) FELOG_K(18) FELOG_K(19) FELOG_K(20)
-#undef FELOG_K
-        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", K);
-    }
-}
-
-static void launch_forward(int dim, int K, dim3 grid, hipStream_t s, const SgnsArgs& a)
-{
-    if (dim == 64) launch_forward_k<1>(K, grid, s, a);
-    else if (dim == 128) launch_forward_k<2>(K, grid, s, a);
-    else launch_forward_k<4>(K, grid, s, a);
-    FELOG_HIP(hipGetLastError());
-}
-
 // (j, slot) slices with both positions inside a walk of length L, in pair order.
 static std::vector<int32_t> make_slices(int32_t L, int32_t w)
 {
@@ -407,6 +662,74 @@ int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_
     return s.B;
 }
 
+
+struct MinibatchLaunch {
+    dim3 fwd_grid;
+    uint32_t npairs;
+    int dim, K;
+    int fill_blocks, reduce_blocks;
+    uint32_t nb_in, nb_out;
+};
+
+template <int D, int K>
+static void launch_minibatch_t(Model& m, const SgnsArgs& a, const MinibatchLaunch& ml,
+                               float* cap_in, float* cap_out, hipStream_t s, hipEvent_t ev_mid)
+{
+    hipLaunchKernelGGL((sgns_forward_kernel<D, K>), ml.fwd_grid, dim3(256), 0, s, a);
+    if (ev_mid) FELOG_HIP(hipEventRecord(ev_mid, s));
+    TouchView tv{m.pair_ctx.as<int32_t>(), m.pair_t.as<int32_t>(), m.rank_in.as<uint32_t>(),
+                 m.rank_out.as<uint32_t>(), m.cnt_in.as<uint32_t>(), m.cnt_out.as<uint32_t>()};
+    uint32_t* meta = m.meta.as<uint32_t>();
+    const uint32_t n_in = ml.npairs, n_out = ml.npairs * (K + 1);
+    const uint32_t nb = ml.nb_in + ml.nb_out;
+    unsigned long long* part_ec = m.partials.as<unsigned long long>();
+    uint32_t* part_rows = reinterpret_cast<uint32_t*>(part_ec + nb);
+    hipLaunchKernelGGL(sgns_scan_partials, dim3(nb), dim3(256), 0, s, tv, n_in, n_out, ml.nb_in,
+                       part_ec, part_rows);
+    ScanOut so_in{m.list_in.as<int32_t>(), m.off_in.as<int32_t>(), m.chunks_in.as<int32_t>()};
+    ScanOut so_out{m.list_out.as<int32_t>(), m.off_out.as<int32_t>(), m.chunks_out.as<int32_t>()};
+    hipLaunchKernelGGL(sgns_scan_write, dim3(nb), dim3(256), 0, s, tv, n_in, n_out, ml.nb_in,
+                       part_ec, part_rows, so_in, so_out, meta);
+    hipLaunchKernelGGL(sgns_fill_kernel<K>, dim3(ml.fill_blocks), dim3(256), 0, s, ml.npairs,
+                       m.pair_ctx.as<int32_t>(), m.pair_t.as<int32_t>(),
+                       m.rank_in.as<uint32_t>(), m.rank_out.as<uint32_t>(),
+                       m.off_in.as<int32_t>(), m.off_out.as<int32_t>(),
+                       m.entries_in.as<int32_t>(), m.entries_out.as<int32_t>());
+    hipLaunchKernelGGL((sgns_reduce_kernel<D, K, true>), dim3(ml.reduce_blocks), dim3(256), 0, s,
+                       m.tout.as<float>(), m.tin.as<float>(), m.dinp.as<float>(),
+                       m.pair_g.as<float>(), m.pair_ctx.as<int32_t>(), m.entries_out.as<int32_t>(),
+                       m.chunks_out.as<int32_t>(), m.cnt_out.as<uint32_t>(), meta, cap_out,
+                       m.row_totals.as<unsigned long long>());
+    hipLaunchKernelGGL((sgns_reduce_kernel<D, K, false>), dim3(ml.reduce_blocks), dim3(256), 0, s,
+                       m.tin.as<float>(), m.tin.as<float>(), m.dinp.as<float>(),
+                       m.pair_g.as<float>(), m.pair_ctx.as<int32_t>(), m.entries_in.as<int32_t>(),
+                       m.chunks_in.as<int32_t>(), m.cnt_in.as<uint32_t>(), meta, cap_in,
+                       m.row_totals.as<unsigned long long>());
+    FELOG_HIP(hipGetLastError());
+}
+
+template <int D>
+static void launch_minibatch_k(int K, Model& m, const SgnsArgs& a, const MinibatchLaunch& ml,
+                               float* ci, float* co, hipStream_t s, hipEvent_t ev)
+{
+    switch (K) {
+#define FELOG_K(k) case k: launch_minibatch_t<D, k>(m, a, ml, ci, co, s, ev); break;
+        FELOG_K(1) FELOG_K(2) FELOG_K(3) FELOG_K(4) FELOG_K(5) FELOG_K(6) FELOG_K(7)
+        FELOG_K(8) FELOG_K(9) FELOG_K(10) FELOG_K(11) FELOG_K(12) FELOG_K(13) FELOG_K(14)
+        FELOG_K(15) FELOG_K(16) FELOG_K(17) FELOG_K(18) FELOG_K(19) FELOG_K(20)
+#undef FELOG_K
+        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", K);
+    }
+}
+
+static void launch_minibatch(Model& m, const SgnsArgs& a, const MinibatchLaunch& ml, float* ci,
+                             float* co, hipStream_t s, hipEvent_t ev)
+{
+    if (ml.dim == 64) launch_minibatch_k<64>(ml.K, m, a, ml, ci, co, s, ev);
+    else if (ml.dim == 128) launch_minibatch_k<128>(ml.K, m, a, ml, ci, co, s, ev);
+    else launch_minibatch_k<256>(ml.K, m, a, ml, ci, co, s, ev);
+}
+
 void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, int64_t first_mb,
                        int64_t n_mb, bool apply, felog_train_stats* stats, int32_t* rows_in,
                        float* d_in_host, int64_t cap_in, int64_t* n_in, int32_t* rows_out,
@@ -427,8 +750,22 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     if (m.cap_pairs < P || m.cap_K < K) {
         m.cap_pairs = std::max<int64_t>(m.cap_pairs, P);
         m.cap_K = std::max(m.cap_K, K);
-        m.touched_in.alloc(&c, sizeof(int32_t) * m.cap_pairs);
-        m.touched_out.alloc(&c, sizeof(int32_t) * m.cap_pairs * (m.cap_K + 1));
+        const int64_t cp = m.cap_pairs, ck = m.cap_K;
+        m.pair_ctx.alloc(&c, sizeof(int32_t) * cp);
+        m.pair_t.alloc(&c, sizeof(int32_t) * cp * (ck + 1));
+        m.pair_g.alloc(&c, sizeof(float) * cp * (ck + 1));
+        m.rank_in.alloc(&c, sizeof(uint32_t) * cp);
+        m.rank_out.alloc(&c, sizeof(uint32_t) * cp * (ck + 1));
+        m.dinp.alloc(&c, sizeof(float) * cp * m.dim);
+        m.list_in.alloc(&c, sizeof(int32_t) * cp);
+        m.list_out.alloc(&c, sizeof(int32_t) * cp * (ck + 1));
+        m.entries_in.alloc(&c, sizeof(int32_t) * cp);
+        m.entries_out.alloc(&c, sizeof(int32_t) * cp * (ck + 1));
+        m.chunks_in.alloc(&c, sizeof(int32_t) * 4 * cp);
+        m.chunks_out.alloc(&c, sizeof(int32_t) * 4 * cp * (ck + 1));
+        const int64_t nbmax = (cp + kScanSpanS - 1) / kScanSpanS +
+                              (cp * (ck + 1) + kScanSpanS - 1) / kScanSpanS;
+        m.partials.alloc(&c, (sizeof(unsigned long long) + sizeof(uint32_t)) * nbmax);
     }
     const int ppw_max = 64 / (K + 2);
     int ppw = (int)std::min<int64_t>(ppw_max, std::max<int64_t>(1, P / ((int64_t)c.num_cus * 32)));
@@ -437,10 +774,10 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     DevBuf loss_part;
     loss_part.alloc(&c, sizeof(double) * blocks * 4);
     FELOG_HIP(hipMemsetAsync(loss_part.ptr, 0, sizeof(double) * blocks * 4, c.stream));
-    FELOG_HIP(hipMemsetAsync(m.counters.ptr, 0, sizeof(uint32_t) * 4, c.stream));
+    FELOG_HIP(hipMemsetAsync(m.meta.ptr, 0, sizeof(uint32_t) * 8, c.stream));
     FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
 
-    // sampled kernel timing: events before forward, between forward and apply, after apply
+    // sampled kernel timing: events before forward, after forward, after the reductions
     const int every = apply ? c.timing_every : 0;
     const size_t pool = c.timing_pool.size() / 3;
     size_t next_slot = 0, used_slots = 0;
@@ -467,8 +804,6 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     SgnsArgs a{};
     a.tin = m.tin.as<float>();
     a.tout = m.tout.as<float>();
-    a.din = m.din.as<float>();
-    a.dout = m.dout.as<float>();
     a.walks = w.data.as<int32_t>();
     a.W = w.W;
     a.slices = slices.as<int32_t>();
@@ -477,14 +812,22 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     a.ppw = ppw;
     a.seed = p.seed;
     a.noise = NoiseTable{m.cdf.as<uint64_t>(), m.guide.as<int32_t>(), m.total_weight, m.guide_bits};
-    a.stamp_in = m.stamp_in.as<uint32_t>();
-    a.stamp_out = m.stamp_out.as<uint32_t>();
-    a.list_in = m.touched_in.as<int32_t>();
-    a.list_out = m.touched_out.as<int32_t>();
+    a.cnt_in = m.cnt_in.as<uint32_t>();
+    a.cnt_out = m.cnt_out.as<uint32_t>();
+    a.pair_ctx = m.pair_ctx.as<int32_t>();
+    a.pair_t = m.pair_t.as<int32_t>();
+    a.pair_g = m.pair_g.as<float>();
+    a.rank_in = m.rank_in.as<uint32_t>();
+    a.rank_out = m.rank_out.as<uint32_t>();
+    a.dinp = m.dinp.as<float>();
     a.loss_part = loss_part.as<double>();
 
+    MinibatchLaunch ml{};
+    ml.dim = m.dim;
+    ml.K = K;
+    ml.reduce_blocks = std::max(1, c.num_cus * 8);
+
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
-    const int apply_blocks = std::max(1, c.num_cus * 8);
     int64_t pairs_done = 0;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     size_t chunk = 0;
@@ -499,10 +842,12 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         a.npairs = (uint32_t)np;
         double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
         a.lr = (float)lr;
-        const int parity = (int)(m.serial & 1u);
-        a.serial = m.serial;
-        a.cnt = m.counters.as<uint32_t>() + 2 * parity;
         int64_t nwaves = (np + ppw - 1) / ppw;
+        ml.fwd_grid = dim3((uint32_t)((nwaves + 3) / 4));
+        ml.npairs = (uint32_t)np;
+        ml.fill_blocks = (int)((np * (K + 2) + 255) / 256);
+        ml.nb_in = (uint32_t)((np + kScanSpanS - 1) / kScanSpanS);
+        ml.nb_out = (uint32_t)((np * (K + 1) + kScanSpanS - 1) / kScanSpanS);
         const bool timed_mb = every > 0 && pool > 0 && (b - first_mb) % every == 0;
         hipEvent_t* ev = nullptr;
         if (timed_mb) {
@@ -512,73 +857,42 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
             next_slot = (next_slot + 1) % pool;
             FELOG_HIP(hipEventRecord(ev[0], c.stream));
         }
-        launch_forward(m.dim, K, dim3((uint32_t)((nwaves + 3) / 4)), c.stream, a);
-        if (timed_mb) FELOG_HIP(hipEventRecord(ev[1], c.stream));
         if (apply) {
-            uint32_t* next = m.counters.as<uint32_t>() + 2 * (1 - parity);
-            if (m.dim == 64)
-                hipLaunchKernelGGL(sgns_apply_kernel<1>, dim3(apply_blocks), dim3(256), 0,
-                                   c.stream, m.tin.as<float>(), m.tout.as<float>(), a.din,
-                                   a.dout, a.list_in, a.list_out, a.cnt, next,
-                                   m.row_totals.as<unsigned long long>());
-            else if (m.dim == 128)
-                hipLaunchKernelGGL(sgns_apply_kernel<2>, dim3(apply_blocks), dim3(256), 0,
-                                   c.stream, m.tin.as<float>(), m.tout.as<float>(), a.din,
-                                   a.dout, a.list_in, a.list_out, a.cnt, next,
-                                   m.row_totals.as<unsigned long long>());
-            else
-                hipLaunchKernelGGL(sgns_apply_kernel<4>, dim3(apply_blocks), dim3(256), 0,
-                                   c.stream, m.tin.as<float>(), m.tout.as<float>(), a.din,
-                                   a.dout, a.list_in, a.list_out, a.cnt, next,
-                                   m.row_totals.as<unsigned long long>());
-            FELOG_HIP(hipGetLastError());
-            if (timed_mb) FELOG_HIP(hipEventRecord(ev[2], c.stream));
+            launch_minibatch(m, a, ml, nullptr, nullptr, c.stream, ev ? ev[1] : nullptr);
+            if (ev) FELOG_HIP(hipEventRecord(ev[2], c.stream));
         } else {
-            uint32_t h_cnt[2];
-            FELOG_HIP(hipMemcpyAsync(h_cnt, a.cnt, sizeof h_cnt, hipMemcpyDeviceToHost,
+            // capture: deltas of this minibatch, by touched-list position, not applied
+            DevBuf vin, vout;
+            vin.alloc(&c, sizeof(float) * (size_t)P * m.dim);
+            vout.alloc(&c, sizeof(float) * (size_t)P * (K + 1) * m.dim);
+            FELOG_HIP(hipMemsetAsync(vin.ptr, 0, vin.bytes, c.stream));
+            FELOG_HIP(hipMemsetAsync(vout.ptr, 0, vout.bytes, c.stream));
+            // the last kernel adds the list lengths to row_totals (zeroed above)
+            FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
+            launch_minibatch(m, a, ml, vin.as<float>(), vout.as<float>(), c.stream, nullptr);
+            unsigned long long tot[2];
+            FELOG_HIP(hipMemcpyAsync(tot, m.row_totals.ptr, sizeof tot, hipMemcpyDeviceToHost,
                                      c.stream));
             c.sync();
+            const int64_t ui = (int64_t)tot[0], uo = (int64_t)tot[1];
             FELOG_REQUIRE(rows_in && d_in_host && rows_out && d_out_host,
                           "capture buffers must not be NULL");
-            FELOG_REQUIRE((int64_t)h_cnt[0] <= cap_in && (int64_t)h_cnt[1] <= cap_out,
-                          "capture buffers hold %lld / %lld rows, need %u / %u",
-                          (long long)cap_in, (long long)cap_out, h_cnt[0], h_cnt[1]);
-            DevBuf vin, vout, rin, rout;
-            vin.alloc(&c, sizeof(float) * (size_t)std::max(1u, h_cnt[0]) * m.dim);
-            vout.alloc(&c, sizeof(float) * (size_t)std::max(1u, h_cnt[1]) * m.dim);
-            rin.alloc(&c, sizeof(int32_t) * std::max(1u, h_cnt[0]));
-            rout.alloc(&c, sizeof(int32_t) * std::max(1u, h_cnt[1]));
-            auto cap = [&](float* delta, const int32_t* list, uint32_t count, DevBuf& vals,
-                           DevBuf& rows) {
-                if (!count) return;
-                dim3 grid(std::min<uint32_t>((count + 3) / 4, 4096));
-                if (m.dim == 64)
-                    hipLaunchKernelGGL(sgns_capture_kernel<1>, grid, dim3(256), 0, c.stream, delta,
-                                       list, count, vals.as<float>(), rows.as<int32_t>());
-                else if (m.dim == 128)
-                    hipLaunchKernelGGL(sgns_capture_kernel<2>, grid, dim3(256), 0, c.stream, delta,
-                                       list, count, vals.as<float>(), rows.as<int32_t>());
-                else
-                    hipLaunchKernelGGL(sgns_capture_kernel<4>, grid, dim3(256), 0, c.stream, delta,
-                                       list, count, vals.as<float>(), rows.as<int32_t>());
-                FELOG_HIP(hipGetLastError());
-            };
-            cap(a.din, a.list_in, h_cnt[0], vin, rin);
-            cap(a.dout, a.list_out, h_cnt[1], vout, rout);
-            FELOG_HIP(hipMemcpyAsync(rows_in, rin.ptr, sizeof(int32_t) * h_cnt[0],
+            FELOG_REQUIRE(ui <= cap_in && uo <= cap_out,
+                          "capture buffers hold %lld / %lld rows, need %lld / %lld",
+                          (long long)cap_in, (long long)cap_out, (long long)ui, (long long)uo);
+            FELOG_HIP(hipMemcpyAsync(rows_in, m.list_in.ptr, sizeof(int32_t) * ui,
                                      hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemcpyAsync(rows_out, rout.ptr, sizeof(int32_t) * h_cnt[1],
+            FELOG_HIP(hipMemcpyAsync(rows_out, m.list_out.ptr, sizeof(int32_t) * uo,
                                      hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemcpyAsync(d_in_host, vin.ptr, sizeof(float) * h_cnt[0] * m.dim,
+            FELOG_HIP(hipMemcpyAsync(d_in_host, vin.ptr, sizeof(float) * ui * m.dim,
                                      hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemcpyAsync(d_out_host, vout.ptr, sizeof(float) * h_cnt[1] * m.dim,
+            FELOG_HIP(hipMemcpyAsync(d_out_host, vout.ptr, sizeof(float) * uo * m.dim,
                                      hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemsetAsync(m.counters.ptr, 0, sizeof(uint32_t) * 4, c.stream));
+            FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
             c.sync();
-            if (n_in) *n_in = h_cnt[0];
-            if (n_out) *n_out = h_cnt[1];
+            if (n_in) *n_in = ui;
+            if (n_out) *n_out = uo;
         }
-        ++m.serial;
         pairs_done += np;
     }
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, c.stream,
