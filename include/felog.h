@@ -147,11 +147,15 @@ void felog_walks_destroy(felog_walks* w);
 
 enum { FELOG_NEG_DEGREE = 0, FELOG_NEG_UNIGRAM = 1 };
 enum { FELOG_TABLE_IN = 0, FELOG_TABLE_OUT = 1 };
+enum { FELOG_PREC_FP32 = 0, FELOG_PREC_BF16 = 1 };
 
 typedef struct felog_model_params {
     int32_t dim;              /* d; 64, 128 or 256                                */
     int32_t neg_dist;         /* FELOG_NEG_DEGREE or FELOG_NEG_UNIGRAM             */
     uint64_t seed;            /* Philox key of the initial in-table                */
+    int32_t precision;        /* FELOG_PREC_FP32: FP32 tables, per-pair negatives;
+                                 FELOG_PREC_BF16: FP32 master tables plus BF16
+                                 copies read by shared-negative MFMA training      */
 } felog_model_params;
 
 /* Create FP32 tables [n][d]: in[v][c] = ((x >> 8) * 2^-24 - 0.5) / d with x
@@ -172,7 +176,12 @@ felog_status felog_model_set_unigram(felog_model* m, const felog_walks* corpus);
 /* Copy the integer cumulative weights cdf[n+1] (uint64) to host memory. */
 felog_status felog_model_read_cdf(const felog_model* m, uint64_t* cdf, int64_t cap);
 
-/* Copy a table (FELOG_TABLE_IN / FELOG_TABLE_OUT) as row-major float32 [n][d]. */
+/* Copy a BF16 model's BF16 copy of a table (bit patterns, row-major [n][d]);
+ * every row equals its FP32 master rounded to nearest even. */
+felog_status felog_embeddings_read_bf16(const felog_model* m, int32_t which, uint16_t* host,
+                                        int64_t cap);
+/* Copy a table (FELOG_TABLE_IN / FELOG_TABLE_OUT) as row-major float32 [n][d]
+ * (the FP32 masters of a BF16 model). */
 felog_status felog_embeddings_read(const felog_model* m, int32_t which, float* host, int64_t cap);
 /* Same into device memory (e.g. a torch tensor's data pointer) on the context's stream. */
 felog_status felog_embeddings_read_dev(const felog_model* m, int32_t which, void* dev,
@@ -197,6 +206,8 @@ typedef struct felog_train_params {
     int64_t chunk_walks;      /* pairs are ordered within chunks of this many walks
                                  (0 = 2^20)                                        */
     uint64_t seed;            /* Philox key of the negative draws                  */
+    int32_t shared_negatives; /* BF16 models: M negatives shared by the pairs of a
+                                 minibatch (P and M multiples of 64); 0 for FP32   */
 } felog_train_params;
 
 typedef struct felog_train_stats {
@@ -225,6 +236,17 @@ typedef struct felog_train_stats {
  * 3 << 24 | k / 2)); a negative equal to the centre is skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1). */
 felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
                                const felog_train_params* params, felog_train_stats* stats);
+/* BF16 models (shared negatives, not in the paper; a systems form of Eq. (2)):
+ * minibatch b of a corpus whose first walk id is B draws M negatives, m-th from
+ * words 2(m mod 2), 2(m mod 2)+1 of Philox(key = seed, counter = (b, low 32 bits
+ * of B, m / 2, 6 << 24)); every (pair, negative) term has weight K / M, terms
+ * whose negative equals the pair's centre are dropped.  With C = BF16 rows of
+ * in[ctx], N = BF16 rows of out[neg], O = BF16 rows of out[ctr]:
+ *   S = C N^T (MFMA, FP32 accumulation),  G = bf16(-lr (K/M) sigma(S) o mask),
+ *   delta in[ctx] += G N + g0 O,  delta out[neg] += G^T C,  delta out[ctr] += g0 C,
+ * g0 = lr (1 - sigma(rowwise C.O)); the FP32 masters take the deltas and the
+ * BF16 copies of the touched rows are refreshed. */
+
 /* Minibatches [first_mb, first_mb + n_mb) of the same schedule (the tables must
  * hold the state at the start of first_mb). */
 felog_status felog_train_steps(felog_model* m, const felog_walks* corpus,

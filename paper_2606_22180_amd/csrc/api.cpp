@@ -427,12 +427,15 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
                       "dim must be 64, 128 or 256 (got %d)", p->dim);
         FELOG_REQUIRE(p->neg_dist == FELOG_NEG_DEGREE || p->neg_dist == FELOG_NEG_UNIGRAM,
                       "unknown noise distribution %d", p->neg_dist);
+        FELOG_REQUIRE(p->precision == FELOG_PREC_FP32 || p->precision == FELOG_PREC_BF16,
+                      "unknown precision %d", p->precision);
         Ctx* c = g->ctx;
         auto m = std::make_unique<felog_model>();
         m->ctx = c;
         m->g = g;
         m->dim = p->dim;
         m->neg_dist = p->neg_dist;
+        m->precision = p->precision;
         size_t tb = sizeof(float) * (size_t)g->n * p->dim;
         m->tin.alloc(c, tb);
         m->tout.alloc(c, tb);
@@ -446,7 +449,12 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
         FELOG_HIP(hipMemsetAsync(m->cnt_in.ptr, 0, sizeof(uint32_t) * g->n, c->stream));
         FELOG_HIP(hipMemsetAsync(m->cnt_out.ptr, 0, sizeof(uint32_t) * g->n, c->stream));
         FELOG_HIP(hipMemsetAsync(m->meta.ptr, 0, sizeof(uint32_t) * 8, c->stream));
+        if (p->precision == FELOG_PREC_BF16) {
+            m->bin.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
+            m->bout.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
+        }
         launch_init_tables(*m, p->seed);
+        bf16_refresh_all(*m);
         if (p->neg_dist == FELOG_NEG_DEGREE) {
             DevBuf counts;
             counts.alloc(c, sizeof(uint32_t) * g->n);
@@ -466,6 +474,7 @@ felog_status felog_model_reset(felog_model* m, uint64_t seed)
     return guarded([&] {
         NEED(m);
         launch_init_tables(*m, seed);
+        bf16_refresh_all(*m);
         if (m->neg_dist == FELOG_NEG_UNIGRAM) m->have_noise = false;
         m->ctx->sync();
     });
@@ -548,6 +557,25 @@ felog_status felog_embeddings_write(felog_model* m, int32_t which, const float* 
                       (long long)m->g->n * m->dim);
         FELOG_HIP(hipMemcpyAsync(t.ptr, host, sizeof(float) * count, hipMemcpyHostToDevice,
                                  m->ctx->stream));
+        bf16_refresh_all(*m);
+        m->ctx->sync();
+    });
+}
+
+felog_status felog_embeddings_read_bf16(const felog_model* m, int32_t which, uint16_t* host,
+                                        int64_t cap)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(host);
+        FELOG_REQUIRE(m->precision == FELOG_PREC_BF16, "the model has no BF16 tables");
+        FELOG_REQUIRE(which == FELOG_TABLE_IN || which == FELOG_TABLE_OUT, "unknown table %d",
+                      which);
+        int64_t count = (int64_t)m->g->n * m->dim;
+        FELOG_REQUIRE(cap >= count, "buffer holds %lld values, need %lld", (long long)cap,
+                      (long long)count);
+        FELOG_HIP(hipMemcpyAsync(host, (which == FELOG_TABLE_IN ? m->bin : m->bout).ptr,
+                                 sizeof(uint16_t) * count, hipMemcpyDeviceToHost, m->ctx->stream));
         m->ctx->sync();
     });
 }
@@ -570,6 +598,15 @@ static void check_train_params(const felog_model* m, const felog_walks* w,
     FELOG_REQUIRE(w->L <= (1 << 23), "walks longer than 2^23 are not supported");
     FELOG_REQUIRE(m->have_noise, "the noise distribution is not set (unigram models need "
                   "felog_model_set_unigram or a first felog_run round)");
+    if (m->precision == FELOG_PREC_BF16) {
+        FELOG_REQUIRE(p->shared_negatives >= 64 && p->shared_negatives % 64 == 0 &&
+                          p->shared_negatives <= (1 << 16),
+                      "BF16 models need shared_negatives, a multiple of 64 in [64, 65536]");
+        FELOG_REQUIRE(p->minibatch_pairs % 64 == 0 && p->minibatch_pairs <= (1 << 16),
+                      "BF16 models need minibatch_pairs a multiple of 64, at most 65536");
+    } else {
+        FELOG_REQUIRE(p->shared_negatives == 0, "shared negatives need a BF16 model");
+    }
 }
 
 felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,

@@ -1,0 +1,457 @@
+// Shared-negative SGNS on BF16 tables with MFMA (a systems form of Eq. (2);
+// the paper trains in FP32 and does not describe it).
+//
+// A minibatch of P pairs (the same pair order as the FP32 path) shares M
+// negatives.  With C = bf16 in[ctx] (P x d), O = bf16 out[ctr] (P x d) and
+// N = bf16 out[neg] (M x d):
+//   S  = C N^T                       (P x M, MFMA, FP32 accumulation)
+//   G  = bf16(-lr (K/M) sigma(S) o mask),  mask = [neg != ctr] (and real pairs)
+//   dC = G N,  dN = G^T C            (MFMA, FP32 accumulation)
+//   g0 = lr (1 - sigma(C.O)) row-wise (FP32 dot of the BF16 rows)
+//   in[ctx] += dC + g0 O,  out[neg] += dN,  out[ctr] += g0 C   on FP32 masters,
+// then the BF16 copies of every touched row are refreshed from the masters
+// (round to nearest even).  Each (pair, negative) term weighs K/M, so the
+// expected update equals Eq. (2) with K negatives per pair.
+//
+// Kernels per minibatch: gather (rows, transposed copies, positive terms),
+// scores (S and G on 64x64 tiles, 4 waves of 32x32), grads (dC and dN on
+// 32x32 tiles, one wave each, K = M or P), apply (FP32 atomics on masters;
+// rows repeat only when a node is drawn twice), refresh.
+// MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds 8 consecutive k of row
+// (l mod 16) of A and of column (l mod 16) of B, k chunk l / 16; it receives
+// D[4 (l / 16) + j][l mod 16], j = 0..3.
+#include <algorithm>
+
+#include "common.h"
+#include "noise.h"
+
+namespace felog {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u) {                // inf / nan
+        uint16_t h = (uint16_t)(u >> 16);
+        if (u & 0x007FFFFFu) h |= 0x0040u;
+        return h;
+    }
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p)
+{
+    uint4 v = *reinterpret_cast<const uint4*>(p);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+struct Bf16Args {
+    // tables
+    float* tin;
+    float* tout;
+    uint16_t* bin;
+    uint16_t* bout;
+    int32_t d;
+    // pair order (as the FP32 path)
+    const int32_t* walks;
+    int64_t W;
+    const int32_t* vcols;
+    uint32_t Wv;
+    const int32_t* slices;
+    uint32_t first_pair;
+    uint32_t np;          // real pairs in this minibatch (<= P)
+    int32_t window;
+    // shared negatives
+    uint32_t P, M;
+    int32_t K;
+    uint32_t mb;          // minibatch index b
+    uint32_t id_lo;       // low 32 bits of the corpus's first walk id
+    uint64_t seed;
+    NoiseTable noise;
+    float lr;
+    // scratch
+    int32_t* ids;         // ctx[P], ctr[P], neg[M]
+    uint16_t* C;          // [P][d]
+    uint16_t* O;          // [P][d]
+    uint16_t* N;          // [M][d]
+    uint16_t* Ct;         // [d][P]
+    uint16_t* Nt;         // [d][M]
+    uint16_t* G;          // [P][M]
+    uint16_t* Gt;         // [M][P]
+    float* g0;            // [P]
+    float* dC;            // [P][d]
+    float* dN;            // [M][d]
+    double* loss_part;    // [P + M] gather slots, then one per scores wave
+    float* cap_in;        // capture (dense [n][d]) instead of updating masters
+    float* cap_out;
+};
+
+__device__ __forceinline__ float wave_sum32(float x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+__device__ __forceinline__ double softplus_d(double x)   // log(1 + exp(x))
+{
+    return fmax(x, 0.0) + log1p(exp(-fabs(x)));
+}
+
+// One wave per row: waves [0, P) pairs, [P, P + M) negatives.
+__global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.P + a.M) return;
+    if (w < a.P) {
+        const uint32_t p = w;
+        int32_t ctx = -1, ctr = -1;
+        if (p < a.np) {
+            uint32_t gq = a.first_pair + p;
+            uint32_t sidx = gq / a.Wv;
+            uint32_t rank = gq - sidx * a.Wv;
+            int32_t js = a.slices[sidx];
+            int32_t col = a.vcols[rank];
+            int32_t j = js >> 8, s = js & 255;
+            int32_t off = s < a.window ? s - a.window : s - a.window + 1;
+            ctx = a.walks[(int64_t)(j + off) * a.W + col];
+            ctr = a.walks[(int64_t)j * a.W + col];
+        }
+        float dot = 0.0f;
+        for (int e = lane; e < a.d; e += 64) {
+            uint16_t c = ctx >= 0 ? a.bin[(int64_t)ctx * a.d + e] : 0;
+            uint16_t o = ctr >= 0 ? a.bout[(int64_t)ctr * a.d + e] : 0;
+            a.C[(int64_t)p * a.d + e] = c;
+            a.O[(int64_t)p * a.d + e] = o;
+            a.Ct[(int64_t)e * a.P + p] = c;
+            dot = fmaf(bf16_to_f32(c), bf16_to_f32(o), dot);
+        }
+        dot = wave_sum32(dot);
+        if (lane == 0) {
+            a.ids[p] = ctx;
+            a.ids[a.P + p] = ctr;
+            float g = 0.0f;
+            if (ctx >= 0) {
+                g = a.lr * (1.0f - 1.0f / (1.0f + expf(-dot)));
+                a.loss_part[w] += softplus_d(-(double)dot);      // -log sigma(s0)
+            }
+            a.g0[p] = g;
+        }
+    } else {
+        const uint32_t m = w - a.P;
+        Rand4 r = philox4x32(a.mb, a.id_lo, m >> 1, kTagSharedNeg, a.seed);
+        uint32_t lo = (m & 1) ? r.v[2] : r.v[0];
+        uint32_t hi = (m & 1) ? r.v[3] : r.v[1];
+        const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
+        for (int e = lane; e < a.d; e += 64) {
+            uint16_t x = a.bout[(int64_t)neg * a.d + e];
+            a.N[(int64_t)m * a.d + e] = x;
+            a.Nt[(int64_t)e * a.M + m] = x;
+        }
+        if (lane == 0) a.ids[2 * a.P + m] = neg;
+    }
+}
+
+// S and G on a 64x64 tile per block; wave w computes rows 32 (w / 2), cols 32 (w % 2).
+__global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t r0 = blockIdx.x * 64 + (wv >> 1) * 32;
+    const uint32_t c0 = blockIdx.y * 64 + (wv & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < a.d; k0 += 32) {
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            fa[i] = load8(a.C + (int64_t)(r0 + 16 * i + li) * a.d + k0 + 8 * lk);
+            fb[i] = load8(a.N + (int64_t)(c0 + 16 * i + li) * a.d + k0 + 8 * lk);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    const float wk = -a.lr * (float)a.K / (float)a.M;
+    const double lw = (double)a.K / (double)a.M;
+    double lacc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t n = c0 + 16 * j + li;
+        const int32_t neg = a.ids[2 * a.P + n];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t row = r0 + 16 * i + 4 * lk + q;
+                const float s = acc[i][j][q];
+                const bool keep = row < a.np && a.ids[a.P + row] != neg;
+                float g = 0.0f;
+                if (keep) {
+                    g = wk / (1.0f + expf(-s));
+                    lacc += lw * softplus_d((double)s);           // -(K/M) log sigma(-s)
+                }
+                const uint16_t gb = bf16_rne(g);
+                a.G[(int64_t)row * a.M + n] = gb;
+                a.Gt[(int64_t)n * a.P + row] = gb;
+            }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lacc += __shfl_xor(lacc, off);
+    if (lane == 0) {
+        const uint32_t slot = a.P + a.M + (blockIdx.y * gridDim.x + blockIdx.x) * 4 + wv;
+        a.loss_part[slot] += lacc;
+    }
+}
+
+// dC = G N (tiles [0, P/32 * d/32)) and dN = G^T C (the rest), one wave per 32x32 tile.
+__global__ __launch_bounds__(256) void bf16_grads_kernel(Bf16Args a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t te = a.d / 32;
+    const uint32_t tiles_c = (a.P / 32) * te, tiles_n = (a.M / 32) * te;
+    if (t >= tiles_c + tiles_n) return;
+    const bool isC = t < tiles_c;
+    const uint32_t tt = isC ? t : t - tiles_c;
+    const uint32_t r0 = (tt / te) * 32, e0 = (tt % te) * 32;
+    const uint16_t* A = isC ? a.G : a.Gt;       // rows r, k over the shared dimension
+    const uint16_t* B = isC ? a.Nt : a.Ct;      // rows e, k over the shared dimension
+    const uint32_t kdim = isC ? a.M : a.P;
+    const int li = lane & 15, lk = lane >> 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t k0 = 0; k0 < kdim; k0 += 32) {
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            fa[i] = load8(A + (int64_t)(r0 + 16 * i + li) * kdim + k0 + 8 * lk);
+            fb[i] = load8(B + (int64_t)(e0 + 16 * i + li) * kdim + k0 + 8 * lk);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    float* out = isC ? a.dC : a.dN;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                out[(int64_t)(r0 + 16 * i + 4 * lk + q) * a.d + e0 + 16 * j + li] = acc[i][j][q];
+}
+
+// FP32 master updates (or captured deltas), one wave per pair / negative.
+__global__ __launch_bounds__(256) void bf16_apply_kernel(Bf16Args a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.P + a.M) return;
+    float* tin = a.cap_in ? a.cap_in : a.tin;
+    float* tout = a.cap_out ? a.cap_out : a.tout;
+    if (w < a.P) {
+        const int32_t ctx = a.ids[w], ctr = a.ids[a.P + w];
+        if (ctx < 0) return;
+        const float g = a.g0[w];
+        for (int e = lane; e < a.d; e += 64) {
+            const float o = bf16_to_f32(a.O[(int64_t)w * a.d + e]);
+            const float c = bf16_to_f32(a.C[(int64_t)w * a.d + e]);
+            unsafeAtomicAdd(&tin[(int64_t)ctx * a.d + e], a.dC[(int64_t)w * a.d + e] + g * o);
+            unsafeAtomicAdd(&tout[(int64_t)ctr * a.d + e], g * c);
+        }
+    } else {
+        const uint32_t m = w - a.P;
+        const int32_t neg = a.ids[2 * a.P + m];
+        for (int e = lane; e < a.d; e += 64)
+            unsafeAtomicAdd(&tout[(int64_t)neg * a.d + e], a.dN[(int64_t)m * a.d + e]);
+    }
+}
+
+// BF16 copies of the touched rows from their masters.
+__global__ __launch_bounds__(256) void bf16_refresh_kernel(Bf16Args a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= a.P + a.M) return;
+    int32_t rows[2];
+    const float* src[2];
+    uint16_t* dst[2];
+    int nr = 0;
+    if (w < a.P) {
+        if (a.ids[w] < 0) return;
+        rows[0] = a.ids[w];
+        src[0] = a.tin;
+        dst[0] = a.bin;
+        rows[1] = a.ids[a.P + w];
+        src[1] = a.tout;
+        dst[1] = a.bout;
+        nr = 2;
+    } else {
+        rows[0] = a.ids[2 * a.P + (w - a.P)];
+        src[0] = a.tout;
+        dst[0] = a.bout;
+        nr = 1;
+    }
+    for (int r = 0; r < nr; ++r)
+        for (int e = lane; e < a.d; e += 64)
+            dst[r][(int64_t)rows[r] * a.d + e] = bf16_rne(src[r][(int64_t)rows[r] * a.d + e]);
+}
+
+__global__ void bf16_from_master_kernel(const float* src, uint16_t* dst, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) dst[i] = bf16_rne(src[i]);
+}
+
+void bf16_refresh_all(Model& m)
+{
+    if (m.precision != FELOG_PREC_BF16) return;
+    Ctx& c = *m.ctx;
+    const int64_t count = (int64_t)m.g->n * m.dim;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(bf16_from_master_kernel, dim3(blocks), dim3(256), 0, c.stream,
+                       m.tin.as<float>(), m.bin.as<uint16_t>(), count);
+    hipLaunchKernelGGL(bf16_from_master_kernel, dim3(blocks), dim3(256), 0, c.stream,
+                       m.tout.as<float>(), m.bout.as<uint16_t>(), count);
+    FELOG_HIP(hipGetLastError());
+}
+
+__global__ void loss_sum_kernel(const double* part, int64_t n, double* out)
+{
+    __shared__ double lds[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = lds[0];
+}
+
+void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
+                            const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
+                            int64_t end, float* cap_in, float* cap_out, felog_train_stats* stats)
+{
+    Ctx& c = *m.ctx;
+    const uint32_t P = (uint32_t)p.minibatch_pairs, M = (uint32_t)p.shared_negatives;
+    const int d = m.dim;
+    if (m.bf_P < P || m.bf_M < M) {
+        m.bf_P = std::max(m.bf_P, P);
+        m.bf_M = std::max(m.bf_M, M);
+        const size_t cp = m.bf_P, cm = m.bf_M;
+        m.bf_ids.alloc(&c, sizeof(int32_t) * (2 * cp + cm));
+        m.bf_C.alloc(&c, sizeof(uint16_t) * cp * d);
+        m.bf_O.alloc(&c, sizeof(uint16_t) * cp * d);
+        m.bf_N.alloc(&c, sizeof(uint16_t) * cm * d);
+        m.bf_Ct.alloc(&c, sizeof(uint16_t) * cp * d);
+        m.bf_Nt.alloc(&c, sizeof(uint16_t) * cm * d);
+        m.bf_G.alloc(&c, sizeof(uint16_t) * cp * cm);
+        m.bf_Gt.alloc(&c, sizeof(uint16_t) * cp * cm);
+        m.bf_g0.alloc(&c, sizeof(float) * cp);
+        m.bf_dC.alloc(&c, sizeof(float) * cp * d);
+        m.bf_dN.alloc(&c, sizeof(float) * cm * d);
+    }
+    const uint32_t score_waves = (P / 64) * (M / 64) * 4;
+    const int64_t nslots = (int64_t)P + M + score_waves;
+    DevBuf loss_part;
+    loss_part.alloc(&c, sizeof(double) * nslots);
+    FELOG_HIP(hipMemsetAsync(loss_part.ptr, 0, sizeof(double) * nslots, c.stream));
+
+    Bf16Args a{};
+    a.tin = m.tin.as<float>();
+    a.tout = m.tout.as<float>();
+    a.bin = m.bin.as<uint16_t>();
+    a.bout = m.bout.as<uint16_t>();
+    a.d = d;
+    a.walks = w.data.as<int32_t>();
+    a.W = w.W;
+    a.slices = d_slices;
+    a.window = p.window;
+    a.P = P;
+    a.M = M;
+    a.K = p.negatives;
+    a.id_lo = (uint32_t)w.id_base;
+    a.seed = p.seed;
+    a.noise = NoiseTable{m.cdf.as<uint64_t>(), m.guide.as<int32_t>(), m.total_weight, m.guide_bits};
+    a.ids = m.bf_ids.as<int32_t>();
+    a.C = m.bf_C.as<uint16_t>();
+    a.O = m.bf_O.as<uint16_t>();
+    a.N = m.bf_N.as<uint16_t>();
+    a.Ct = m.bf_Ct.as<uint16_t>();
+    a.Nt = m.bf_Nt.as<uint16_t>();
+    a.G = m.bf_G.as<uint16_t>();
+    a.Gt = m.bf_Gt.as<uint16_t>();
+    a.g0 = m.bf_g0.as<float>();
+    a.dC = m.bf_dC.as<float>();
+    a.dN = m.bf_dN.as<float>();
+    a.loss_part = loss_part.as<double>();
+    a.cap_in = cap_in;
+    a.cap_out = cap_out;
+
+    const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
+    const uint32_t row_blocks = (P + M + 3) / 4;
+    const uint32_t te = d / 32;
+    const uint32_t grad_blocks = ((P / 32) * te + (M / 32) * te + 3) / 4;
+    int64_t pairs_done = 0;
+    FELOG_HIP(hipEventRecord(c.ev0, c.stream));
+    size_t chunk = 0;
+    for (int64_t b = first_mb; b < end; ++b) {
+        while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
+        const int64_t local = b - sch.chunk_first_mb[chunk];
+        const int64_t first = local * (int64_t)P;
+        const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
+        a.vcols = w.valid_cols.as<int32_t>() + sch.chunk_valid_base[chunk];
+        a.Wv = (uint32_t)w.chunk_valid[chunk];
+        a.first_pair = (uint32_t)first;
+        a.np = (uint32_t)np;
+        a.mb = (uint32_t)b;
+        a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
+        hipLaunchKernelGGL(bf16_gather_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL(bf16_scores_kernel, dim3(P / 64, M / 64), dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL(bf16_grads_kernel, dim3(grad_blocks), dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL(bf16_apply_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        if (!cap_in) hipLaunchKernelGGL(bf16_refresh_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        FELOG_HIP(hipGetLastError());
+        pairs_done += np;
+    }
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, c.stream, loss_part.as<double>(),
+                       nslots, m.loss_out.as<double>());
+    FELOG_HIP(hipGetLastError());
+    FELOG_HIP(hipEventRecord(c.ev1, c.stream));
+    double loss = 0.0;
+    FELOG_HIP(hipMemcpyAsync(&loss, m.loss_out.ptr, sizeof loss, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    float ms = 0.0f;
+    FELOG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    if (stats) {
+        *stats = felog_train_stats{};
+        stats->minibatches = end - first_mb;
+        stats->pairs = pairs_done;
+        stats->minibatches_total = sch.B;
+        stats->loss = loss;
+        stats->ms = ms;
+    }
+}
+
+}  // namespace felog

@@ -111,8 +111,10 @@ struct Model {
     Graph* g = nullptr;
     int32_t dim = 0;
     int32_t neg_dist = FELOG_NEG_DEGREE;
+    int32_t precision = FELOG_PREC_FP32;
     bool have_noise = false;
-    DevBuf tin, tout;             // float [n][d]
+    DevBuf tin, tout;             // float [n][d] (the masters of a BF16 model)
+    DevBuf bin, bout;             // uint16 [n][d]: BF16 copies (BF16 models)
     DevBuf cnt_in, cnt_out;       // uint32 [n]: touches of each row in this minibatch (0 between)
     DevBuf off_in, off_out;       // int32 [n]: first entry of each touched row's segment
     DevBuf cdf;                   // uint64 [n+1]
@@ -135,6 +137,19 @@ struct Model {
     DevBuf meta;                  // uint32 [8]: list lengths (in, out), chunk counts (in, out)
     DevBuf loss_out;              // double [1]
     DevBuf row_totals;            // uint64 [2]: summed touched-list lengths (in, out)
+    // shared-negative (BF16) minibatch scratch
+    uint32_t bf_P = 0, bf_M = 0;
+    DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0, bf_dC, bf_dN;
+};
+
+// Minibatch schedule of one training call over a corpus.
+struct TrainSchedule {
+    std::vector<int64_t> chunk_first_mb;   // first global minibatch of each chunk
+    std::vector<int64_t> chunk_pairs;
+    std::vector<int64_t> chunk_valid_base; // offset of the chunk in valid_cols
+    int64_t B = 0;
+    int64_t total_pairs = 0;
+    int64_t nslices = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -189,6 +204,10 @@ void train_minibatches(Model& m, const Walks& w, const felog_train_params& p, in
                        int32_t* rows_in, float* d_in, int64_t cap_in, int64_t* n_in,
                        int32_t* rows_out, float* d_out, int64_t cap_out, int64_t* n_out);
 int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_pairs);
+void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
+                            const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
+                            int64_t end, float* cap_in, float* cap_out, felog_train_stats* stats);
+void bf16_refresh_all(Model& m);
 void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
               double* psi_host, int64_t psi_cap);
 // Order-preserving compaction of nodes[i] where flags[i] != 0; returns the count.

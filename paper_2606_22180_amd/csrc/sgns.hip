@@ -624,20 +624,11 @@ static std::vector<int32_t> make_slices(int32_t L, int32_t w)
     return out;
 }
 
-struct Schedule {
-    std::vector<int64_t> chunk_first_mb;   // first global minibatch of each chunk
-    std::vector<int64_t> chunk_pairs;
-    std::vector<int64_t> chunk_valid_base; // offset of the chunk in valid_cols
-    int64_t B = 0;
-    int64_t total_pairs = 0;
-    int64_t nslices = 0;
-};
-
-static Schedule make_schedule(Walks& w, const felog_train_params& p)
+static TrainSchedule make_schedule(Walks& w, const felog_train_params& p)
 {
     int64_t chunk = p.chunk_walks ? p.chunk_walks : (int64_t)1 << 20;
     launch_valid_columns(w, chunk);
-    Schedule s;
+    TrainSchedule s;
     s.nslices = (int64_t)make_slices(w.L, p.window).size();
     int64_t base = 0;
     for (size_t c = 0; c < w.chunk_valid.size(); ++c) {
@@ -657,7 +648,7 @@ static Schedule make_schedule(Walks& w, const felog_train_params& p)
 
 int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_pairs)
 {
-    Schedule s = make_schedule(w, p);
+    TrainSchedule s = make_schedule(w, p);
     if (total_pairs) *total_pairs = s.total_pairs;
     return s.B;
 }
@@ -738,13 +729,69 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     Walks& w = const_cast<Walks&>(wc);
     Ctx& c = *m.ctx;
     c.make_current();
-    Schedule sch = make_schedule(w, p);
+    TrainSchedule sch = make_schedule(w, p);
     const int K = p.negatives;
     const int64_t P = p.minibatch_pairs;
     int64_t end = n_mb < 0 ? sch.B : std::min<int64_t>(sch.B, first_mb + n_mb);
     if (first_mb > sch.B) first_mb = sch.B;
     if (!apply) FELOG_REQUIRE(first_mb < sch.B, "minibatch %lld out of range (%lld minibatches)",
                               (long long)first_mb, (long long)sch.B);
+
+    if (m.precision == FELOG_PREC_BF16) {
+        std::vector<int32_t> sl = make_slices(w.L, p.window);
+        DevBuf slices;
+        slices.alloc(&c, sizeof(int32_t) * std::max<size_t>(sl.size(), 1));
+        if (!sl.empty())
+            FELOG_HIP(hipMemcpyAsync(slices.ptr, sl.data(), sizeof(int32_t) * sl.size(),
+                                     hipMemcpyHostToDevice, c.stream));
+        if (apply) {
+            train_minibatches_bf16(m, w, p, sch, slices.as<int32_t>(), first_mb, end, nullptr,
+                                   nullptr, stats);
+            return;
+        }
+        // capture: deltas into dense zeroed tables, then the touched rows
+        const int64_t cnt = (int64_t)m.g->n * m.dim;
+        FELOG_REQUIRE(cnt <= ((int64_t)1 << 28), "delta capture of a BF16 model is limited to "
+                      "n * d <= 2^28");
+        DevBuf din, dout;
+        din.alloc(&c, sizeof(float) * cnt);
+        dout.alloc(&c, sizeof(float) * cnt);
+        FELOG_HIP(hipMemsetAsync(din.ptr, 0, din.bytes, c.stream));
+        FELOG_HIP(hipMemsetAsync(dout.ptr, 0, dout.bytes, c.stream));
+        felog_train_stats st{};
+        train_minibatches_bf16(m, w, p, sch, slices.as<int32_t>(), first_mb, first_mb + 1,
+                               din.as<float>(), dout.as<float>(), &st);
+        std::vector<int32_t> ids(2 * (size_t)p.minibatch_pairs + p.shared_negatives);
+        FELOG_HIP(hipMemcpyAsync(ids.data(), m.bf_ids.ptr, sizeof(int32_t) * ids.size(),
+                                 hipMemcpyDeviceToHost, c.stream));
+        std::vector<float> hin(cnt), hout(cnt);
+        FELOG_HIP(hipMemcpyAsync(hin.data(), din.ptr, sizeof(float) * cnt, hipMemcpyDeviceToHost,
+                                 c.stream));
+        FELOG_HIP(hipMemcpyAsync(hout.data(), dout.ptr, sizeof(float) * cnt,
+                                 hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        std::vector<char> seen_in(m.g->n, 0), seen_out(m.g->n, 0);
+        int64_t ui = 0, uo = 0;
+        const int64_t Pn = p.minibatch_pairs;
+        auto put = [&](int32_t row, bool out) {
+            std::vector<char>& seen = out ? seen_out : seen_in;
+            if (row < 0 || seen[row]) return;
+            seen[row] = 1;
+            int64_t& u = out ? uo : ui;
+            FELOG_REQUIRE(u < (out ? cap_out : cap_in), "capture buffers too small");
+            (out ? rows_out : rows_in)[u] = row;
+            std::copy_n((out ? hout : hin).data() + (int64_t)row * m.dim, m.dim,
+                        (out ? d_out_host : d_in_host) + u * m.dim);
+            ++u;
+        };
+        for (int64_t q = 0; q < Pn; ++q) put(ids[q], false);
+        for (int64_t q = 0; q < Pn; ++q) if (ids[q] >= 0) put(ids[Pn + q], true);
+        for (int64_t q = 0; q < p.shared_negatives; ++q) put(ids[2 * Pn + q], true);
+        if (n_in) *n_in = ui;
+        if (n_out) *n_out = uo;
+        if (stats) *stats = st;
+        return;
+    }
 
     // scratch sized for this minibatch size
     if (m.cap_pairs < P || m.cap_K < K) {

@@ -242,12 +242,22 @@ struct ColumnId {
     __device__ int32_t operator()(int64_t col) const { return (int32_t)col; }
 };
 
-__global__ void chunk_count_kernel(const int32_t* second_step, int64_t W, int64_t chunk,
-                                   unsigned long long* counts)
+// Walks per chunk that yield pairs: valid_cols is sorted, so the count of chunk
+// c is the number of entries in [c * chunk, (c + 1) * chunk), by binary search.
+__global__ void chunk_count_kernel(const int32_t* valid_cols, int64_t n_valid, int64_t n_chunks,
+                                   int64_t chunk, unsigned long long* counts)
 {
-    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= W || second_step[col] < 0) return;
-    atomicAdd(&counts[col / chunk], 1ull);
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    auto lower = [&](int64_t x) {
+        int64_t lo = 0, hi = n_valid;
+        while (lo < hi) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (valid_cols[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    counts[c] = (unsigned long long)(lower((c + 1) * chunk) - lower(c * chunk));
 }
 
 void launch_valid_columns(Walks& w, int64_t chunk)
@@ -264,9 +274,9 @@ void launch_valid_columns(Walks& w, int64_t chunk)
         w.n_valid = compact(c, LongWalk{second}, ColumnId{}, w.W, w.valid_cols);
         DevBuf cnt;
         cnt.alloc(&c, sizeof(unsigned long long) * n_chunks);
-        FELOG_HIP(hipMemsetAsync(cnt.ptr, 0, sizeof(unsigned long long) * n_chunks, c.stream));
-        hipLaunchKernelGGL(chunk_count_kernel, dim3((w.W + 255) / 256), dim3(256), 0, c.stream,
-                           second, w.W, chunk, cnt.as<unsigned long long>());
+        hipLaunchKernelGGL(chunk_count_kernel, dim3((n_chunks + 255) / 256), dim3(256), 0,
+                           c.stream, w.valid_cols.as<int32_t>(), w.n_valid, n_chunks, chunk,
+                           cnt.as<unsigned long long>());
         FELOG_HIP(hipGetLastError());
         std::vector<unsigned long long> h(n_chunks);
         FELOG_HIP(hipMemcpyAsync(h.data(), cnt.ptr, sizeof(unsigned long long) * n_chunks,

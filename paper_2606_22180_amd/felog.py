@@ -22,6 +22,7 @@ FELOG_OK, FELOG_EINVAL, FELOG_ENOMEM, FELOG_EDEVICE, FELOG_ESTATE, FELOG_EUNSUPP
 WALK_UNIFORM, WALK_NODE2VEC = 0, 1
 NEG_DEGREE, NEG_UNIGRAM = 0, 1
 TABLE_IN, TABLE_OUT = 0, 1
+PREC_FP32, PREC_BF16 = 0, 1
 FEEDBACK_MONOTONE, FEEDBACK_RECOMPUTE_ALL = 0, 1
 MAX_ROUNDS = 64
 
@@ -43,13 +44,15 @@ class felog_walk_params(C.Structure):
 
 
 class felog_model_params(C.Structure):
-    _fields_ = [("dim", C.c_int32), ("neg_dist", C.c_int32), ("seed", C.c_uint64)]
+    _fields_ = [("dim", C.c_int32), ("neg_dist", C.c_int32), ("seed", C.c_uint64),
+                ("precision", C.c_int32)]
 
 
 class felog_train_params(C.Structure):
     _fields_ = [("window", C.c_int32), ("negatives", C.c_int32), ("lr_start", C.c_float),
                 ("lr_end", C.c_float), ("minibatch_pairs", C.c_int64),
-                ("chunk_walks", C.c_int64), ("seed", C.c_uint64)]
+                ("chunk_walks", C.c_int64), ("seed", C.c_uint64),
+                ("shared_negatives", C.c_int32)]
 
 
 class felog_train_stats(C.Structure):
@@ -109,6 +112,7 @@ SIGNATURES = {
     "felog_model_reset": (_i32, [_p, _u64]),
     "felog_embeddings_read": (_i32, [_p, _i32, _p, _i64]),
     "felog_embeddings_read_dev": (_i32, [_p, _i32, _p, _i64]),
+    "felog_embeddings_read_bf16": (_i32, [_p, _i32, _p, _i64]),
     "felog_embeddings_write": (_i32, [_p, _i32, _p, _i64]),
     "felog_train_epoch": (_i32, [_p, _p, C.POINTER(felog_train_params),
                                  C.POINTER(felog_train_stats)]),
@@ -282,17 +286,18 @@ class Walks(_Handle):
 
 
 def train_params(*, window, negatives, lr_start=0.025, lr_end=1e-4, minibatch_pairs,
-                 chunk_walks=0, seed=0) -> felog_train_params:
+                 chunk_walks=0, seed=0, shared_negatives=0) -> felog_train_params:
     return felog_train_params(window, negatives, lr_start, lr_end, minibatch_pairs,
-                              chunk_walks, seed)
+                              chunk_walks, seed, shared_negatives)
 
 
 class Model(_Handle):
     _destroy = "felog_model_destroy"
 
     @classmethod
-    def create(cls, g: Graph, *, dim: int, neg_dist: int = NEG_DEGREE, seed: int = 0) -> "Model":
-        prm = felog_model_params(dim, neg_dist, seed)
+    def create(cls, g: Graph, *, dim: int, neg_dist: int = NEG_DEGREE, seed: int = 0,
+               precision: int = PREC_FP32) -> "Model":
+        prm = felog_model_params(dim, neg_dist, seed, precision)
         h = C.c_void_p()
         _check(load().felog_model_create(g.handle, C.byref(prm), C.byref(h)))
         m = cls(h, g)
@@ -314,6 +319,11 @@ class Model(_Handle):
     def read(self, which: int = TABLE_IN) -> np.ndarray:
         out = np.zeros((self.n, self.dim), np.float32)
         _check(load().felog_embeddings_read(self.handle, which, out.ctypes.data, out.size))
+        return out
+
+    def read_bf16(self, which: int = TABLE_IN) -> np.ndarray:
+        out = np.zeros((self.n, self.dim), np.uint16)
+        _check(load().felog_embeddings_read_bf16(self.handle, which, out.ctypes.data, out.size))
         return out
 
     def read_dev(self, which: int, ptr: int, cap: int):

@@ -1,0 +1,149 @@
+"""GPU parity of the BF16 shared-negative form against the oracle's emulation.
+
+The oracle rounds rows and the coefficients G to BF16 exactly as the form
+defines and sums in FP64; the GPU sums in FP32 on MFMA.  A G entry whose FP32
+and FP64 values round to different BF16 neighbours differs by one BF16 ulp
+(2^-8 relative), so per updated row
+  ||d_gpu - d_orc|| <= 2^-8 ||m|| + 1e-5 ||d_orc||,
+with m the row's sum of |term| vectors.  The FP32 masters and BF16 copies are
+checked bit-exactly (copy = round-to-nearest-even of the master).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import os
+    from paper_2606_22180_amd import build, felog
+    if not os.path.exists(build.LIB):
+        build.build()
+    felog.load()
+    return felog
+
+
+@pytest.fixture(scope="module")
+def ctx(fl):
+    return fl.Context(0)
+
+
+@pytest.fixture(scope="module")
+def sbm():
+    return synth.build_graph("sbm1k")
+
+
+def _bf16_bits(orc, x):
+    return orc.bf16_round(x).view(np.uint32) >> 16
+
+
+def _setup(fl, ctx, g, *, dim, P, M, K, L=40, window=5, r=10, seed=3):
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=r, L=L, seed=11)
+    Mo = fl.Model.create(G, dim=dim, neg_dist=fl.NEG_DEGREE, seed=5, precision=fl.PREC_BF16)
+    prm = fl.train_params(window=window, negatives=K, minibatch_pairs=P, seed=seed,
+                          shared_negatives=M)
+    return G, W, Mo, prm
+
+
+def test_bf16_copies_track_masters(fl, ctx, orc, sbm):
+    g = sbm.train
+    _say("bf16 copies = rne(masters)")
+    G, W, Mo, prm = _setup(fl, ctx, g, dim=64, P=1024, M=1024, K=5)
+    for step in range(2):
+        for which in (fl.TABLE_IN, fl.TABLE_OUT):
+            master = Mo.read(which)
+            assert np.array_equal(Mo.read_bf16(which).astype(np.uint32),
+                                  _bf16_bits(orc, master))
+        Mo.train_steps(W, prm, step * 100, 100)
+
+
+def _agg(n, d, rows, vals):
+    out = np.zeros((n, d))
+    np.add.at(out, rows, vals)
+    return out
+
+
+@pytest.mark.parametrize("dim,pre", [(64, 0), (128, 300), (256, 50)])
+def test_bf16_step_parity(fl, ctx, orc, sbm, dim, pre):
+    g = sbm.train
+    P, M, K = 1024, 1024, 5
+    _say("bf16 step parity sbm1k d=%d after %d minibatches" % (dim, pre))
+    G, W, Mo, prm = _setup(fl, ctx, g, dim=dim, P=P, M=M, K=K)
+    walks = W.read()
+    cdf = Mo.read_cdf()
+    B, _ = orc.count_minibatches(walks, 5, P)
+    if pre:
+        Mo.train_steps(W, prm, 0, pre)
+    for b in (pre, pre + 1, B - 1):
+        tin = Mo.read(fl.TABLE_IN)
+        tout = Mo.read(fl.TABLE_OUT)
+        ri, di, ro, do, loss = Mo.train_delta(W, prm, b)
+        mb = orc.minibatch_pairs(walks, 5, P, b)
+        neg = orc.shared_negatives(b, 0, M, prm.seed, cdf)
+        lr = orc.lr_at(b, B, prm.lr_start, prm.lr_end)
+        dctx, dneg, dctr, oloss = orc.shared_neg_step(tin, tout, mb.ctx, mb.ctr, neg, K, lr,
+                                                      bf16=True)
+        n = g.n
+        assert set(ri.tolist()) == set(mb.ctx.tolist())
+        assert set(ro.tolist()) == set(mb.ctr.tolist()) | set(neg.tolist())
+        ref_in = _agg(n, dim, mb.ctx, dctx)
+        ref_out = _agg(n, dim, neg, dneg) + _agg(n, dim, mb.ctr, dctr)
+        # |term| mass per row, from the same BF16-rounded operands
+        C = orc.bf16_round(tin[mb.ctx]).astype(np.float64)
+        O = orc.bf16_round(tout[mb.ctr]).astype(np.float64)
+        N = orc.bf16_round(tout[neg]).astype(np.float64)
+        S = C @ N.T
+        Gm = lr * K / M / (1 + np.exp(-S)) * (neg[None, :] != mb.ctr[:, None])
+        s0 = (C * O).sum(1)
+        g0 = lr / (1 + np.exp(s0))
+        m_in = _agg(n, dim, mb.ctx, Gm @ np.abs(N) + g0[:, None] * np.abs(O))
+        m_out = _agg(n, dim, neg, Gm.T @ np.abs(C)) + _agg(n, dim, mb.ctr, g0[:, None] * np.abs(C))
+        for what, gpu_rows, gpu_vals, ref, mass in (("in", ri, di, ref_in, m_in),
+                                                   ("out", ro, do, ref_out, m_out)):
+            gpu = np.zeros((n, dim))
+            gpu[gpu_rows] = gpu_vals
+            err = np.linalg.norm(gpu - ref, axis=1)
+            tol = 2.0 ** -8 * np.linalg.norm(mass, axis=1) + 1e-5 * np.linalg.norm(ref, axis=1)
+            rel = err / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+            nz = np.abs(ref).sum(1) > 0
+            _say("mb %d %s: rows %d, max rel err vs bf16 emulation %.3e, max abs %.3e, bad %d" % (
+                b, what, int(nz.sum()), rel[nz].max() if nz.any() else 0.0, err.max(),
+                int((err > tol + 1e-30).sum())))
+            assert (err <= tol + 1e-30).all()
+        assert abs(loss - oloss) <= 1e-4 * abs(oloss)
+        # the same step without BF16 rounding (FP64 throughout): the form's error
+        f_ctx, f_neg, f_ctr, _ = orc.shared_neg_step(tin, tout, mb.ctx, mb.ctr, neg, K, lr,
+                                                     bf16=False)
+        f_out = _agg(n, dim, neg, f_neg) + _agg(n, dim, mb.ctr, f_ctr)
+        gpu = np.zeros((n, dim))
+        gpu[ro] = do
+        e64 = np.linalg.norm(gpu - f_out) / max(np.linalg.norm(f_out), 1e-30)
+        _say("mb %d: relative error of the BF16 step vs FP64: %.3e" % (b, e64))
+        Mo.train_steps(W, prm, b, 1)
+
+
+def test_bf16_epoch_auc(fl, ctx, orc, sbm):
+    """One epoch of the BF16 shared-negative form on sbm1k next to the FP32
+    per-pair form (same walks): link-prediction AUC within 0.01 (the two forms
+    differ in their negative estimator, so this is a matched-quality check,
+    not a parity bound)."""
+    g = sbm.train
+    G, W, Mo, prm = _setup(fl, ctx, g, dim=64, P=1024, M=1024, K=5)
+    st = Mo.train_epoch(W, prm)
+    a16 = orc.link_auc(Mo.read(fl.TABLE_IN), sbm)
+    M32 = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=5)
+    st32 = M32.train_epoch(W, fl.train_params(window=5, negatives=5, minibatch_pairs=1024,
+                                              seed=3))
+    a32 = orc.link_auc(M32.read(fl.TABLE_IN), sbm)
+    _say("epoch sbm1k: AUC bf16 shared=%.4f fp32 per-pair=%.4f; ms bf16=%.1f fp32=%.1f" % (
+        a16, a32, st.ms, st32.ms))
+    assert st.pairs == st32.pairs
+    assert abs(a16 - a32) <= 0.01
