@@ -91,6 +91,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walks", type=int, default=1 << 17)
     ap.add_argument("--cpu-minibatches", type=int, default=30)
+    ap.add_argument("--progress-every", type=int, default=0,
+                    help="drive the rounds from Python (same ABI calls and kernels as "
+                         "felog_run) and print a line every N minibatches; for profiler runs")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="after the run, build a BF16 model once: its two table conversions "
+                         "read n*d*4 and write n*d*2 bytes each (known sizes, for HBM "
+                         "counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
@@ -127,10 +134,52 @@ def main():
                                               cfg["seed_psi"], 0)
     rp.max_rounds = cfg["r_max"]
 
+    deg = g.degrees()
+
+    def run_rounds_python():
+        """Algorithm 1 through the separate ABI calls (what felog_run does), with a
+        progress line every --progress-every minibatches."""
+        st = felog.felog_run_stats()
+        act = None
+        n_active = g.n
+        id_base = 0
+        for r in range(cfg["r_max"]):
+            if n_active == 0:
+                break
+            t0 = time.perf_counter()
+            W = felog.Walks.generate(G, r=cfg["r"], L=cfg["L"], seed=cfg["seed_walk"],
+                                     id_base=id_base, starts=act)
+            if r == 0:
+                M.set_unigram(W)
+            st.ms_walk[r] = (time.perf_counter() - t0) * 1e3
+            B = M.train_steps(W, rp.train, 0, 0).minibatches_total
+            tr = felog.felog_train_stats()
+            for b0 in range(0, B, args.progress_every):
+                s = M.train_steps(W, rp.train, b0, args.progress_every)
+                for f in ("minibatches", "pairs", "rows_in", "rows_out", "timed_launches"):
+                    setattr(tr, f, getattr(tr, f) + getattr(s, f))
+                for f in ("loss", "ms", "ms_forward", "ms_apply"):
+                    setattr(tr, f, getattr(tr, f) + getattr(s, f))
+                log("round %d: minibatches %d/%d" % (r, min(B, b0 + args.progress_every), B))
+            st.train[r] = tr
+            st.active[r] = n_active
+            st.walks[r] = W.info()[0]
+            starts = np.arange(g.n) if act is None else act.read()
+            st.walk_steps[r] = int(cfg["r"] * (cfg["L"] - 1) * (deg[starts] > 0).sum())
+            id_base += st.walks[r]
+            t1 = time.perf_counter()
+            act = M.feedback(mu=cfg["mu"], k_s=cfg["k_s"], seed=cfg["seed_psi"], round=r,
+                             active=act)
+            st.ms_feedback[r] = (time.perf_counter() - t1) * 1e3
+            n_active = act.count()
+            st.rounds = r + 1
+        st.final_active = n_active
+        return st
+
     def step():
         M.reset(cfg["seed_model"])
         t0 = time.perf_counter()
-        st = M.run(rp)
+        st = run_rounds_python() if args.progress_every else M.run(rp)
         return st, time.perf_counter() - t0
 
     for i in range(args.warmup):
@@ -171,6 +220,12 @@ def main():
                            minibatches=int(tr.minibatches)))
     pairs_per_step = pairs
     value = pairs_per_step * len(times) / total
+    if args.calibrate:
+        Mb = felog.Model.create(G, dim=cfg["dim"], neg_dist=felog.NEG_DEGREE,
+                                seed=cfg["seed_model"], precision=felog.PREC_BF16)
+        log("calibration: 2 conversions of %d bytes read, %d bytes written" % (
+            g.n * cfg["dim"] * 4, g.n * cfg["dim"] * 2))
+        Mb.close()
     emb = M.read(felog.TABLE_IN)
     auc = auc_score(emb, split.test_pos, split.test_neg)
     log("pairs/step=%d walk_steps/step=%d value=%.4g pairs/s auc=%.4f" % (
