@@ -315,6 +315,70 @@ typedef struct felog_run_stats {
  * feedback on V_a (or on V in RECOMPUTE_ALL mode), V_a = result. */
 felog_status felog_run(felog_model* m, const felog_run_params* params, felog_run_stats* stats);
 
+/* ------------------------------------------------------------------------- */
+/* Serving: continuous admission of embedding jobs under an HBM budget       */
+/* (a systems form, not in the paper)                                        */
+/* ------------------------------------------------------------------------- */
+
+typedef struct felog_server felog_server;
+
+typedef struct felog_server_params {
+    int32_t slots;            /* jobs on the device at once (1..16), one HIP stream each */
+    int64_t minibatch_pairs;  /* P for every job                                       */
+    int32_t negatives;        /* K for every job                                       */
+    float lr_start, lr_end;   /* learning-rate decay over each job's epoch             */
+} felog_server_params;
+
+typedef struct felog_job_desc {
+    int32_t n_nodes;
+    int64_t nnz;
+    const int64_t* indptr;    /* symmetric CSR as for felog_graph_load_csr; copied at  */
+    const int32_t* indices;   /* submission                                            */
+    int32_t dim;              /* 64, 128 or 256                                        */
+    int32_t walks_per_node;   /* r                                                     */
+    int32_t walk_length;      /* L                                                     */
+    int32_t window;           /* w                                                     */
+    uint64_t seed;            /* the job's Philox key (walks, init, negatives)         */
+    double arrival_time;      /* scheduled arrival on the server clock (s); 0 = now    */
+} felog_job_desc;
+
+enum { FELOG_JOB_QUEUED = 0, FELOG_JOB_RUNNING = 1, FELOG_JOB_DONE = 2, FELOG_JOB_FAILED = 3 };
+
+typedef struct felog_job_state {
+    int32_t state;
+    double t_arrive, t_admit, t_done;   /* server clock (s); latency = t_done - t_arrive */
+    int64_t pairs;
+    double loss;
+    uint64_t device_bytes;              /* the job's admission estimate (its reservation) */
+    uint64_t peak_bytes;                /* device bytes the job held at its peak; a job   */
+                                        /* never holds more than its reservation: an      */
+                                        /* allocation beyond it fails the job (ENOMEM)    */
+} felog_job_state;
+
+/* A server with `slots` worker threads on `device`.  Jobs queue in arrival order;
+ * the head job is admitted when a slot is free and its estimated device bytes
+ * fit hbm_budget_bytes minus those of the running jobs (0 = no budget).  The head
+ * is never bypassed, so no job starves.  An admitted job runs uniform walks, the
+ * degree^0.75 noise table and one training epoch on its own stream; its in-table
+ * is then copied to host memory and its device memory released. */
+felog_status felog_server_create(int device, uint64_t hbm_budget_bytes,
+                                 const felog_server_params* params, felog_server** out);
+/* Queue a job (the CSR is copied); a job larger than the whole budget gives EINVAL. */
+felog_status felog_server_submit(felog_server* s, const felog_job_desc* job, uint64_t* job_id);
+felog_status felog_server_poll(felog_server* s, uint64_t job_id, felog_job_state* state);
+/* Block until the job is done or failed (timeout_s < 0: no limit). */
+felog_status felog_server_wait(felog_server* s, uint64_t job_id, double timeout_s,
+                               felog_job_state* state);
+/* Copy a done job's in-table (float32 [n][d]) to host memory. */
+felog_status felog_server_fetch(felog_server* s, uint64_t job_id, float* host, int64_t cap);
+/* Forget a finished job and its result. */
+felog_status felog_server_release(felog_server* s, uint64_t job_id);
+/* Server clock (s since creation), peak admitted estimate (bytes), queued jobs. */
+felog_status felog_server_stats(felog_server* s, double* clock_s, uint64_t* peak_reserved,
+                                int64_t* queued);
+/* Finish the running jobs, drop the queued ones, stop the workers. */
+void felog_server_destroy(felog_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,7 @@ void DevBuf::alloc(Ctx* c, size_t nbytes)
     ptr = p;
     bytes = nbytes;
     c->in_use += nbytes;
+    c->peak = std::max(c->peak, c->in_use);
 }
 
 void DevBuf::release()

@@ -64,6 +64,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     uint64_t budget = 0;     // 0 = no cap
     uint64_t in_use = 0;
+    uint64_t peak = 0;       // largest in_use seen
     int num_cus = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t timing_every = 0;             // time every n-th training launch (0 = off)

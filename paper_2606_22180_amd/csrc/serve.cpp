@@ -1,0 +1,420 @@
+// Serving loop: continuous admission of embedding jobs under an HBM budget.
+//
+// Each job embeds its own graph with the hot path (uniform walks, one SGNS
+// epoch, degree^0.75 noise; no feedback rounds).  Jobs wait in a FIFO queue;
+// a job is admitted when one of the worker slots is free and its estimated
+// device footprint fits the remaining budget.  The head of the queue is never
+// bypassed, so every job is admitted after finitely many earlier jobs finish
+// (no starvation).  An admitted job runs on its worker's own HIP stream, so
+// the kernels of the jobs in flight overlap on the GPU's hardware queues;
+// its in-table is copied to host memory at the end and its device memory is
+// released for the next admission.  A job's results depend only on its own
+// inputs: its RNG counters and minibatch sequence are job-local.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "common.h"
+
+struct felog_server;
+
+namespace felog {
+
+struct Job {
+    uint64_t id = 0;
+    felog_job_desc desc{};
+    std::vector<int64_t> indptr;
+    std::vector<int32_t> indices;
+    uint64_t est_bytes = 0;
+    uint64_t peak_bytes = 0;
+    int32_t state = FELOG_JOB_QUEUED;
+    double t_arrive = 0, t_admit = 0, t_done = 0;
+    int64_t pairs = 0;
+    double loss = 0;
+    std::string error;
+    std::vector<float> result;   // in-table [n][d]
+};
+
+struct Server {
+    int device = 0;
+    uint64_t budget = 0;
+    felog_server_params params{};
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, std::shared_ptr<Job>> jobs;
+    uint64_t next_id = 1;
+    uint64_t reserved = 0;       // estimated bytes of the running jobs
+    uint64_t peak_reserved = 0;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// Upper bound of a job's device bytes: CSR, two FP32 tables, per-row counters
+// and offsets, walks and their column list, noise table, minibatch scratch.
+static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_params& p)
+{
+    const uint64_t n = (uint64_t)d.n_nodes, nnz = (uint64_t)d.nnz, dim = (uint64_t)d.dim;
+    const uint64_t W = n * (uint64_t)d.walks_per_node, L = (uint64_t)d.walk_length;
+    const uint64_t P = (uint64_t)p.minibatch_pairs, K = (uint64_t)p.negatives;
+    uint64_t b = 0;
+    b += 8 * (n + 1) + 4 * nnz + 4 * n;            // indptr, indices, wmax
+    b += 2 * 4 * n * dim;                          // tables
+    b += 4 * 4 * n;                                // counts and offsets
+    b += 8 * (n + 1) + 8 * n + 12 * n;             // cdf, guide (<= 2n entries), temporaries
+    b += 4 * W * L + 4 * W + 8 * (W / 2048 + 2);   // walks, valid columns, scan counts
+    b += P * (4 + 12 * (K + 1) + 4 + 4 * dim + 4 + 4 * (K + 1) + 4 + 4 * (K + 1) +
+              16 + 16 * (K + 1));                  // pair arrays, lists, entries, chunks
+    b += 12 * ((P * (K + 2)) / 2048 + 2) + 8 * (P + 64) + 4096;   // partials, loss slots
+    b += 16 * 64 * 16 + 4 * L * 256;               // small buffers (meta, totals, slices)
+    return b + b / 16;                             // headroom for allocation granularity
+}
+
+static void run_job(Server& s, Job& job)
+{
+    Ctx ctx;
+    ctx.device = s.device;
+    ctx.budget = job.est_bytes;   // the job's allocations stay within its reservation
+    ctx.make_current();
+    FELOG_HIP(hipStreamCreateWithFlags(&ctx.stream, hipStreamNonBlocking));
+    hipDeviceProp_t prop;
+    FELOG_HIP(hipGetDeviceProperties(&prop, s.device));
+    ctx.num_cus = prop.multiProcessorCount;
+    FELOG_HIP(hipEventCreate(&ctx.ev0));
+    FELOG_HIP(hipEventCreate(&ctx.ev1));
+    struct StreamGuard {
+        Ctx& c;
+        ~StreamGuard()
+        {
+            (void)hipStreamSynchronize(c.stream);
+            (void)hipEventDestroy(c.ev0);
+            (void)hipEventDestroy(c.ev1);
+            (void)hipStreamDestroy(c.stream);
+        }
+    } guard{ctx};
+    {
+        const felog_job_desc& d = job.desc;
+        Graph g;
+        g.ctx = &ctx;
+        g.n = d.n_nodes;
+        g.nnz = d.nnz;
+        g.indptr.alloc(&ctx, sizeof(int64_t) * (g.n + 1));
+        g.indices.alloc(&ctx, sizeof(int32_t) * std::max<int64_t>(g.nnz, 1));
+        FELOG_HIP(hipMemcpyAsync(g.indptr.ptr, job.indptr.data(), sizeof(int64_t) * (g.n + 1),
+                                 hipMemcpyHostToDevice, ctx.stream));
+        if (g.nnz)
+            FELOG_HIP(hipMemcpyAsync(g.indices.ptr, job.indices.data(), sizeof(int32_t) * g.nnz,
+                                     hipMemcpyHostToDevice, ctx.stream));
+        DevBuf bad;
+        bad.alloc(&ctx, sizeof(unsigned long long));
+        launch_validate_graph(g, bad.as<unsigned long long>());
+        unsigned long long code = 0;
+        FELOG_HIP(hipMemcpyAsync(&code, bad.ptr, sizeof code, hipMemcpyDeviceToHost, ctx.stream));
+        ctx.sync();
+        FELOG_REQUIRE(code == ~0ull, "job graph is not a valid symmetric CSR (row %llu)",
+                      (unsigned long long)(code >> 3));
+        launch_row_wmax(g);
+
+        Model m;
+        m.ctx = &ctx;
+        m.g = &g;
+        m.dim = d.dim;
+        m.neg_dist = FELOG_NEG_DEGREE;
+        const size_t tb = sizeof(float) * (size_t)g.n * d.dim;
+        m.tin.alloc(&ctx, tb);
+        m.tout.alloc(&ctx, tb);
+        m.cnt_in.alloc(&ctx, sizeof(uint32_t) * g.n);
+        m.cnt_out.alloc(&ctx, sizeof(uint32_t) * g.n);
+        m.off_in.alloc(&ctx, sizeof(int32_t) * g.n);
+        m.off_out.alloc(&ctx, sizeof(int32_t) * g.n);
+        m.meta.alloc(&ctx, sizeof(uint32_t) * 8);
+        m.row_totals.alloc(&ctx, sizeof(uint64_t) * 2);
+        m.loss_out.alloc(&ctx, sizeof(double));
+        FELOG_HIP(hipMemsetAsync(m.cnt_in.ptr, 0, sizeof(uint32_t) * g.n, ctx.stream));
+        FELOG_HIP(hipMemsetAsync(m.cnt_out.ptr, 0, sizeof(uint32_t) * g.n, ctx.stream));
+        launch_init_tables(m, d.seed);
+        {
+            DevBuf counts;
+            counts.alloc(&ctx, sizeof(uint32_t) * g.n);
+            launch_degree_counts(g, counts.as<uint32_t>());
+            build_noise_from_counts(m, counts.as<uint32_t>());
+        }
+        Walks w;
+        w.g = &g;
+        w.L = d.walk_length;
+        w.W = (int64_t)g.n * d.walks_per_node;
+        w.id_base = 0;
+        w.data.alloc(&ctx, sizeof(int32_t) * std::max<int64_t>(w.W * w.L, 1));
+        felog_walk_params wp{};
+        wp.kind = FELOG_WALK_UNIFORM;
+        wp.walks_per_node = d.walks_per_node;
+        wp.length = d.walk_length;
+        wp.seed = d.seed;
+        wp.id_base = 0;
+        launch_walks(w, wp, nullptr, g.n);
+        felog_train_params tp{};
+        tp.window = d.window;
+        tp.negatives = s.params.negatives;
+        tp.lr_start = s.params.lr_start;
+        tp.lr_end = s.params.lr_end;
+        tp.minibatch_pairs = s.params.minibatch_pairs;
+        tp.chunk_walks = 0;
+        tp.seed = d.seed;
+        felog_train_stats st{};
+        train_minibatches(m, w, tp, 0, -1, true, &st, nullptr, nullptr, 0, nullptr, nullptr,
+                          nullptr, 0, nullptr);
+        job.result.resize((size_t)g.n * d.dim);
+        FELOG_HIP(hipMemcpyAsync(job.result.data(), m.tin.ptr, tb, hipMemcpyDeviceToHost,
+                                 ctx.stream));
+        ctx.sync();
+        job.pairs = st.pairs;
+        job.loss = st.loss;
+        job.peak_bytes = ctx.peak;
+    }
+}
+
+static void worker_loop(Server* s)
+{
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        std::shared_ptr<Job> job;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] {
+                if (s->stopping) return true;
+                if (s->queue.empty()) return false;
+                const Job& head = *s->jobs[s->queue.front()];
+                return s->budget == 0 || s->reserved + head.est_bytes <= s->budget;
+            });
+            if (s->stopping) return;
+            job = s->jobs[s->queue.front()];
+            s->queue.pop_front();
+            s->reserved += job->est_bytes;
+            s->peak_reserved = std::max(s->peak_reserved, s->reserved);
+            job->state = FELOG_JOB_RUNNING;
+            job->t_admit = s->now();
+        }
+        std::string err;
+        try {
+            run_job(*s, *job);
+        } catch (const Error&) {
+            err = felog_last_error();
+            if (err.empty()) err = "job failed";
+        } catch (...) {
+            err = "job failed with an unexpected internal error";
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->reserved -= job->est_bytes;
+            job->t_done = s->now();
+            job->state = err.empty() ? FELOG_JOB_DONE : FELOG_JOB_FAILED;
+            job->error = err;
+            job->indptr.clear();
+            job->indptr.shrink_to_fit();
+            job->indices.clear();
+            job->indices.shrink_to_fit();
+        }
+        s->cv.notify_all();
+    }
+}
+
+}  // namespace felog
+
+using namespace felog;
+
+struct felog_server : Server {};
+
+template <class F>
+static felog_status guarded_s(F&& body)
+{
+    clear_error();
+    try {
+        body();
+        return FELOG_OK;
+    } catch (const Error& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return FELOG_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FELOG_EDEVICE;
+    }
+}
+
+#define NEED_S(p) FELOG_REQUIRE((p) != nullptr, "%s must not be NULL", #p)
+
+extern "C" {
+
+felog_status felog_server_create(int device, uint64_t hbm_budget_bytes,
+                                 const felog_server_params* params, felog_server** out)
+{
+    return guarded_s([&] {
+        NEED_S(params);
+        NEED_S(out);
+        *out = nullptr;
+        int n = 0;
+        FELOG_HIP(hipGetDeviceCount(&n));
+        FELOG_REQUIRE(device >= 0 && device < n, "device %d out of range", device);
+        FELOG_REQUIRE(params->slots >= 1 && params->slots <= 16, "slots must be in [1, 16]");
+        FELOG_REQUIRE(params->minibatch_pairs >= 1 && params->minibatch_pairs <= (1 << 24),
+                      "minibatch_pairs must be in [1, 2^24]");
+        FELOG_REQUIRE(params->negatives >= 1 && params->negatives <= 20,
+                      "negatives must be in [1, 20]");
+        auto s = std::make_unique<felog_server>();
+        s->device = device;
+        s->budget = hbm_budget_bytes;
+        s->params = *params;
+        s->t0 = std::chrono::steady_clock::now();
+        for (int i = 0; i < params->slots; ++i) s->workers.emplace_back(worker_loop, s.get());
+        *out = s.release();
+    });
+}
+
+felog_status felog_server_submit(felog_server* s, const felog_job_desc* d, uint64_t* job_id)
+{
+    return guarded_s([&] {
+        NEED_S(s);
+        NEED_S(d);
+        NEED_S(job_id);
+        FELOG_REQUIRE(d->n_nodes >= 1 && d->nnz >= 0 && d->indptr, "bad job graph");
+        FELOG_REQUIRE(d->nnz == 0 || d->indices, "indices must not be NULL when nnz > 0");
+        FELOG_REQUIRE(d->dim == 64 || d->dim == 128 || d->dim == 256, "dim must be 64/128/256");
+        FELOG_REQUIRE(d->walks_per_node >= 1 && d->walk_length >= 1 && d->walk_length <= 65536,
+                      "bad walk parameters");
+        FELOG_REQUIRE(d->window >= 1 && d->window <= 127, "window must be in [1, 127]");
+        FELOG_REQUIRE(d->indptr[0] == 0 && d->indptr[d->n_nodes] == d->nnz,
+                      "indptr must start at 0 and end at nnz");
+        auto job = std::make_shared<Job>();
+        job->desc = *d;
+        job->indptr.assign(d->indptr, d->indptr + d->n_nodes + 1);
+        job->indices.assign(d->indices, d->indices + d->nnz);
+        job->desc.indptr = nullptr;
+        job->desc.indices = nullptr;
+        job->est_bytes = estimate_bytes(*d, s->params);
+        FELOG_REQUIRE(s->budget == 0 || job->est_bytes <= s->budget,
+                      "job needs about %llu device bytes, more than the server's budget %llu",
+                      (unsigned long long)job->est_bytes, (unsigned long long)s->budget);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            job->id = s->next_id++;
+            job->t_arrive = d->arrival_time > 0 ? d->arrival_time : s->now();
+            s->jobs[job->id] = job;
+            s->queue.push_back(job->id);
+            *job_id = job->id;
+        }
+        s->cv.notify_all();
+    });
+}
+
+static void fill_state(const Job& j, felog_job_state* st)
+{
+    st->state = j.state;
+    st->t_arrive = j.t_arrive;
+    st->t_admit = j.t_admit;
+    st->t_done = j.t_done;
+    st->pairs = j.pairs;
+    st->loss = j.loss;
+    st->device_bytes = j.est_bytes;
+    st->peak_bytes = j.peak_bytes;
+}
+
+felog_status felog_server_poll(felog_server* s, uint64_t job_id, felog_job_state* st)
+{
+    return guarded_s([&] {
+        NEED_S(s);
+        NEED_S(st);
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(job_id);
+        FELOG_REQUIRE(it != s->jobs.end(), "unknown job %llu", (unsigned long long)job_id);
+        fill_state(*it->second, st);
+    });
+}
+
+felog_status felog_server_wait(felog_server* s, uint64_t job_id, double timeout_s,
+                               felog_job_state* st)
+{
+    return guarded_s([&] {
+        NEED_S(s);
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(job_id);
+        FELOG_REQUIRE(it != s->jobs.end(), "unknown job %llu", (unsigned long long)job_id);
+        std::shared_ptr<Job> j = it->second;
+        auto done = [&] { return j->state == FELOG_JOB_DONE || j->state == FELOG_JOB_FAILED; };
+        if (timeout_s < 0) s->cv.wait(lk, done);
+        else s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), done);
+        if (st) fill_state(*j, st);
+        FELOG_REQUIRE(done(), "job %llu not finished within the timeout",
+                      (unsigned long long)job_id);
+        if (j->state == FELOG_JOB_FAILED) fail(FELOG_EDEVICE, "job %llu failed: %s",
+                                               (unsigned long long)job_id, j->error.c_str());
+    });
+}
+
+felog_status felog_server_fetch(felog_server* s, uint64_t job_id, float* host, int64_t cap)
+{
+    return guarded_s([&] {
+        NEED_S(s);
+        NEED_S(host);
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(job_id);
+        FELOG_REQUIRE(it != s->jobs.end(), "unknown job %llu", (unsigned long long)job_id);
+        Job& j = *it->second;
+        if (j.state != FELOG_JOB_DONE)
+            fail(FELOG_ESTATE, "job %llu is not done", (unsigned long long)job_id);
+        FELOG_REQUIRE(cap >= (int64_t)j.result.size(), "buffer holds %lld floats, need %lld",
+                      (long long)cap, (long long)j.result.size());
+        std::memcpy(host, j.result.data(), sizeof(float) * j.result.size());
+    });
+}
+
+felog_status felog_server_release(felog_server* s, uint64_t job_id)
+{
+    return guarded_s([&] {
+        NEED_S(s);
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(job_id);
+        FELOG_REQUIRE(it != s->jobs.end(), "unknown job %llu", (unsigned long long)job_id);
+        if (it->second->state == FELOG_JOB_QUEUED || it->second->state == FELOG_JOB_RUNNING)
+            fail(FELOG_ESTATE, "job %llu has not finished", (unsigned long long)job_id);
+        s->jobs.erase(it);
+    });
+}
+
+felog_status felog_server_stats(felog_server* s, double* clock_s, uint64_t* peak_reserved,
+                                int64_t* queued)
+{
+    return guarded_s([&] {
+        NEED_S(s);
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (clock_s) *clock_s = s->now();
+        if (peak_reserved) *peak_reserved = s->peak_reserved;
+        if (queued) *queued = (int64_t)s->queue.size();
+    });
+}
+
+void felog_server_destroy(felog_server* s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv.notify_all();
+    for (auto& t : s->workers) t.join();
+    delete s;
+}
+
+}  // extern "C"

@@ -81,6 +81,26 @@ class felog_run_stats(C.Structure):
                 ("train", felog_train_stats * MAX_ROUNDS), ("final_active", C.c_int64)]
 
 
+class felog_server_params(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("minibatch_pairs", C.c_int64), ("negatives", C.c_int32),
+                ("lr_start", C.c_float), ("lr_end", C.c_float)]
+
+
+class felog_job_desc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("nnz", C.c_int64), ("indptr", C.c_void_p),
+                ("indices", C.c_void_p), ("dim", C.c_int32), ("walks_per_node", C.c_int32),
+                ("walk_length", C.c_int32), ("window", C.c_int32), ("seed", C.c_uint64),
+                ("arrival_time", C.c_double)]
+
+
+class felog_job_state(C.Structure):
+    _fields_ = [("state", C.c_int32), ("t_arrive", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("pairs", C.c_int64), ("loss", C.c_double),
+                ("device_bytes", C.c_uint64), ("peak_bytes", C.c_uint64)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
 _p = C.c_void_p
 _pp = C.POINTER(C.c_void_p)
 _i32, _i64, _u32, _u64, _f32, _f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float, C.c_double
@@ -123,6 +143,14 @@ SIGNATURES = {
                                  C.POINTER(_f64)]),
     "felog_feedback": (_i32, [_p, C.POINTER(felog_feedback_params), _p, _pp, _p, _i64]),
     "felog_run": (_i32, [_p, C.POINTER(felog_run_params), C.POINTER(felog_run_stats)]),
+    "felog_server_create": (_i32, [C.c_int, _u64, C.POINTER(felog_server_params), _pp]),
+    "felog_server_submit": (_i32, [_p, C.POINTER(felog_job_desc), C.POINTER(_u64)]),
+    "felog_server_poll": (_i32, [_p, _u64, C.POINTER(felog_job_state)]),
+    "felog_server_wait": (_i32, [_p, _u64, _f64, C.POINTER(felog_job_state)]),
+    "felog_server_fetch": (_i32, [_p, _u64, _p, _i64]),
+    "felog_server_release": (_i32, [_p, _u64]),
+    "felog_server_stats": (_i32, [_p, C.POINTER(_f64), C.POINTER(_u64), C.POINTER(_i64)]),
+    "felog_server_destroy": (None, [_p]),
 }
 
 _lib = None
@@ -379,3 +407,62 @@ class Model(_Handle):
         st = felog_run_stats()
         _check(load().felog_run(self.handle, C.byref(prm), C.byref(st)))
         return st
+
+
+class Server:
+    """Continuous-admission serving loop (felog_server)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, *, slots: int = 4,
+                 minibatch_pairs: int = 65536, negatives: int = 5, lr_start: float = 0.025,
+                 lr_end: float = 1e-4):
+        prm = felog_server_params(slots, minibatch_pairs, negatives, lr_start, lr_end)
+        h = C.c_void_p()
+        _check(load().felog_server_create(device, hbm_budget, C.byref(prm), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, indptr, indices, *, dim, r, L, window, seed, arrival_time=0.0) -> int:
+        ip, ipp = _arr(indptr, np.int64)
+        ix, ixp = _arr(indices, np.int32)
+        d = felog_job_desc(ip.shape[0] - 1, ix.shape[0], ipp, ixp, dim, r, L, window, seed,
+                           arrival_time)
+        jid = C.c_uint64()
+        _check(load().felog_server_submit(self.handle, C.byref(d), C.byref(jid)))
+        self._keep[jid.value] = (ip.shape[0] - 1, dim)
+        return jid.value
+
+    def poll(self, jid: int) -> felog_job_state:
+        st = felog_job_state()
+        _check(load().felog_server_poll(self.handle, jid, C.byref(st)))
+        return st
+
+    def wait(self, jid: int, timeout: float = -1.0) -> felog_job_state:
+        st = felog_job_state()
+        _check(load().felog_server_wait(self.handle, jid, timeout, C.byref(st)))
+        return st
+
+    def fetch(self, jid: int) -> np.ndarray:
+        n, dim = self._keep[jid]
+        out = np.zeros((n, dim), np.float32)
+        _check(load().felog_server_fetch(self.handle, jid, out.ctypes.data, out.size))
+        return out
+
+    def release(self, jid: int):
+        _check(load().felog_server_release(self.handle, jid))
+        self._keep.pop(jid, None)
+
+    def stats(self):
+        c, pk, q = C.c_double(), C.c_uint64(), C.c_int64()
+        _check(load().felog_server_stats(self.handle, C.byref(c), C.byref(pk), C.byref(q)))
+        return c.value, pk.value, q.value
+
+    def close(self):
+        if self.handle:
+            load().felog_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

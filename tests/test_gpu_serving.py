@@ -1,0 +1,124 @@
+"""GPU tests of the serving loop (felog_server_*).
+
+A serving job is the plain path (uniform walks, degree^0.75 noise, one SGNS
+epoch) with job-local seeds, so its result must not depend on the other jobs
+in flight.  The SGNS row sums are FP32 sums whose order follows integer
+atomics, so two runs of one job agree to FP32 rounding, not bitwise; the mix
+check bounds the difference the same way for every job, alone or mixed.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import os
+    from paper_2606_22180_amd import build, felog
+    if not os.path.exists(build.LIB):
+        build.build()
+    felog.load()
+    return felog
+
+
+def _jobs():
+    mix = synth.job_mix(12, seed=9, n_min=200, n_max=6000)
+    out = []
+    for j in mix:
+        g = synth.job_graph(j)
+        out.append((j, g))
+    return out
+
+
+def test_serving_job_matches_oracle(fl, orc):
+    """A job on the sbm1k training graph reaches the oracle's AUC."""
+    sp = synth.build_graph("sbm1k")
+    g = sp.train
+    _say("serving job sbm1k vs oracle")
+    S = fl.Server(0, 0, slots=2, minibatch_pairs=1024, negatives=5)
+    jid = S.submit(g.indptr, g.indices, dim=64, r=10, L=40, window=5, seed=21)
+    st = S.wait(jid, 120.0)
+    emb = S.fetch(jid)
+    S.close()
+    walks = orc.walks_uniform(g, np.arange(g.n), 10, 40, 21)
+    tin, tout = orc.init_tables(g.n, 64, 21)
+    ref = orc.train_epoch(tin, tout, walks, window=5, K=5, lr0=float(np.float32(0.025)),
+                          lr_end=float(np.float32(1e-4)), P=1024, seed=21,
+                          cdf=orc.neg_cdf(g.degrees().astype(np.uint64)))
+    a_gpu, a_orc = orc.link_auc(emb, sp), orc.link_auc(tin, sp)
+    _say("AUC serving=%.5f oracle=%.5f pairs %d/%d latency %.3f s" % (
+        a_gpu, a_orc, st.pairs, ref.pairs, st.t_done - st.t_arrive))
+    assert st.state == fl.JOB_DONE and st.pairs == ref.pairs
+    assert abs(a_gpu - a_orc) <= 0.005
+    assert abs(st.loss - ref.loss) <= 1e-4 * ref.loss
+
+
+def test_serving_alone_equals_mix(fl):
+    jobs = _jobs()
+    _say("serving alone vs mix: %d jobs, n = %s" % (len(jobs), [j["n"] for j, _ in jobs]))
+    alone = {}
+    S1 = fl.Server(0, 0, slots=1, minibatch_pairs=4096, negatives=5)
+    for j, g in jobs[:4]:
+        jid = S1.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                        window=j["window"], seed=j["seed"])
+        S1.wait(jid, 300.0)
+        alone[j["job"]] = (S1.fetch(jid), S1.poll(jid).loss)
+    S1.close()
+    S4 = fl.Server(0, 0, slots=4, minibatch_pairs=4096, negatives=5)
+    ids = []
+    for j, g in jobs:
+        ids.append((j, S4.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                                 window=j["window"], seed=j["seed"])))
+    for j, jid in ids:
+        st = S4.wait(jid, 300.0)
+        assert st.state == fl.JOB_DONE
+        if j["job"] in alone:
+            emb, loss = alone[j["job"]]
+            mixed = S4.fetch(jid)
+            rel = np.abs(mixed - emb).max() / np.abs(emb).max()
+            _say("job %d n=%d: max |mix - alone| / max|alone| = %.2e, loss %.9e vs %.9e" % (
+                j["job"], j["n"], rel, st.loss, loss))
+            assert rel <= 1e-3
+            assert abs(st.loss - loss) <= 1e-5 * abs(loss)
+    S4.close()
+
+
+def test_serving_budget_and_fifo(fl):
+    jobs = _jobs()[:8]
+    # a budget that fits the largest job but not two of them at once
+    sizes = []
+    probe = fl.Server(0, 0, slots=1, minibatch_pairs=4096, negatives=5)
+    for j, g in jobs:
+        jid = probe.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                           window=j["window"], seed=j["seed"])
+        sizes.append(probe.poll(jid).device_bytes)
+    probe.close()
+    budget = max(sizes) + min(sizes) // 2
+    _say("budget %d bytes, job estimates %s" % (budget, sizes))
+    S = fl.Server(0, budget, slots=4, minibatch_pairs=4096, negatives=5)
+    ids = [S.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"], window=j["window"],
+                    seed=j["seed"]) for j, g in jobs]
+    states = [S.wait(i, 300.0) for i in ids]
+    _, peak, queued = S.stats()
+    assert queued == 0 and all(s.state == fl.JOB_DONE for s in states)
+    assert peak <= budget
+    admits = [s.t_admit for s in states]
+    assert admits == sorted(admits)                      # FIFO admission
+    for s_, size in zip(states, sizes):
+        assert s_.device_bytes == size and 0 < s_.peak_bytes <= size
+    # running intervals: the estimates of overlapping jobs fit the budget
+    for a in states:
+        live = [b.device_bytes for b in states if b.t_admit <= a.t_admit < b.t_done]
+        assert sum(live) <= budget
+    with pytest.raises(fl.FelogError):
+        g = jobs[0][1]
+        big = fl.Server(0, 1 << 20, slots=1, minibatch_pairs=4096, negatives=5)
+        big.submit(g.indptr, g.indices, dim=256, r=10, L=80, window=5, seed=1)
+    S.close()
