@@ -231,21 +231,35 @@ def main():
     log("pairs/step=%d walk_steps/step=%d value=%.4g pairs/s auc=%.4f" % (
         pairs_per_step, walk_steps, value, auc))
 
-    # roofline of the dominant kernel (SGNS forward): algorithmic bytes per launch =
-    # each distinct touched row read once (d*4 B) and its delta written once (d*4 B),
-    # plus the pair's node ids (2*4 B) and one 8 B cumulative-weight read per negative.
+    # Roofline of the dominant kernel, the SGNS forward.  Its algorithmic bytes per
+    # launch: every distinct row the minibatch touches read once (d*4 B; the forward
+    # reads all of them and writes none), the pair's two node ids (8 B) and one 8 B
+    # cumulative-weight read per negative.  The whole minibatch update (forward,
+    # destination sort, both reductions) also writes each touched row once, so its
+    # algorithmic bytes are rows*d*8 + pairs*(8 + 8K).
     d = cfg["dim"]
-    alg_bytes = rows * d * 8 + pairs * (8 + 8 * cfg["K"])
-    per_launch = alg_bytes / max(1, mbs)
+    K = cfg["K"]
+    row_bytes = rows * d * 4
+    id_bytes = pairs * (8 + 8 * K)
+    per_launch = (row_bytes + id_bytes) / max(1, mbs)
+    per_update = (2 * row_bytes + id_bytes) / max(1, mbs)
     avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
+    avg_upd_s = (fwd_ms + apply_ms) / 1e3 / max(1, timed)
     achieved = per_launch / avg_fwd_s / 1e9 if timed else None
+    upd_achieved = per_update / avg_upd_s / 1e9 if timed else None
     traffic = forward_traffic()
-    roof = {"bound": "hbm", "kernel": "sgns_forward_kernel<2,5>", "achieved": achieved,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    roof = {"bound": "hbm", "kernel": "sgns_forward_kernel<%d, %d>" % (d, K),
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_fwd_s * 1e6,
-            "timed_launches": timed, "avg_apply_us": apply_ms / 1e3 / max(1, timed) * 1e6}
+            "timed_launches": timed,
+            "touched_rows_per_minibatch": rows / max(1, mbs),
+            "sgns_update": {"kernels": "forward, scan_partials, scan_write, fill, reduce out, "
+                                       "reduce in",
+                            "algorithmic_bytes": per_update, "avg_us": avg_upd_s * 1e6,
+                            "achieved": upd_achieved,
+                            "frac": (upd_achieved / HBM_PEAK_GBS) if upd_achieved else None}}
 
     out = {
         "metric": METRIC, "value": value, "unit": "pair-updates/s", "n_gpus": 1,

@@ -324,7 +324,10 @@ typedef struct felog_server felog_server;
 
 typedef struct felog_server_params {
     int32_t slots;            /* jobs on the device at once (1..16), one HIP stream each */
-    int64_t minibatch_pairs;  /* P for every job                                       */
+    int64_t minibatch_pairs;  /* largest P of a job; a job on n nodes uses            */
+                              /* min(minibatch_pairs, the next power of two >= n):    */
+                              /* summed minibatch updates diverge once P is large     */
+                              /* next to n (rows touched hundreds of times per step)  */
     int32_t negatives;        /* K for every job                                       */
     float lr_start, lr_end;   /* learning-rate decay over each job's epoch             */
 } felog_server_params;
@@ -350,6 +353,7 @@ typedef struct felog_job_state {
     int64_t pairs;
     double loss;
     uint64_t device_bytes;              /* the job's admission estimate (its reservation) */
+    int64_t minibatch_pairs;            /* the P the job ran with                          */
     uint64_t peak_bytes;                /* device bytes the job held at its peak; a job   */
                                         /* never holds more than its reservation: an      */
                                         /* allocation beyond it fails the job (ENOMEM)    */

@@ -33,6 +33,7 @@ struct Job {
     std::vector<int32_t> indices;
     uint64_t est_bytes = 0;
     uint64_t peak_bytes = 0;
+    int64_t minibatch = 0;       // P of this job
     int32_t state = FELOG_JOB_QUEUED;
     double t_arrive = 0, t_admit = 0, t_done = 0;
     int64_t pairs = 0;
@@ -62,13 +63,23 @@ struct Server {
     }
 };
 
+// Minibatch of a job on n nodes: the server's P, capped at the next power of two
+// >= n.  Minibatch updates are sums, so with P far above n every row takes
+// hundreds of summed steps per minibatch and training diverges.
+static int64_t job_minibatch(const felog_job_desc& d, const felog_server_params& p)
+{
+    int64_t cap = 1;
+    while (cap < (int64_t)d.n_nodes) cap <<= 1;
+    return std::min<int64_t>(p.minibatch_pairs, cap);
+}
+
 // Upper bound of a job's device bytes: CSR, two FP32 tables, per-row counters
 // and offsets, walks and their column list, noise table, minibatch scratch.
 static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_params& p)
 {
     const uint64_t n = (uint64_t)d.n_nodes, nnz = (uint64_t)d.nnz, dim = (uint64_t)d.dim;
     const uint64_t W = n * (uint64_t)d.walks_per_node, L = (uint64_t)d.walk_length;
-    const uint64_t P = (uint64_t)p.minibatch_pairs, K = (uint64_t)p.negatives;
+    const uint64_t P = (uint64_t)job_minibatch(d, p), K = (uint64_t)p.negatives;
     uint64_t b = 0;
     b += 8 * (n + 1) + 4 * nnz + 4 * n;            // indptr, indices, wmax
     b += 2 * 4 * n * dim;                          // tables
@@ -169,7 +180,7 @@ static void run_job(Server& s, Job& job)
         tp.negatives = s.params.negatives;
         tp.lr_start = s.params.lr_start;
         tp.lr_end = s.params.lr_end;
-        tp.minibatch_pairs = s.params.minibatch_pairs;
+        tp.minibatch_pairs = job.minibatch;
         tp.chunk_walks = 0;
         tp.seed = d.seed;
         felog_train_stats st{};
@@ -304,6 +315,7 @@ felog_status felog_server_submit(felog_server* s, const felog_job_desc* d, uint6
         job->desc.indptr = nullptr;
         job->desc.indices = nullptr;
         job->est_bytes = estimate_bytes(*d, s->params);
+        job->minibatch = job_minibatch(*d, s->params);
         FELOG_REQUIRE(s->budget == 0 || job->est_bytes <= s->budget,
                       "job needs about %llu device bytes, more than the server's budget %llu",
                       (unsigned long long)job->est_bytes, (unsigned long long)s->budget);
@@ -329,6 +341,7 @@ static void fill_state(const Job& j, felog_job_state* st)
     st->loss = j.loss;
     st->device_bytes = j.est_bytes;
     st->peak_bytes = j.peak_bytes;
+    st->minibatch_pairs = j.minibatch;
 }
 
 felog_status felog_server_poll(felog_server* s, uint64_t job_id, felog_job_state* st)

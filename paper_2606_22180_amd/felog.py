@@ -96,7 +96,8 @@ class felog_job_desc(C.Structure):
 class felog_job_state(C.Structure):
     _fields_ = [("state", C.c_int32), ("t_arrive", C.c_double), ("t_admit", C.c_double),
                 ("t_done", C.c_double), ("pairs", C.c_int64), ("loss", C.c_double),
-                ("device_bytes", C.c_uint64), ("peak_bytes", C.c_uint64)]
+                ("device_bytes", C.c_uint64), ("minibatch_pairs", C.c_int64),
+                ("peak_bytes", C.c_uint64)]
 
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3

@@ -42,7 +42,7 @@ def test_serving_job_matches_oracle(fl, orc):
     sp = synth.build_graph("sbm1k")
     g = sp.train
     _say("serving job sbm1k vs oracle")
-    S = fl.Server(0, 0, slots=2, minibatch_pairs=1024, negatives=5)
+    S = fl.Server(0, 0, slots=2, minibatch_pairs=65536, negatives=5)
     jid = S.submit(g.indptr, g.indices, dim=64, r=10, L=40, window=5, seed=21)
     st = S.wait(jid, 120.0)
     emb = S.fetch(jid)
@@ -55,7 +55,7 @@ def test_serving_job_matches_oracle(fl, orc):
     a_gpu, a_orc = orc.link_auc(emb, sp), orc.link_auc(tin, sp)
     _say("AUC serving=%.5f oracle=%.5f pairs %d/%d latency %.3f s" % (
         a_gpu, a_orc, st.pairs, ref.pairs, st.t_done - st.t_arrive))
-    assert st.state == fl.JOB_DONE and st.pairs == ref.pairs
+    assert st.state == fl.JOB_DONE and st.pairs == ref.pairs and st.minibatch_pairs == 1024
     assert abs(a_gpu - a_orc) <= 0.005
     assert abs(st.loss - ref.loss) <= 1e-4 * ref.loss
 
@@ -78,10 +78,11 @@ def test_serving_alone_equals_mix(fl):
                                  window=j["window"], seed=j["seed"])))
     for j, jid in ids:
         st = S4.wait(jid, 300.0)
-        assert st.state == fl.JOB_DONE
+        assert st.state == fl.JOB_DONE and np.isfinite(st.loss)
         if j["job"] in alone:
             emb, loss = alone[j["job"]]
             mixed = S4.fetch(jid)
+            assert np.isfinite(mixed).all() and np.isfinite(emb).all()
             rel = np.abs(mixed - emb).max() / np.abs(emb).max()
             _say("job %d n=%d: max |mix - alone| / max|alone| = %.2e, loss %.9e vs %.9e" % (
                 j["job"], j["n"], rel, st.loss, loss))
