@@ -158,7 +158,7 @@ def main():
                 s = M.train_steps(W, rp.train, b0, args.progress_every)
                 for f in ("minibatches", "pairs", "rows_in", "rows_out", "timed_launches"):
                     setattr(tr, f, getattr(tr, f) + getattr(s, f))
-                for f in ("loss", "ms", "ms_forward", "ms_apply"):
+                for f in ("loss", "ms", "ms_forward", "ms_apply", "ms_prep"):
                     setattr(tr, f, getattr(tr, f) + getattr(s, f))
                 log("round %d: minibatches %d/%d" % (r, min(B, b0 + args.progress_every), B))
             st.train[r] = tr
@@ -199,7 +199,7 @@ def main():
     R = st.rounds
     rounds = []
     pairs = walk_steps = 0
-    fwd_ms = apply_ms = 0.0
+    fwd_ms = apply_ms = prep_ms = 0.0
     timed = 0
     mbs = rows = 0
     ms_walk = 0.0
@@ -209,6 +209,7 @@ def main():
         walk_steps += st.walk_steps[r]
         fwd_ms += tr.ms_forward
         apply_ms += tr.ms_apply
+        prep_ms += tr.ms_prep
         timed += tr.timed_launches
         mbs += tr.minibatches
         rows += tr.rows_in + tr.rows_out
@@ -234,9 +235,12 @@ def main():
     # Roofline of the dominant kernel, the SGNS forward.  Its algorithmic bytes per
     # launch: every distinct row the minibatch touches read once (d*4 B; the forward
     # reads all of them and writes none), the pair's two node ids (8 B) and one 8 B
-    # cumulative-weight read per negative.  The whole minibatch update (forward,
-    # destination sort, both reductions) also writes each touched row once, so its
-    # algorithmic bytes are rows*d*8 + pairs*(8 + 8K).
+    # cumulative-weight read per negative.  The whole minibatch update (ids, the
+    # destination sort, forward, both apply launches) also writes each touched row
+    # once, so its algorithmic bytes are rows*d*8 + pairs*(8 + 8K).  Durations come
+    # from HIP events on every timing_every-th minibatch; the id work of the next
+    # minibatch runs concurrently on a second stream, so the forward's duration
+    # includes that contention.
     d = cfg["dim"]
     K = cfg["K"]
     row_bytes = rows * d * 4
@@ -244,7 +248,7 @@ def main():
     per_launch = (row_bytes + id_bytes) / max(1, mbs)
     per_update = (2 * row_bytes + id_bytes) / max(1, mbs)
     avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
-    avg_upd_s = (fwd_ms + apply_ms) / 1e3 / max(1, timed)
+    avg_upd_s = (prep_ms + fwd_ms + apply_ms) / 1e3 / max(1, timed)
     achieved = per_launch / avg_fwd_s / 1e9 if timed else None
     upd_achieved = per_update / avg_upd_s / 1e9 if timed else None
     traffic = forward_traffic()
@@ -255,8 +259,10 @@ def main():
             "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_fwd_s * 1e6,
             "timed_launches": timed,
             "touched_rows_per_minibatch": rows / max(1, mbs),
-            "sgns_update": {"kernels": "forward, scan_partials, scan_write, fill, reduce out, "
-                                       "reduce in",
+            "sgns_update": {"kernels": "prep and scan (second stream), forward, two apply "
+                                       "launches",
+                            "avg_prep_us": prep_ms / 1e3 / max(1, timed) * 1e6,
+                            "avg_reduce_us": apply_ms / 1e3 / max(1, timed) * 1e6,
                             "algorithmic_bytes": per_update, "avg_us": avg_upd_s * 1e6,
                             "achieved": upd_achieved,
                             "frac": (upd_achieved / HBM_PEAK_GBS) if upd_achieved else None}}

@@ -222,6 +222,8 @@ typedef struct felog_train_stats {
     int64_t timed_launches;   /* forward (and apply) launches timed with events    */
     double ms_forward;        /* summed duration of the timed forward launches     */
     double ms_apply;          /* summed duration of the timed apply launches       */
+    double ms_prep;           /* summed duration of the timed id / rank / offset   */
+                              /* launches that precede each timed forward          */
 } felog_train_stats;
 
 /* One Train() call: every minibatch of the corpus in order.  Pairs: within each

@@ -94,6 +94,27 @@ void Ctx::make_current() const { (void)hipSetDevice(device); }
 
 void Ctx::sync() const { FELOG_HIP(hipStreamSynchronize(stream)); }
 
+void Ctx::ensure_aux()
+{
+    if (aux) return;
+    make_current();
+    FELOG_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    for (hipEvent_t& e : pipe_ev) FELOG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+void Ctx::release_aux()
+{
+    if (!aux) return;
+    make_current();
+    (void)hipStreamSynchronize(aux);
+    for (hipEvent_t& e : pipe_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    (void)hipStreamDestroy(aux);
+    aux = nullptr;
+}
+
 }  // namespace felog
 
 using namespace felog;
@@ -152,6 +173,7 @@ void felog_ctx_destroy(felog_ctx* ctx)
     if (!ctx) return;
     ctx->make_current();
     (void)hipStreamSynchronize(ctx->stream);
+    ctx->release_aux();
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->timing_pool) (void)hipEventDestroy(e);
@@ -165,7 +187,7 @@ felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every)
         FELOG_REQUIRE(every >= 0, "every must be >= 0");
         ctx->make_current();
         if (every > 0 && ctx->timing_pool.empty()) {
-            ctx->timing_pool.resize(3 * 256);
+            ctx->timing_pool.resize(5 * 256);
             for (hipEvent_t& e : ctx->timing_pool) FELOG_HIP(hipEventCreate(&e));
         }
         ctx->timing_every = every;
@@ -440,16 +462,7 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
         size_t tb = sizeof(float) * (size_t)g->n * p->dim;
         m->tin.alloc(c, tb);
         m->tout.alloc(c, tb);
-        m->cnt_in.alloc(c, sizeof(uint32_t) * g->n);
-        m->cnt_out.alloc(c, sizeof(uint32_t) * g->n);
-        m->off_in.alloc(c, sizeof(int32_t) * g->n);
-        m->off_out.alloc(c, sizeof(int32_t) * g->n);
-        m->meta.alloc(c, sizeof(uint32_t) * 8);
-        m->row_totals.alloc(c, sizeof(uint64_t) * 2);
-        m->loss_out.alloc(c, sizeof(double));
-        FELOG_HIP(hipMemsetAsync(m->cnt_in.ptr, 0, sizeof(uint32_t) * g->n, c->stream));
-        FELOG_HIP(hipMemsetAsync(m->cnt_out.ptr, 0, sizeof(uint32_t) * g->n, c->stream));
-        FELOG_HIP(hipMemsetAsync(m->meta.ptr, 0, sizeof(uint32_t) * 8, c->stream));
+        model_alloc_update_state(*m);
         if (p->precision == FELOG_PREC_BF16) {
             m->bin.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
             m->bout.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);

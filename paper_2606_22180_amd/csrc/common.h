@@ -68,9 +68,15 @@ struct Ctx {
     int num_cus = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t timing_every = 0;             // time every n-th training launch (0 = off)
-    std::vector<hipEvent_t> timing_pool;  // 3 events per timed minibatch
+    std::vector<hipEvent_t> timing_pool;  // 5 events per timed minibatch
+    // second stream for the table-independent part of the next minibatch, and
+    // its events: [0] start, [1 + parity] ids ready, [3 + parity] buffers free
+    hipStream_t aux = nullptr;
+    hipEvent_t pipe_ev[5] = {};
     void make_current() const;
     void sync() const;
+    void ensure_aux();
+    void release_aux();
 };
 
 struct Graph {
@@ -107,6 +113,20 @@ struct Walks {
     int64_t chunk_for_valid = 0;
 };
 
+// Buffers of one minibatch's ids and destination sort; two sets let the next
+// minibatch's ids be computed while the current one trains.
+struct MinibatchBufs {
+    DevBuf cnt_in, cnt_out;       // uint32 [n]: touches of each row (0 between minibatches)
+    DevBuf off_in, off_out;       // int32 [n]: first entry of each touched row's segment
+    DevBuf touch_row;             // int32 [P][K+2]: context, centre, negatives (-1 = skipped)
+    DevBuf touch_pos;             // uint32 [P][K+2]: rank of the touch within its row
+    DevBuf list_in, list_out;     // int32: touched rows
+    DevBuf chunks_in, chunks_out; // int4 per row of <= 16 touches: row, first entry, length, slot
+    DevBuf split_in, split_out;   // int4 per chunk of a split row: row, first entry, length, partial
+    DevBuf mrows_in, mrows_out;   // int4 per split row: row, first chunk, chunks, list slot
+    DevBuf partials;              // per scan block: uint4 (rows, split rows, their chunks), uint64
+};
+
 struct Model {
     Ctx* ctx = nullptr;
     Graph* g = nullptr;
@@ -116,8 +136,6 @@ struct Model {
     bool have_noise = false;
     DevBuf tin, tout;             // float [n][d] (the masters of a BF16 model)
     DevBuf bin, bout;             // uint16 [n][d]: BF16 copies (BF16 models)
-    DevBuf cnt_in, cnt_out;       // uint32 [n]: touches of each row in this minibatch (0 between)
-    DevBuf off_in, off_out;       // int32 [n]: first entry of each touched row's segment
     DevBuf cdf;                   // uint64 [n+1]
     DevBuf guide;                 // int32 [2^guide_bits]
     int32_t guide_bits = 0;
@@ -125,17 +143,13 @@ struct Model {
     // minibatch scratch, sized for the largest (pairs, negatives) seen
     int64_t cap_pairs = 0;
     int32_t cap_K = 0;
-    DevBuf pair_ctx;              // int32 [P]
-    DevBuf pair_t;                // int32 [P][K+1]: centre, negatives (-1 = skipped)
-    DevBuf pair_g;                // float [P][K+1]: coefficients g_k
-    DevBuf rank_in, rank_out;     // uint32 [P], [P][K+1]: order of the touch within its row
-    DevBuf dinp;                  // float [P][d]: sum_k g_k out[t_k] of each pair
-    DevBuf list_in, list_out;     // int32: touched rows, in order of first touch
-    DevBuf entries_in;            // int32 [P]: in-touches (pair ids) grouped by row
-    DevBuf entries_out;           // int32 [P(K+1)]: out-touches (touch ids) grouped by row
-    DevBuf chunks_in, chunks_out; // int32 [4 per chunk]: row, list slot, first entry, length|flags
-    DevBuf partials;              // per scan block: uint64 (entries | chunks << 32), uint32 rows
-    DevBuf meta;                  // uint32 [8]: list lengths (in, out), chunk counts (in, out)
+    MinibatchBufs mb[2];          // by minibatch parity: ids and sort of one minibatch
+    DevBuf ent_out;               // int2 [P(K+1)]: (g, ctx) of each out-touch, by row segment
+    DevBuf key_in, key_out;       // uint32: pair-order key of each segment position
+    DevBuf dinp;                  // float [P][d]: sum_k g_k out[t_k] of each pair, by row segment
+    DevBuf partial;               // double [chunks of split rows][d]: each chunk's exact sums
+    int64_t split_rows_in = 0;    // partial rows reserved for the in-table; the out-table's follow
+    DevBuf meta;                  // uint32 [2][16]: list lengths and cursors, by minibatch parity
     DevBuf loss_out;              // double [1]
     DevBuf row_totals;            // uint64 [2]: summed touched-list lengths (in, out)
     // shared-negative (BF16) minibatch scratch
@@ -205,6 +219,7 @@ void train_minibatches(Model& m, const Walks& w, const felog_train_params& p, in
                        int32_t* rows_in, float* d_in, int64_t cap_in, int64_t* n_in,
                        int32_t* rows_out, float* d_out, int64_t cap_out, int64_t* n_out);
 int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_pairs);
+void model_alloc_update_state(Model& m);   // row counters, offsets, minibatch counters
 void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
                             int64_t end, float* cap_in, float* cap_out, felog_train_stats* stats);

@@ -73,24 +73,32 @@ static int64_t job_minibatch(const felog_job_desc& d, const felog_server_params&
     return std::min<int64_t>(p.minibatch_pairs, cap);
 }
 
-// Upper bound of a job's device bytes: CSR, two FP32 tables, per-row counters
-// and offsets, walks and their column list, noise table, minibatch scratch.
+// Upper bound of a job's device bytes: every buffer the job allocates, counted
+// as if all were held at once (temporaries of the noise build and the walk
+// compaction included).
 static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_params& p)
 {
-    const uint64_t n = (uint64_t)d.n_nodes, nnz = (uint64_t)d.nnz, dim = (uint64_t)d.dim;
+    const uint64_t n = (uint64_t)d.n_nodes, nnz = std::max<uint64_t>((uint64_t)d.nnz, 1);
+    const uint64_t dim = (uint64_t)d.dim;
     const uint64_t W = n * (uint64_t)d.walks_per_node, L = (uint64_t)d.walk_length;
     const uint64_t P = (uint64_t)job_minibatch(d, p), K = (uint64_t)p.negatives;
+    uint64_t pow2 = 1;
+    while (pow2 < n) pow2 <<= 1;
     uint64_t b = 0;
-    b += 8 * (n + 1) + 4 * nnz + 4 * n;            // indptr, indices, wmax
-    b += 2 * 4 * n * dim;                          // tables
-    b += 4 * 4 * n;                                // counts and offsets
-    b += 8 * (n + 1) + 8 * n + 12 * n;             // cdf, guide (<= 2n entries), temporaries
-    b += 4 * W * L + 4 * W + 8 * (W / 2048 + 2);   // walks, valid columns, scan counts
-    b += P * (4 + 12 * (K + 1) + 4 + 4 * dim + 4 + 4 * (K + 1) + 4 + 4 * (K + 1) +
-              16 + 16 * (K + 1));                  // pair arrays, lists, entries, chunks
-    b += 12 * ((P * (K + 2)) / 2048 + 2) + 8 * (P + 64) + 4096;   // partials, loss slots
-    b += 16 * 64 * 16 + 4 * L * 256;               // small buffers (meta, totals, slices)
-    return b + b / 16;                             // headroom for allocation granularity
+    b += 8 * (n + 1) + 4 * nnz + 4 * n + 16;                     // CSR, row maxima, check word
+    b += 8 * n * dim + 16 * n + 4 * 32 + 16 + 16;                // tables, counters, offsets
+    b += 4 * n + 8 * n + 8 * (n / 2048 + 2) + 8 * (n + 1) + 4 * std::max<uint64_t>(pow2, 2);
+    b += 4 * W * L + 4 * W + 4 * (W / 2048 + 2) + 8 * (W / (1u << 20) + 2);   // walks
+    const uint64_t T = P * (K + 2);                              // touches per minibatch
+    const uint64_t sc = P / 8 + 1 + P * (K + 1) / 8 + 1;         // chunks of split rows
+    const uint64_t sr = P / 17 + 1 + P * (K + 1) / 17 + 1;       // split rows
+    const uint64_t nbs = P / 2048 + 1 + P * (K + 1) / 2048 + 1;  // scan blocks
+    b += 16 * n;                                                 // second set of counters, offsets
+    b += 2 * (8 * T + 4 * T + 16 * T + 16 * sc + 16 * sr + 24 * nbs);   // two id/sort sets
+    b += 8 * P * (K + 1) + 4 * T + 4 * P * dim + 8 * sc * dim;   // outputs, keys, split sums
+    b += 8 * (P + 4) + 4 * L * 2 * (uint64_t)d.window;           // loss slots, slices
+    b += 64 * 16;                                                // small allocations of 16 B
+    return b + b / 16;                                           // headroom
 }
 
 static void run_job(Server& s, Job& job)
@@ -110,6 +118,7 @@ static void run_job(Server& s, Job& job)
         ~StreamGuard()
         {
             (void)hipStreamSynchronize(c.stream);
+            c.release_aux();
             (void)hipEventDestroy(c.ev0);
             (void)hipEventDestroy(c.ev1);
             (void)hipStreamDestroy(c.stream);
@@ -146,15 +155,7 @@ static void run_job(Server& s, Job& job)
         const size_t tb = sizeof(float) * (size_t)g.n * d.dim;
         m.tin.alloc(&ctx, tb);
         m.tout.alloc(&ctx, tb);
-        m.cnt_in.alloc(&ctx, sizeof(uint32_t) * g.n);
-        m.cnt_out.alloc(&ctx, sizeof(uint32_t) * g.n);
-        m.off_in.alloc(&ctx, sizeof(int32_t) * g.n);
-        m.off_out.alloc(&ctx, sizeof(int32_t) * g.n);
-        m.meta.alloc(&ctx, sizeof(uint32_t) * 8);
-        m.row_totals.alloc(&ctx, sizeof(uint64_t) * 2);
-        m.loss_out.alloc(&ctx, sizeof(double));
-        FELOG_HIP(hipMemsetAsync(m.cnt_in.ptr, 0, sizeof(uint32_t) * g.n, ctx.stream));
-        FELOG_HIP(hipMemsetAsync(m.cnt_out.ptr, 0, sizeof(uint32_t) * g.n, ctx.stream));
+        model_alloc_update_state(m);
         launch_init_tables(m, d.seed);
         {
             DevBuf counts;

@@ -9,94 +9,57 @@
 // exactly the order "next P pairs whose positions both hold a node".
 //
 // Every pair reads the tables as they stand at the minibatch's start; each
-// row's deltas are summed and added once.  FP32 atomics on table rows are
-// slow on this part (an L2 atomic unit handles a few dwords per clock, and
-// hot rows serialise), so the update is a sort by destination instead:
-//   forward   per pair: gather in[ctx], out[ctr], out[neg_1..K]; K+1 dots,
-//             sigma, coefficients g; store g and sum_k g_k out[t_k] per pair;
-//             count each touched row with an integer atomic whose result is
-//             the touch's rank within its row (rank 0 lists the row).
-//   scan      two passes over the touched rows: segment offsets and work
-//             items (chunks of at most kChunk touches per row).
-//   fill      each touch writes its id at its row's offset + rank.
-//   reduce    one wave per chunk: out rows sum g * in[ctx] over their
-//             touches, in rows sum the per-pair deltas; plain read-modify-
-//             write of the row (atomic only for rows split over chunks),
-//             and the row's counter is cleared.  Out rows run first, since
-//             they read the in-table as of the minibatch start.
-// Lanes own elements lane + 64 v of a row, so each row access is one
-// coalesced 256-byte transaction per v.
+// row's deltas are summed and added once.  A pair touches K + 2 rows: its
+// context (in-table) and its centre and K negatives (out-table).  FP32
+// atomics on table rows are slow on this part (an L2 atomic unit handles a
+// few dwords per clock and hot rows serialise), so the deltas are sorted by
+// destination row instead.  Per minibatch:
+//   prep     one thread per touch: node ids (walk reads, noise draws) and an
+//            integer atomic per touched row whose old value is the touch's
+//            rank within the row (rank 0 marks the row's first touch).
+//   scan     two passes over the touches: segment offsets of the touched
+//            rows, their list, one work item per row of at most kChunk
+//            touches and one per kChunk touches of the rows with more.  No
+//            atomics: same-address device atomics serialise at about one per
+//            12 ns on this part.
+//   forward  one 16-lane group per pair: gather in[ctx], out[ctr],
+//            out[neg_1..K]; K+1 dots, sigma, coefficients g; writes
+//            (g_k, ctx) and the touch's pair-order key at the out-row's
+//            segment position, sum_k g_k out[t_k] and the pair at the
+//            in-row's.
+//   split    chunks of the rows with more than kChunk touches: exact sums
+//            (below), stored per chunk.
+//   reduce   rows of at most kChunk touches, out rows first (they read the
+//            in-table as of the minibatch start), then in rows: the touches
+//            are sorted by key inside a 16-lane group and summed in FP32 in
+//            pair order.
+//   merge    each split row adds its chunks' sums in chunk order.
+// prep and scan read only the walks and the noise table, so with two sets
+// of their buffers the next minibatch's run on a second stream while this
+// one trains.  Every sum is independent of the order the atomics produced,
+// so a minibatch's update is bit-identical from run to run.  The split rows'
+// sums are exact: each term (an exact FP64 product g * x, or an FP32 per-pair
+// delta) is bounded by lr 2^15 in magnitude and rounded once to a multiple
+// of 2^(e - 35), e = floor(log2 lr); in FP64, sums of such multiples below
+// lr 2^17 carry no rounding error in any order.
+// Lanes own elements 4 (gl + 16 i) .. +3 of a row, so each row access is a
+// coalesced 256-byte transaction per i.
 #include <algorithm>
+#include <cmath>
 
 #include "common.h"
 #include "noise.h"
 
 namespace felog {
 
-constexpr int kChunk = 16;                 // touches per reduction work item (one per lane of a group)
-constexpr uint32_t kFirstChunk = 1u << 31; // flags in chunk_len
-constexpr uint32_t kMultiChunk = 1u << 30;
-constexpr uint32_t kLenMask = (1u << 30) - 1;
+constexpr int kChunk = 16;                // touches per reduction work item (one per lane of a group)
+constexpr int kMetaWords = 16;            // per minibatch parity
+// meta words (in, out): [0, 1] list lengths, [2, 3] rows of one chunk,
+// [4, 5] rows split over chunks, [6, 7] chunks of split rows
 
-struct SgnsArgs {
-    const float* __restrict__ tin;
-    const float* __restrict__ tout;
-    const int32_t* __restrict__ walks;   // step-major [L][W]
-    int64_t W;
-    const int32_t* __restrict__ vcols;   // valid columns of this chunk
-    uint32_t Wv;
-    const int32_t* __restrict__ slices;  // (j << 8) | slot
-    uint32_t first_pair;
-    uint32_t npairs;
-    int64_t id_base;
-    int32_t window;
-    int32_t ppw;                          // pairs per wave (<= 64 / (K + 2))
-    uint64_t seed;
-    NoiseTable noise;
-    float lr;
-    uint32_t* cnt_in;
-    uint32_t* cnt_out;
-    int32_t* pair_ctx;
-    int32_t* pair_t;
-    float* pair_g;
-    uint32_t* rank_in;
-    uint32_t* rank_out;
-    float* dinp;
-    double* loss_part;                    // one slot per wave
-};
-
-// Sum of 8 per-lane values over the wave with 10 exchanges: three halving
-// steps leave value k summed over 8-lane groups in lanes 8k..8k+7, then three
-// xor steps finish each group.  Returns the total of value k in every lane
-// of group k.
-__device__ __forceinline__ float reduce8(float v[8], int lane)
-{
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        bool hi = lane & 32;
-        float send = hi ? v[i] : v[i + 4];
-        float keep = hi ? v[i + 4] : v[i];
-        v[i] = keep + __shfl_xor(send, 32);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        bool hi = lane & 16;
-        float send = hi ? v[i] : v[i + 2];
-        float keep = hi ? v[i + 2] : v[i];
-        v[i] = keep + __shfl_xor(send, 16);
-    }
-    {
-        bool hi = lane & 8;
-        float send = hi ? v[0] : v[1];
-        float keep = hi ? v[1] : v[0];
-        v[0] = keep + __shfl_xor(send, 8);
-    }
-    float x = v[0];
-    x += __shfl_xor(x, 4);
-    x += __shfl_xor(x, 2);
-    x += __shfl_xor(x, 1);
-    return x;   // lane group g = lane >> 3 holds value g
-}
+// Adding c = 1.5 * 2^k rounds a value below 2^(k-1) in magnitude to a
+// multiple of 2^(k-52); taking c off again is exact.
+__device__ __forceinline__ double on_grid(double t, double c) { return __dsub_rn(__dadd_rn(t, c), c); }
 
 __device__ __forceinline__ double wave_sum_f64(double x)
 {
@@ -107,15 +70,13 @@ __device__ __forceinline__ double wave_sum_f64(double x)
 
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// -log sigma(x) = log(1 + exp(-x)), evaluated without overflow.
-__device__ __forceinline__ double neg_log_sigmoid(double x)
+// -log sigma(x) = log(1 + exp(-x)), evaluated without overflow.  The dot x is
+// FP32, so is the term; the terms are summed in FP64.
+__device__ __forceinline__ float neg_log_sigmoid(float x)
 {
-    return fmax(-x, 0.0) + log1p(exp(-fabs(x)));
+    return fmaxf(-x, 0.0f) + log1pf(expf(-fabsf(x)));
 }
 
-// ----------------------------------------------------------------- forward
-// A row is handled by a group of 16 lanes (lane j of a group owns the float4s
-// j + 16 i of the row), so one wave works on 4 pairs at a time.
 template <int D>
 __device__ __forceinline__ const float4* row4(const float* base, int64_t row)
 {
@@ -130,8 +91,283 @@ __device__ __forceinline__ float dot4(float4 a, float4 b, float acc)
     return fmaf(a.w, b.w, acc);
 }
 
-__device__ __forceinline__ float group16_sum(float x)
+// ------------------------------------------------------------------- prep
+struct PrepArgs {
+    const int32_t* __restrict__ walks;   // step-major [L][W]
+    int64_t W;
+    const int32_t* __restrict__ vcols;   // valid columns of this chunk
+    uint32_t Wv;
+    const int32_t* __restrict__ slices;  // (j << 8) | slot
+    uint32_t first_pair;
+    uint32_t npairs;
+    int64_t id_base;
+    int32_t window;
+    uint64_t seed;
+    NoiseTable noise;
+    uint32_t* cnt_in;
+    uint32_t* cnt_out;
+    int32_t* touch_row;      // [P][K+2]: context, centre, negatives (-1: negative == centre)
+    uint32_t* touch_pos;     // [P][K+2]: rank of the touch within its row
+};
+
+template <int K>
+__global__ __launch_bounds__(256) void sgns_prep_kernel(PrepArgs a)
 {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t nt = a.npairs * (K + 2);
+    int32_t row = -1;
+    bool out = false;
+    if (t < nt) {
+        const uint32_t p = t / (K + 2), r = t - p * (K + 2);
+        const uint32_t gq = a.first_pair + p;
+        const uint32_t sidx = gq / a.Wv;
+        const uint32_t rank = gq - sidx * a.Wv;
+        const int32_t js = a.slices[sidx];
+        const int32_t col = a.vcols[rank];
+        const int32_t j = js >> 8, s = js & 255;
+        const int32_t ctr = a.walks[(int64_t)j * a.W + col];
+        if (r == 0) {
+            const int32_t off = s < a.window ? s - a.window : s - a.window + 1;
+            row = a.walks[(int64_t)(j + off) * a.W + col];
+        } else if (r == 1) {
+            row = ctr;
+            out = true;
+        } else {
+            // negative k = r - 2: Philox(walk id, (j << 8) | slot, NEG | k / 2), words
+            // 2 (k mod 2) and 2 (k mod 2) + 1
+            const uint32_t k = r - 2;
+            const int64_t wid = a.id_base + col;
+            const Rand4 x = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)js,
+                                       kTagNeg | (k >> 1), a.seed);
+            const uint32_t lo = (k & 1) ? x.v[2] : x.v[0];
+            const uint32_t hi = (k & 1) ? x.v[3] : x.v[1];
+            const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
+            row = neg != ctr ? neg : -1;   // a negative equal to the centre is skipped
+            out = true;
+        }
+    }
+    if (t < nt) {
+        a.touch_row[t] = row;
+        a.touch_pos[t] = row >= 0 ? atomicAdd((out ? a.cnt_out : a.cnt_in) + row, 1u) : 0u;
+    }
+}
+
+// ------------------------------------------------------------------- scan
+// Items: the in-touches i (touch i (K+2)) and, in further blocks, the
+// out-touches e (touch (e / (K+1)) (K+2) + 1 + e mod (K+1)).  A first touch
+// (rank 0) lists its row; the scanned values are (entries | chunks << 32),
+// the rows listed, the rows split over chunks and their chunks.
+constexpr int kScanT = 256, kScanI = 8, kScanSpanS = kScanT * kScanI;
+
+struct ScanArgs {
+    const int32_t* touch_row;
+    const uint32_t* touch_pos;
+    const uint32_t* cnt_in;
+    const uint32_t* cnt_out;
+    uint32_t n_in, n_out, nb_in;
+    unsigned long long* part_ec;   // per block
+    uint4* part_rm;                // per block: rows, split rows, chunks of split rows
+    int32_t* list_in;
+    int32_t* list_out;
+    int32_t* off_in;
+    int32_t* off_out;
+    int4* chunks_in;
+    int4* chunks_out;
+    int4* split_in;                // chunks of split rows: row, first entry, length, partial row
+    int4* split_out;
+    int4* mrows_in;                // split rows: row, first chunk, chunks, list slot
+    int4* mrows_out;
+    uint32_t* meta;
+};
+
+template <int K>
+__device__ __forceinline__ void scan_item(const ScanArgs& a, bool out, uint32_t i, int32_t& row,
+                                          uint32_t& c)
+{
+    const uint32_t t = out ? (i / (K + 1)) * (K + 2) + 1 + i % (K + 1) : i * (K + 2);
+    const int32_t r = a.touch_row[t];
+    const bool first = r >= 0 && a.touch_pos[t] == 0u;
+    row = first ? r : -1;
+    c = first ? (out ? a.cnt_out : a.cnt_in)[r] : 0u;
+}
+
+__device__ __forceinline__ uint4 add4(uint4 a, uint4 b)
+{
+    return make_uint4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
+__device__ __forceinline__ uint4 split_counts(uint32_t c)
+{
+    const uint32_t nch = (c + kChunk - 1) / kChunk;
+    return make_uint4(1u, nch > 1 ? 1u : 0u, nch > 1 ? nch : 0u, 0u);
+}
+
+__device__ __forceinline__ unsigned long long pack_ec(uint32_t c)
+{
+    return (unsigned long long)c | ((unsigned long long)((c + kChunk - 1) / kChunk) << 32);
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
+{
+    __shared__ unsigned long long s_ec[kScanT];
+    __shared__ uint4 s_rm[kScanT];
+    const bool out = blockIdx.x >= a.nb_in;
+    const uint32_t nb = out ? blockIdx.x - a.nb_in : blockIdx.x;
+    const uint32_t n = out ? a.n_out : a.n_in;
+    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
+    unsigned long long ec = 0;
+    uint4 rm = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) {
+        if (base + k < n) {
+            int32_t row;
+            uint32_t c;
+            scan_item<K>(a, out, base + k, row, c);
+            if (row >= 0) {
+                ec += pack_ec(c);
+                rm = add4(rm, split_counts(c));
+            }
+        }
+    }
+    s_ec[threadIdx.x] = ec;
+    s_rm[threadIdx.x] = rm;
+    __syncthreads();
+    for (int s = kScanT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            s_ec[threadIdx.x] += s_ec[threadIdx.x + s];
+            s_rm[threadIdx.x] = add4(s_rm[threadIdx.x], s_rm[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.part_ec[blockIdx.x] = s_ec[0];
+        a.part_rm[blockIdx.x] = s_rm[0];
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
+{
+    __shared__ unsigned long long s_ec[kScanT];
+    __shared__ uint4 s_rm[kScanT];
+    const bool out = blockIdx.x >= a.nb_in;
+    const uint32_t b0 = out ? a.nb_in : 0u;   // first block of this table
+    const uint32_t n = out ? a.n_out : a.n_in;
+    const uint32_t nb = blockIdx.x - b0;
+    // offset of this block: partials of the earlier blocks of the same table
+    unsigned long long pre = 0;
+    uint4 pre_rm = make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t b = b0 + threadIdx.x; b < blockIdx.x; b += kScanT) {
+        pre += a.part_ec[b];
+        pre_rm = add4(pre_rm, a.part_rm[b]);
+    }
+    s_ec[threadIdx.x] = pre;
+    s_rm[threadIdx.x] = pre_rm;
+    __syncthreads();
+    for (int s = kScanT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            s_ec[threadIdx.x] += s_ec[threadIdx.x + s];
+            s_rm[threadIdx.x] = add4(s_rm[threadIdx.x], s_rm[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    const unsigned long long blk_ec = s_ec[0];
+    const uint4 blk_rm = s_rm[0];
+    __syncthreads();
+
+    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
+    // (entries scanned in the low word; the chunk count in the high word is unused here)
+    int32_t rows[kScanI];
+    uint32_t cs[kScanI];
+    unsigned long long mine = 0;
+    uint4 mine_rm = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) {
+        rows[k] = -1;
+        cs[k] = 0;
+        if (base + k < n) scan_item<K>(a, out, base + k, rows[k], cs[k]);
+        if (rows[k] >= 0) {
+            mine += pack_ec(cs[k]);
+            mine_rm = add4(mine_rm, split_counts(cs[k]));
+        }
+    }
+    // block exclusive scans
+    s_ec[threadIdx.x] = mine;
+    s_rm[threadIdx.x] = mine_rm;
+    __syncthreads();
+    for (int off = 1; off < kScanT; off <<= 1) {
+        const unsigned long long add = threadIdx.x >= off ? s_ec[threadIdx.x - off] : 0ull;
+        const uint4 add_rm = threadIdx.x >= off ? s_rm[threadIdx.x - off] : make_uint4(0u, 0u, 0u, 0u);
+        __syncthreads();
+        s_ec[threadIdx.x] += add;
+        s_rm[threadIdx.x] = add4(s_rm[threadIdx.x], add_rm);
+        __syncthreads();
+    }
+    const unsigned long long run = blk_ec + s_ec[threadIdx.x] - mine;
+    const uint4 at = s_rm[threadIdx.x];
+    uint32_t slot = blk_rm.x + at.x - mine_rm.x;    // list slot
+    uint32_t mrow = blk_rm.y + at.y - mine_rm.y;    // split-row index
+    uint32_t mchunk = blk_rm.z + at.z - mine_rm.z;  // first chunk of the next split row
+    uint32_t entry = (uint32_t)run;
+    int32_t* list = out ? a.list_out : a.list_in;
+    int32_t* off = out ? a.off_out : a.off_in;
+    int4* chunks = out ? a.chunks_out : a.chunks_in;   // one per row of at most kChunk touches
+    int4* split = out ? a.split_out : a.split_in;      // chunks of the split rows
+    int4* mrows = out ? a.mrows_out : a.mrows_in;
+#pragma unroll
+    for (int k = 0; k < kScanI; ++k) {
+        if (rows[k] >= 0) {
+            const uint32_t c = cs[k];
+            const uint32_t nch = (c + kChunk - 1) / kChunk;
+            list[slot] = rows[k];
+            off[rows[k]] = (int32_t)entry;
+            if (nch == 1) {
+                chunks[slot - mrow] = make_int4(rows[k], (int32_t)entry, (int32_t)c, (int32_t)slot);
+            } else {
+                mrows[mrow] = make_int4(rows[k], (int32_t)mchunk, (int32_t)nch, (int32_t)slot);
+                for (uint32_t j = 0; j < nch; ++j)
+                    split[mchunk + j] = make_int4(rows[k], (int32_t)(entry + j * kChunk),
+                                                  (int32_t)min((uint32_t)kChunk, c - j * kChunk),
+                                                  (int32_t)(mchunk + j));
+                ++mrow;
+                mchunk += nch;
+            }
+            entry += c;
+            ++slot;
+        }
+        if (base + k + 1 == n) {   // the table's last item: totals
+            a.meta[out ? 1 : 0] = slot;
+            a.meta[out ? 3 : 2] = slot - mrow;   // rows of one chunk
+            a.meta[out ? 5 : 4] = mrow;          // split rows
+            a.meta[out ? 7 : 6] = mchunk;        // their chunks
+        }
+    }
+}
+
+// ---------------------------------------------------------------- forward
+struct FwdArgs {
+    const float* __restrict__ tin;
+    const float* __restrict__ tout;
+    const int32_t* __restrict__ touch_row;
+    const uint32_t* __restrict__ touch_pos;
+    const int32_t* __restrict__ off_in;
+    const int32_t* __restrict__ off_out;
+    uint32_t npairs;
+    int32_t ppw;             // pairs per wave, ppw (K + 2) <= 64
+    float lr;
+    int2* ent_out;           // (g bits, ctx) by out-row segment position
+    uint32_t* key_out;       // the touch's pair-order key p (K+1) + k, same position
+    float* dinp;             // [P][d] sum_k g_k out[t_k] by in-row segment position
+    uint32_t* key_in;        // the pair p, same position
+    double* loss_part;       // one slot per wave
+};
+
+// Sum over the L lanes of a lane group (L = 16 or 32).
+template <int L>
+__device__ __forceinline__ float group_sum(float x)
+{
+    if (L > 16) x += __shfl_xor(x, 16);
     x += __shfl_xor(x, 8);
     x += __shfl_xor(x, 4);
     x += __shfl_xor(x, 2);
@@ -139,71 +375,62 @@ __device__ __forceinline__ float group16_sum(float x)
     return x;
 }
 
+// One pair per group of LPP lanes (32 for d >= 128, so that a lane holds one
+// float4 of each of the pair's K + 2 rows at d = 128), 64 / LPP pairs at a time.
 template <int D, int K>
-__global__ __launch_bounds__(256) void sgns_forward_kernel(SgnsArgs a)
+__global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
 {
-    constexpr int V4 = D / 64;   // float4s per lane
+    constexpr int LPP = D >= 128 ? 32 : 16;   // lanes per pair
+    constexpr int G = 64 / LPP;               // pairs in flight per wave
+    constexpr int V4 = D / (4 * LPP);         // float4s per lane and row
+    constexpr int T = K + 2;                  // touches per pair
     const int lane = threadIdx.x & 63;
-    const int grp = lane >> 4, gl = lane & 15;
+    const int grp = lane / LPP, gl = lane % LPP;
     const uint32_t gwave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t q0 = gwave * (uint32_t)a.ppw;
     if (q0 >= a.npairs) return;
     const int np = (int)min((uint32_t)a.ppw, a.npairs - q0);
 
-    // ---- pair metadata: lane p < np handles pair q0 + p
-    int32_t m_ctx = 0, m_ctr = 0, m_js = 0, m_col = 0;
-    if (lane < np) {
-        uint32_t gq = a.first_pair + q0 + lane;
-        uint32_t sidx = gq / a.Wv;
-        uint32_t rank = gq - sidx * a.Wv;
-        m_js = a.slices[sidx];
-        m_col = a.vcols[rank];
-        int32_t j = m_js >> 8, s = m_js & 255;
-        int32_t off = s < a.window ? s - a.window : s - a.window + 1;
-        m_ctx = a.walks[(int64_t)(j + off) * a.W + m_col];
-        m_ctr = a.walks[(int64_t)j * a.W + m_col];
+    // ---- touch metadata: lane l < np T holds touch l of the wave's pairs and
+    //      its position in its row's segment
+    int32_t m_row = -1;
+    uint32_t m_pos = 0;
+    if (lane < np * T) {
+        const uint32_t t = q0 * T + lane;
+        m_row = a.touch_row[t];
+        const uint32_t rk = a.touch_pos[t];
+        const bool in = (lane % T) == 0;
+        if (m_row >= 0) m_pos = (uint32_t)(in ? a.off_in : a.off_out)[m_row] + rk;
     }
 
-    // ---- noise draws: lane l < np*K draws negative l % K of pair l / K
-    int32_t m_neg = 0;
-    {
-        int p = lane / K;
-        int k = lane - p * K;
-        int32_t col = __shfl(m_col, p < np ? p : 0);
-        int32_t js = __shfl(m_js, p < np ? p : 0);
-        if (lane < np * K) {
-            int64_t wid = a.id_base + col;
-            Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)js,
-                                 kTagNeg | (uint32_t)(k >> 1), a.seed);
-            uint32_t lo = (k & 1) ? r.v[2] : r.v[0];
-            uint32_t hi = (k & 1) ? r.v[3] : r.v[1];
-            m_neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
-        }
-    }
-
-    // ---- rows, dots, coefficients, per-pair in-row delta: 4 pairs at a time
     double lacc = 0.0;
-    for (int base = 0; base < np; base += 4) {
+    for (int base = 0; base < np; base += G) {
         const int p = base + grp;
         const bool live = p < np;
-        const int ps = live ? p : 0;
-        const uint32_t q = q0 + ps;
-        const int32_t ctx = __shfl(m_ctx, ps);
+        const uint32_t q = q0 + (uint32_t)p;   // pair index within the minibatch
+        const int src = (live ? p : 0) * T;
+        const int32_t ctx = __shfl(m_row, src);
+        const uint32_t pos_in = __shfl(m_pos, src);
         int32_t t[K + 1];
-        t[0] = __shfl(m_ctr, ps);
 #pragma unroll
-        for (int k = 0; k < K; ++k) t[k + 1] = __shfl(m_neg, ps * K + k);
+        for (int k = 0; k <= K; ++k) t[k] = __shfl(m_row, src + 1 + k);
+        // out position of touch k = gl (and, with 16 lanes, k = gl + 16)
+        const uint32_t my_pos = __shfl(m_pos, src + 1 + (gl <= K ? gl : 0));
+        uint32_t my_pos_hi = 0;
+        if (LPP == 16 && K >= 16) my_pos_hi = __shfl(m_pos, src + 1 + (gl + 16 <= K ? gl + 16 : 0));
 
         float4 vin[V4];
         float4 vo[K + 1][V4];
-        const float4* ri = row4<D>(a.tin, ctx);
+        const float4* ri = row4<D>(a.tin, live ? ctx : 0);
 #pragma unroll
-        for (int i = 0; i < V4; ++i) vin[i] = ri[i * 16 + gl];
+        for (int i = 0; i < V4; ++i) vin[i] = ri[i * LPP + gl];
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
-            const float4* ro = row4<D>(a.tout, t[k]);
+            const bool ok = live && t[k] >= 0;
+            const float4* ro = row4<D>(a.tout, ok ? t[k] : 0);
 #pragma unroll
-            for (int i = 0; i < V4; ++i) vo[k][i] = ro[i * 16 + gl];
+            for (int i = 0; i < V4; ++i)
+                vo[k][i] = ok ? ro[i * LPP + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         float dot[K + 1];
 #pragma unroll
@@ -211,36 +438,37 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(SgnsArgs a)
             float acc = 0.0f;
 #pragma unroll
             for (int i = 0; i < V4; ++i) acc = dot4(vin[i], vo[k][i], acc);
-            dot[k] = group16_sum(acc);
+            dot[k] = group_sum<LPP>(acc);
         }
         float g[K + 1];
         g[0] = a.lr * (1.0f - sigmoidf_(dot[0]));
 #pragma unroll
-        for (int k = 1; k <= K; ++k) g[k] = t[k] != t[0] ? -a.lr * sigmoidf_(dot[k]) : 0.0f;
+        for (int k = 1; k <= K; ++k) g[k] = t[k] >= 0 ? -a.lr * sigmoidf_(dot[k]) : 0.0f;
 
-        // lane j of the group stores g_k and takes loss term k for k = j and
-        // k = j + 16 (K + 1 may exceed the 16 lanes of a group)
-        float s_lo = 0.0f, s_hi = 0.0f;
-        bool v_lo = false, v_hi = false;
+        // lane j of the group writes touch k = j (and j + 16) and takes its loss term
 #pragma unroll
-        for (int k = 0; k <= K; ++k) {
-            if ((k & 15) == gl) {
-                if (live) a.pair_g[q * (K + 1) + k] = g[k];
-                const float sk = k == 0 ? dot[0] : -dot[k];   // -log sigma(sk) is the term
-                const bool vk = live && (k == 0 || t[k] != t[0]);
-                if (k < 16) {
-                    s_lo = sk;
-                    v_lo = vk;
-                } else {
-                    s_hi = sk;
-                    v_hi = vk;
+        for (int h = 0; h < (K + LPP) / LPP; ++h) {
+            const int k = gl + h * LPP;
+            float gk = g[0], dk = dot[0];
+            int32_t tk = t[0];
+#pragma unroll
+            for (int j = 1; j <= K; ++j)
+                if (k == j) {
+                    gk = g[j];
+                    dk = dot[j];
+                    tk = t[j];
                 }
+            if (k <= K && live && tk >= 0) {
+                const uint32_t pos = h == 0 ? my_pos : my_pos_hi;
+                a.ent_out[pos] = make_int2(__float_as_int(gk), ctx);
+                a.key_out[pos] = q * (K + 1) + (uint32_t)k;
+                // -log sigma(s0) for the centre, -log sigma(-s_k) for a negative
+                lacc += (double)neg_log_sigmoid(k == 0 ? dk : -dk);
             }
         }
-        if (v_lo) lacc += neg_log_sigmoid((double)s_lo);
-        if (K >= 16 && v_hi) lacc += neg_log_sigmoid((double)s_hi);
         if (live) {
-            float4* dp = reinterpret_cast<float4*>(a.dinp + (int64_t)q * D);
+            if (gl == 0) a.key_in[pos_in] = q;
+            float4* dp = reinterpret_cast<float4*>(a.dinp + (int64_t)pos_in * D);
 #pragma unroll
             for (int i = 0; i < V4; ++i) {
                 float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -251,345 +479,234 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(SgnsArgs a)
                     acc.z = fmaf(g[k], vo[k][i].z, acc.z);
                     acc.w = fmaf(g[k], vo[k][i].w, acc.w);
                 }
-                dp[i * 16 + gl] = acc;
+                dp[i * LPP + gl] = acc;
             }
         }
     }
-
-    // ---- touches: lane l < np*(K+2) handles touch r = l % (K+2) of pair l / (K+2):
-    //      r = 0 centre, 1..K negatives (out table), K+1 context (in table).  The
-    //      count's old value is the touch's rank within its row.
-    {
-        const int p = lane / (K + 2);
-        const int r = lane - p * (K + 2);
-        const int ps = p < np ? p : 0;
-        int32_t ctr = __shfl(m_ctr, ps);
-        int32_t ctx = __shfl(m_ctx, ps);
-        int32_t neg = __shfl(m_neg, ps * K + (r >= 1 && r <= K ? r - 1 : 0));
-        if (lane < np * (K + 2)) {
-            const uint32_t q = q0 + p;
-            if (r == 0) {
-                a.rank_out[q * (K + 1)] = atomicAdd(&a.cnt_out[ctr], 1u);
-                a.pair_t[q * (K + 1)] = ctr;
-            } else if (r <= K) {
-                const bool keep = neg != ctr;
-                a.rank_out[q * (K + 1) + r] = keep ? atomicAdd(&a.cnt_out[neg], 1u) : 0u;
-                a.pair_t[q * (K + 1) + r] = keep ? neg : -1;
-            } else {
-                a.rank_in[q] = atomicAdd(&a.cnt_in[ctx], 1u);
-                a.pair_ctx[q] = ctx;
-            }
-        }
-    }
-
-    // ---- loss: -log sigma(s0) - sum_k log sigma(-s_k) = softplus(-s0) + sum_k softplus(s_k)
     lacc = wave_sum_f64(lacc);
     if (lane == 0) a.loss_part[gwave] += lacc;
 }
 
-// ------------------------------------------------------------------ scan
-// Touched rows are the touches of rank 0, listed in touch order: for the in
-// table the touches are the pairs (p = 0..P-1), for the out table the
-// (pair, slot) ids e = p (K+1) + k.  Scan blocks [0, nb_in) cover the in
-// table, the rest the out table; per item the scanned values are
-// (rank 0 ? 1 : 0) and (rank 0 ? c : 0 | chunks << 32), c = the row's count.
-constexpr int kScanT = 256, kScanI = 8, kScanSpanS = kScanT * kScanI;
-
-struct TouchView {
-    const int32_t* pair_ctx;
-    const int32_t* pair_t;
-    const uint32_t* rank_in;
-    const uint32_t* rank_out;
-    const uint32_t* cnt_in;
-    const uint32_t* cnt_out;
-    // row of item i (-1 = not a first touch) and its count
-    __device__ void item(bool out, uint32_t i, int32_t& row, uint32_t& c) const
-    {
-        int32_t r;
-        uint32_t rk;
-        if (out) {
-            r = pair_t[i];
-            rk = r >= 0 ? rank_out[i] : 1u;
-        } else {
-            r = pair_ctx[i];
-            rk = rank_in[i];
-        }
-        row = rk == 0 ? r : -1;
-        c = rk == 0 ? (out ? cnt_out[r] : cnt_in[r]) : 0u;
-    }
-};
-
-__device__ __forceinline__ unsigned long long pack_ec(uint32_t c)
-{
-    return (unsigned long long)c | ((unsigned long long)((c + kChunk - 1) / kChunk) << 32);
-}
-
-__global__ __launch_bounds__(256) void sgns_scan_partials(TouchView tv, uint32_t n_in,
-                                                          uint32_t n_out, uint32_t nb_in,
-                                                          unsigned long long* part_ec,
-                                                          uint32_t* part_rows)
-{
-    __shared__ unsigned long long lds[kScanT];
-    __shared__ uint32_t lds_r[kScanT];
-    const bool out = blockIdx.x >= nb_in;
-    const uint32_t nb = out ? blockIdx.x - nb_in : blockIdx.x;
-    const uint32_t n = out ? n_out : n_in;
-    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
-    unsigned long long acc = 0;
-    uint32_t rows = 0;
-#pragma unroll
-    for (int k = 0; k < kScanI; ++k) {
-        if (base + k < n) {
-            int32_t row;
-            uint32_t c;
-            tv.item(out, base + k, row, c);
-            if (row >= 0) {
-                acc += pack_ec(c);
-                ++rows;
-            }
-        }
-    }
-    lds[threadIdx.x] = acc;
-    lds_r[threadIdx.x] = rows;
-    __syncthreads();
-    for (int s = kScanT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            lds[threadIdx.x] += lds[threadIdx.x + s];
-            lds_r[threadIdx.x] += lds_r[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        part_ec[blockIdx.x] = lds[0];
-        part_rows[blockIdx.x] = lds_r[0];
-    }
-}
-
-struct ScanOut {
-    int32_t* list;      // touched rows
-    int32_t* off;       // [n] first entry of each row's segment
-    int32_t* chunks;    // 4 ints per chunk
-};
-
-// meta[0 + out] = rows listed, meta[2 + out] = chunks.
-__global__ __launch_bounds__(256) void sgns_scan_write(TouchView tv, uint32_t n_in, uint32_t n_out,
-                                                       uint32_t nb_in,
-                                                       const unsigned long long* part_ec,
-                                                       const uint32_t* part_rows, ScanOut so_in,
-                                                       ScanOut so_out, uint32_t* meta)
-{
-    __shared__ unsigned long long lds[kScanT];
-    __shared__ uint32_t lds_r[kScanT];
-    const bool out = blockIdx.x >= nb_in;
-    const uint32_t b0 = out ? nb_in : 0u;          // first block of this table
-    const uint32_t n = out ? n_out : n_in;
-    const uint32_t nb = blockIdx.x - b0;
-    const ScanOut so = out ? so_out : so_in;
-    // offset of this block: partials of the earlier blocks of the same table
-    unsigned long long pre = 0;
-    uint32_t pre_r = 0;
-    for (uint32_t b = b0 + threadIdx.x; b < blockIdx.x; b += kScanT) {
-        pre += part_ec[b];
-        pre_r += part_rows[b];
-    }
-    lds[threadIdx.x] = pre;
-    lds_r[threadIdx.x] = pre_r;
-    __syncthreads();
-    for (int s = kScanT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            lds[threadIdx.x] += lds[threadIdx.x + s];
-            lds_r[threadIdx.x] += lds_r[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    const unsigned long long block_ec = lds[0];
-    const uint32_t block_r = lds_r[0];
-    __syncthreads();
-
-    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
-    int32_t rows[kScanI];
-    uint32_t cs[kScanI];
-    unsigned long long mine = 0;
-    uint32_t mine_r = 0;
-#pragma unroll
-    for (int k = 0; k < kScanI; ++k) {
-        rows[k] = -1;
-        cs[k] = 0;
-        if (base + k < n) tv.item(out, base + k, rows[k], cs[k]);
-        if (rows[k] >= 0) {
-            mine += pack_ec(cs[k]);
-            ++mine_r;
-        }
-    }
-    // block exclusive scans
-    lds[threadIdx.x] = mine;
-    lds_r[threadIdx.x] = mine_r;
-    __syncthreads();
-    for (int off = 1; off < kScanT; off <<= 1) {
-        unsigned long long add = threadIdx.x >= off ? lds[threadIdx.x - off] : 0ull;
-        uint32_t add_r = threadIdx.x >= off ? lds_r[threadIdx.x - off] : 0u;
-        __syncthreads();
-        lds[threadIdx.x] += add;
-        lds_r[threadIdx.x] += add_r;
-        __syncthreads();
-    }
-    unsigned long long run = block_ec + lds[threadIdx.x] - mine;
-    uint32_t slot = block_r + lds_r[threadIdx.x] - mine_r;
-    uint32_t entry = (uint32_t)run, chunk = (uint32_t)(run >> 32);
-#pragma unroll
-    for (int k = 0; k < kScanI; ++k) {
-        const uint32_t i = base + k;
-        if (rows[k] >= 0) {
-            so.list[slot] = rows[k];
-            so.off[rows[k]] = (int32_t)entry;
-            const uint32_t nch = (cs[k] + kChunk - 1) / kChunk;
-            for (uint32_t j = 0; j < nch; ++j) {
-                const uint32_t len = min((uint32_t)kChunk, cs[k] - j * kChunk);
-                int32_t* d = so.chunks + 4 * (int64_t)(chunk + j);
-                d[0] = rows[k];
-                d[1] = (int32_t)slot;
-                d[2] = (int32_t)(entry + j * kChunk);
-                d[3] = (int32_t)(len | (j == 0 ? kFirstChunk : 0u) | (nch > 1 ? kMultiChunk : 0u));
-            }
-            entry += cs[k];
-            chunk += nch;
-            ++slot;
-        }
-        if (i + 1 == n) {       // last item of the table: totals
-            meta[out ? 1 : 0] = slot;
-            meta[out ? 3 : 2] = chunk;
-        }
-    }
-}
-
-// ------------------------------------------------------------------ fill
-template <int K>
-__global__ __launch_bounds__(256) void sgns_fill_kernel(uint32_t npairs, const int32_t* pair_ctx,
-                                                        const int32_t* pair_t,
-                                                        const uint32_t* rank_in,
-                                                        const uint32_t* rank_out,
-                                                        const int32_t* off_in,
-                                                        const int32_t* off_out,
-                                                        int32_t* entries_in, int32_t* entries_out)
-{
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < npairs * (K + 1)) {
-        const int32_t row = pair_t[t];
-        if (row >= 0) entries_out[off_out[row] + rank_out[t]] = (int32_t)t;
-    } else if (t < npairs * (K + 2)) {
-        const uint32_t p = t - npairs * (K + 1);
-        entries_in[off_in[pair_ctx[p]] + rank_in[p]] = (int32_t)p;
-    }
-}
-
 // ---------------------------------------------------------------- reduce
-// Out rows: delta out[t] = sum over touches (p, k) of g_pk * in[ctx_p].
-// In rows:  delta in[c]  = sum over touches p of dinp[p].
-// Groups of 16 lanes take one chunk each, 4 chunks per wave.  capture !=
-// NULL: write the deltas to capture[slot][d] (zeroed) instead of the table.
-template <int D, int K, bool OUT>
-__global__ __launch_bounds__(256) void sgns_reduce_kernel(
-    float* __restrict__ table, const float* __restrict__ tin, const float* __restrict__ dinp,
-    const float* __restrict__ pair_g, const int32_t* __restrict__ pair_ctx,
-    const int32_t* __restrict__ entries, const int32_t* __restrict__ chunks,
-    uint32_t* __restrict__ cnt, const uint32_t* meta, float* __restrict__ capture,
-    unsigned long long* row_totals)
+// Out rows: delta out[t] = sum over touches of g * in[ctx].
+// In rows:  delta in[c]  = sum over touches of the pair's in-row delta.
+// Rows of at most kChunk touches: one 16-lane group per row sorts the
+// touches by their pair-order key (a bitonic network over the group) and
+// sums them in FP32 in that order, so the result is the sequential sum in
+// pair order whatever the atomics did.  Chunks of the rows with more
+// touches (their membership follows the atomics' order) get exact sums
+// instead, which a merge adds in chunk order.
+// Sort (key, a, b) ascending over the 16 lanes of a group.
+__device__ __forceinline__ void sort16(uint32_t& key, float& va, int32_t& vb, int gl)
+{
+#pragma unroll
+    for (int k = 2; k <= 16; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t pk = __shfl_xor(key, j);
+            const float pa = __shfl_xor(va, j);
+            const int32_t pb = __shfl_xor(vb, j);
+            const bool up = (gl & k) == 0;        // this pair of lanes sorts ascending
+            const bool low = (gl & j) == 0;       // this lane keeps the smaller key
+            const bool take = (low == up) ? pk < key : pk > key;
+            if (take) {
+                key = pk;
+                va = pa;
+                vb = pb;
+            }
+        }
+}
+
+// Two launches per minibatch, each over a list of work items of three kinds:
+//   first:  chunks of split out rows, chunks of split in rows (exact sums,
+//           stored), out rows of at most kChunk touches (sorted FP32 sums);
+//   second: in rows of at most kChunk touches, then the merge of the split
+//           out rows and split in rows (their chunks' sums in chunk order).
+// Out rows need the in-table as of the minibatch start, so every in row is
+// written in the second launch.
+struct ApplyArgs {
+    float* tin;
+    float* tout;
+    const int2* ent_out;          // (g, ctx) by out segment position
+    const uint32_t* key_out;      // pair-order key by out segment position
+    const float* dinp;            // in-row delta of each pair, by in segment position
+    const uint32_t* key_in;       // pair by in segment position
+    const int4* chunks_in;        // rows of at most kChunk touches
+    const int4* chunks_out;
+    const int4* split_in;         // chunks of split rows
+    const int4* split_out;
+    const int4* mrows_in;         // split rows
+    const int4* mrows_out;
+    double* partial_in;           // exact sums of the split rows' chunks
+    double* partial_out;
+    uint32_t* cnt_in;
+    uint32_t* cnt_out;
+    const uint32_t* meta;         // this minibatch's counters
+    float* cap_in;                // capture != NULL: deltas to capture[list slot][d]
+    float* cap_out;
+    unsigned long long* row_totals;
+    double grid_c;                // 1.5 * 2^(floor(log2 lr) + 17)
+};
+
+// Adds a row's delta to the table, or stores it in the capture buffer.
+template <int D>
+__device__ __forceinline__ void put_row(float* table, float* cap, int32_t row, int32_t slot,
+                                        const float (&delta)[D / 16], int gl)
 {
     constexpr int V4 = D / 64;
+    float4* d4 = reinterpret_cast<float4*>(cap ? cap + (int64_t)slot * D : table + (int64_t)row * D);
+#pragma unroll
+    for (int i = 0; i < V4; ++i) {
+        float4 v = cap ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : d4[i * 16 + gl];
+        v.x += delta[4 * i + 0];
+        v.y += delta[4 * i + 1];
+        v.z += delta[4 * i + 2];
+        v.w += delta[4 * i + 3];
+        d4[i * 16 + gl] = v;
+    }
+}
+
+template <int D, int PHASE>
+__global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
+{
+    constexpr int V4 = D / 64;
+    constexpr int kRows = 4;    // rows in flight per group, rows of one chunk
+    constexpr int kRowsS = 2;   // rows in flight per group, chunks of split rows
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4, gl = lane & 15;
-    const uint32_t n_chunks = meta[OUT ? 3 : 2];
+    const int g0 = grp << 4;
+    // item ranges [0, e1) [e1, e2) [e2, e3)
+    const uint32_t e1 = PHASE == 0 ? a.meta[7] : a.meta[2];
+    const uint32_t e2 = e1 + (PHASE == 0 ? a.meta[6] : a.meta[5]);
+    const uint32_t e3 = e2 + (PHASE == 0 ? a.meta[3] : a.meta[4]);
     const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    const float* src = OUT ? tin : dinp;
-    for (uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4u;
-         base < n_chunks; base += nw * 4u) {
+    for (uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4u; base < e3;
+         base += nw * 4u) {
         const uint32_t c = base + grp;
-        const bool live = c < n_chunks;
-        int32_t row = 0, slot = 0, start = 0, len = 0;
-        uint32_t lf = 0;
-        if (live) {
-            const int4 d = reinterpret_cast<const int4*>(chunks)[c];
-            row = d.x;
-            slot = d.y;
-            start = d.z;
-            lf = (uint32_t)d.w;
-            len = (int32_t)(lf & kLenMask);
-        }
-        float my_g = 0.0f;
-        int32_t my_src = 0;
-        if (gl < len) {
-            const int32_t e = entries[start + gl];
-            if (OUT) {
-                my_g = pair_g[e];
-                my_src = pair_ctx[e / (K + 1)];
-            } else {
-                my_g = 1.0f;
-                my_src = e;
-            }
-        }
-        // longest chunk among the wave's four groups
-        int32_t mlen = max(len, __shfl_xor(len, 16));
-        mlen = max(mlen, __shfl_xor(mlen, 32));
-        float4 acc[V4];
+        if (c >= e3) continue;
+        const int kind = c < e1 ? 0 : (c < e2 ? 1 : 2);
+        const uint32_t ci = kind == 0 ? c : (kind == 1 ? c - e1 : c - e2);
+        if (PHASE == 1 && kind > 0) {
+            // merge of a split row: its chunks' exact sums in chunk order
+            const bool out = kind == 1;
+            const int4 m = (out ? a.mrows_out : a.mrows_in)[ci];
+            const double* partial = out ? a.partial_out : a.partial_in;
+            double acc[D / 16];
 #pragma unroll
-        for (int i = 0; i < V4; ++i) acc[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int32_t i0 = 0; i0 < mlen; i0 += 4) {
-            float gg[4];
-            float4 x[4][V4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t idx = min(i0 + u, kChunk - 1);
-                gg[u] = __shfl(my_g, (grp << 4) + idx);
-                const int32_t rr = __shfl(my_src, (grp << 4) + idx);
-                if (i0 + u < len) {
-                    const float4* rp = row4<D>(src, rr);
-#pragma unroll
-                    for (int i = 0; i < V4; ++i) x[u][i] = rp[i * 16 + gl];
-                } else {
-                    gg[u] = 0.0f;
-#pragma unroll
-                    for (int i = 0; i < V4; ++i) x[u][i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
+            for (int32_t j = 0; j < m.z; ++j) {
+                const double* pr = partial + (int64_t)(m.y + j) * D;
 #pragma unroll
                 for (int i = 0; i < V4; ++i) {
-                    acc[i].x = fmaf(gg[u], x[u][i].x, acc[i].x);
-                    acc[i].y = fmaf(gg[u], x[u][i].y, acc[i].y);
-                    acc[i].z = fmaf(gg[u], x[u][i].z, acc[i].z);
-                    acc[i].w = fmaf(gg[u], x[u][i].w, acc[i].w);
-                }
-        }
-        if (live) {
-            float* dst = capture ? capture + (int64_t)slot * D : table + (int64_t)row * D;
-            float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll
-            for (int i = 0; i < V4; ++i) {
-                if (lf & kMultiChunk) {
-                    float* f = dst + (i * 16 + gl) * 4;
-                    unsafeAtomicAdd(f + 0, acc[i].x);
-                    unsafeAtomicAdd(f + 1, acc[i].y);
-                    unsafeAtomicAdd(f + 2, acc[i].z);
-                    unsafeAtomicAdd(f + 3, acc[i].w);
-                } else if (capture) {
-                    d4[i * 16 + gl] = acc[i];
-                } else {
-                    float4 v = d4[i * 16 + gl];
-                    v.x += acc[i].x;
-                    v.y += acc[i].y;
-                    v.z += acc[i].z;
-                    v.w += acc[i].w;
-                    d4[i * 16 + gl] = v;
+                    const double2* q = reinterpret_cast<const double2*>(pr + (i * 16 + gl) * 4);
+                    const double2 u = q[0], v = q[1];
+                    acc[4 * i + 0] += u.x;
+                    acc[4 * i + 1] += u.y;
+                    acc[4 * i + 2] += v.x;
+                    acc[4 * i + 3] += v.y;
                 }
             }
-            if ((lf & kFirstChunk) && gl == 0) cnt[row] = 0;
+            float delta[D / 16];
+#pragma unroll
+            for (int e = 0; e < D / 16; ++e) delta[e] = (float)acc[e];
+            put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, m.w, delta, gl);
+            if (gl == 0) (out ? a.cnt_out : a.cnt_in)[m.x] = 0;
+            continue;
         }
+        // out rows draw on in[ctx] with coefficient g, in rows on the per-pair deltas
+        const bool split = PHASE == 0 && kind < 2;
+        const bool out = PHASE == 0 ? kind != 1 : false;
+        const int4 d = split ? (out ? a.split_out : a.split_in)[ci]
+                             : (out ? a.chunks_out : a.chunks_in)[ci];
+        const int32_t row = d.x, start = d.y, len = d.z, slot = d.w;
+        const float* src = out ? a.tin : a.dinp;
+        float my_g = 1.0f;
+        int32_t my_src = start + gl;
+        if (out && gl < len) {
+            const int2 e = a.ent_out[start + gl];
+            my_g = __int_as_float(e.x);
+            my_src = e.y;
+        }
+        if (split) {
+            // exact sums, stored for the merge
+            double acc[D / 16];
+#pragma unroll
+            for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
+            const double gc = a.grid_c;
+            for (int32_t i0 = 0; i0 < len; i0 += kRowsS) {
+                float gg[kRowsS];
+                float4 x[kRowsS][V4];
+#pragma unroll
+                for (int u = 0; u < kRowsS; ++u) {
+                    const int32_t idx = min(i0 + u, kChunk - 1);
+                    const bool ok = i0 + u < len;
+                    gg[u] = ok ? __shfl(my_g, g0 + idx) : 0.0f;
+                    const int32_t rr = __shfl(my_src, g0 + idx);
+                    const float4* rp = row4<D>(src, ok ? rr : 0);
+#pragma unroll
+                    for (int i = 0; i < V4; ++i)
+                        x[u][i] = ok ? rp[i * 16 + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+#pragma unroll
+                for (int u = 0; u < kRowsS; ++u) {
+                    // g * x is exact in FP64 (two 24-bit significands)
+                    const double gd = (double)gg[u];
+#pragma unroll
+                    for (int i = 0; i < V4; ++i) {
+                        acc[4 * i + 0] += on_grid(gd * (double)x[u][i].x, gc);
+                        acc[4 * i + 1] += on_grid(gd * (double)x[u][i].y, gc);
+                        acc[4 * i + 2] += on_grid(gd * (double)x[u][i].z, gc);
+                        acc[4 * i + 3] += on_grid(gd * (double)x[u][i].w, gc);
+                    }
+                }
+            }
+            double* pr = (out ? a.partial_out : a.partial_in) + (int64_t)slot * D;
+#pragma unroll
+            for (int i = 0; i < V4; ++i) {
+                double2* q = reinterpret_cast<double2*>(pr + (i * 16 + gl) * 4);
+                q[0] = make_double2(acc[4 * i + 0], acc[4 * i + 1]);
+                q[1] = make_double2(acc[4 * i + 2], acc[4 * i + 3]);
+            }
+            continue;
+        }
+        // a row of at most kChunk touches: sum in pair order
+        uint32_t key = gl < len ? (out ? a.key_out : a.key_in)[start + gl] : 0xffffffffu;
+        sort16(key, my_g, my_src, gl);
+        float acc[D / 16];
+#pragma unroll
+        for (int e = 0; e < D / 16; ++e) acc[e] = 0.0f;
+        for (int32_t i0 = 0; i0 < len; i0 += kRows) {
+            float gg[kRows];
+            float4 x[kRows][V4];
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) {
+                const int32_t idx = min(i0 + u, kChunk - 1);
+                const bool ok = i0 + u < len;
+                gg[u] = __shfl(my_g, g0 + idx);
+                const int32_t rr = __shfl(my_src, g0 + idx);
+                const float4* rp = row4<D>(src, ok ? rr : 0);
+#pragma unroll
+                for (int i = 0; i < V4; ++i)
+                    x[u][i] = ok ? rp[i * 16 + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int u = 0; u < kRows; ++u)
+#pragma unroll
+                for (int i = 0; i < V4; ++i) {
+                    // in rows: g = 1, and 1 * x + acc is exactly x + acc
+                    acc[4 * i + 0] = fmaf(gg[u], x[u][i].x, acc[4 * i + 0]);
+                    acc[4 * i + 1] = fmaf(gg[u], x[u][i].y, acc[4 * i + 1]);
+                    acc[4 * i + 2] = fmaf(gg[u], x[u][i].z, acc[4 * i + 2]);
+                    acc[4 * i + 3] = fmaf(gg[u], x[u][i].w, acc[4 * i + 3]);
+                }
+        }
+        put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, slot, acc, gl);
+        if (gl == 0) (out ? a.cnt_out : a.cnt_in)[row] = 0;
     }
-    // the in-row reduction is the minibatch's last kernel: count the touched rows
-    if (!OUT && blockIdx.x == 0 && threadIdx.x == 0) {
-        row_totals[0] += meta[0];
-        row_totals[1] += meta[1];
+    // the second launch counts the minibatch's touched rows
+    if (PHASE == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.row_totals[0] += a.meta[0];
+        a.row_totals[1] += a.meta[1];
     }
 }
 
@@ -653,72 +770,134 @@ int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_
     return s.B;
 }
 
+void model_alloc_update_state(Model& m)
+{
+    Ctx& c = *m.ctx;
+    const int64_t n = m.g->n;
+    for (MinibatchBufs& b : m.mb) {
+        b.cnt_in.alloc(&c, sizeof(uint32_t) * n);
+        b.cnt_out.alloc(&c, sizeof(uint32_t) * n);
+        b.off_in.alloc(&c, sizeof(int32_t) * n);
+        b.off_out.alloc(&c, sizeof(int32_t) * n);
+        FELOG_HIP(hipMemsetAsync(b.cnt_in.ptr, 0, sizeof(uint32_t) * n, c.stream));
+        FELOG_HIP(hipMemsetAsync(b.cnt_out.ptr, 0, sizeof(uint32_t) * n, c.stream));
+    }
+    m.meta.alloc(&c, sizeof(uint32_t) * 2 * kMetaWords);
+    m.row_totals.alloc(&c, sizeof(uint64_t) * 2);
+    m.loss_out.alloc(&c, sizeof(double));
+    FELOG_HIP(hipMemsetAsync(m.meta.ptr, 0, m.meta.bytes, c.stream));
+}
 
+// Rows split over chunks have more than kChunk touches, so at most
+// touches / (kChunk + 1) of them, with ceil(c / kChunk) <= 2 c / (kChunk + 1)
+// chunks each: at most touches / 8 + 1 chunks in all.
+static int64_t max_split_rows(int64_t touches) { return touches / (kChunk + 1) + 1; }
+static int64_t max_split_chunks(int64_t touches) { return touches / 8 + 1; }
+
+// Launch geometry and per-minibatch values of one minibatch.
 struct MinibatchLaunch {
-    dim3 fwd_grid;
     uint32_t npairs;
     int dim, K;
-    int fill_blocks, reduce_blocks;
-    uint32_t nb_in, nb_out;
+    uint32_t prep_blocks, fwd_blocks, nb_in, nb_out, reduce_blocks;
+    int64_t split_in;     // partial-sum rows reserved for the in-table (the out-table's follow)
+    double grid_c;        // exact-sum grid constant of this minibatch's learning rate
 };
 
-template <int D, int K>
-static void launch_minibatch_t(Model& m, const SgnsArgs& a, const MinibatchLaunch& ml,
-                               float* cap_in, float* cap_out, hipStream_t s, hipEvent_t ev_mid)
+// Ids, ranks and the destination sort of one minibatch (reads only the walks
+// and the noise table, so it may run ahead of the training of earlier ones).
+template <int K>
+static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& ml,
+                         uint32_t* meta, hipStream_t s)
 {
-    hipLaunchKernelGGL((sgns_forward_kernel<D, K>), ml.fwd_grid, dim3(256), 0, s, a);
-    if (ev_mid) FELOG_HIP(hipEventRecord(ev_mid, s));
-    TouchView tv{m.pair_ctx.as<int32_t>(), m.pair_t.as<int32_t>(), m.rank_in.as<uint32_t>(),
-                 m.rank_out.as<uint32_t>(), m.cnt_in.as<uint32_t>(), m.cnt_out.as<uint32_t>()};
-    uint32_t* meta = m.meta.as<uint32_t>();
-    const uint32_t n_in = ml.npairs, n_out = ml.npairs * (K + 1);
+    pa.cnt_in = mb.cnt_in.as<uint32_t>();
+    pa.cnt_out = mb.cnt_out.as<uint32_t>();
+    pa.touch_row = mb.touch_row.as<int32_t>();
+    pa.touch_pos = mb.touch_pos.as<uint32_t>();
+    hipLaunchKernelGGL((sgns_prep_kernel<K>), dim3(ml.prep_blocks), dim3(256), 0, s, pa);
     const uint32_t nb = ml.nb_in + ml.nb_out;
-    unsigned long long* part_ec = m.partials.as<unsigned long long>();
-    uint32_t* part_rows = reinterpret_cast<uint32_t*>(part_ec + nb);
-    hipLaunchKernelGGL(sgns_scan_partials, dim3(nb), dim3(256), 0, s, tv, n_in, n_out, ml.nb_in,
-                       part_ec, part_rows);
-    ScanOut so_in{m.list_in.as<int32_t>(), m.off_in.as<int32_t>(), m.chunks_in.as<int32_t>()};
-    ScanOut so_out{m.list_out.as<int32_t>(), m.off_out.as<int32_t>(), m.chunks_out.as<int32_t>()};
-    hipLaunchKernelGGL(sgns_scan_write, dim3(nb), dim3(256), 0, s, tv, n_in, n_out, ml.nb_in,
-                       part_ec, part_rows, so_in, so_out, meta);
-    hipLaunchKernelGGL(sgns_fill_kernel<K>, dim3(ml.fill_blocks), dim3(256), 0, s, ml.npairs,
-                       m.pair_ctx.as<int32_t>(), m.pair_t.as<int32_t>(),
-                       m.rank_in.as<uint32_t>(), m.rank_out.as<uint32_t>(),
-                       m.off_in.as<int32_t>(), m.off_out.as<int32_t>(),
-                       m.entries_in.as<int32_t>(), m.entries_out.as<int32_t>());
-    hipLaunchKernelGGL((sgns_reduce_kernel<D, K, true>), dim3(ml.reduce_blocks), dim3(256), 0, s,
-                       m.tout.as<float>(), m.tin.as<float>(), m.dinp.as<float>(),
-                       m.pair_g.as<float>(), m.pair_ctx.as<int32_t>(), m.entries_out.as<int32_t>(),
-                       m.chunks_out.as<int32_t>(), m.cnt_out.as<uint32_t>(), meta, cap_out,
-                       m.row_totals.as<unsigned long long>());
-    hipLaunchKernelGGL((sgns_reduce_kernel<D, K, false>), dim3(ml.reduce_blocks), dim3(256), 0, s,
-                       m.tin.as<float>(), m.tin.as<float>(), m.dinp.as<float>(),
-                       m.pair_g.as<float>(), m.pair_ctx.as<int32_t>(), m.entries_in.as<int32_t>(),
-                       m.chunks_in.as<int32_t>(), m.cnt_in.as<uint32_t>(), meta, cap_in,
-                       m.row_totals.as<unsigned long long>());
+    uint4* part_rm = mb.partials.as<uint4>();
+    unsigned long long* part_ec = reinterpret_cast<unsigned long long*>(part_rm + nb);
+    ScanArgs sa{pa.touch_row, pa.touch_pos, pa.cnt_in, pa.cnt_out, ml.npairs,
+                ml.npairs * (uint32_t)(K + 1), ml.nb_in, part_ec, part_rm,
+                mb.list_in.as<int32_t>(), mb.list_out.as<int32_t>(), mb.off_in.as<int32_t>(),
+                mb.off_out.as<int32_t>(), mb.chunks_in.as<int4>(), mb.chunks_out.as<int4>(),
+                mb.split_in.as<int4>(), mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),
+                mb.mrows_out.as<int4>(), meta};
+    hipLaunchKernelGGL((sgns_scan_partials<K>), dim3(nb), dim3(256), 0, s, sa);
+    hipLaunchKernelGGL((sgns_scan_write<K>), dim3(nb), dim3(256), 0, s, sa);
     FELOG_HIP(hipGetLastError());
 }
 
-template <int D>
-static void launch_minibatch_k(int K, Model& m, const SgnsArgs& a, const MinibatchLaunch& ml,
-                               float* ci, float* co, hipStream_t s, hipEvent_t ev)
+// Forward, reductions and merge of one minibatch whose ids are ready.
+// ev (optional): [0] recorded before the forward, [1] after it, [2] at the end.
+template <int D, int K>
+static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const MinibatchLaunch& ml,
+                           uint32_t* meta, float* cap_in, float* cap_out, hipStream_t s,
+                           hipEvent_t* ev)
 {
-    switch (K) {
-#define FELOG_K(k) case k: launch_minibatch_t<D, k>(m, a, ml, ci, co, s, ev); break;
-        FELOG_K(1) FELOG_K(2) FELOG_K(3) FELOG_K(4) FELOG_K(5) FELOG_K(6) FELOG_K(7)
-        FELOG_K(8) FELOG_K(9) FELOG_K(10) FELOG_K(11) FELOG_K(12) FELOG_K(13) FELOG_K(14)
-        FELOG_K(15) FELOG_K(16) FELOG_K(17) FELOG_K(18) FELOG_K(19) FELOG_K(20)
-#undef FELOG_K
-        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", K);
+    fa.touch_row = mb.touch_row.as<int32_t>();
+    fa.touch_pos = mb.touch_pos.as<uint32_t>();
+    fa.off_in = mb.off_in.as<int32_t>();
+    fa.off_out = mb.off_out.as<int32_t>();
+    if (ev) FELOG_HIP(hipEventRecord(ev[0], s));
+    hipLaunchKernelGGL((sgns_forward_kernel<D, K>), dim3(ml.fwd_blocks), dim3(256), 0, s, fa);
+    if (ev) FELOG_HIP(hipEventRecord(ev[1], s));
+    double* part_in = m.partial.as<double>();
+    double* part_out = part_in + ml.split_in * D;
+    ApplyArgs aa{m.tin.as<float>(),       m.tout.as<float>(),      fa.ent_out,
+                 fa.key_out,              fa.dinp,                 fa.key_in,
+                 mb.chunks_in.as<int4>(), mb.chunks_out.as<int4>(), mb.split_in.as<int4>(),
+                 mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),  mb.mrows_out.as<int4>(),
+                 part_in,                 part_out,                mb.cnt_in.as<uint32_t>(),
+                 mb.cnt_out.as<uint32_t>(), meta,                  cap_in,
+                 cap_out,                 m.row_totals.as<unsigned long long>(), ml.grid_c};
+    hipLaunchKernelGGL((sgns_apply_kernel<D, 0>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
+    hipLaunchKernelGGL((sgns_apply_kernel<D, 1>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
+    if (ev) FELOG_HIP(hipEventRecord(ev[2], s));
+    FELOG_HIP(hipGetLastError());
+}
+
+#define FELOG_FOR_K(X)                                                               \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
+    X(16) X(17) X(18) X(19) X(20)
+
+static void launch_ids(MinibatchBufs& mb, const PrepArgs& pa, const MinibatchLaunch& ml,
+                       uint32_t* meta, hipStream_t s)
+{
+    switch (ml.K) {
+#define FELOG_CASE(k)                                  \
+    case k:                                            \
+        launch_ids_t<k>(mb, pa, ml, meta, s);          \
+        break;
+        FELOG_FOR_K(FELOG_CASE)
+#undef FELOG_CASE
+        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", ml.K);
     }
 }
 
-static void launch_minibatch(Model& m, const SgnsArgs& a, const MinibatchLaunch& ml, float* ci,
-                             float* co, hipStream_t s, hipEvent_t ev)
+template <int D>
+static void launch_train_d(Model& m, MinibatchBufs& mb, const FwdArgs& fa,
+                           const MinibatchLaunch& ml, uint32_t* meta, float* ci, float* co,
+                           hipStream_t s, hipEvent_t* ev)
 {
-    if (ml.dim == 64) launch_minibatch_k<64>(ml.K, m, a, ml, ci, co, s, ev);
-    else if (ml.dim == 128) launch_minibatch_k<128>(ml.K, m, a, ml, ci, co, s, ev);
-    else launch_minibatch_k<256>(ml.K, m, a, ml, ci, co, s, ev);
+    switch (ml.K) {
+#define FELOG_CASE(k)                                                  \
+    case k:                                                            \
+        launch_train_t<D, k>(m, mb, fa, ml, meta, ci, co, s, ev);      \
+        break;
+        FELOG_FOR_K(FELOG_CASE)
+#undef FELOG_CASE
+        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", ml.K);
+    }
+}
+
+static void launch_train(Model& m, MinibatchBufs& mb, const FwdArgs& fa,
+                         const MinibatchLaunch& ml, uint32_t* meta, float* ci, float* co,
+                         hipStream_t s, hipEvent_t* ev)
+{
+    if (ml.dim == 64) launch_train_d<64>(m, mb, fa, ml, meta, ci, co, s, ev);
+    else if (ml.dim == 128) launch_train_d<128>(m, mb, fa, ml, meta, ci, co, s, ev);
+    else launch_train_d<256>(m, mb, fa, ml, meta, ci, co, s, ev);
 }
 
 void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, int64_t first_mb,
@@ -798,48 +977,39 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         m.cap_pairs = std::max<int64_t>(m.cap_pairs, P);
         m.cap_K = std::max(m.cap_K, K);
         const int64_t cp = m.cap_pairs, ck = m.cap_K;
-        m.pair_ctx.alloc(&c, sizeof(int32_t) * cp);
-        m.pair_t.alloc(&c, sizeof(int32_t) * cp * (ck + 1));
-        m.pair_g.alloc(&c, sizeof(float) * cp * (ck + 1));
-        m.rank_in.alloc(&c, sizeof(uint32_t) * cp);
-        m.rank_out.alloc(&c, sizeof(uint32_t) * cp * (ck + 1));
-        m.dinp.alloc(&c, sizeof(float) * cp * m.dim);
-        m.list_in.alloc(&c, sizeof(int32_t) * cp);
-        m.list_out.alloc(&c, sizeof(int32_t) * cp * (ck + 1));
-        m.entries_in.alloc(&c, sizeof(int32_t) * cp);
-        m.entries_out.alloc(&c, sizeof(int32_t) * cp * (ck + 1));
-        m.chunks_in.alloc(&c, sizeof(int32_t) * 4 * cp);
-        m.chunks_out.alloc(&c, sizeof(int32_t) * 4 * cp * (ck + 1));
+        const int64_t touches_out = cp * (ck + 1);
         const int64_t nbmax = (cp + kScanSpanS - 1) / kScanSpanS +
-                              (cp * (ck + 1) + kScanSpanS - 1) / kScanSpanS;
-        m.partials.alloc(&c, (sizeof(unsigned long long) + sizeof(uint32_t)) * nbmax);
+                              (touches_out + kScanSpanS - 1) / kScanSpanS;
+        for (MinibatchBufs& b : m.mb) {
+            b.touch_row.alloc(&c, sizeof(int32_t) * cp * (ck + 2));
+            b.touch_pos.alloc(&c, sizeof(uint32_t) * cp * (ck + 2));
+            b.list_in.alloc(&c, sizeof(int32_t) * cp);
+            b.list_out.alloc(&c, sizeof(int32_t) * touches_out);
+            b.chunks_in.alloc(&c, sizeof(int4) * cp);
+            b.chunks_out.alloc(&c, sizeof(int4) * touches_out);
+            b.split_in.alloc(&c, sizeof(int4) * max_split_chunks(cp));
+            b.split_out.alloc(&c, sizeof(int4) * max_split_chunks(touches_out));
+            b.mrows_in.alloc(&c, sizeof(int4) * max_split_rows(cp));
+            b.mrows_out.alloc(&c, sizeof(int4) * max_split_rows(touches_out));
+            b.partials.alloc(&c, (sizeof(uint4) + sizeof(unsigned long long)) * nbmax);
+        }
+        m.ent_out.alloc(&c, sizeof(int2) * touches_out);
+        m.key_out.alloc(&c, sizeof(uint32_t) * touches_out);
+        m.dinp.alloc(&c, sizeof(float) * cp * m.dim);
+        m.key_in.alloc(&c, sizeof(uint32_t) * cp);
+        m.split_rows_in = max_split_chunks(cp);
+        m.partial.alloc(&c, sizeof(double) * (m.split_rows_in + max_split_chunks(touches_out)) *
+                                m.dim);
     }
-    const int ppw_max = 64 / (K + 2);
-    int ppw = (int)std::min<int64_t>(ppw_max, std::max<int64_t>(1, P / ((int64_t)c.num_cus * 32)));
+    const int ppw_max = std::max(1, std::min(8, 64 / (K + 2)));
+    const int ppw = (int)std::min<int64_t>(ppw_max,
+                                           std::max<int64_t>(1, P / ((int64_t)c.num_cus * 32)));
     const int64_t waves = (P + ppw - 1) / ppw;
     const int64_t blocks = (waves + 3) / 4;
     DevBuf loss_part;
     loss_part.alloc(&c, sizeof(double) * blocks * 4);
     FELOG_HIP(hipMemsetAsync(loss_part.ptr, 0, sizeof(double) * blocks * 4, c.stream));
-    FELOG_HIP(hipMemsetAsync(m.meta.ptr, 0, sizeof(uint32_t) * 8, c.stream));
     FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
-
-    // sampled kernel timing: events before forward, after forward, after the reductions
-    const int every = apply ? c.timing_every : 0;
-    const size_t pool = c.timing_pool.size() / 3;
-    size_t next_slot = 0, used_slots = 0;
-    int64_t timed = 0;
-    double ms_fwd = 0.0, ms_apply = 0.0;
-    auto harvest = [&](size_t slot) {
-        hipEvent_t* e = &c.timing_pool[3 * slot];
-        FELOG_HIP(hipEventSynchronize(e[2]));
-        float f = 0.0f, ap = 0.0f;
-        FELOG_HIP(hipEventElapsedTime(&f, e[0], e[1]));
-        FELOG_HIP(hipEventElapsedTime(&ap, e[1], e[2]));
-        ms_fwd += f;
-        ms_apply += ap;
-        ++timed;
-    };
 
     std::vector<int32_t> sl = make_slices(w.L, p.window);
     DevBuf slices;
@@ -848,99 +1018,164 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         FELOG_HIP(hipMemcpyAsync(slices.ptr, sl.data(), sizeof(int32_t) * sl.size(),
                                  hipMemcpyHostToDevice, c.stream));
 
-    SgnsArgs a{};
-    a.tin = m.tin.as<float>();
-    a.tout = m.tout.as<float>();
-    a.walks = w.data.as<int32_t>();
-    a.W = w.W;
-    a.slices = slices.as<int32_t>();
-    a.id_base = w.id_base;
-    a.window = p.window;
-    a.ppw = ppw;
-    a.seed = p.seed;
-    a.noise = NoiseTable{m.cdf.as<uint64_t>(), m.guide.as<int32_t>(), m.total_weight, m.guide_bits};
-    a.cnt_in = m.cnt_in.as<uint32_t>();
-    a.cnt_out = m.cnt_out.as<uint32_t>();
-    a.pair_ctx = m.pair_ctx.as<int32_t>();
-    a.pair_t = m.pair_t.as<int32_t>();
-    a.pair_g = m.pair_g.as<float>();
-    a.rank_in = m.rank_in.as<uint32_t>();
-    a.rank_out = m.rank_out.as<uint32_t>();
-    a.dinp = m.dinp.as<float>();
-    a.loss_part = loss_part.as<double>();
+    PrepArgs pa{};
+    pa.walks = w.data.as<int32_t>();
+    pa.W = w.W;
+    pa.slices = slices.as<int32_t>();
+    pa.id_base = w.id_base;
+    pa.window = p.window;
+    pa.seed = p.seed;
+    pa.noise = NoiseTable{m.cdf.as<uint64_t>(), m.guide.as<int32_t>(), m.total_weight,
+                          m.guide_bits};
 
-    MinibatchLaunch ml{};
-    ml.dim = m.dim;
-    ml.K = K;
-    ml.reduce_blocks = std::max(1, c.num_cus * 8);
+    FwdArgs fa{};
+    fa.tin = m.tin.as<float>();
+    fa.tout = m.tout.as<float>();
+    fa.ppw = ppw;
+    fa.ent_out = m.ent_out.as<int2>();
+    fa.key_out = m.key_out.as<uint32_t>();
+    fa.dinp = m.dinp.as<float>();
+    fa.key_in = m.key_in.as<uint32_t>();
+    fa.loss_part = loss_part.as<double>();
 
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
-    int64_t pairs_done = 0;
-    FELOG_HIP(hipEventRecord(c.ev0, c.stream));
+    // the launch values of minibatch b
     size_t chunk = 0;
-    for (int64_t b = first_mb; b < end; ++b) {
+    auto frame = [&](int64_t b, MinibatchLaunch& ml, PrepArgs& a) {
         while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
-        int64_t local = b - sch.chunk_first_mb[chunk];
-        int64_t first = local * P;
-        int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
+        const int64_t first = (b - sch.chunk_first_mb[chunk]) * P;
+        const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
         a.vcols = w.valid_cols.as<int32_t>() + sch.chunk_valid_base[chunk];
         a.Wv = (uint32_t)w.chunk_valid[chunk];
         a.first_pair = (uint32_t)first;
         a.npairs = (uint32_t)np;
-        double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
-        a.lr = (float)lr;
-        int64_t nwaves = (np + ppw - 1) / ppw;
-        ml.fwd_grid = dim3((uint32_t)((nwaves + 3) / 4));
+        ml = MinibatchLaunch{};
+        ml.dim = m.dim;
+        ml.K = K;
         ml.npairs = (uint32_t)np;
-        ml.fill_blocks = (int)((np * (K + 2) + 255) / 256);
+        ml.prep_blocks = (uint32_t)((np * (K + 2) + 255) / 256);
+        ml.fwd_blocks = (uint32_t)(((np + ppw - 1) / ppw + 3) / 4);
         ml.nb_in = (uint32_t)((np + kScanSpanS - 1) / kScanSpanS);
         ml.nb_out = (uint32_t)((np * (K + 1) + kScanSpanS - 1) / kScanSpanS);
-        const bool timed_mb = every > 0 && pool > 0 && (b - first_mb) % every == 0;
-        hipEvent_t* ev = nullptr;
-        if (timed_mb) {
-            if (used_slots == pool) harvest(next_slot);   // reuse the oldest slot
-            else ++used_slots;
-            ev = &c.timing_pool[3 * next_slot];
-            next_slot = (next_slot + 1) % pool;
-            FELOG_HIP(hipEventRecord(ev[0], c.stream));
+        ml.reduce_blocks = (uint32_t)std::max(1, c.num_cus * 8);
+        ml.split_in = m.split_rows_in;
+        const double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
+        const float lr32 = (float)lr;
+        ml.grid_c = lr32 > 0.0f ? std::ldexp(1.5, std::ilogb(lr32) + 17) : 1.5;
+        return lr32;
+    };
+    uint32_t* meta0 = m.meta.as<uint32_t>();
+
+    // sampled timing: [0] before the ids (on the id stream), [1] after them,
+    // [2] before the forward, [3] after it, [4] after the merge
+    const int every = apply ? c.timing_every : 0;
+    const size_t pool = c.timing_pool.size() / 5;
+    size_t next_slot = 0, used_slots = 0;
+    int64_t timed = 0;
+    double ms_prep = 0.0, ms_fwd = 0.0, ms_apply = 0.0;
+    auto harvest = [&](size_t slot) {
+        hipEvent_t* e = &c.timing_pool[5 * slot];
+        FELOG_HIP(hipEventSynchronize(e[4]));
+        float a0 = 0.0f, f = 0.0f, ap = 0.0f;
+        FELOG_HIP(hipEventElapsedTime(&a0, e[0], e[1]));
+        FELOG_HIP(hipEventElapsedTime(&f, e[2], e[3]));
+        FELOG_HIP(hipEventElapsedTime(&ap, e[3], e[4]));
+        ms_prep += a0;
+        ms_fwd += f;
+        ms_apply += ap;
+        ++timed;
+    };
+    hipEvent_t* slot_of[2] = {nullptr, nullptr};   // timing events of the minibatch of each parity
+    auto take_slot = [&](int64_t b) -> hipEvent_t* {
+        if (!(every > 0 && pool > 0 && (b - first_mb) % every == 0)) return nullptr;
+        if (used_slots == pool) harvest(next_slot);   // reuse the oldest slot
+        else ++used_slots;
+        hipEvent_t* e = &c.timing_pool[5 * next_slot];
+        next_slot = (next_slot + 1) % pool;
+        return e;
+    };
+
+    int64_t pairs_done = 0;
+    FELOG_HIP(hipEventRecord(c.ev0, c.stream));
+    if (apply && end > first_mb) {
+        // ids of minibatch b + 1 on the second stream while b trains on the first
+        c.ensure_aux();
+        hipStream_t ids_s = c.aux;
+        FELOG_HIP(hipEventRecord(c.pipe_ev[0], c.stream));
+        FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[0], 0));
+        MinibatchLaunch mls[2];
+        float lrs[2];
+        auto issue_ids = [&](int64_t b) {
+            const int par = (int)(b & 1);
+            PrepArgs a = pa;
+            lrs[par] = frame(b, mls[par], a);
+            if (b >= first_mb + 2)   // the buffers' previous minibatch must be done with them
+                FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[3 + par], 0));
+            hipEvent_t* e = take_slot(b);
+            slot_of[par] = e;
+            if (e) FELOG_HIP(hipEventRecord(e[0], ids_s));
+            launch_ids(m.mb[par], a, mls[par], meta0 + kMetaWords * par, ids_s);
+            if (e) FELOG_HIP(hipEventRecord(e[1], ids_s));
+            FELOG_HIP(hipEventRecord(c.pipe_ev[1 + par], ids_s));
+        };
+        issue_ids(first_mb);
+        for (int64_t b = first_mb; b < end; ++b) {
+            const int par = (int)(b & 1);
+            const MinibatchLaunch ml = mls[par];
+            const float lr = lrs[par];
+            hipEvent_t* e = slot_of[par];
+            if (b + 1 < end) issue_ids(b + 1);
+            FELOG_HIP(hipStreamWaitEvent(c.stream, c.pipe_ev[1 + par], 0));
+            FwdArgs f = fa;
+            f.lr = lr;
+            f.npairs = ml.npairs;
+            launch_train(m, m.mb[par], f, ml, meta0 + kMetaWords * par, nullptr, nullptr,
+                         c.stream, e ? e + 2 : nullptr);
+            FELOG_HIP(hipEventRecord(c.pipe_ev[3 + par], c.stream));
+            pairs_done += ml.npairs;
         }
-        if (apply) {
-            launch_minibatch(m, a, ml, nullptr, nullptr, c.stream, ev ? ev[1] : nullptr);
-            if (ev) FELOG_HIP(hipEventRecord(ev[2], c.stream));
-        } else {
-            // capture: deltas of this minibatch, by touched-list position, not applied
-            DevBuf vin, vout;
-            vin.alloc(&c, sizeof(float) * (size_t)P * m.dim);
-            vout.alloc(&c, sizeof(float) * (size_t)P * (K + 1) * m.dim);
-            FELOG_HIP(hipMemsetAsync(vin.ptr, 0, vin.bytes, c.stream));
-            FELOG_HIP(hipMemsetAsync(vout.ptr, 0, vout.bytes, c.stream));
-            // the last kernel adds the list lengths to row_totals (zeroed above)
-            FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
-            launch_minibatch(m, a, ml, vin.as<float>(), vout.as<float>(), c.stream, nullptr);
-            unsigned long long tot[2];
-            FELOG_HIP(hipMemcpyAsync(tot, m.row_totals.ptr, sizeof tot, hipMemcpyDeviceToHost,
-                                     c.stream));
-            c.sync();
-            const int64_t ui = (int64_t)tot[0], uo = (int64_t)tot[1];
-            FELOG_REQUIRE(rows_in && d_in_host && rows_out && d_out_host,
-                          "capture buffers must not be NULL");
-            FELOG_REQUIRE(ui <= cap_in && uo <= cap_out,
-                          "capture buffers hold %lld / %lld rows, need %lld / %lld",
-                          (long long)cap_in, (long long)cap_out, (long long)ui, (long long)uo);
-            FELOG_HIP(hipMemcpyAsync(rows_in, m.list_in.ptr, sizeof(int32_t) * ui,
-                                     hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemcpyAsync(rows_out, m.list_out.ptr, sizeof(int32_t) * uo,
-                                     hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemcpyAsync(d_in_host, vin.ptr, sizeof(float) * ui * m.dim,
-                                     hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemcpyAsync(d_out_host, vout.ptr, sizeof(float) * uo * m.dim,
-                                     hipMemcpyDeviceToHost, c.stream));
-            FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
-            c.sync();
-            if (n_in) *n_in = ui;
-            if (n_out) *n_out = uo;
-        }
-        pairs_done += np;
+    } else if (!apply) {
+        // capture: the deltas of one minibatch, by touched-list position, not applied
+        const int64_t b = first_mb;
+        const int par = (int)(b & 1);
+        MinibatchLaunch ml;
+        PrepArgs a = pa;
+        const float lr = frame(b, ml, a);
+        uint32_t* meta = meta0 + kMetaWords * par;
+        DevBuf vin, vout;
+        vin.alloc(&c, sizeof(float) * (size_t)P * m.dim);
+        vout.alloc(&c, sizeof(float) * (size_t)P * (K + 1) * m.dim);
+        FELOG_HIP(hipMemsetAsync(vin.ptr, 0, vin.bytes, c.stream));
+        FELOG_HIP(hipMemsetAsync(vout.ptr, 0, vout.bytes, c.stream));
+        launch_ids(m.mb[par], a, ml, meta, c.stream);
+        FwdArgs f = fa;
+        f.lr = lr;
+        f.npairs = ml.npairs;
+        launch_train(m, m.mb[par], f, ml, meta, vin.as<float>(), vout.as<float>(), c.stream,
+                     nullptr);
+        unsigned long long tot[2];
+        FELOG_HIP(hipMemcpyAsync(tot, m.row_totals.ptr, sizeof tot, hipMemcpyDeviceToHost,
+                                 c.stream));
+        c.sync();
+        const int64_t ui = (int64_t)tot[0], uo = (int64_t)tot[1];
+        FELOG_REQUIRE(rows_in && d_in_host && rows_out && d_out_host,
+                      "capture buffers must not be NULL");
+        FELOG_REQUIRE(ui <= cap_in && uo <= cap_out,
+                      "capture buffers hold %lld / %lld rows, need %lld / %lld",
+                      (long long)cap_in, (long long)cap_out, (long long)ui, (long long)uo);
+        FELOG_HIP(hipMemcpyAsync(rows_in, m.mb[par].list_in.ptr, sizeof(int32_t) * ui,
+                                 hipMemcpyDeviceToHost, c.stream));
+        FELOG_HIP(hipMemcpyAsync(rows_out, m.mb[par].list_out.ptr, sizeof(int32_t) * uo,
+                                 hipMemcpyDeviceToHost, c.stream));
+        FELOG_HIP(hipMemcpyAsync(d_in_host, vin.ptr, sizeof(float) * ui * m.dim,
+                                 hipMemcpyDeviceToHost, c.stream));
+        FELOG_HIP(hipMemcpyAsync(d_out_host, vout.ptr, sizeof(float) * uo * m.dim,
+                                 hipMemcpyDeviceToHost, c.stream));
+        FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
+        c.sync();
+        if (n_in) *n_in = ui;
+        if (n_out) *n_out = uo;
+        pairs_done += ml.npairs;
     }
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, c.stream,
                        loss_part.as<double>(), blocks * 4, m.loss_out.as<double>());
@@ -952,6 +1187,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost,
                              c.stream));
     c.sync();
+    if (c.aux) FELOG_HIP(hipStreamSynchronize(c.aux));
     // harvest the slots still pending, oldest first
     for (size_t k = 0; k < used_slots; ++k)
         harvest((next_slot + pool - used_slots + k) % pool);
@@ -968,6 +1204,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         stats->timed_launches = timed;
         stats->ms_forward = ms_fwd;
         stats->ms_apply = ms_apply;
+        stats->ms_prep = ms_prep;
     }
 }
 

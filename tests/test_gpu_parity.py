@@ -215,6 +215,22 @@ def test_sgns_step_parity_k_and_dims(fl, ctx, orc, sbm):
                           neg=fl.NEG_DEGREE, mbs=[0, 5], pre_mb=20)
 
 
+def test_sgns_epoch_is_deterministic(fl, ctx, sbm):
+    """Row sums are exact, so two epochs from the same state give identical tables."""
+    g = sbm.train
+    _say("sgns determinism sbm1k, P=1024 and P=16384")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=10, L=40, seed=5)
+    for P in (1024, 16384):
+        out = []
+        for _ in range(2):
+            M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=1)
+            st = M.train_epoch(W, fl.train_params(window=5, negatives=5, minibatch_pairs=P, seed=2))
+            out.append((M.read(fl.TABLE_IN), M.read(fl.TABLE_OUT), st.loss))
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+        assert out[0][2] == out[1][2]
+
+
 def test_sgns_epoch_auc_matches_oracle(fl, ctx, orc, sbm):
     """Free-running epoch on sbm1k: AUC within 0.005 of the oracle's."""
     g = sbm.train
