@@ -80,6 +80,55 @@ def cpu_baseline(g, cfg, n_walks: int, n_mb: int):
     }
 
 
+def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
+    """p50/p99 job latency of the serving loop on a bounded sample of the serving
+    mix: capacity = 1 / mean service time of the jobs run alone, then the same
+    jobs arrive as a seeded Poisson process at 0.5, 0.8 and 0.95 x capacity."""
+    import synth
+    t0 = time.perf_counter()
+    mix = synth.job_mix(n_jobs, seed=seed)
+    graphs = [synth.job_graph(j) for j in mix]
+    log("serving: %d jobs, n = %s (graphs %.1f s)" % (n_jobs, [j["n"] for j in mix],
+                                                     time.perf_counter() - t0))
+
+    def submit(S, j, g, at=0.0):
+        return S.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                        window=j["window"], seed=j["seed"], arrival_time=at)
+
+    S = felog.Server(0, 0, slots=1, minibatch_pairs=65536, negatives=5)
+    service, pairs = [], []
+    for j, g in zip(mix, graphs):
+        st = S.wait(submit(S, j, g), -1.0)
+        service.append(st.t_done - st.t_admit)
+        pairs.append(st.pairs)
+    S.close()
+    capacity = 1.0 / float(np.mean(service))
+    log("serving: mean service %.3f s, capacity %.3f jobs/s" % (1.0 / capacity, capacity))
+    out = {"jobs": n_jobs, "slots": slots, "capacity_jobs_per_s": capacity,
+           "mean_service_s": 1.0 / capacity, "pairs_per_job": float(np.mean(pairs)), "rates": []}
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    for frac in (0.5, 0.8, 0.95):
+        lam = frac * capacity
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_jobs))
+        S = felog.Server(0, 0, slots=slots, minibatch_pairs=65536, negatives=5)
+        base = S.stats()[0] + 0.05
+        ids = []
+        for (j, g), at in zip(zip(mix, graphs), arrivals):
+            while S.stats()[0] < base + at:
+                time.sleep(min(0.002, max(0.0, base + at - S.stats()[0])))
+            ids.append(submit(S, j, g, base + at))
+        states = [S.wait(i, -1.0) for i in ids]
+        S.close()
+        lat = np.array([s.t_done - s.t_arrive for s in states])
+        span = max(s.t_done for s in states) - (base + arrivals[0])
+        r = {"load": frac, "arrival_rate_jobs_per_s": lam, "p50_latency_s": float(np.percentile(lat, 50)),
+             "p99_latency_s": float(np.percentile(lat, 99)), "jobs_per_s": n_jobs / span,
+             "pair_updates_per_s": float(np.sum(pairs)) / span}
+        log("serving: load %.2f p50 %.3f s p99 %.3f s" % (frac, r["p50_latency_s"], r["p99_latency_s"]))
+        out["rates"].append(r)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +143,9 @@ def main():
     ap.add_argument("--progress-every", type=int, default=0,
                     help="drive the rounds from Python (same ABI calls and kernels as "
                          "felog_run) and print a line every N minibatches; for profiler runs")
+    ap.add_argument("--serving-jobs", type=int, default=8,
+                    help="jobs in the serving-latency sample (0: skip)")
+    ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--calibrate", action="store_true",
                     help="after the run, build a BF16 model once: its two table conversions "
                          "read n*d*4 and write n*d*2 bytes each (known sizes, for HBM "
@@ -248,7 +300,9 @@ def main():
     per_launch = (row_bytes + id_bytes) / max(1, mbs)
     per_update = (2 * row_bytes + id_bytes) / max(1, mbs)
     avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
-    avg_upd_s = (prep_ms + fwd_ms + apply_ms) / 1e3 / max(1, timed)
+    # the next minibatch's ids overlap this one's update, so the update's cost is
+    # the training wall time per minibatch
+    avg_upd_s = sum(st.train[r].ms for r in range(R)) / 1e3 / max(1, mbs)
     achieved = per_launch / avg_fwd_s / 1e9 if timed else None
     upd_achieved = per_update / avg_upd_s / 1e9 if timed else None
     traffic = forward_traffic()
@@ -281,6 +335,9 @@ def main():
         "walk_steps_per_step": int(walk_steps), "pairs_per_step": int(pairs_per_step),
         "link_pred_auc": auc, "rounds": rounds, "roofline": roof,
     }
+    if args.serving_jobs > 0:
+        out["serving"] = serving_sample(felog, args.serving_jobs, args.serving_slots)
+        out["p99_job_latency_s"] = out["serving"]["rates"][1]["p99_latency_s"]   # at 0.8 x capacity
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, cfg, args.cpu_walks, args.cpu_minibatches)
     print(json.dumps(out), flush=True)

@@ -137,6 +137,10 @@ felog_status felog_walks_info(const felog_walks* w, int64_t* n_walks, int32_t* l
 /* Copy walks to host memory as walk-major int32 [n_walks][length], -1 after a
  * walk's end.  cap is the element capacity of `walks`. */
 felog_status felog_walks_read(const felog_walks* w, int32_t* walks, int64_t cap);
+/* Walks first .. first + count - 1 only, walk-major int32 [count][L] into host
+ * memory (cap ints); EINVAL if the range leaves [0, W). */
+felog_status felog_walks_read_range(const felog_walks* w, int64_t first, int64_t count,
+                                    int32_t* walks, int64_t cap);
 /* Number of node2vec proposals that hit the attempt cap (expected 0). */
 felog_status felog_walks_capped(const felog_walks* w, int64_t* capped);
 void felog_walks_destroy(felog_walks* w);

@@ -407,24 +407,38 @@ felog_status felog_walks_info(const felog_walks* w, int64_t* n_walks, int32_t* l
     });
 }
 
-felog_status felog_walks_read(const felog_walks* w, int32_t* walks, int64_t cap)
+felog_status felog_walks_read_range(const felog_walks* w, int64_t first, int64_t count,
+                                    int32_t* walks, int64_t cap)
 {
     return guarded([&] {
         NEED(w);
-        int64_t total = w->W * w->L;
+        FELOG_REQUIRE(first >= 0 && count >= 0 && first + count <= w->W,
+                      "walks [%lld, %lld) outside [0, %lld)", (long long)first,
+                      (long long)(first + count), (long long)w->W);
+        const int64_t total = count * w->L;
         if (total == 0) return;
         NEED(walks);
         FELOG_REQUIRE(cap >= total, "buffer holds %lld ints, need %lld", (long long)cap,
                       (long long)total);
         Ctx* c = w->g->ctx;
-        // Device layout is step-major [L][W]; transpose to walk-major on the host.
+        // Device layout is step-major [L][W]: one strided copy of the L rows'
+        // column range, then a transpose to walk-major on the host.
         std::vector<int32_t> tmp(total);
-        FELOG_HIP(hipMemcpyAsync(tmp.data(), w->data.ptr, sizeof(int32_t) * total,
-                                 hipMemcpyDeviceToHost, c->stream));
+        FELOG_HIP(hipMemcpy2DAsync(tmp.data(), sizeof(int32_t) * count,
+                                   w->data.as<int32_t>() + first, sizeof(int32_t) * w->W,
+                                   sizeof(int32_t) * count, w->L, hipMemcpyDeviceToHost,
+                                   c->stream));
         c->sync();
         for (int32_t t = 0; t < w->L; ++t)
-            for (int64_t col = 0; col < w->W; ++col) walks[col * w->L + t] = tmp[t * w->W + col];
+            for (int64_t col = 0; col < count; ++col)
+                walks[col * w->L + t] = tmp[t * count + col];
     });
+}
+
+felog_status felog_walks_read(const felog_walks* w, int32_t* walks, int64_t cap)
+{
+    if (!w) return felog_walks_read_range(w, 0, 0, walks, cap);
+    return felog_walks_read_range(w, 0, w->W, walks, cap);
 }
 
 felog_status felog_walks_capped(const felog_walks* w, int64_t* capped)

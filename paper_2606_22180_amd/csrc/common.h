@@ -70,9 +70,10 @@ struct Ctx {
     int32_t timing_every = 0;             // time every n-th training launch (0 = off)
     std::vector<hipEvent_t> timing_pool;  // 5 events per timed minibatch
     // second stream for the table-independent part of the next minibatch, and
-    // its events: [0] start, [1 + parity] ids ready, [3 + parity] buffers free
+    // its events: [0] start, [1 + parity] ids ready, [3 + parity] buffers free,
+    // [5] forward done
     hipStream_t aux = nullptr;
-    hipEvent_t pipe_ev[5] = {};
+    hipEvent_t pipe_ev[6] = {};
     void make_current() const;
     void sync() const;
     void ensure_aux();

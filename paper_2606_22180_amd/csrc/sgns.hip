@@ -828,12 +828,13 @@ static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& 
     FELOG_HIP(hipGetLastError());
 }
 
-// Forward, reductions and merge of one minibatch whose ids are ready.
-// ev (optional): [0] recorded before the forward, [1] after it, [2] at the end.
+// Forward and the two apply launches of one minibatch whose ids are ready.
+// ev (optional): [0] recorded before the forward, [1] after it, [2] at the end;
+// fwd_done (optional) is recorded after the forward.
 template <int D, int K>
 static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const MinibatchLaunch& ml,
                            uint32_t* meta, float* cap_in, float* cap_out, hipStream_t s,
-                           hipEvent_t* ev)
+                           hipEvent_t* ev, hipEvent_t fwd_done)
 {
     fa.touch_row = mb.touch_row.as<int32_t>();
     fa.touch_pos = mb.touch_pos.as<uint32_t>();
@@ -842,6 +843,7 @@ static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const Miniba
     if (ev) FELOG_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL((sgns_forward_kernel<D, K>), dim3(ml.fwd_blocks), dim3(256), 0, s, fa);
     if (ev) FELOG_HIP(hipEventRecord(ev[1], s));
+    if (fwd_done) FELOG_HIP(hipEventRecord(fwd_done, s));
     double* part_in = m.partial.as<double>();
     double* part_out = part_in + ml.split_in * D;
     ApplyArgs aa{m.tin.as<float>(),       m.tout.as<float>(),      fa.ent_out,
@@ -878,12 +880,12 @@ static void launch_ids(MinibatchBufs& mb, const PrepArgs& pa, const MinibatchLau
 template <int D>
 static void launch_train_d(Model& m, MinibatchBufs& mb, const FwdArgs& fa,
                            const MinibatchLaunch& ml, uint32_t* meta, float* ci, float* co,
-                           hipStream_t s, hipEvent_t* ev)
+                           hipStream_t s, hipEvent_t* ev, hipEvent_t fd)
 {
     switch (ml.K) {
-#define FELOG_CASE(k)                                                  \
-    case k:                                                            \
-        launch_train_t<D, k>(m, mb, fa, ml, meta, ci, co, s, ev);      \
+#define FELOG_CASE(k)                                                      \
+    case k:                                                                \
+        launch_train_t<D, k>(m, mb, fa, ml, meta, ci, co, s, ev, fd);      \
         break;
         FELOG_FOR_K(FELOG_CASE)
 #undef FELOG_CASE
@@ -893,11 +895,11 @@ static void launch_train_d(Model& m, MinibatchBufs& mb, const FwdArgs& fa,
 
 static void launch_train(Model& m, MinibatchBufs& mb, const FwdArgs& fa,
                          const MinibatchLaunch& ml, uint32_t* meta, float* ci, float* co,
-                         hipStream_t s, hipEvent_t* ev)
+                         hipStream_t s, hipEvent_t* ev, hipEvent_t fd = nullptr)
 {
-    if (ml.dim == 64) launch_train_d<64>(m, mb, fa, ml, meta, ci, co, s, ev);
-    else if (ml.dim == 128) launch_train_d<128>(m, mb, fa, ml, meta, ci, co, s, ev);
-    else launch_train_d<256>(m, mb, fa, ml, meta, ci, co, s, ev);
+    if (ml.dim == 64) launch_train_d<64>(m, mb, fa, ml, meta, ci, co, s, ev, fd);
+    else if (ml.dim == 128) launch_train_d<128>(m, mb, fa, ml, meta, ci, co, s, ev, fd);
+    else launch_train_d<256>(m, mb, fa, ml, meta, ci, co, s, ev, fd);
 }
 
 void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, int64_t first_mb,
@@ -930,8 +932,8 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         }
         // capture: deltas into dense zeroed tables, then the touched rows
         const int64_t cnt = (int64_t)m.g->n * m.dim;
-        FELOG_REQUIRE(cnt <= ((int64_t)1 << 28), "delta capture of a BF16 model is limited to "
-                      "n * d <= 2^28");
+        FELOG_REQUIRE(cnt <= ((int64_t)1 << 31), "delta capture of a BF16 model is limited to "
+                      "n * d <= 2^31");
         DevBuf din, dout;
         din.alloc(&c, sizeof(float) * cnt);
         dout.alloc(&c, sizeof(float) * cnt);
@@ -1124,15 +1126,20 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
             const MinibatchLaunch ml = mls[par];
             const float lr = lrs[par];
             hipEvent_t* e = slot_of[par];
-            if (b + 1 < end) issue_ids(b + 1);
             FELOG_HIP(hipStreamWaitEvent(c.stream, c.pipe_ev[1 + par], 0));
             FwdArgs f = fa;
             f.lr = lr;
             f.npairs = ml.npairs;
             launch_train(m, m.mb[par], f, ml, meta0 + kMetaWords * par, nullptr, nullptr,
-                         c.stream, e ? e + 2 : nullptr);
+                         c.stream, e ? e + 2 : nullptr, c.pipe_ev[5]);
             FELOG_HIP(hipEventRecord(c.pipe_ev[3 + par], c.stream));
             pairs_done += ml.npairs;
+            // the next minibatch's ids run beside this one's apply launches, not
+            // beside its forward, which they would slow down
+            if (b + 1 < end) {
+                FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[5], 0));
+                issue_ids(b + 1);
+            }
         }
     } else if (!apply) {
         // capture: the deltas of one minibatch, by touched-list position, not applied

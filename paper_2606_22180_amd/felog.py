@@ -124,6 +124,7 @@ SIGNATURES = {
     "felog_walks_generate": (_i32, [_p, C.POINTER(felog_walk_params), _p, _pp]),
     "felog_walks_info": (_i32, [_p, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i64)]),
     "felog_walks_read": (_i32, [_p, _p, _i64]),
+    "felog_walks_read_range": (_i32, [_p, _i64, _i64, _p, _i64]),
     "felog_walks_capped": (_i32, [_p, C.POINTER(_i64)]),
     "felog_walks_destroy": (None, [_p]),
     "felog_model_create": (_i32, [_p, C.POINTER(felog_model_params), _pp]),
@@ -307,6 +308,14 @@ class Walks(_Handle):
         out = np.zeros((max(W, 1), L), np.int32)
         _check(load().felog_walks_read(self.handle, out.ctypes.data, out.size))
         return out[:W]
+
+    def read_range(self, first: int, count: int) -> np.ndarray:
+        """Walks first .. first + count - 1, walk-major [count][L]."""
+        _, L, _ = self.info()
+        out = np.zeros((max(count, 1), L), np.int32)
+        _check(load().felog_walks_read_range(self.handle, first, count, out.ctypes.data,
+                                             out.size))
+        return out[:count]
 
     def capped(self) -> int:
         c = C.c_int64()

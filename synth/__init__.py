@@ -23,6 +23,7 @@ import dataclasses
 import math
 
 import numpy as np
+import pandas as pd
 
 __all__ = [
     "Graph", "sbm_edges", "rmat_edges", "csr_from_edges", "edge_weights",
@@ -115,11 +116,10 @@ def rmat_edges(scale: int, n_edges: int, a: float = 0.57, b: float = 0.19,
         keys_all.append(u * n + v)
         have += u.shape[0]
         if have >= n_edges:
-            keys = np.concatenate(keys_all)
-            uniq, first = np.unique(keys, return_index=True)
-            if uniq.shape[0] >= n_edges:
-                order = np.argsort(first, kind="stable")[:n_edges]
-                keys = uniq[order]
+            # distinct keys in order of first appearance (a hash pass)
+            keys = pd.unique(np.concatenate(keys_all))
+            if keys.shape[0] >= n_edges:
+                keys = keys[:n_edges]
                 break
             keys_all = [keys]
     u = keys // n
@@ -146,15 +146,19 @@ def csr_from_edges(n: int, edges: np.ndarray,
     src = np.concatenate([u, v])
     dst = np.concatenate([v, u])
     key = src * n + dst
-    order = np.argsort(key, kind="stable")
-    src = src[order]
-    dst = dst[order]
+    w = None
+    if weights is None:
+        key = np.sort(key)   # keys are distinct: no order among equals to keep
+        src = key // n
+        dst = key - src * n
+    else:
+        order = np.argsort(key)
+        src = src[order]
+        dst = dst[order]
+        w = np.concatenate([weights, weights])[order].astype(np.float32)
     counts = np.bincount(src, minlength=n)
     indptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=indptr[1:])
-    w = None
-    if weights is not None:
-        w = np.concatenate([weights, weights])[order].astype(np.float32)
     return Graph(n=n, indptr=indptr, indices=dst.astype(np.int32), weights=w)
 
 
@@ -186,8 +190,7 @@ def holdout_split(n: int, edges: np.ndarray, frac: float = 0.1, seed: int = 7,
         pos = np.minimum(pos, full_sorted.shape[0] - 1)
         ok = full_sorted[pos] != k
         k = k[ok]
-        _, first = np.unique(k, return_index=True)
-        k = k[np.sort(first)]
+        k = pd.unique(k)   # distinct, in order of first appearance
         k = k[~np.isin(k, seen)]
         seen = np.concatenate([seen, k])
         take = k[: n_test - neg.shape[0]]

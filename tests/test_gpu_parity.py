@@ -1,6 +1,9 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle.
 
-Integer work (walks, noise tables, active lists) must be bit-exact.  SGNS
+Every oracle input is the oracle's own (its walks, noise table and tables;
+teacher forcing writes the oracle's tables into the library, never the other
+way round).  Integer work (walks, noise tables, active lists) must be
+bit-exact.  SGNS
 deltas are FP32 sums in any order against the oracle's FP64; per updated row
   ||d_gpu - d_orc|| <= 1e-5 ||d_orc|| + 2^-20 ||m_orc||,
 where m_orc is the row's sum of |term| vectors (the natural scale of FP32
@@ -11,6 +14,7 @@ import numpy as np
 import pytest
 
 import synth
+from conftest import link_auc_of
 
 pytestmark = pytest.mark.gpu
 
@@ -116,7 +120,9 @@ def test_unigram_noise_table(fl, ctx, orc):
     W = fl.Walks.generate(G, r=4, L=30, seed=8)
     M = fl.Model.create(G, dim=128, neg_dist=fl.NEG_UNIGRAM, seed=1)
     M.set_unigram(W)
-    counts = orc.corpus_counts(W.read(), g.n)
+    ow = orc.walks_uniform(g, np.arange(g.n), 4, 30, 8)
+    assert np.array_equal(W.read(), ow)
+    counts = orc.corpus_counts(ow, g.n)
     assert np.array_equal(M.read_cdf(), orc.neg_cdf(counts))
 
 
@@ -156,21 +162,31 @@ def _check_delta(gpu, ref, mass, what):
 
 
 def _sgns_step_parity(fl, ctx, orc, g, *, dim, K, P, window, L, neg, mbs, seed=3, pre_mb=0):
+    """Teacher-forced per-step parity: the oracle runs from its own walks, noise
+    table and tables (trained by the oracle for pre_mb minibatches), and the
+    library gets the oracle's tables written in before every checked step."""
+    r = 10 if g.n < 5000 else 1
     G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
-    W = fl.Walks.generate(G, r=10 if g.n < 5000 else 1, L=L, seed=11)
+    W = fl.Walks.generate(G, r=r, L=L, seed=11)
     M = fl.Model.create(G, dim=dim, neg_dist=neg, seed=5)
+    walks = orc.walks_uniform(g, np.arange(g.n), r, L, 11)
+    assert np.array_equal(W.read(), walks)
     if neg == fl.NEG_UNIGRAM:
         M.set_unigram(W)
-    cdf = M.read_cdf()
+        cdf = orc.neg_cdf(orc.corpus_counts(walks, g.n))
+    else:
+        cdf = orc.neg_cdf(g.degrees().astype(np.uint64))
+    assert np.array_equal(M.read_cdf(), cdf)
     prm = fl.train_params(window=window, negatives=K, minibatch_pairs=P, seed=seed)
-    walks = W.read()
     B, _ = orc.count_minibatches(walks, window, P)
-    if pre_mb:
-        M.train_steps(W, prm, 0, pre_mb)          # move away from the initial state
+    tin, tout = orc.init_tables(g.n, dim, 5)
+    if pre_mb:                                    # move away from the initial state
+        orc.train_epoch(tin, tout, walks, window=window, K=K, lr0=prm.lr_start,
+                        lr_end=prm.lr_end, P=P, seed=seed, cdf=cdf, mb_end=pre_mb)
     for b in mbs:
         b = b % B
-        tin = M.read(fl.TABLE_IN)
-        tout = M.read(fl.TABLE_OUT)
+        M.write(fl.TABLE_IN, tin)
+        M.write(fl.TABLE_OUT, tout)
         ri, di, ro, do, loss = M.train_delta(W, prm, b)
         mb = orc.minibatch_pairs(walks, window, P, b)
         ng = orc.draw_negatives(mb, 0, K, seed, cdf)
@@ -184,8 +200,8 @@ def _sgns_step_parity(fl, ctx, orc, g, *, dim, K, P, window, L, neg, mbs, seed=3
         _check_delta(_dense(ro, do, g.n, dim), _dense(ref.rows_out, ref.d_out, g.n, dim), aout,
                      "mb %d out" % b)
         assert abs(loss - ref.loss) <= 1e-5 * abs(ref.loss)
-        # advance the GPU state by this minibatch so the next check starts elsewhere
-        M.train_steps(W, prm, b, 1)
+        # the oracle applies its own step, so the next check starts elsewhere
+        orc.sgns_step(tin, tout, mb.ctx, mb.ctr, ng, lr, apply=True)
     return M
 
 
@@ -241,10 +257,12 @@ def test_sgns_epoch_auc_matches_oracle(fl, ctx, orc, sbm):
     prm = fl.train_params(window=5, negatives=5, minibatch_pairs=1024, seed=3)
     st = M.train_epoch(W, prm)
     tin, tout = orc.init_tables(g.n, 64, 0)
-    ref = orc.train_epoch(tin, tout, W.read(), window=5, K=5, lr0=prm.lr_start,
+    ow = orc.walks_uniform(g, np.arange(g.n), 10, 40, 11)
+    assert np.array_equal(W.read(), ow)
+    ref = orc.train_epoch(tin, tout, ow, window=5, K=5, lr0=prm.lr_start,
                           lr_end=prm.lr_end, P=1024, seed=3,
                           cdf=orc.neg_cdf(g.degrees().astype(np.uint64)))
-    a_gpu = orc.link_auc(M.read(fl.TABLE_IN), sbm)
+    a_gpu = link_auc_of(M.read(fl.TABLE_IN), sbm)
     a_orc = orc.link_auc(tin, sbm)
     _say("AUC gpu=%.5f oracle=%.5f loss gpu=%.6e oracle=%.6e" % (a_gpu, a_orc, st.loss,
                                                                  ref.loss))
@@ -311,7 +329,7 @@ def test_run_algorithm1_matches_oracle(fl, ctx, orc, sbm):
         if gpu_act[r] == orc_act[r]:
             assert st.train[r].pairs == ostats[r].pairs
             assert abs(st.train[r].loss - ostats[r].loss) <= 1e-3 * ostats[r].loss
-    a_gpu = orc.link_auc(M.read(fl.TABLE_IN), sbm)
+    a_gpu = link_auc_of(M.read(fl.TABLE_IN), sbm)
     a_orc = orc.link_auc(tin, sbm)
     _say("AUC gpu=%.5f oracle=%.5f" % (a_gpu, a_orc))
     assert abs(a_gpu - a_orc) <= 0.005

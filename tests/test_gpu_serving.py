@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from conftest import link_auc_of
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +52,7 @@ def test_serving_job_matches_oracle(fl, orc):
     ref = orc.train_epoch(tin, tout, walks, window=5, K=5, lr0=float(np.float32(0.025)),
                           lr_end=float(np.float32(1e-4)), P=1024, seed=21,
                           cdf=orc.neg_cdf(g.degrees().astype(np.uint64)))
-    a_gpu, a_orc = orc.link_auc(emb, sp), orc.link_auc(tin, sp)
+    a_gpu, a_orc = link_auc_of(emb, sp), orc.link_auc(tin, sp)
     _say("AUC serving=%.5f oracle=%.5f pairs %d/%d latency %.3f s" % (
         a_gpu, a_orc, st.pairs, ref.pairs, st.t_done - st.t_arrive))
     assert st.state == fl.JOB_DONE and st.pairs == ref.pairs and st.minibatch_pairs == 1024
