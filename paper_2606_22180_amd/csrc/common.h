@@ -59,6 +59,8 @@ struct DevBuf {
     template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
 
+constexpr int kIdSets = 3;   // minibatch id buffer sets: ids run kIdSets - 1 minibatches ahead
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -69,11 +71,11 @@ struct Ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t timing_every = 0;             // time every n-th training launch (0 = off)
     std::vector<hipEvent_t> timing_pool;  // 5 events per timed minibatch
-    // second stream for the table-independent part of the next minibatch, and
-    // its events: [0] start, [1 + parity] ids ready, [3 + parity] buffers free,
-    // [5] forward done
+    // second stream for the table-independent part of later minibatches, and
+    // its events: [0] start, [1 + set] ids ready, [1 + kIdSets + set] buffers
+    // free, [1 + 2 kIdSets] forward done
     hipStream_t aux = nullptr;
-    hipEvent_t pipe_ev[6] = {};
+    hipEvent_t pipe_ev[2 + 2 * kIdSets] = {};
     void make_current() const;
     void sync() const;
     void ensure_aux();
@@ -114,8 +116,8 @@ struct Walks {
     int64_t chunk_for_valid = 0;
 };
 
-// Buffers of one minibatch's ids and destination sort; two sets let the next
-// minibatch's ids be computed while the current one trains.
+// Buffers of one minibatch's ids and destination sort; kIdSets sets let the
+// ids of the next kIdSets - 1 minibatches be computed while one trains.
 struct MinibatchBufs {
     DevBuf cnt_in, cnt_out;       // uint32 [n]: touches of each row (0 between minibatches)
     DevBuf off_in, off_out;       // int32 [n]: first entry of each touched row's segment
@@ -144,13 +146,13 @@ struct Model {
     // minibatch scratch, sized for the largest (pairs, negatives) seen
     int64_t cap_pairs = 0;
     int32_t cap_K = 0;
-    MinibatchBufs mb[2];          // by minibatch parity: ids and sort of one minibatch
+    MinibatchBufs mb[kIdSets];    // by minibatch index mod kIdSets: ids and sort of one minibatch
     DevBuf ent_out;               // int2 [P(K+1)]: (g, ctx) of each out-touch, by row segment
     DevBuf key_in, key_out;       // uint32: pair-order key of each segment position
     DevBuf dinp;                  // float [P][d]: sum_k g_k out[t_k] of each pair, by row segment
     DevBuf partial;               // double [chunks of split rows][d]: each chunk's exact sums
     int64_t split_rows_in = 0;    // partial rows reserved for the in-table; the out-table's follow
-    DevBuf meta;                  // uint32 [2][16]: list lengths and cursors, by minibatch parity
+    DevBuf meta;                  // uint32 [kIdSets][16]: list lengths and counts, by id set
     DevBuf loss_out;              // double [1]
     DevBuf row_totals;            // uint64 [2]: summed touched-list lengths (in, out)
     // shared-negative (BF16) minibatch scratch

@@ -86,15 +86,15 @@ static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_param
     while (pow2 < n) pow2 <<= 1;
     uint64_t b = 0;
     b += 8 * (n + 1) + 4 * nnz + 4 * n + 16;                     // CSR, row maxima, check word
-    b += 8 * n * dim + 16 * n + 4 * 32 + 16 + 16;                // tables, counters, offsets
+    b += 8 * n * dim + 16 * n + 4 * 16 * kIdSets + 16 + 16;      // tables, counters, offsets
     b += 4 * n + 8 * n + 8 * (n / 2048 + 2) + 8 * (n + 1) + 4 * std::max<uint64_t>(pow2, 2);
     b += 4 * W * L + 4 * W + 4 * (W / 2048 + 2) + 8 * (W / (1u << 20) + 2);   // walks
     const uint64_t T = P * (K + 2);                              // touches per minibatch
     const uint64_t sc = P / 8 + 1 + P * (K + 1) / 8 + 1;         // chunks of split rows
     const uint64_t sr = P / 17 + 1 + P * (K + 1) / 17 + 1;       // split rows
     const uint64_t nbs = P / 2048 + 1 + P * (K + 1) / 2048 + 1;  // scan blocks
-    b += 16 * n;                                                 // second set of counters, offsets
-    b += 2 * (8 * T + 4 * T + 16 * T + 16 * sc + 16 * sr + 24 * nbs);   // two id/sort sets
+    b += 16 * n * (kIdSets - 1);                                 // more sets of counters, offsets
+    b += kIdSets * (8 * T + 4 * T + 16 * T + 16 * sc + 16 * sr + 24 * nbs);   // id/sort sets
     b += 8 * P * (K + 1) + 4 * T + 4 * P * dim + 8 * sc * dim;   // outputs, keys, split sums
     b += 8 * (P + 4) + 4 * L * 2 * (uint64_t)d.window;           // loss slots, slices
     b += 64 * 16;                                                // small allocations of 16 B

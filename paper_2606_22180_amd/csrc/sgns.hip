@@ -782,7 +782,7 @@ void model_alloc_update_state(Model& m)
         FELOG_HIP(hipMemsetAsync(b.cnt_in.ptr, 0, sizeof(uint32_t) * n, c.stream));
         FELOG_HIP(hipMemsetAsync(b.cnt_out.ptr, 0, sizeof(uint32_t) * n, c.stream));
     }
-    m.meta.alloc(&c, sizeof(uint32_t) * 2 * kMetaWords);
+    m.meta.alloc(&c, sizeof(uint32_t) * kIdSets * kMetaWords);
     m.row_totals.alloc(&c, sizeof(uint64_t) * 2);
     m.loss_out.alloc(&c, sizeof(double));
     FELOG_HIP(hipMemsetAsync(m.meta.ptr, 0, m.meta.bytes, c.stream));
@@ -1087,7 +1087,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         ms_apply += ap;
         ++timed;
     };
-    hipEvent_t* slot_of[2] = {nullptr, nullptr};   // timing events of the minibatch of each parity
+    hipEvent_t* slot_of[kIdSets] = {};   // timing events of the minibatch of each id set
     auto take_slot = [&](int64_t b) -> hipEvent_t* {
         if (!(every > 0 && pool > 0 && (b - first_mb) % every == 0)) return nullptr;
         if (used_slots == pool) harvest(next_slot);   // reuse the oldest slot
@@ -1105,46 +1105,50 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         hipStream_t ids_s = c.aux;
         FELOG_HIP(hipEventRecord(c.pipe_ev[0], c.stream));
         FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[0], 0));
-        MinibatchLaunch mls[2];
-        float lrs[2];
+        MinibatchLaunch mls[kIdSets];
+        float lrs[kIdSets];
+        hipEvent_t* ready = c.pipe_ev + 1;               // [set] ids ready
+        hipEvent_t* freed = c.pipe_ev + 1 + kIdSets;     // [set] buffers free
+        hipEvent_t fwd_done = c.pipe_ev[1 + 2 * kIdSets];
         auto issue_ids = [&](int64_t b) {
-            const int par = (int)(b & 1);
+            const int set = (int)(b % kIdSets);
             PrepArgs a = pa;
-            lrs[par] = frame(b, mls[par], a);
-            if (b >= first_mb + 2)   // the buffers' previous minibatch must be done with them
-                FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[3 + par], 0));
+            lrs[set] = frame(b, mls[set], a);
+            if (b >= first_mb + kIdSets)   // the set's previous minibatch must be done with it
+                FELOG_HIP(hipStreamWaitEvent(ids_s, freed[set], 0));
             hipEvent_t* e = take_slot(b);
-            slot_of[par] = e;
+            slot_of[set] = e;
             if (e) FELOG_HIP(hipEventRecord(e[0], ids_s));
-            launch_ids(m.mb[par], a, mls[par], meta0 + kMetaWords * par, ids_s);
+            launch_ids(m.mb[set], a, mls[set], meta0 + kMetaWords * set, ids_s);
             if (e) FELOG_HIP(hipEventRecord(e[1], ids_s));
-            FELOG_HIP(hipEventRecord(c.pipe_ev[1 + par], ids_s));
+            FELOG_HIP(hipEventRecord(ready[set], ids_s));
         };
-        issue_ids(first_mb);
+        const int64_t ahead = kIdSets - 1;
+        for (int64_t k = 0; k < ahead && first_mb + k < end; ++k) issue_ids(first_mb + k);
         for (int64_t b = first_mb; b < end; ++b) {
-            const int par = (int)(b & 1);
-            const MinibatchLaunch ml = mls[par];
-            const float lr = lrs[par];
-            hipEvent_t* e = slot_of[par];
-            FELOG_HIP(hipStreamWaitEvent(c.stream, c.pipe_ev[1 + par], 0));
+            const int set = (int)(b % kIdSets);
+            const MinibatchLaunch ml = mls[set];
+            const float lr = lrs[set];
+            hipEvent_t* e = slot_of[set];
+            FELOG_HIP(hipStreamWaitEvent(c.stream, ready[set], 0));
             FwdArgs f = fa;
             f.lr = lr;
             f.npairs = ml.npairs;
-            launch_train(m, m.mb[par], f, ml, meta0 + kMetaWords * par, nullptr, nullptr,
-                         c.stream, e ? e + 2 : nullptr, c.pipe_ev[5]);
-            FELOG_HIP(hipEventRecord(c.pipe_ev[3 + par], c.stream));
+            launch_train(m, m.mb[set], f, ml, meta0 + kMetaWords * set, nullptr, nullptr,
+                         c.stream, e ? e + 2 : nullptr, fwd_done);
+            FELOG_HIP(hipEventRecord(freed[set], c.stream));
             pairs_done += ml.npairs;
-            // the next minibatch's ids run beside this one's apply launches, not
-            // beside its forward, which they would slow down
-            if (b + 1 < end) {
-                FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[5], 0));
-                issue_ids(b + 1);
+            // later minibatches' ids run beside this one's apply launches and the
+            // next forward, not beside this forward
+            if (b + ahead < end) {
+                FELOG_HIP(hipStreamWaitEvent(ids_s, fwd_done, 0));
+                issue_ids(b + ahead);
             }
         }
     } else if (!apply) {
         // capture: the deltas of one minibatch, by touched-list position, not applied
         const int64_t b = first_mb;
-        const int par = (int)(b & 1);
+        const int par = (int)(b % kIdSets);
         MinibatchLaunch ml;
         PrepArgs a = pa;
         const float lr = frame(b, ml, a);
