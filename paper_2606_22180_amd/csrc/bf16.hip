@@ -15,8 +15,9 @@
 //
 // Kernels per minibatch: gather (rows, transposed copies, positive terms),
 // scores (S and G on 64x64 tiles, 4 waves of 32x32), grads (dC and dN on
-// 32x32 tiles, one wave each, K = M or P), apply (FP32 atomics on masters;
-// rows repeat only when a node is drawn twice), refresh.
+// 32x32 tiles, the shared dimension M or P split over a block's 4 waves),
+// apply (FP32 atomics on masters; rows repeat only when a node is drawn
+// twice), refresh.
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds 8 consecutive k of row
 // (l mod 16) of A and of column (l mod 16) of B, k chunk l / 16; it receives
 // D[4 (l / 16) + j][l mod 16], j = 0..3.
@@ -98,9 +99,10 @@ __device__ __forceinline__ float wave_sum32(float x)
     return x;
 }
 
-__device__ __forceinline__ double softplus_d(double x)   // log(1 + exp(x))
+// log(1 + exp(x)) in FP32, without overflow; the loss sums these terms in FP64.
+__device__ __forceinline__ float softplus_f(float x)
 {
-    return fmax(x, 0.0) + log1p(exp(-fabs(x)));
+    return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
 }
 
 // One wave per row: waves [0, P) pairs, [P, P + M) negatives.
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
             float g = 0.0f;
             if (ctx >= 0) {
                 g = a.lr * (1.0f - 1.0f / (1.0f + expf(-dot)));
-                a.loss_part[w] += softplus_d(-(double)dot);      // -log sigma(s0)
+                a.loss_part[w] += (double)softplus_f(-dot);       // -log sigma(s0)
             }
             a.g0[p] = g;
         }
@@ -187,26 +189,38 @@ __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
     const float wk = -a.lr * (float)a.K / (float)a.M;
     const double lw = (double)a.K / (double)a.M;
     double lacc = 0.0;
+    int32_t ctr[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t row = r0 + 16 * i + 4 * lk + q;
+            ctr[i][q] = row < a.np ? a.ids[a.P + row] : -2;   // -2: no pair in this row
+        }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const uint32_t n = c0 + 16 * j + li;
         const int32_t neg = a.ids[2 * a.P + n];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
+            uint32_t gb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t row = r0 + 16 * i + 4 * lk + q;
                 const float s = acc[i][j][q];
-                const bool keep = row < a.np && a.ids[a.P + row] != neg;
+                const bool keep = ctr[i][q] != -2 && ctr[i][q] != neg;
                 float g = 0.0f;
                 if (keep) {
                     g = wk / (1.0f + expf(-s));
-                    lacc += lw * softplus_d((double)s);           // -(K/M) log sigma(-s)
+                    lacc += lw * (double)softplus_f(s);           // -(K/M) log sigma(-s)
                 }
-                const uint16_t gb = bf16_rne(g);
-                a.G[(int64_t)row * a.M + n] = gb;
-                a.Gt[(int64_t)n * a.P + row] = gb;
+                gb[q] = bf16_rne(g);
+                a.G[(int64_t)row * a.M + n] = (uint16_t)gb[q];
             }
+            // rows 4 lk .. 4 lk + 3 of column n are consecutive in G^T
+            *reinterpret_cast<uint2*>(a.Gt + (int64_t)n * a.P + r0 + 16 * i + 4 * lk) =
+                make_uint2(gb[0] | (gb[1] << 16), gb[2] | (gb[3] << 16));
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lacc += __shfl_xor(lacc, off);
@@ -216,27 +230,34 @@ __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
     }
 }
 
-// dC = G N (tiles [0, P/32 * d/32)) and dN = G^T C (the rest), one wave per 32x32 tile.
+// dC = G N (tiles [0, P/32 * d/32)) and dN = G^T C (the rest): one block per
+// 32x32 output tile.  Its four waves take four contiguous parts of the shared
+// dimension (M or P), and their sums are added in wave order through LDS.
 __global__ __launch_bounds__(256) void bf16_grads_kernel(Bf16Args a)
 {
+    __shared__ float part[3][2][2][4][64];   // waves 1..3: acc[i][j][q] by lane
     const int lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const uint32_t t = blockIdx.x;
     const uint32_t te = a.d / 32;
-    const uint32_t tiles_c = (a.P / 32) * te, tiles_n = (a.M / 32) * te;
-    if (t >= tiles_c + tiles_n) return;
+    const uint32_t tiles_c = (a.P / 32) * te;
     const bool isC = t < tiles_c;
     const uint32_t tt = isC ? t : t - tiles_c;
     const uint32_t r0 = (tt / te) * 32, e0 = (tt % te) * 32;
     const uint16_t* A = isC ? a.G : a.Gt;       // rows r, k over the shared dimension
     const uint16_t* B = isC ? a.Nt : a.Ct;      // rows e, k over the shared dimension
     const uint32_t kdim = isC ? a.M : a.P;
+    const uint32_t steps = kdim / 32;
+    const uint32_t s0 = steps * wv / 4, s1 = steps * (wv + 1) / 4;
     const int li = lane & 15, lk = lane >> 4;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t k0 = 0; k0 < kdim; k0 += 32) {
+#pragma unroll 4
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint32_t k0 = s * 32;
         bf16x8 fa[2], fb[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -249,14 +270,29 @@ __global__ __launch_bounds__(256) void bf16_grads_kernel(Bf16Args a)
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
+    if (wv > 0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) part[wv - 1][i][j][q][lane] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (wv != 0) return;
     float* out = isC ? a.dC : a.dN;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                out[(int64_t)(r0 + 16 * i + 4 * lk + q) * a.d + e0 + 16 * j + li] = acc[i][j][q];
+            for (int q = 0; q < 4; ++q) {
+                float v = acc[i][j][q];
+                v += part[0][i][j][q][lane];
+                v += part[1][i][j][q][lane];
+                v += part[2][i][j][q][lane];
+                out[(int64_t)(r0 + 16 * i + 4 * lk + q) * a.d + e0 + 16 * j + li] = v;
+            }
 }
 
 // FP32 master updates (or captured deltas), one wave per pair / negative.
@@ -412,7 +448,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
     const uint32_t row_blocks = (P + M + 3) / 4;
     const uint32_t te = d / 32;
-    const uint32_t grad_blocks = ((P / 32) * te + (M / 32) * te + 3) / 4;
+    const uint32_t grad_blocks = (P / 32) * te + (M / 32) * te;
     int64_t pairs_done = 0;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     size_t chunk = 0;
