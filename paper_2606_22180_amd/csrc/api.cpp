@@ -482,7 +482,6 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
             m->bout.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
         }
         launch_init_tables(*m, p->seed);
-        bf16_refresh_all(*m);
         if (p->neg_dist == FELOG_NEG_DEGREE) {
             DevBuf counts;
             counts.alloc(c, sizeof(uint32_t) * g->n);
@@ -502,7 +501,6 @@ felog_status felog_model_reset(felog_model* m, uint64_t seed)
     return guarded([&] {
         NEED(m);
         launch_init_tables(*m, seed);
-        bf16_refresh_all(*m);
         if (m->neg_dist == FELOG_NEG_UNIGRAM) m->have_noise = false;
         m->ctx->sync();
     });
@@ -585,7 +583,6 @@ felog_status felog_embeddings_write(felog_model* m, int32_t which, const float* 
                       (long long)m->g->n * m->dim);
         FELOG_HIP(hipMemcpyAsync(t.ptr, host, sizeof(float) * count, hipMemcpyHostToDevice,
                                  m->ctx->stream));
-        bf16_refresh_all(*m);
         m->ctx->sync();
     });
 }
@@ -602,6 +599,7 @@ felog_status felog_embeddings_read_bf16(const felog_model* m, int32_t which, uin
         int64_t count = (int64_t)m->g->n * m->dim;
         FELOG_REQUIRE(cap >= count, "buffer holds %lld values, need %lld", (long long)cap,
                       (long long)count);
+        bf16_refresh_all(*const_cast<felog_model*>(m));   // round the masters as they stand
         FELOG_HIP(hipMemcpyAsync(host, (which == FELOG_TABLE_IN ? m->bin : m->bout).ptr,
                                  sizeof(uint16_t) * count, hipMemcpyDeviceToHost, m->ctx->stream));
         m->ctx->sync();

@@ -8,16 +8,17 @@
 //   G  = bf16(-lr (K/M) sigma(S) o mask),  mask = [neg != ctr] (and real pairs)
 //   dC = G N,  dN = G^T C            (MFMA, FP32 accumulation)
 //   g0 = lr (1 - sigma(C.O)) row-wise (FP32 dot of the BF16 rows)
-//   in[ctx] += dC + g0 O,  out[neg] += dN,  out[ctr] += g0 C   on FP32 masters,
-// then the BF16 copies of every touched row are refreshed from the masters
-// (round to nearest even).  Each (pair, negative) term weighs K/M, so the
-// expected update equals Eq. (2) with K negatives per pair.
+//   in[ctx] += dC + g0 O,  out[neg] += dN,  out[ctr] += g0 C   on FP32 masters.
+// The BF16 rows are the masters rounded to nearest even as they stand at the
+// minibatch's start; the gather rounds them as it reads them, so no BF16
+// copy of the tables has to be kept current.  Each (pair, negative) term
+// weighs K/M, so the expected update equals Eq. (2) with K negatives per pair.
 //
 // Kernels per minibatch: gather (rows, transposed copies, positive terms),
 // scores (S and G on 64x64 tiles, 4 waves of 32x32), grads (dC and dN on
-// 32x32 tiles, the shared dimension M or P split over a block's 4 waves),
-// apply (FP32 atomics on masters; rows repeat only when a node is drawn
-// twice), refresh.
+// 32x32 tiles, the shared dimension M or P split over a block's 4 waves,
+// added to the masters with FP32 atomics; rows repeat only when a node is
+// drawn twice or is both a centre and a negative).
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds 8 consecutive k of row
 // (l mod 16) of A and of column (l mod 16) of B, k chunk l / 16; it receives
 // D[4 (l / 16) + j][l mod 16], j = 0..3.
@@ -55,8 +56,6 @@ struct Bf16Args {
     // tables
     float* tin;
     float* tout;
-    uint16_t* bin;
-    uint16_t* bout;
     int32_t d;
     // pair order (as the FP32 path)
     const int32_t* walks;
@@ -85,8 +84,6 @@ struct Bf16Args {
     uint16_t* G;          // [P][M]
     uint16_t* Gt;         // [M][P]
     float* g0;            // [P]
-    float* dC;            // [P][d]
-    float* dN;            // [M][d]
     double* loss_part;    // [P + M] gather slots, then one per scores wave
     float* cap_in;        // capture (dense [n][d]) instead of updating masters
     float* cap_out;
@@ -127,8 +124,8 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
         }
         float dot = 0.0f;
         for (int e = lane; e < a.d; e += 64) {
-            uint16_t c = ctx >= 0 ? a.bin[(int64_t)ctx * a.d + e] : 0;
-            uint16_t o = ctr >= 0 ? a.bout[(int64_t)ctr * a.d + e] : 0;
+            uint16_t c = ctx >= 0 ? bf16_rne(a.tin[(int64_t)ctx * a.d + e]) : 0;
+            uint16_t o = ctr >= 0 ? bf16_rne(a.tout[(int64_t)ctr * a.d + e]) : 0;
             a.C[(int64_t)p * a.d + e] = c;
             a.O[(int64_t)p * a.d + e] = o;
             a.Ct[(int64_t)e * a.P + p] = c;
@@ -152,7 +149,7 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
         uint32_t hi = (m & 1) ? r.v[3] : r.v[1];
         const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
         for (int e = lane; e < a.d; e += 64) {
-            uint16_t x = a.bout[(int64_t)neg * a.d + e];
+            uint16_t x = bf16_rne(a.tout[(int64_t)neg * a.d + e]);
             a.N[(int64_t)m * a.d + e] = x;
             a.Nt[(int64_t)e * a.M + m] = x;
         }
@@ -161,34 +158,25 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
 }
 
 // S and G on a 64x64 tile per block; wave w computes rows 32 (w / 2), cols 32 (w % 2).
+// The d / 32 steps are unrolled, so every operand load (and the ids the
+// epilogue needs) is in flight before the first MFMA waits.
+template <int D>
 __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
 {
+    constexpr int S = D / 32;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const uint32_t r0 = blockIdx.x * 64 + (wv >> 1) * 32;
     const uint32_t c0 = blockIdx.y * 64 + (wv & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    f32x4 acc[2][2];
+    bf16x8 fa[S][2], fb[S][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < a.d; k0 += 32) {
-        bf16x8 fa[2], fb[2];
+    for (int k = 0; k < S; ++k)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            fa[i] = load8(a.C + (int64_t)(r0 + 16 * i + li) * a.d + k0 + 8 * lk);
-            fb[i] = load8(a.N + (int64_t)(c0 + 16 * i + li) * a.d + k0 + 8 * lk);
+            fa[k][i] = load8(a.C + (int64_t)(r0 + 16 * i + li) * D + 32 * k + 8 * lk);
+            fb[k][i] = load8(a.N + (int64_t)(c0 + 16 * i + li) * D + 32 * k + 8 * lk);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-    }
-    const float wk = -a.lr * (float)a.K / (float)a.M;
-    const double lw = (double)a.K / (double)a.M;
-    double lacc = 0.0;
     int32_t ctr[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -197,10 +185,28 @@ __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
             const uint32_t row = r0 + 16 * i + 4 * lk + q;
             ctr[i][q] = row < a.np ? a.ids[a.P + row] : -2;   // -2: no pair in this row
         }
+    int32_t negs[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) negs[j] = a.ids[2 * a.P + c0 + 16 * j + li];
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[k][i], fb[k][j], acc[i][j], 0, 0, 0);
+    const float wk = -a.lr * (float)a.K / (float)a.M;
+    const double lw = (double)a.K / (double)a.M;
+    double lacc = 0.0;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const uint32_t n = c0 + 16 * j + li;
-        const int32_t neg = a.ids[2 * a.P + n];
+        const int32_t neg = negs[j];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             uint32_t gb[4];
@@ -230,12 +236,18 @@ __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
     }
 }
 
-// dC = G N (tiles [0, P/32 * d/32)) and dN = G^T C (the rest): one block per
-// 32x32 output tile.  Its four waves take four contiguous parts of the shared
-// dimension (M or P), and their sums are added in wave order through LDS.
-__global__ __launch_bounds__(256) void bf16_grads_kernel(Bf16Args a)
+// dC = G N (tiles [0, P/32 * d/32)) and dN = G^T C (the rest): one block of
+// kGradWaves waves per 32x32 output tile.  The waves take contiguous parts of
+// the shared dimension (M or P), loading up to kGradBatch steps of operands
+// before their MFMAs; the parts meet in LDS and every thread adds two
+// elements' parts in wave order and applies them: in[ctx] += dC + g0 O and
+// out[ctr] += g0 C for a pair's row, out[neg] += dN for a negative's, with
+// FP32 atomics on the masters (or the capture tables).
+constexpr int kGradWaves = 8, kGradBatch = 4;
+
+__global__ __launch_bounds__(64 * kGradWaves) void bf16_grads_kernel(Bf16Args a)
 {
-    __shared__ float part[3][2][2][4][64];   // waves 1..3: acc[i][j][q] by lane
+    __shared__ float part[kGradWaves][32][33];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const uint32_t t = blockIdx.x;
@@ -248,107 +260,75 @@ __global__ __launch_bounds__(256) void bf16_grads_kernel(Bf16Args a)
     const uint16_t* B = isC ? a.Nt : a.Ct;      // rows e, k over the shared dimension
     const uint32_t kdim = isC ? a.M : a.P;
     const uint32_t steps = kdim / 32;
-    const uint32_t s0 = steps * wv / 4, s1 = steps * (wv + 1) / 4;
+    const uint32_t s0 = steps * wv / kGradWaves, s1 = steps * (wv + 1) / kGradWaves;
     const int li = lane & 15, lk = lane >> 4;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t k0 = s * 32;
-        bf16x8 fa[2], fb[2];
+    for (uint32_t sb = s0; sb < s1; sb += kGradBatch) {
+        bf16x8 fa[kGradBatch][2], fb[kGradBatch][2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            fa[i] = load8(A + (int64_t)(r0 + 16 * i + li) * kdim + k0 + 8 * lk);
-            fb[i] = load8(B + (int64_t)(e0 + 16 * i + li) * kdim + k0 + 8 * lk);
+        for (int u = 0; u < kGradBatch; ++u) {
+            const uint32_t k0 = min(sb + u, s1 - 1) * 32;   // past the end: reloads the last step
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                fa[u][i] = load8(A + (int64_t)(r0 + 16 * i + li) * kdim + k0 + 8 * lk);
+                fb[u][i] = load8(B + (int64_t)(e0 + 16 * i + li) * kdim + k0 + 8 * lk);
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int u = 0; u < kGradBatch; ++u) {
+            if (sb + u >= s1) break;
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[u][i], fb[u][j],
+                                                                        acc[i][j], 0, 0, 0);
+        }
     }
-    if (wv > 0) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) part[wv - 1][i][j][q][lane] = acc[i][j][q];
-    }
-    __syncthreads();
-    if (wv != 0) return;
-    float* out = isC ? a.dC : a.dN;
+    // acc[i][j][q] is element (16 i + 4 lk + q, 16 j + li) of the tile
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float v = acc[i][j][q];
-                v += part[0][i][j][q][lane];
-                v += part[1][i][j][q][lane];
-                v += part[2][i][j][q][lane];
-                out[(int64_t)(r0 + 16 * i + 4 * lk + q) * a.d + e0 + 16 * j + li] = v;
-            }
-}
-
-// FP32 master updates (or captured deltas), one wave per pair / negative.
-__global__ __launch_bounds__(256) void bf16_apply_kernel(Bf16Args a)
-{
-    const int lane = threadIdx.x & 63;
-    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= a.P + a.M) return;
+            for (int q = 0; q < 4; ++q) part[wv][16 * i + 4 * lk + q][16 * j + li] = acc[i][j][q];
+    __syncthreads();
+    const int row = threadIdx.x >> 4;            // 32 rows of 16 threads, two elements each
+    const int col = (threadIdx.x & 15) * 2;
+    float v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float x = part[0][row][col + h];
+#pragma unroll
+        for (int w = 1; w < kGradWaves; ++w) x += part[w][row][col + h];
+        v[h] = x;
+    }
     float* tin = a.cap_in ? a.cap_in : a.tin;
     float* tout = a.cap_out ? a.cap_out : a.tout;
-    if (w < a.P) {
-        const int32_t ctx = a.ids[w], ctr = a.ids[a.P + w];
-        if (ctx < 0) return;
-        const float g = a.g0[w];
-        for (int e = lane; e < a.d; e += 64) {
-            const float o = bf16_to_f32(a.O[(int64_t)w * a.d + e]);
-            const float c = bf16_to_f32(a.C[(int64_t)w * a.d + e]);
-            unsafeAtomicAdd(&tin[(int64_t)ctx * a.d + e], a.dC[(int64_t)w * a.d + e] + g * o);
-            unsafeAtomicAdd(&tout[(int64_t)ctr * a.d + e], g * c);
+    const uint32_t r = r0 + row, e = e0 + col;
+    if (isC) {
+        const int32_t ctx = a.ids[r];
+        if (ctx < 0) return;                    // no pair in this row
+        const int32_t ctr = a.ids[a.P + r];
+        const float g = a.g0[r];
+        const uint32_t o2 = *reinterpret_cast<const uint32_t*>(a.O + (int64_t)r * a.d + e);
+        const uint32_t c2 = *reinterpret_cast<const uint32_t*>(a.C + (int64_t)r * a.d + e);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float o = bf16_to_f32((uint16_t)(o2 >> (16 * h)));
+            const float c = bf16_to_f32((uint16_t)(c2 >> (16 * h)));
+            unsafeAtomicAdd(&tin[(int64_t)ctx * a.d + e + h], v[h] + g * o);
+            unsafeAtomicAdd(&tout[(int64_t)ctr * a.d + e + h], g * c);
         }
     } else {
-        const uint32_t m = w - a.P;
-        const int32_t neg = a.ids[2 * a.P + m];
-        for (int e = lane; e < a.d; e += 64)
-            unsafeAtomicAdd(&tout[(int64_t)neg * a.d + e], a.dN[(int64_t)m * a.d + e]);
+        const int32_t neg = a.ids[2 * a.P + r];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) unsafeAtomicAdd(&tout[(int64_t)neg * a.d + e + h], v[h]);
     }
-}
-
-// BF16 copies of the touched rows from their masters.
-__global__ __launch_bounds__(256) void bf16_refresh_kernel(Bf16Args a)
-{
-    const int lane = threadIdx.x & 63;
-    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= a.P + a.M) return;
-    int32_t rows[2];
-    const float* src[2];
-    uint16_t* dst[2];
-    int nr = 0;
-    if (w < a.P) {
-        if (a.ids[w] < 0) return;
-        rows[0] = a.ids[w];
-        src[0] = a.tin;
-        dst[0] = a.bin;
-        rows[1] = a.ids[a.P + w];
-        src[1] = a.tout;
-        dst[1] = a.bout;
-        nr = 2;
-    } else {
-        rows[0] = a.ids[2 * a.P + (w - a.P)];
-        src[0] = a.tout;
-        dst[0] = a.bout;
-        nr = 1;
-    }
-    for (int r = 0; r < nr; ++r)
-        for (int e = lane; e < a.d; e += 64)
-            dst[r][(int64_t)rows[r] * a.d + e] = bf16_rne(src[r][(int64_t)rows[r] * a.d + e]);
 }
 
 __global__ void bf16_from_master_kernel(const float* src, uint16_t* dst, int64_t count)
@@ -405,8 +385,6 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         m.bf_G.alloc(&c, sizeof(uint16_t) * cp * cm);
         m.bf_Gt.alloc(&c, sizeof(uint16_t) * cp * cm);
         m.bf_g0.alloc(&c, sizeof(float) * cp);
-        m.bf_dC.alloc(&c, sizeof(float) * cp * d);
-        m.bf_dN.alloc(&c, sizeof(float) * cm * d);
     }
     const uint32_t score_waves = (P / 64) * (M / 64) * 4;
     const int64_t nslots = (int64_t)P + M + score_waves;
@@ -417,8 +395,6 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     Bf16Args a{};
     a.tin = m.tin.as<float>();
     a.tout = m.tout.as<float>();
-    a.bin = m.bin.as<uint16_t>();
-    a.bout = m.bout.as<uint16_t>();
     a.d = d;
     a.walks = w.data.as<int32_t>();
     a.W = w.W;
@@ -439,8 +415,6 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     a.G = m.bf_G.as<uint16_t>();
     a.Gt = m.bf_Gt.as<uint16_t>();
     a.g0 = m.bf_g0.as<float>();
-    a.dC = m.bf_dC.as<float>();
-    a.dN = m.bf_dN.as<float>();
     a.loss_part = loss_part.as<double>();
     a.cap_in = cap_in;
     a.cap_out = cap_out;
@@ -464,10 +438,12 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         a.mb = (uint32_t)b;
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
         hipLaunchKernelGGL(bf16_gather_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
-        hipLaunchKernelGGL(bf16_scores_kernel, dim3(P / 64, M / 64), dim3(256), 0, c.stream, a);
-        hipLaunchKernelGGL(bf16_grads_kernel, dim3(grad_blocks), dim3(256), 0, c.stream, a);
-        hipLaunchKernelGGL(bf16_apply_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
-        if (!cap_in) hipLaunchKernelGGL(bf16_refresh_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        const dim3 sgrid(P / 64, M / 64);
+        if (d == 64) hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
+        else if (d == 128) hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
+        else hipLaunchKernelGGL(bf16_scores_kernel<256>, sgrid, dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL(bf16_grads_kernel, dim3(grad_blocks), dim3(64 * kGradWaves), 0,
+                           c.stream, a);
         FELOG_HIP(hipGetLastError());
         pairs_done += np;
     }

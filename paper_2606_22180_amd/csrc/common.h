@@ -138,7 +138,8 @@ struct Model {
     int32_t precision = FELOG_PREC_FP32;
     bool have_noise = false;
     DevBuf tin, tout;             // float [n][d] (the masters of a BF16 model)
-    DevBuf bin, bout;             // uint16 [n][d]: BF16 copies (BF16 models)
+    DevBuf bin, bout;             // uint16 [n][d]: BF16 copies (BF16 models), rounded from
+                                  // the masters when read out (training rounds as it gathers)
     DevBuf cdf;                   // uint64 [n+1]
     DevBuf guide;                 // int32 [2^guide_bits]
     int32_t guide_bits = 0;
@@ -157,7 +158,7 @@ struct Model {
     DevBuf row_totals;            // uint64 [2]: summed touched-list lengths (in, out)
     // shared-negative (BF16) minibatch scratch
     uint32_t bf_P = 0, bf_M = 0;
-    DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0, bf_dC, bf_dN;
+    DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0;
 };
 
 // Minibatch schedule of one training call over a corpus.
