@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SGNS pair-updates/s + walk steps/s at matched link-pred AUC; p99 job latency"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0     # dense BF16 MFMA
 COUNTERS = os.path.join(ROOT, "profiles", "sgns_forward_rmat20_counters.json")
 FORWARD_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
 
@@ -129,6 +130,33 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
     return out
 
 
+def small_minibatch_sample(felog, G, n_mb: int, seed: int = 3):
+    """The FP32 per-pair form against the BF16 shared-negative form at P = M = 1024
+    (d = 128, K = 5, w = 10, degree noise) on the bench graph: time per minibatch
+    over n_mb minibatches from the middle of the corpus."""
+    W = felog.Walks.generate(G, r=10, L=80, seed=1)
+    out = {"minibatch_pairs": 1024, "shared_negatives": 1024, "dim": 128, "negatives": 5,
+           "window": 10, "minibatches": n_mb}
+    for prec, msh, name in ((felog.PREC_FP32, 0, "fp32_per_pair"),
+                            (felog.PREC_BF16, 1024, "bf16_shared_negative")):
+        M = felog.Model.create(G, dim=128, neg_dist=felog.NEG_DEGREE, seed=2, precision=prec)
+        prm = felog.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=seed,
+                                 shared_negatives=msh)
+        M.train_steps(W, prm, 0, 200)
+        st = M.train_steps(W, prm, 300000, n_mb)
+        us = st.ms / st.minibatches * 1e3
+        r = {"us_per_minibatch": us, "pair_updates_per_s": st.pairs / (st.ms / 1e3)}
+        if msh:
+            flops = 3 * 2 * 1024 * 1024 * 128   # S, dC and dN
+            r["mfma_tflops"] = flops / (us * 1e-6) / 1e12
+            r["mfma_frac"] = r["mfma_tflops"] / BF16_PEAK_TFLOPS
+        out[name] = r
+        log("%s at P=1024: %.1f us/minibatch" % (name, us))
+        M.close()
+    W.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +174,8 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=8,
                     help="jobs in the serving-latency sample (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--small-minibatches", type=int, default=20000,
+                    help="minibatches of the FP32 vs BF16 comparison at P = 1024 (0 = skip)")
     ap.add_argument("--calibrate", action="store_true",
                     help="after the run, build a BF16 model once: its two table conversions "
                          "read n*d*4 and write n*d*2 bytes each (known sizes, for HBM "
@@ -335,6 +365,8 @@ def main():
         "walk_steps_per_step": int(walk_steps), "pairs_per_step": int(pairs_per_step),
         "link_pred_auc": auc, "rounds": rounds, "roofline": roof,
     }
+    if args.small_minibatches > 0:
+        out["small_minibatch_forms"] = small_minibatch_sample(felog, G, args.small_minibatches)
     if args.serving_jobs > 0:
         out["serving"] = serving_sample(felog, args.serving_jobs, args.serving_slots)
         out["p99_job_latency_s"] = out["serving"]["rates"][1]["p99_latency_s"]   # at 0.8 x capacity

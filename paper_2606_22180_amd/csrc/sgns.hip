@@ -180,15 +180,52 @@ struct ScanArgs {
     uint32_t* meta;
 };
 
-template <int K>
-__device__ __forceinline__ void scan_item(const ScanArgs& a, bool out, uint32_t i, int32_t& row,
-                                          uint32_t& c)
+// Items base .. base + kScanI - 1 of a table (n items): the row each one
+// lists (-1 if none) and the row's touch count.  BATCH issues the loads of
+// all the items before it uses any (indices past the end clamped, their
+// values dropped): two round trips to memory instead of 2 kScanI, for when
+// the scan is on the minibatch's critical path.  Otherwise each item's loads
+// wait for the previous item, which leaves more bandwidth to the launches
+// that run beside the scan.
+template <int K, bool BATCH>
+__device__ __forceinline__ void scan_items(const ScanArgs& a, bool out, uint32_t base, uint32_t n,
+                                           int32_t (&rows)[kScanI], uint32_t (&cs)[kScanI])
 {
-    const uint32_t t = out ? (i / (K + 1)) * (K + 2) + 1 + i % (K + 1) : i * (K + 2);
-    const int32_t r = a.touch_row[t];
-    const bool first = r >= 0 && a.touch_pos[t] == 0u;
-    row = first ? r : -1;
-    c = first ? (out ? a.cnt_out : a.cnt_in)[r] : 0u;
+    const uint32_t* cnt = out ? a.cnt_out : a.cnt_in;
+    if (BATCH) {
+        const uint32_t last = n > 0 ? n - 1 : 0;
+        uint32_t pos[kScanI];
+#pragma unroll
+        for (int k = 0; k < kScanI; ++k) {
+            const uint32_t i = min(base + k, last);
+            const uint32_t t = out ? (i / (K + 1)) * (K + 2) + 1 + i % (K + 1) : i * (K + 2);
+            rows[k] = a.touch_row[t];
+            pos[k] = a.touch_pos[t];
+        }
+#pragma unroll
+        for (int k = 0; k < kScanI; ++k) {
+            const bool first = base + k < n && rows[k] >= 0 && pos[k] == 0u;
+            rows[k] = first ? rows[k] : -1;
+            cs[k] = cnt[first ? rows[k] : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < kScanI; ++k) cs[k] = rows[k] >= 0 ? cs[k] : 0u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanI; ++k) {
+            rows[k] = -1;
+            cs[k] = 0u;
+            if (base + k < n) {
+                const uint32_t i = base + k;
+                const uint32_t t = out ? (i / (K + 1)) * (K + 2) + 1 + i % (K + 1) : i * (K + 2);
+                const int32_t r = a.touch_row[t];
+                if (r >= 0 && a.touch_pos[t] == 0u) {
+                    rows[k] = r;
+                    cs[k] = cnt[r];
+                }
+            }
+        }
+    }
 }
 
 __device__ __forceinline__ uint4 add4(uint4 a, uint4 b)
@@ -207,7 +244,7 @@ __device__ __forceinline__ unsigned long long pack_ec(uint32_t c)
     return (unsigned long long)c | ((unsigned long long)((c + kChunk - 1) / kChunk) << 32);
 }
 
-template <int K>
+template <int K, bool BATCH>
 __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
 {
     __shared__ unsigned long long s_ec[kScanT];
@@ -218,16 +255,14 @@ __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
     const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
     unsigned long long ec = 0;
     uint4 rm = make_uint4(0u, 0u, 0u, 0u);
+    int32_t rows[kScanI];
+    uint32_t cs[kScanI];
+    scan_items<K, BATCH>(a, out, base, n, rows, cs);
 #pragma unroll
     for (int k = 0; k < kScanI; ++k) {
-        if (base + k < n) {
-            int32_t row;
-            uint32_t c;
-            scan_item<K>(a, out, base + k, row, c);
-            if (row >= 0) {
-                ec += pack_ec(c);
-                rm = add4(rm, split_counts(c));
-            }
+        if (rows[k] >= 0) {
+            ec += pack_ec(cs[k]);
+            rm = add4(rm, split_counts(cs[k]));
         }
     }
     s_ec[threadIdx.x] = ec;
@@ -246,7 +281,7 @@ __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
     }
 }
 
-template <int K>
+template <int K, bool BATCH>
 __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
 {
     __shared__ unsigned long long s_ec[kScanT];
@@ -282,11 +317,9 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
     uint32_t cs[kScanI];
     unsigned long long mine = 0;
     uint4 mine_rm = make_uint4(0u, 0u, 0u, 0u);
+    scan_items<K, BATCH>(a, out, base, n, rows, cs);
 #pragma unroll
     for (int k = 0; k < kScanI; ++k) {
-        rows[k] = -1;
-        cs[k] = 0;
-        if (base + k < n) scan_item<K>(a, out, base + k, rows[k], cs[k]);
         if (rows[k] >= 0) {
             mine += pack_ec(cs[k]);
             mine_rm = add4(mine_rm, split_counts(cs[k]));
@@ -792,6 +825,9 @@ void model_alloc_update_state(Model& m)
 // touches / (kChunk + 1) of them, with ceil(c / kChunk) <= 2 c / (kChunk + 1)
 // chunks each: at most touches / 8 + 1 chunks in all.
 static int64_t max_split_rows(int64_t touches) { return touches / (kChunk + 1) + 1; }
+
+// Largest minibatch whose launches all go to the training stream.
+constexpr int64_t kOneStreamPairs = 2048;
 static int64_t max_split_chunks(int64_t touches) { return touches / 8 + 1; }
 
 // Launch geometry and per-minibatch values of one minibatch.
@@ -801,6 +837,7 @@ struct MinibatchLaunch {
     uint32_t prep_blocks, fwd_blocks, nb_in, nb_out, reduce_blocks;
     int64_t split_in;     // partial-sum rows reserved for the in-table (the out-table's follow)
     double grid_c;        // exact-sum grid constant of this minibatch's learning rate
+    bool one_stream;      // ids on the training stream (on the critical path)
 };
 
 // Ids, ranks and the destination sort of one minibatch (reads only the walks
@@ -823,8 +860,13 @@ static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& 
                 mb.off_out.as<int32_t>(), mb.chunks_in.as<int4>(), mb.chunks_out.as<int4>(),
                 mb.split_in.as<int4>(), mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),
                 mb.mrows_out.as<int4>(), meta};
-    hipLaunchKernelGGL((sgns_scan_partials<K>), dim3(nb), dim3(256), 0, s, sa);
-    hipLaunchKernelGGL((sgns_scan_write<K>), dim3(nb), dim3(256), 0, s, sa);
+    if (ml.one_stream) {
+        hipLaunchKernelGGL((sgns_scan_partials<K, true>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_write<K, true>), dim3(nb), dim3(256), 0, s, sa);
+    } else {
+        hipLaunchKernelGGL((sgns_scan_partials<K, false>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_write<K, false>), dim3(nb), dim3(256), 0, s, sa);
+    }
     FELOG_HIP(hipGetLastError());
 }
 
@@ -1041,6 +1083,10 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     fa.loss_part = loss_part.as<double>();
 
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
+    // Small minibatches run everything on one stream: their launches are
+    // chains of a few dependent loads each, and waiting on another stream's
+    // events costs more than the overlap gains.
+    const bool one_stream = P <= kOneStreamPairs;
     // the launch values of minibatch b
     size_t chunk = 0;
     auto frame = [&](int64_t b, MinibatchLaunch& ml, PrepArgs& a) {
@@ -1061,6 +1107,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         ml.nb_out = (uint32_t)((np * (K + 1) + kScanSpanS - 1) / kScanSpanS);
         ml.reduce_blocks = (uint32_t)std::max(1, c.num_cus * 8);
         ml.split_in = m.split_rows_in;
+        ml.one_stream = one_stream;
         const double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
         const float lr32 = (float)lr;
         ml.grid_c = lr32 > 0.0f ? std::ldexp(1.5, std::ilogb(lr32) + 17) : 1.5;
@@ -1100,11 +1147,15 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     int64_t pairs_done = 0;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     if (apply && end > first_mb) {
-        // ids of minibatch b + 1 on the second stream while b trains on the first
-        c.ensure_aux();
-        hipStream_t ids_s = c.aux;
-        FELOG_HIP(hipEventRecord(c.pipe_ev[0], c.stream));
-        FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[0], 0));
+        // ids of minibatches b + 1 and b + 2 on the second stream while b trains
+        // on the first (or all in order on the first, for small minibatches)
+        hipStream_t ids_s = c.stream;
+        if (!one_stream) {
+            c.ensure_aux();
+            ids_s = c.aux;
+            FELOG_HIP(hipEventRecord(c.pipe_ev[0], c.stream));
+            FELOG_HIP(hipStreamWaitEvent(ids_s, c.pipe_ev[0], 0));
+        }
         MinibatchLaunch mls[kIdSets];
         float lrs[kIdSets];
         hipEvent_t* ready = c.pipe_ev + 1;               // [set] ids ready
@@ -1114,14 +1165,15 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
             const int set = (int)(b % kIdSets);
             PrepArgs a = pa;
             lrs[set] = frame(b, mls[set], a);
-            if (b >= first_mb + kIdSets)   // the set's previous minibatch must be done with it
+            // the set's previous minibatch must be done with it
+            if (!one_stream && b >= first_mb + kIdSets)
                 FELOG_HIP(hipStreamWaitEvent(ids_s, freed[set], 0));
             hipEvent_t* e = take_slot(b);
             slot_of[set] = e;
             if (e) FELOG_HIP(hipEventRecord(e[0], ids_s));
             launch_ids(m.mb[set], a, mls[set], meta0 + kMetaWords * set, ids_s);
             if (e) FELOG_HIP(hipEventRecord(e[1], ids_s));
-            FELOG_HIP(hipEventRecord(ready[set], ids_s));
+            if (!one_stream) FELOG_HIP(hipEventRecord(ready[set], ids_s));
         };
         const int64_t ahead = kIdSets - 1;
         for (int64_t k = 0; k < ahead && first_mb + k < end; ++k) issue_ids(first_mb + k);
@@ -1130,18 +1182,18 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
             const MinibatchLaunch ml = mls[set];
             const float lr = lrs[set];
             hipEvent_t* e = slot_of[set];
-            FELOG_HIP(hipStreamWaitEvent(c.stream, ready[set], 0));
+            if (!one_stream) FELOG_HIP(hipStreamWaitEvent(c.stream, ready[set], 0));
             FwdArgs f = fa;
             f.lr = lr;
             f.npairs = ml.npairs;
             launch_train(m, m.mb[set], f, ml, meta0 + kMetaWords * set, nullptr, nullptr,
-                         c.stream, e ? e + 2 : nullptr, fwd_done);
-            FELOG_HIP(hipEventRecord(freed[set], c.stream));
+                         c.stream, e ? e + 2 : nullptr, one_stream ? nullptr : fwd_done);
+            if (!one_stream) FELOG_HIP(hipEventRecord(freed[set], c.stream));
             pairs_done += ml.npairs;
             // later minibatches' ids run beside this one's apply launches and the
             // next forward, not beside this forward
             if (b + ahead < end) {
-                FELOG_HIP(hipStreamWaitEvent(ids_s, fwd_done, 0));
+                if (!one_stream) FELOG_HIP(hipStreamWaitEvent(ids_s, fwd_done, 0));
                 issue_ids(b + ahead);
             }
         }
