@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "SGNS pair-updates/s + walk steps/s at matched link-pred AUC; p99 job latency"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0     # dense BF16 MFMA
-COUNTERS = os.path.join(ROOT, "profiles", "sgns_forward_rmat20_counters.json")
-FORWARD_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "sgns_apply_rmat20_counters.json")
+APPLY_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
 
 
 def log(*a):
@@ -44,13 +44,13 @@ def auc_score(emb: np.ndarray, pos: np.ndarray, neg: np.ndarray) -> float:
     return float(roc_auc_score(y, np.r_[sp, sn]))
 
 
-def forward_traffic():
-    """HBM bytes per forward launch from the committed rocprofv3 counters, if
-    they were taken on the current kernel source; else None."""
+def apply_traffic():
+    """HBM bytes per first apply launch from the committed rocprofv3 counters,
+    if they were taken on the current kernel source; else None."""
     if not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
-    src = hashlib.sha256(open(FORWARD_SRC, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
     if rec.get("source_sha256") != src:
         return None
     return rec.get("bytes_per_launch")
@@ -240,7 +240,7 @@ def main():
                 s = M.train_steps(W, rp.train, b0, args.progress_every)
                 for f in ("minibatches", "pairs", "rows_in", "rows_out", "timed_launches"):
                     setattr(tr, f, getattr(tr, f) + getattr(s, f))
-                for f in ("loss", "ms", "ms_forward", "ms_apply", "ms_prep"):
+                for f in ("loss", "ms", "ms_forward", "ms_apply", "ms_prep", "ms_apply_first"):
                     setattr(tr, f, getattr(tr, f) + getattr(s, f))
                 log("round %d: minibatches %d/%d" % (r, min(B, b0 + args.progress_every), B))
             st.train[r] = tr
@@ -281,9 +281,9 @@ def main():
     R = st.rounds
     rounds = []
     pairs = walk_steps = 0
-    fwd_ms = apply_ms = prep_ms = 0.0
+    fwd_ms = apply_ms = prep_ms = apply0_ms = 0.0
     timed = 0
-    mbs = rows = 0
+    mbs = rows = rows_in = rows_out = 0
     ms_walk = 0.0
     for r in range(R):
         tr = st.train[r]
@@ -292,9 +292,12 @@ def main():
         fwd_ms += tr.ms_forward
         apply_ms += tr.ms_apply
         prep_ms += tr.ms_prep
+        apply0_ms += tr.ms_apply_first
         timed += tr.timed_launches
         mbs += tr.minibatches
         rows += tr.rows_in + tr.rows_out
+        rows_in += tr.rows_in
+        rows_out += tr.rows_out
         ms_walk += st.ms_walk[r]
         rounds.append(dict(active=int(st.active[r]), walks=int(st.walks[r]),
                            walk_steps=int(st.walk_steps[r]), pairs=int(tr.pairs),
@@ -314,35 +317,47 @@ def main():
     log("pairs/step=%d walk_steps/step=%d value=%.4g pairs/s auc=%.4f" % (
         pairs_per_step, walk_steps, value, auc))
 
-    # Roofline of the dominant kernel, the SGNS forward.  Its algorithmic bytes per
-    # launch: every distinct row the minibatch touches read once (d*4 B; the forward
-    # reads all of them and writes none), the pair's two node ids (8 B) and one 8 B
-    # cumulative-weight read per negative.  The whole minibatch update (ids, the
-    # destination sort, forward, both apply launches) also writes each touched row
-    # once, so its algorithmic bytes are rows*d*8 + pairs*(8 + 8K).  Durations come
-    # from HIP events on every timing_every-th minibatch; the id work of the next
-    # minibatch runs concurrently on a second stream, so the forward's duration
-    # includes that contention.
+    # Roofline of the dominant kernel by time, the first apply launch
+    # (sgns_apply_kernel<d, 0>): the out-rows' sums.  Its algorithmic bytes per
+    # launch: each distinct out row read and written once (d*8 B), each distinct
+    # in row (a pair's context) read once (d*4 B), and 12 B per out touch (its
+    # coefficient, context id and pair-order key).  Rows with more than 16
+    # touches are summed here and written by the second launch; their writes are
+    # counted here.  The forward reads every distinct row once (d*4 B), the
+    # pair's two node ids (8 B) and one 8 B cumulative-weight read per negative.
+    # The whole minibatch update (ids, the destination sort, forward, both apply
+    # launches) also writes each touched row once: rows*d*8 + pairs*(8 + 8K).
+    # Durations come from HIP events on every timing_every-th minibatch, on the
+    # stream the kernels run on; the id work of later minibatches runs
+    # concurrently on a second stream, so the durations include that contention.
     d = cfg["dim"]
     K = cfg["K"]
     row_bytes = rows * d * 4
     id_bytes = pairs * (8 + 8 * K)
-    per_launch = (row_bytes + id_bytes) / max(1, mbs)
+    per_apply0 = (rows_out * d * 8 + rows_in * d * 4 + pairs * (K + 1) * 12) / max(1, mbs)
+    per_fwd = (row_bytes + id_bytes) / max(1, mbs)
     per_update = (2 * row_bytes + id_bytes) / max(1, mbs)
+    avg_apply0_s = apply0_ms / 1e3 / max(1, timed)
     avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
-    # the next minibatch's ids overlap this one's update, so the update's cost is
+    # the next minibatches' ids overlap this one's update, so the update's cost is
     # the training wall time per minibatch
     avg_upd_s = sum(st.train[r].ms for r in range(R)) / 1e3 / max(1, mbs)
-    achieved = per_launch / avg_fwd_s / 1e9 if timed else None
+    achieved = per_apply0 / avg_apply0_s / 1e9 if timed else None
+    fwd_achieved = per_fwd / avg_fwd_s / 1e9 if timed else None
     upd_achieved = per_update / avg_upd_s / 1e9 if timed else None
-    traffic = forward_traffic()
-    roof = {"bound": "hbm", "kernel": "sgns_forward_kernel<%d, %d>" % (d, K),
+    roof = {"bound": "hbm", "kernel": "sgns_apply_kernel<%d, 0>" % d,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_fwd_s * 1e6,
+            "traffic": apply_traffic(),
+            "algorithmic_bytes_per_launch": per_apply0, "avg_launch_us": avg_apply0_s * 1e6,
             "timed_launches": timed,
             "touched_rows_per_minibatch": rows / max(1, mbs),
+            "in_rows_per_minibatch": rows_in / max(1, mbs),
+            "out_rows_per_minibatch": rows_out / max(1, mbs),
+            "forward": {"kernel": "sgns_forward_kernel<%d, %d>" % (d, K),
+                        "algorithmic_bytes_per_launch": per_fwd,
+                        "avg_launch_us": avg_fwd_s * 1e6, "achieved": fwd_achieved,
+                        "frac": (fwd_achieved / HBM_PEAK_GBS) if fwd_achieved else None},
             "sgns_update": {"kernels": "prep and scan (second stream), forward, two apply "
                                        "launches",
                             "avg_prep_us": prep_ms / 1e3 / max(1, timed) * 1e6,

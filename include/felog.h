@@ -228,6 +228,8 @@ typedef struct felog_train_stats {
     double ms_apply;          /* summed duration of the timed apply launches       */
     double ms_prep;           /* summed duration of the timed id / rank / offset   */
                               /* launches that precede each timed forward          */
+    double ms_apply_first;    /* summed duration of the first of the timed apply
+                                 launches (out rows, chunks of split rows)         */
 } felog_train_stats;
 
 /* One Train() call: every minibatch of the corpus in order.  Pairs: within each

@@ -187,7 +187,7 @@ felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every)
         FELOG_REQUIRE(every >= 0, "every must be >= 0");
         ctx->make_current();
         if (every > 0 && ctx->timing_pool.empty()) {
-            ctx->timing_pool.resize(5 * 256);
+            ctx->timing_pool.resize(kTimingEvents * 256);
             for (hipEvent_t& e : ctx->timing_pool) FELOG_HIP(hipEventCreate(&e));
         }
         ctx->timing_every = every;

@@ -60,6 +60,7 @@ struct DevBuf {
 };
 
 constexpr int kIdSets = 3;   // minibatch id buffer sets: ids run kIdSets - 1 minibatches ahead
+constexpr int kTimingEvents = 6;   // events per timed minibatch
 
 struct Ctx {
     int device = 0;
@@ -70,7 +71,7 @@ struct Ctx {
     int num_cus = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t timing_every = 0;             // time every n-th training launch (0 = off)
-    std::vector<hipEvent_t> timing_pool;  // 5 events per timed minibatch
+    std::vector<hipEvent_t> timing_pool;  // kTimingEvents events per timed minibatch
     // second stream for the table-independent part of later minibatches, and
     // its events: [0] start, [1 + set] ids ready, [1 + kIdSets + set] buffers
     // free, [1 + 2 kIdSets] forward done

@@ -110,14 +110,15 @@ struct PrepArgs {
     uint32_t* touch_pos;     // [P][K+2]: rank of the touch within its row
 };
 
+// Grid-stride over the touches: the launch is capped at a few blocks per CU,
+// which leaves room for the training launches it runs beside.
 template <int K>
 __global__ __launch_bounds__(256) void sgns_prep_kernel(PrepArgs a)
 {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     const uint32_t nt = a.npairs * (K + 2);
-    int32_t row = -1;
-    bool out = false;
-    if (t < nt) {
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < nt; t += gridDim.x * 256) {
+        int32_t row = -1;
+        bool out = false;
         const uint32_t p = t / (K + 2), r = t - p * (K + 2);
         const uint32_t gq = a.first_pair + p;
         const uint32_t sidx = gq / a.Wv;
@@ -145,8 +146,6 @@ __global__ __launch_bounds__(256) void sgns_prep_kernel(PrepArgs a)
             row = neg != ctr ? neg : -1;   // a negative equal to the centre is skipped
             out = true;
         }
-    }
-    if (t < nt) {
         a.touch_row[t] = row;
         a.touch_pos[t] = row >= 0 ? atomicAdd((out ? a.cnt_out : a.cnt_in) + row, 1u) : 0u;
     }
@@ -871,7 +870,8 @@ static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& 
 }
 
 // Forward and the two apply launches of one minibatch whose ids are ready.
-// ev (optional): [0] recorded before the forward, [1] after it, [2] at the end;
+// ev (optional): [0] recorded before the forward, [1] after it, [2] after the
+// first apply launch, [3] at the end;
 // fwd_done (optional) is recorded after the forward.
 template <int D, int K>
 static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const MinibatchLaunch& ml,
@@ -896,8 +896,9 @@ static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const Miniba
                  mb.cnt_out.as<uint32_t>(), meta,                  cap_in,
                  cap_out,                 m.row_totals.as<unsigned long long>(), ml.grid_c};
     hipLaunchKernelGGL((sgns_apply_kernel<D, 0>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
-    hipLaunchKernelGGL((sgns_apply_kernel<D, 1>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
     if (ev) FELOG_HIP(hipEventRecord(ev[2], s));
+    hipLaunchKernelGGL((sgns_apply_kernel<D, 1>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
+    if (ev) FELOG_HIP(hipEventRecord(ev[3], s));
     FELOG_HIP(hipGetLastError());
 }
 
@@ -1101,7 +1102,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         ml.dim = m.dim;
         ml.K = K;
         ml.npairs = (uint32_t)np;
-        ml.prep_blocks = (uint32_t)((np * (K + 2) + 255) / 256);
+        ml.prep_blocks = (uint32_t)std::min<int64_t>((int64_t)c.num_cus * 4, (np * (K + 2) + 255) / 256);
         ml.fwd_blocks = (uint32_t)(((np + ppw - 1) / ppw + 3) / 4);
         ml.nb_in = (uint32_t)((np + kScanSpanS - 1) / kScanSpanS);
         ml.nb_out = (uint32_t)((np * (K + 1) + kScanSpanS - 1) / kScanSpanS);
@@ -1116,22 +1117,25 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     uint32_t* meta0 = m.meta.as<uint32_t>();
 
     // sampled timing: [0] before the ids (on the id stream), [1] after them,
-    // [2] before the forward, [3] after it, [4] after the merge
+    // [2] before the forward, [3] after it, [4] after the first apply launch,
+    // [5] after the second
     const int every = apply ? c.timing_every : 0;
-    const size_t pool = c.timing_pool.size() / 5;
+    const size_t pool = c.timing_pool.size() / kTimingEvents;
     size_t next_slot = 0, used_slots = 0;
     int64_t timed = 0;
-    double ms_prep = 0.0, ms_fwd = 0.0, ms_apply = 0.0;
+    double ms_prep = 0.0, ms_fwd = 0.0, ms_apply = 0.0, ms_apply_first = 0.0;
     auto harvest = [&](size_t slot) {
-        hipEvent_t* e = &c.timing_pool[5 * slot];
-        FELOG_HIP(hipEventSynchronize(e[4]));
-        float a0 = 0.0f, f = 0.0f, ap = 0.0f;
+        hipEvent_t* e = &c.timing_pool[kTimingEvents * slot];
+        FELOG_HIP(hipEventSynchronize(e[5]));
+        float a0 = 0.0f, f = 0.0f, ap = 0.0f, ap0 = 0.0f;
         FELOG_HIP(hipEventElapsedTime(&a0, e[0], e[1]));
         FELOG_HIP(hipEventElapsedTime(&f, e[2], e[3]));
-        FELOG_HIP(hipEventElapsedTime(&ap, e[3], e[4]));
+        FELOG_HIP(hipEventElapsedTime(&ap, e[3], e[5]));
+        FELOG_HIP(hipEventElapsedTime(&ap0, e[3], e[4]));
         ms_prep += a0;
         ms_fwd += f;
         ms_apply += ap;
+        ms_apply_first += ap0;
         ++timed;
     };
     hipEvent_t* slot_of[kIdSets] = {};   // timing events of the minibatch of each id set
@@ -1139,7 +1143,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         if (!(every > 0 && pool > 0 && (b - first_mb) % every == 0)) return nullptr;
         if (used_slots == pool) harvest(next_slot);   // reuse the oldest slot
         else ++used_slots;
-        hipEvent_t* e = &c.timing_pool[5 * next_slot];
+        hipEvent_t* e = &c.timing_pool[kTimingEvents * next_slot];
         next_slot = (next_slot + 1) % pool;
         return e;
     };
@@ -1267,6 +1271,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         stats->timed_launches = timed;
         stats->ms_forward = ms_fwd;
         stats->ms_apply = ms_apply;
+        stats->ms_apply_first = ms_apply_first;
         stats->ms_prep = ms_prep;
     }
 }
