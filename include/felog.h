@@ -48,6 +48,7 @@ enum {
 typedef struct felog_ctx felog_ctx;
 typedef struct felog_graph felog_graph;
 typedef struct felog_walks felog_walks;
+typedef struct felog_packed felog_packed;
 typedef struct felog_active felog_active;
 typedef struct felog_model felog_model;
 
@@ -144,6 +145,56 @@ felog_status felog_walks_read_range(const felog_walks* w, int64_t first, int64_t
 /* Number of node2vec proposals that hit the attempt cap (expected 0). */
 felog_status felog_walks_capped(const felog_walks* w, int64_t* capped);
 void felog_walks_destroy(felog_walks* w);
+
+/* ------------------------------------------------------------------------- */
+/* Walk-corpus codec (FaBC: frequency-aware bitmap compression, Section 5.2.2, */
+/* Eq. (6)-(8)).  Symbols are node ids and -1, the padding after an isolated */
+/* start's only node.                                                         */
+/* ------------------------------------------------------------------------- */
+
+#define FELOG_FABC_MAX_SYMBOLS 16
+
+/* Profile a corpus: every symbol's share p of the W*L positions, ranked by
+ * count (descending) then symbol (ascending); then the target set of Eq. (8):
+ * k grows while p(k+1) >= c + 0.1 g(k), with c = 1/L + 1/32 and
+ * g(k) = (1 - F_k) + k c (Eq. (7), F_k the top k's share), evaluated in FP64
+ * as written, k <= k_max <= 16.  Outputs: *k; the first *n_ranked (<= k_max)
+ * ranked symbols and their counts in symbols[k_max] / counts[k_max] (host
+ * buffers; fewer when fewer symbols occur); *total = W*L. */
+felog_status felog_fabc_profile(const felog_walks* w, int32_t k_max, int32_t* k,
+                                int32_t* symbols, uint64_t* counts, int32_t* n_ranked,
+                                uint64_t* total);
+
+/* Pack a corpus with the given k <= 16 distinct symbols (in [-1, n)), on the
+ * device.  Byte format (little endian):
+ *   header    u32 0x43426146, u32 k, u32 L, u32 0, u64 W, i64 id_base   32 B
+ *   symbols   i32[k]
+ *   bitmaps   u8[k][ceil(L/8)][W]: bit j%8 of byte j/8 of symbol b's bitmap
+ *             of walk w is set iff position j of walk w holds symbol b
+ *   padding   zero bytes to a multiple of 8
+ *   offsets   u64[ceil(W/256)]: residual positions before walk 256 i
+ *   residuals i32[R]: every other position, walk by walk, position ascending
+ * Its size is Eq. (6) with the symbols stored once per corpus, plus the
+ * header, padding and offsets.  ms (nullable, double[2]): device time of the
+ * counting and the writing launches. */
+felog_status felog_walks_pack(const felog_walks* w, int32_t k, const int32_t* symbols,
+                              felog_packed** out, double* ms);
+/* Sizes: total bytes, k, walks W, length L, residual positions R (each nullable). */
+felog_status felog_packed_info(const felog_packed* p, int64_t* bytes, int32_t* k,
+                               int64_t* n_walks, int32_t* length, int64_t* residuals);
+/* Copy the packed bytes to host memory (cap >= bytes). */
+felog_status felog_packed_read(const felog_packed* p, void* host, int64_t cap);
+/* Upload packed bytes for a graph.  The header, the symbols (in [-1, n),
+ * distinct) and the size are checked here; the bitmaps, offsets and residuals
+ * when unpacking. */
+felog_status felog_packed_from_host(felog_graph* g, const void* host, int64_t bytes,
+                                    felog_packed** out);
+/* Unpack into a new corpus on the device (same walks, length and walk ids as
+ * the packed one).  A corpus whose bitmaps overlap, whose offsets disagree
+ * with its bitmaps or whose residuals are missing or outside [-1, n) gives
+ * FELOG_EINVAL.  ms (nullable): device time of the unpacking launch. */
+felog_status felog_packed_unpack(const felog_packed* p, felog_walks** out, double* ms);
+void felog_packed_destroy(felog_packed* p);
 
 /* ------------------------------------------------------------------------- */
 /* Model: embedding tables phi_in, phi_out (Eq. (2)) and the noise distribution */

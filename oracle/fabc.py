@@ -31,8 +31,11 @@ Byte format (little endian), for W walks of L positions and k symbols:
            symbol b                                                k ceil(L/8) W B
   padding  zero bytes up to a multiple of 8
   offsets  u64[ceil(W/256)]: residuals before walk 256 i           8 ceil(W/256) B
-  residual i32[R]: the positions holding no selected symbol, walk
-           by walk, position ascending                              4R B
+  residual i32[R]: the positions holding no selected symbol; walks in
+           blocks of 256, and within a block position by position,
+           walk ascending                                            4R B
+The paper fixes neither the order of the residual ids nor a layout; this one
+lets 256 GPU threads (one per walk) read and write both coalesced.
 """
 from __future__ import annotations
 
@@ -111,7 +114,9 @@ def encode(walks: np.ndarray, symbols, id_base: int = 0) -> bytes:
     starts = np.concatenate([[0], np.cumsum(per_walk)])
     nblk = (W + BLOCK_WALKS - 1) // BLOCK_WALKS
     parts.append(starts[np.arange(nblk) * BLOCK_WALKS].astype("<u8").tobytes())
-    parts.append(walks[~hit].astype("<i4").tobytes())         # row-major: walk, then position
+    for b0 in range(0, W, BLOCK_WALKS):
+        blk = walks[b0:b0 + BLOCK_WALKS].T                        # [L][walks of the block]
+        parts.append(blk[~hit[b0:b0 + BLOCK_WALKS].T].astype("<i4").tobytes())
     return b"".join(parts)
 
 
@@ -145,7 +150,10 @@ def decode(buf: bytes):
     per_walk = (~hit).sum(axis=1)
     starts = np.concatenate([[0], np.cumsum(per_walk)])
     assert np.array_equal(offsets, starts[np.arange(nblk) * BLOCK_WALKS])
-    out[~hit] = res
+    for i, b0 in enumerate(range(0, W, BLOCK_WALKS)):
+        seg = res[starts[b0]:starts[min(b0 + BLOCK_WALKS, W)]]
+        view = out[b0:b0 + BLOCK_WALKS].T                         # writes through
+        view[~hit[b0:b0 + BLOCK_WALKS].T] = seg
     return out, id_base
 
 

@@ -13,6 +13,7 @@
 struct felog_ctx : felog::Ctx {};
 struct felog_graph : felog::Graph {};
 struct felog_walks : felog::Walks {};
+struct felog_packed : felog::Packed {};
 struct felog_active : felog::Active {};
 struct felog_model : felog::Model {};
 
@@ -451,6 +452,100 @@ felog_status felog_walks_capped(const felog_walks* w, int64_t* capped)
 }
 
 void felog_walks_destroy(felog_walks* w) { delete w; }
+
+// -------------------------------------------------------------- walk codec
+felog_status felog_fabc_profile(const felog_walks* w, int32_t k_max, int32_t* k,
+                                int32_t* symbols, uint64_t* counts, int32_t* n_ranked,
+                                uint64_t* total)
+{
+    return guarded([&] {
+        NEED(w);
+        NEED(k);
+        NEED(symbols);
+        NEED(counts);
+        NEED(n_ranked);
+        NEED(total);
+        FELOG_REQUIRE(k_max >= 0 && k_max <= kFabcMax, "k_max must be in [0, %d]", kFabcMax);
+        fabc_profile(*w, k_max, k, symbols, counts, n_ranked, total);
+    });
+}
+
+felog_status felog_walks_pack(const felog_walks* w, int32_t k, const int32_t* symbols,
+                              felog_packed** out, double* ms)
+{
+    return guarded([&] {
+        NEED(w);
+        NEED(out);
+        *out = nullptr;
+        FELOG_REQUIRE(k >= 0 && k <= kFabcMax, "k must be in [0, %d]", kFabcMax);
+        if (k > 0) NEED(symbols);
+        for (int b = 0; b < k; ++b) {
+            FELOG_REQUIRE(symbols[b] >= -1 && symbols[b] < w->g->n,
+                          "symbol %d outside [-1, %d)", symbols[b], w->g->n);
+            for (int q = 0; q < b; ++q)
+                FELOG_REQUIRE(symbols[q] != symbols[b], "symbol %d repeated", symbols[b]);
+        }
+        auto p = std::make_unique<felog_packed>();
+        fabc_pack(*w, k, symbols, *p, ms);
+        *out = p.release();
+    });
+}
+
+felog_status felog_packed_info(const felog_packed* p, int64_t* bytes, int32_t* k,
+                               int64_t* n_walks, int32_t* length, int64_t* residuals)
+{
+    return guarded([&] {
+        NEED(p);
+        if (bytes) *bytes = p->bytes;
+        if (k) *k = p->k;
+        if (n_walks) *n_walks = p->W;
+        if (length) *length = p->L;
+        if (residuals) *residuals = p->R;
+    });
+}
+
+felog_status felog_packed_read(const felog_packed* p, void* host, int64_t cap)
+{
+    return guarded([&] {
+        NEED(p);
+        NEED(host);
+        FELOG_REQUIRE(cap >= p->bytes, "buffer holds %lld bytes, need %lld", (long long)cap,
+                      (long long)p->bytes);
+        Ctx* c = p->g->ctx;
+        c->make_current();
+        FELOG_HIP(hipMemcpyAsync(host, p->buf.ptr, (size_t)p->bytes, hipMemcpyDeviceToHost,
+                                 c->stream));
+        c->sync();
+    });
+}
+
+felog_status felog_packed_from_host(felog_graph* g, const void* host, int64_t bytes,
+                                    felog_packed** out)
+{
+    return guarded([&] {
+        NEED(g);
+        NEED(host);
+        NEED(out);
+        *out = nullptr;
+        auto p = std::make_unique<felog_packed>();
+        fabc_from_host(*g, host, bytes, *p);
+        *out = p.release();
+    });
+}
+
+felog_status felog_packed_unpack(const felog_packed* p, felog_walks** out, double* ms)
+{
+    return guarded([&] {
+        NEED(p);
+        NEED(out);
+        *out = nullptr;
+        auto w = std::make_unique<felog_walks>();
+        fabc_unpack(*p, *w, ms);
+        *out = w.release();
+    });
+}
+
+void felog_packed_destroy(felog_packed* p) { delete p; }
 
 // ------------------------------------------------------------------- model
 felog_status felog_model_create(felog_graph* g, const felog_model_params* p, felog_model** out)

@@ -117,6 +117,18 @@ struct Walks {
     int64_t chunk_for_valid = 0;
 };
 
+// A walk corpus in the FaBC byte format (fabc.hip), in device memory.
+constexpr int kFabcMax = 16;   // most symbols a corpus is packed with
+struct Packed {
+    Graph* g = nullptr;
+    int32_t k = 0, L = 0;
+    int64_t W = 0, id_base = 0;
+    int64_t R = 0;                  // residual positions
+    int64_t bytes = 0;
+    int32_t symbols[kFabcMax] = {};
+    DevBuf buf;                     // the bytes
+};
+
 // Buffers of one minibatch's ids and destination sort; kIdSets sets let the
 // ids of the next kIdSets - 1 minibatches be computed while one trains.
 struct MinibatchBufs {
@@ -225,6 +237,11 @@ void train_minibatches(Model& m, const Walks& w, const felog_train_params& p, in
                        int32_t* rows_out, float* d_out, int64_t cap_out, int64_t* n_out);
 int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_pairs);
 void model_alloc_update_state(Model& m);   // row counters, offsets, minibatch counters
+void fabc_profile(const Walks& w, int32_t k_max, int32_t* k, int32_t* symbols,
+                  uint64_t* counts, int32_t* n_ranked, uint64_t* total);
+void fabc_pack(const Walks& w, int32_t k, const int32_t* symbols, Packed& p, double* ms);
+void fabc_from_host(Graph& g, const void* host, int64_t bytes, Packed& p);
+void fabc_unpack(const Packed& p, Walks& w, double* ms);
 void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
                             int64_t end, float* cap_in, float* cap_out, felog_train_stats* stats);

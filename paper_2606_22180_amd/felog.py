@@ -24,6 +24,7 @@ NEG_DEGREE, NEG_UNIGRAM = 0, 1
 TABLE_IN, TABLE_OUT = 0, 1
 PREC_FP32, PREC_BF16 = 0, 1
 FEEDBACK_MONOTONE, FEEDBACK_RECOMPUTE_ALL = 0, 1
+FABC_MAX_SYMBOLS = 16
 MAX_ROUNDS = 64
 
 _STATUS = {0: "FELOG_OK", -1: "FELOG_EINVAL", -2: "FELOG_ENOMEM", -3: "FELOG_EDEVICE",
@@ -128,6 +129,15 @@ SIGNATURES = {
     "felog_walks_read_range": (_i32, [_p, _i64, _i64, _p, _i64]),
     "felog_walks_capped": (_i32, [_p, C.POINTER(_i64)]),
     "felog_walks_destroy": (None, [_p]),
+    "felog_fabc_profile": (_i32, [_p, _i32, C.POINTER(_i32), _p, _p, C.POINTER(_i32),
+                                  C.POINTER(C.c_uint64)]),
+    "felog_walks_pack": (_i32, [_p, _i32, _p, C.POINTER(_p), _p]),
+    "felog_packed_info": (_i32, [_p, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i64),
+                                 C.POINTER(_i32), C.POINTER(_i64)]),
+    "felog_packed_read": (_i32, [_p, _p, _i64]),
+    "felog_packed_from_host": (_i32, [_p, _p, _i64, C.POINTER(_p)]),
+    "felog_packed_unpack": (_i32, [_p, C.POINTER(_p), _p]),
+    "felog_packed_destroy": (None, [_p]),
     "felog_model_create": (_i32, [_p, C.POINTER(felog_model_params), _pp]),
     "felog_model_destroy": (None, [_p]),
     "felog_model_set_unigram": (_i32, [_p, _p]),
@@ -322,6 +332,58 @@ class Walks(_Handle):
         c = C.c_int64()
         _check(load().felog_walks_capped(self.handle, C.byref(c)))
         return c.value
+
+    def fabc_profile(self, k_max: int = FABC_MAX_SYMBOLS):
+        """(k, ranked symbols, their counts, total positions): the codec's profile."""
+        k, m, tot = C.c_int32(), C.c_int32(), C.c_uint64()
+        sym = np.zeros(FABC_MAX_SYMBOLS, np.int32)
+        cnt = np.zeros(FABC_MAX_SYMBOLS, np.uint64)
+        _check(load().felog_fabc_profile(self.handle, k_max, C.byref(k), sym.ctypes.data,
+                                         cnt.ctypes.data, C.byref(m), C.byref(tot)))
+        return k.value, sym[:m.value].copy(), cnt[:m.value].copy(), tot.value
+
+    def pack(self, symbols) -> "Packed":
+        s, sp = _arr(np.asarray(symbols, np.int32).reshape(-1), np.int32)
+        h = C.c_void_p()
+        ms = np.zeros(2, np.float64)
+        _check(load().felog_walks_pack(self.handle, s.shape[0], sp if s.shape[0] else None,
+                                       C.byref(h), ms.ctypes.data))
+        pk = Packed(h, self._owner)
+        pk.ms = (float(ms[0]), float(ms[1]))
+        return pk
+
+
+class Packed(_Handle):
+    """A walk corpus in the codec's byte format, in device memory."""
+    _destroy = "felog_packed_destroy"
+
+    @classmethod
+    def from_host(cls, g: Graph, data: bytes) -> "Packed":
+        b = np.frombuffer(data, np.uint8)
+        h = C.c_void_p()
+        _check(load().felog_packed_from_host(g.handle, b.ctypes.data, b.shape[0], C.byref(h)))
+        return cls(h, g)
+
+    def info(self):
+        """(bytes, k, walks, length, residual positions)."""
+        by, k, W, L, R = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64()
+        _check(load().felog_packed_info(self.handle, C.byref(by), C.byref(k), C.byref(W),
+                                        C.byref(L), C.byref(R)))
+        return by.value, k.value, W.value, L.value, R.value
+
+    def read(self) -> bytes:
+        n = self.info()[0]
+        out = np.zeros(max(n, 1), np.uint8)
+        _check(load().felog_packed_read(self.handle, out.ctypes.data, out.shape[0]))
+        return out[:n].tobytes()
+
+    def unpack(self) -> Walks:
+        h = C.c_void_p()
+        ms = np.zeros(1, np.float64)
+        _check(load().felog_packed_unpack(self.handle, C.byref(h), ms.ctypes.data))
+        w = Walks(h, self._owner)
+        w.unpack_ms = float(ms[0])
+        return w
 
 
 def train_params(*, window, negatives, lr_start=0.025, lr_end=1e-4, minibatch_pairs,

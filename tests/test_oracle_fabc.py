@@ -149,3 +149,19 @@ def test_bit_layout():
     # walk 0: positions 0,2,3 -> 0b1101 = 13 in byte 0, position 9 -> bit 1 of byte 1
     # walk 1: position 1 -> 2 in byte 0, position 8 -> bit 0 of byte 1
     assert list(by) == [13, 2, 2, 1]
+
+
+def test_residual_order():
+    """Residuals run position by position within a block of 256 walks, walk
+    ascending, and block after block."""
+    w = np.array([[10, 4, 11], [4, 12, 13]], np.int32)
+    buf = fabc.encode(w, [4])
+    assert list(np.frombuffer(buf, "<i4", count=4, offset=len(buf) - 16)) == [10, 12, 11, 13]
+    w = np.arange(300 * 2, dtype=np.int32).reshape(300, 2)
+    buf = fabc.encode(w, [])
+    res = np.frombuffer(buf, "<i4", count=600, offset=len(buf) - 2400)
+    first = w[:256].T.reshape(-1)
+    second = w[256:].T.reshape(-1)
+    assert np.array_equal(res, np.concatenate([first, second]))
+    offs = np.frombuffer(buf, "<u8", count=2, offset=len(buf) - 2400 - 16)
+    assert list(offs) == [0, 512]
