@@ -157,6 +157,44 @@ def small_minibatch_sample(felog, G, n_mb: int, seed: int = 3):
     return out
 
 
+def codec_sample(felog, G, reps: int = 3):
+    """The FaBC walk-corpus codec (Section 5.2.2) on the round-1 corpus of the
+    bench graph (r = 10, L = 80): profile, the Eq. (8) target set, pack and
+    unpack on the device, best of reps, with a sampled round-trip check."""
+    W = felog.Walks.generate(G, r=10, L=80, seed=1)
+    n_walks, L, _ = W.info()
+    raw = 4 * n_walks * L
+    best = None
+    for _ in range(reps):
+        k, sym, cnt, total = W.fabc_profile()
+        P = W.pack(sym[:k])
+        U = P.unpack()
+        by, _, _, _, R = P.info()
+        for first in (0, n_walks // 2, max(0, n_walks - 4096)):
+            c = min(4096, n_walks - first)
+            assert np.array_equal(U.read_range(first, c), W.read_range(first, c))
+        pack_ms = P.ms[0] + P.ms[1]
+        if best is None or pack_ms + U.unpack_ms < best[0] + best[1]:
+            best = (pack_ms, U.unpack_ms, P.ms)
+        U.close()
+        P.close()
+    W.close()
+    F = float(cnt[:k].sum()) / total
+    moved = raw + by                      # read the corpus once, write the packed bytes
+    pack_gbs = moved / (best[0] * 1e-3) / 1e9
+    unpack_gbs = moved / (best[1] * 1e-3) / 1e9
+    out = {"walks": int(n_walks), "length": int(L), "k": int(k),
+           "symbols": [int(x) for x in sym[:k]], "top_shares": [float(c) / total for c in cnt[:4]],
+           "raw_bytes": int(raw), "packed_bytes": int(by), "residuals": int(R),
+           "ratio": by / raw, "g_eq7": 1.0 - F + k / L + k / 32.0,
+           "pack_ms": best[0], "pack_count_ms": best[2][0], "pack_write_ms": best[2][1],
+           "unpack_ms": best[1], "pack_gbs": pack_gbs, "unpack_gbs": unpack_gbs,
+           "pack_frac": pack_gbs / HBM_PEAK_GBS, "unpack_frac": unpack_gbs / HBM_PEAK_GBS}
+    log("codec: k=%d, %d of %d bytes (%.3f; Eq. (7) g = %.3f), pack %.2f ms, unpack %.2f ms" % (
+        k, by, raw, by / raw, out["g_eq7"], best[0], best[1]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +212,8 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=8,
                     help="jobs in the serving-latency sample (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--no-codec", action="store_true",
+                    help="skip the walk-corpus codec sample")
     ap.add_argument("--small-minibatches", type=int, default=20000,
                     help="minibatches of the FP32 vs BF16 comparison at P = 1024 (0 = skip)")
     ap.add_argument("--calibrate", action="store_true",
@@ -380,6 +420,8 @@ def main():
         "walk_steps_per_step": int(walk_steps), "pairs_per_step": int(pairs_per_step),
         "link_pred_auc": auc, "rounds": rounds, "roofline": roof,
     }
+    if not args.no_codec:
+        out["walk_codec"] = codec_sample(felog, G)
     if args.small_minibatches > 0:
         out["small_minibatch_forms"] = small_minibatch_sample(felog, G, args.small_minibatches)
     if args.serving_jobs > 0:

@@ -22,10 +22,11 @@
 //   offsets   u64[ceil(W/256)]: residuals before walk 256 i
 //   residuals i32[R]: the other positions; per block of 256 walks, position
 //             by position, walk ascending
-// One thread per walk, 256 walks per block (one offsets entry per block):
-// reads of the step-major corpus and the bitmap bytes are coalesced across
-// walks, and at each position the block's residuals are compacted with wave
-// ballots into consecutive slots, so they are written and read coalesced too.
+// The pack and unpack launches give one wave to each 256-walk block of the
+// format and four consecutive walks to each lane, so corpus rows and bitmap
+// bytes are read and written 16 and 4 bytes per lane, and at each position the
+// block's residuals are compacted with four wave ballots into consecutive
+// slots (coalesced, and no barrier).
 #include <algorithm>
 #include <cstring>
 
@@ -129,152 +130,197 @@ __global__ void fabc_select_kernel(const Cand* top, unsigned long long total, in
 }
 
 // -------------------------------------------------------------------- pack
-// codes[s + 1] = index of symbol s among the selected ones, or -1.
-__global__ void fabc_codes_kernel(int8_t* codes, const int32_t* symbols, int32_t k)
+// The selected symbols, by value (k of them, the rest unused).
+struct Symbols {
+    int32_t s[kFabcMax];
+};
+
+// Index of v among the k selected symbols, or -1: compares against registers
+// (a table lookup per position would be a random access per lane).
+__device__ __forceinline__ int symbol_code(int32_t v, const Symbols& sy, int32_t k)
 {
-    if (threadIdx.x < k) codes[symbols[threadIdx.x] + 1] = (int8_t)threadIdx.x;
+    int c = -1;
+    for (int b = k - 1; b >= 0; --b)
+        if (v == sy.s[b]) c = b;
+    return c;
 }
 
-__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
-                                                            unsigned long long* lds)
-{
-    lds[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kFabcBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
-        __syncthreads();
-    }
-    const unsigned long long t = lds[0];
-    __syncthreads();
-    return t;
-}
+constexpr int kWalksPerLane = 4;
 
-// Exclusive scan across the block (Hillis-Steele in LDS).
-__device__ __forceinline__ unsigned long long block_excl_u64(unsigned long long v,
-                                                             unsigned long long* lds)
+__device__ __forceinline__ void load4(const int32_t* row, int64_t w0, int64_t W, bool vec,
+                                      int32_t (&v)[kWalksPerLane])
 {
-    lds[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kFabcBlock; off <<= 1) {
-        const unsigned long long a = threadIdx.x >= off ? lds[threadIdx.x - off] : 0ull;
-        __syncthreads();
-        lds[threadIdx.x] += a;
-        __syncthreads();
-    }
-    const unsigned long long r = lds[threadIdx.x] - v;
-    __syncthreads();
-    return r;
-}
-
-// Residuals of each 256-walk block.
-__global__ __launch_bounds__(kFabcBlock) void fabc_pack_count_kernel(
-    const int32_t* __restrict__ data, int64_t W, int32_t L, const int8_t* __restrict__ codes,
-    unsigned long long* block_res)
-{
-    __shared__ unsigned long long lds[kFabcBlock];
-    const int64_t w = (int64_t)blockIdx.x * kFabcBlock + threadIdx.x;
-    unsigned long long r = 0;
-    if (w < W) {
-        // eight positions' loads in flight before their codes are looked up
-        for (int32_t j0 = 0; j0 < L; j0 += 8) {
-            int32_t v[8];
+    if (vec && w0 + 3 < W) {
+        const int4 q = *reinterpret_cast<const int4*>(row + w0);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                v[u] = j0 + u < L ? data[(int64_t)(j0 + u) * W + w] : 0;
-            int8_t c[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) c[u] = codes[v[u] + 1];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) r += (j0 + u < L && c[u] < 0) ? 1u : 0u;
-        }
+        for (int i = 0; i < kWalksPerLane; ++i) v[i] = w0 + i < W ? row[w0 + i] : 0;
     }
-    const unsigned long long t = block_sum_u64(r, lds);
-    if (threadIdx.x == 0) block_res[blockIdx.x] = t;
 }
 
-// Exclusive scan of the block residual counts (one block), total in out[nblk].
-__global__ __launch_bounds__(kFabcBlock) void fabc_offsets_kernel(
-    const unsigned long long* block_res, int64_t nblk, unsigned long long* out)
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 {
-    __shared__ unsigned long long lds[kFabcBlock];
-    unsigned long long carry = 0;
-    for (int64_t s0 = 0; s0 < nblk; s0 += kFabcBlock) {
-        const int64_t i = s0 + threadIdx.x;
-        const unsigned long long v = i < nblk ? block_res[i] : 0ull;
-        const unsigned long long ex = block_excl_u64(v, lds);
-        if (i < nblk) out[i] = carry + ex;
-        carry += block_sum_u64(v, lds);
-    }
-    if (threadIdx.x == 0) out[nblk] = carry;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
 }
 
-// Slot of this thread's residual among the block's residuals at one position
-// (its rank among the lanes and waves below it that hold one), and the
-// position's total.  cnt: LDS [2][4], alternating by position, so that one
-// barrier per position suffices.
-__device__ __forceinline__ uint32_t block_compact(bool res, uint32_t (*cnt)[kFabcBlock / 64],
-                                                  int par, uint32_t* total)
+// Slots of the lane's flagged walks among the wave's flagged walks at one
+// position (walk order), and their total.
+__device__ __forceinline__ void wave_slots(const bool (&f)[kWalksPerLane],
+                                           uint32_t (&slot)[kWalksPerLane], uint32_t* total)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long m = __ballot(res);
-    if (lane == 0) cnt[par][wv] = (uint32_t)__popcll(m);
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t below = 0, all = 0;
 #pragma unroll
-    for (int q = 0; q < kFabcBlock / 64; ++q) {
-        const uint32_t c = cnt[par][q];
-        below += q < wv ? c : 0u;
-        all += c;
+    for (int i = 0; i < kWalksPerLane; ++i) {
+        const unsigned long long m = __ballot(f[i]);
+        below += (uint32_t)__popcll(m & lt);
+        all += (uint32_t)__popcll(m);
+    }
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < kWalksPerLane; ++i) {
+        slot[i] = below + mine;
+        mine += f[i] ? 1u : 0u;
     }
     *total = all;
-    return below + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Bit t of x moved to bit 4t (x < 256).
+__device__ __forceinline__ uint32_t spread_nibbles(uint32_t x)
+{
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x;
+}
+
+// Residuals of each 256-walk block (one wave per block).
+__global__ __launch_bounds__(256) void fabc_pack_count_kernel(
+    const int32_t* __restrict__ data, int64_t W, int32_t L, Symbols sy, int32_t k,
+    unsigned long long* block_res, int64_t nblk)
+{
+    const int64_t fb = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (fb >= nblk) return;
+    const int64_t w0 = fb * kFabcBlock + (threadIdx.x & 63) * kWalksPerLane;
+    const bool vec = (W & 3) == 0;
+    unsigned long long r = 0;
+    for (int32_t j = 0; j < L; ++j) {
+        int32_t v[kWalksPerLane];
+        load4(data + (int64_t)j * W, w0, W, vec, v);
+#pragma unroll
+        for (int i = 0; i < kWalksPerLane; ++i)
+            r += (w0 + i < W && symbol_code(v[i], sy, k) < 0) ? 1u : 0u;
+    }
+    r = wave_sum_u64(r);
+    if ((threadIdx.x & 63) == 0) block_res[fb] = r;
+}
+
+// Exclusive scan of the block residual counts in one block of 1024 threads,
+// total in out[nblk]: each thread sums a contiguous run, the runs' sums are
+// scanned through wave shuffles and LDS, and each thread writes its run.
+constexpr int kOffsetsThreads = 1024;
+
+__global__ __launch_bounds__(kOffsetsThreads) void fabc_offsets_kernel(
+    const unsigned long long* block_res, int64_t nblk, unsigned long long* out)
+{
+    __shared__ unsigned long long wsum[kOffsetsThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t per = (nblk + kOffsetsThreads - 1) / kOffsetsThreads;
+    const int64_t b = (int64_t)threadIdx.x * per, e = min(nblk, b + per);
+    unsigned long long run = 0;
+#pragma unroll 8
+    for (int64_t i = b; i < e; ++i) run += block_res[i];
+    unsigned long long incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long x = __shfl_up(incl, off);
+        if (lane >= off) incl += x;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    unsigned long long before = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kOffsetsThreads / 64; ++q) {
+        before += q < wv ? wsum[q] : 0ull;
+        total += wsum[q];
+    }
+    unsigned long long at = before + incl - run;
+    for (int64_t i = b; i < e; ++i) {
+        out[i] = at;
+        at += block_res[i];
+    }
+    if (threadIdx.x == 0) out[nblk] = total;
 }
 
 struct PackArgs {
     const int32_t* data;       // step-major [L][W]
-    int64_t W;
+    int64_t W, nblk;
     int32_t L, k, B8;
-    const int8_t* codes;
+    Symbols sy;
     uint8_t* bitmaps;          // [k][B8][W]
     const unsigned long long* offsets;
     int32_t* residuals;
 };
 
-__global__ __launch_bounds__(kFabcBlock) void fabc_pack_write_kernel(PackArgs a)
+__global__ __launch_bounds__(256) void fabc_pack_write_kernel(PackArgs a)
 {
-    __shared__ uint32_t cnt[2][kFabcBlock / 64];
-    const int64_t w = (int64_t)blockIdx.x * kFabcBlock + threadIdx.x;
-    const bool live = w < a.W;
-    unsigned long long at = a.offsets[blockIdx.x];
+    const int64_t fb = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (fb >= a.nblk) return;
+    const int64_t w0 = fb * kFabcBlock + (threadIdx.x & 63) * kWalksPerLane;
+    const bool vec = (a.W & 3) == 0;
+    const bool full = w0 + kWalksPerLane - 1 < a.W;
+    unsigned long long at = a.offsets[fb];
     for (int32_t j8 = 0; j8 < a.B8; ++j8) {
-        uint32_t bytes[kFabcMax];
-#pragma unroll
-        for (int b = 0; b < kFabcMax; ++b) bytes[b] = 0u;
-        // the group's eight loads and code lookups first, then its compactions
-        int32_t v[8];
-        int c[8];
-#pragma unroll
+        // bit t of hm[i]: position 8 j8 + t of walk i holds a selected symbol,
+        // whose index is nibble t of cw[i]
+        uint32_t cw[kWalksPerLane] = {0u, 0u, 0u, 0u}, hm[kWalksPerLane] = {0u, 0u, 0u, 0u};
         for (int t = 0; t < 8; ++t) {
             const int32_t j = 8 * j8 + t;
-            v[t] = live && j < a.L ? a.data[(int64_t)j * a.W + w] : 0;
-        }
+            if (j >= a.L) break;
+            int32_t v[kWalksPerLane];
+            load4(a.data + (int64_t)j * a.W, w0, a.W, vec, v);
+            bool f[kWalksPerLane];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) c[t] = live ? a.codes[v[t] + 1] : 0;
+            for (int i = 0; i < kWalksPerLane; ++i) {
+                const int c = symbol_code(v[i], a.sy, a.k);
+                f[i] = w0 + i < a.W && c < 0;
+                cw[i] |= (uint32_t)(c < 0 ? 0 : c) << (4 * t);
+                hm[i] |= (c >= 0 ? 1u : 0u) << t;
+            }
+            uint32_t slot[kWalksPerLane], total;
+            wave_slots(f, slot, &total);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int32_t j = 8 * j8 + t;
-            if (j >= a.L) break;                 // uniform across the block
-            uint32_t total;
-            const uint32_t slot = block_compact(live && c[t] < 0, cnt, j & 1, &total);
-            if (live && c[t] < 0) a.residuals[at + slot] = v[t];
+            for (int i = 0; i < kWalksPerLane; ++i)
+                if (f[i]) a.residuals[at + slot[i]] = v[i];
             at += total;
-#pragma unroll
-            for (int b = 0; b < kFabcMax; ++b) bytes[b] |= (c[t] == b ? 1u : 0u) << t;
         }
-        if (live) {
+        for (int32_t b = 0; b < a.k; ++b) {
+            uint32_t q = 0;
 #pragma unroll
-            for (int b = 0; b < kFabcMax; ++b)
-                if (b < a.k) a.bitmaps[((int64_t)b * a.B8 + j8) * a.W + w] = (uint8_t)bytes[b];
+            for (int i = 0; i < kWalksPerLane; ++i) {
+                uint32_t by = 0;
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    by |= (((hm[i] >> t) & 1u) && ((cw[i] >> (4 * t)) & 15u) == (uint32_t)b ? 1u
+                                                                                          : 0u)
+                          << t;
+                q |= by << (8 * i);
+            }
+            uint8_t* dst = a.bitmaps + ((int64_t)b * a.B8 + j8) * a.W + w0;
+            if (vec && full) {
+                *reinterpret_cast<uint32_t*>(dst) = q;
+            } else {
+#pragma unroll
+                for (int i = 0; i < kWalksPerLane; ++i)
+                    if (w0 + i < a.W) dst[i] = (uint8_t)(q >> (8 * i));
+            }
         }
     }
 }
@@ -283,7 +329,7 @@ __global__ __launch_bounds__(kFabcBlock) void fabc_pack_write_kernel(PackArgs a)
 // Error bits: 1 overlapping or stray bitmap bits, 2 offsets that disagree with
 // the bitmaps, 4 residuals past the end, 8 a residual outside [-1, n).
 struct UnpackArgs {
-    int64_t W;
+    int64_t W, nblk;
     int32_t L, k, B8;
     int32_t n;                 // nodes of the graph
     const int32_t* symbols;
@@ -295,65 +341,85 @@ struct UnpackArgs {
     uint32_t* err;
 };
 
-__global__ __launch_bounds__(kFabcBlock) void fabc_unpack_kernel(UnpackArgs a)
+__global__ __launch_bounds__(256) void fabc_unpack_kernel(UnpackArgs a)
 {
-    __shared__ uint32_t cnt[2][kFabcBlock / 64];
-    const int64_t w = (int64_t)blockIdx.x * kFabcBlock + threadIdx.x;
-    const bool live = w < a.W;
-    const int64_t nblk = (a.W + kFabcBlock - 1) / kFabcBlock;
-    const unsigned long long first = a.offsets[blockIdx.x];
-    const unsigned long long next = blockIdx.x + 1 < nblk ? a.offsets[blockIdx.x + 1] : a.R;
+    const int64_t fb = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (fb >= a.nblk) return;
+    const int64_t w0 = fb * kFabcBlock + (threadIdx.x & 63) * kWalksPerLane;
+    const bool vec = (a.W & 3) == 0;
+    const bool full = w0 + kWalksPerLane - 1 < a.W;
+    const unsigned long long next = fb + 1 < a.nblk ? a.offsets[fb + 1] : a.R;
+    unsigned long long at = a.offsets[fb];
     uint32_t bad = 0;
-    unsigned long long at = first;
     for (int32_t j8 = 0; j8 < a.B8; ++j8) {
-        uint32_t by[kFabcMax];
-        uint32_t any = 0, sum = 0;
-#pragma unroll
-        for (int b = 0; b < kFabcMax; ++b) {
-            by[b] = live && b < a.k ? a.bitmaps[((int64_t)b * a.B8 + j8) * a.W + w] : 0u;
-            any |= by[b];
-            sum += __popc(by[b]);
-        }
-        const int32_t valid = min(8, a.L - 8 * j8);
-        if (sum != (uint32_t)__popc(any) || (any >> valid) != 0u) bad |= 1u;
-        // the group's eight compactions first, then its residual loads together
-        int hit[8];
-        unsigned long long idx[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int32_t j = 8 * j8 + t;
-            hit[t] = -1;
-            idx[t] = 0;
-            if (j >= a.L) break;                 // uniform across the block
-#pragma unroll
-            for (int b = 0; b < kFabcMax; ++b)
-                if (hit[t] < 0 && ((by[b] >> t) & 1u)) hit[t] = b;
-            uint32_t total;
-            idx[t] = at + block_compact(live && hit[t] < 0, cnt, j & 1, &total);
-            at += total;
-        }
-        int32_t v[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            v[t] = -1;
-            if (!live || 8 * j8 + t >= a.L) continue;
-            if (hit[t] >= 0) {
-                v[t] = a.symbols[hit[t]];
-            } else if (idx[t] < a.R) {
-                v[t] = a.residuals[idx[t]];
-                if (v[t] < -1 || v[t] >= a.n) {
-                    bad |= 8u;
-                    v[t] = -1;
-                }
+        // nibble t of cw[i]: the symbol index at position 8 j8 + t of walk i where
+        // bit t of any[i] is set
+        uint32_t cw[kWalksPerLane] = {0u, 0u, 0u, 0u};
+        uint32_t any[kWalksPerLane] = {0u, 0u, 0u, 0u}, sum[kWalksPerLane] = {0u, 0u, 0u, 0u};
+        for (int32_t b = 0; b < a.k; ++b) {
+            const uint8_t* src = a.bitmaps + ((int64_t)b * a.B8 + j8) * a.W + w0;
+            uint32_t q = 0;
+            if (vec && full) {
+                q = *reinterpret_cast<const uint32_t*>(src);
             } else {
-                bad |= 4u;
+#pragma unroll
+                for (int i = 0; i < kWalksPerLane; ++i)
+                    if (w0 + i < a.W) q |= (uint32_t)src[i] << (8 * i);
+            }
+#pragma unroll
+            for (int i = 0; i < kWalksPerLane; ++i) {
+                const uint32_t by = (q >> (8 * i)) & 255u;
+                any[i] |= by;
+                sum[i] += __popc(by);
+                cw[i] |= spread_nibbles(by) * (uint32_t)b;
             }
         }
+        const int32_t valid = min(8, a.L - 8 * j8);
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-            if (live && 8 * j8 + t < a.L) a.data[(int64_t)(8 * j8 + t) * a.W + w] = v[t];
+        for (int i = 0; i < kWalksPerLane; ++i)
+            if (sum[i] != (uint32_t)__popc(any[i]) || (any[i] >> valid) != 0u) bad |= 1u;
+        for (int t = 0; t < 8; ++t) {
+            const int32_t j = 8 * j8 + t;
+            if (j >= a.L) break;
+            int hit[kWalksPerLane];
+            bool f[kWalksPerLane];
+#pragma unroll
+            for (int i = 0; i < kWalksPerLane; ++i) {
+                hit[i] = ((any[i] >> t) & 1u) ? (int)((cw[i] >> (4 * t)) & 15u) : -1;
+                f[i] = w0 + i < a.W && hit[i] < 0;
+            }
+            uint32_t slot[kWalksPerLane], total;
+            wave_slots(f, slot, &total);
+            int32_t v[kWalksPerLane];
+#pragma unroll
+            for (int i = 0; i < kWalksPerLane; ++i) {
+                v[i] = -1;
+                if (hit[i] >= 0 && hit[i] < a.k) {
+                    v[i] = a.symbols[hit[i]];
+                } else if (f[i]) {
+                    if (at + slot[i] < a.R) {
+                        v[i] = a.residuals[at + slot[i]];
+                        if (v[i] < -1 || v[i] >= a.n) {
+                            bad |= 8u;
+                            v[i] = -1;
+                        }
+                    } else {
+                        bad |= 4u;
+                    }
+                }
+            }
+            at += total;
+            int32_t* row = a.data + (int64_t)j * a.W;
+            if (vec && full) {
+                *reinterpret_cast<int4*>(row + w0) = make_int4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < kWalksPerLane; ++i)
+                    if (w0 + i < a.W) row[w0 + i] = v[i];
+            }
+        }
     }
-    if (threadIdx.x == 0 && at != next) bad |= 2u;
+    if ((threadIdx.x & 63) == 0 && at != next) bad |= 2u;
     if (bad) atomicOr(a.err, bad);
 }
 
@@ -436,26 +502,20 @@ void fabc_pack(const Walks& w, int32_t k, const int32_t* symbols, Packed& p, dou
 {
     Ctx& c = *w.g->ctx;
     c.make_current();
-    const int64_t n = w.g->n, W = w.W;
+    const int64_t W = w.W;
     const int32_t L = w.L;
     const int64_t nblk = (W + kFabcBlock - 1) / kFabcBlock;
-    DevBuf codes, syms, block_res, offs;
-    codes.alloc(&c, (size_t)n + 1);
-    syms.alloc(&c, sizeof(int32_t) * kFabcMax);
+    DevBuf block_res, offs;
+    Symbols sy{};
+    for (int b = 0; b < k; ++b) sy.s[b] = symbols[b];
     block_res.alloc(&c, sizeof(unsigned long long) * std::max<int64_t>(nblk, 1));
     offs.alloc(&c, sizeof(unsigned long long) * (nblk + 1));
-    FELOG_HIP(hipMemsetAsync(codes.ptr, 0xff, codes.bytes, c.stream));
-    if (k > 0)
-        FELOG_HIP(hipMemcpyAsync(syms.ptr, symbols, sizeof(int32_t) * k, hipMemcpyHostToDevice,
-                                 c.stream));
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
-    hipLaunchKernelGGL(fabc_codes_kernel, dim3(1), dim3(64), 0, c.stream, codes.as<int8_t>(),
-                       syms.as<int32_t>(), k);
     if (nblk > 0)
-        hipLaunchKernelGGL(fabc_pack_count_kernel, dim3(nblk), dim3(kFabcBlock), 0, c.stream,
-                           w.data.as<int32_t>(), W, L, codes.as<int8_t>(),
-                           block_res.as<unsigned long long>());
-    hipLaunchKernelGGL(fabc_offsets_kernel, dim3(1), dim3(kFabcBlock), 0, c.stream,
+        hipLaunchKernelGGL(fabc_pack_count_kernel, dim3((nblk + 3) / 4), dim3(256), 0, c.stream,
+                           w.data.as<int32_t>(), W, L, sy, k, block_res.as<unsigned long long>(),
+                           nblk);
+    hipLaunchKernelGGL(fabc_offsets_kernel, dim3(1), dim3(kOffsetsThreads), 0, c.stream,
                        block_res.as<unsigned long long>(), nblk, offs.as<unsigned long long>());
     FELOG_HIP(hipEventRecord(c.ev1, c.stream));
     unsigned long long R = 0;
@@ -491,10 +551,11 @@ void fabc_pack(const Walks& w, int32_t k, const int32_t* symbols, Packed& p, dou
                                  hipMemcpyDeviceToDevice, c.stream));
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     if (nblk > 0) {
-        PackArgs a{w.data.as<int32_t>(), W, L, k, (L + 7) / 8, codes.as<int8_t>(), base + o_bm,
+        PackArgs a{w.data.as<int32_t>(), W, nblk, L, k, (L + 7) / 8, sy, base + o_bm,
                    reinterpret_cast<const unsigned long long*>(base + o_off),
                    reinterpret_cast<int32_t*>(base + o_res)};
-        hipLaunchKernelGGL(fabc_pack_write_kernel, dim3(nblk), dim3(kFabcBlock), 0, c.stream, a);
+        hipLaunchKernelGGL(fabc_pack_write_kernel, dim3((nblk + 3) / 4), dim3(256), 0, c.stream,
+                           a);
     }
     FELOG_HIP(hipGetLastError());
     FELOG_HIP(hipEventRecord(c.ev1, c.stream));
@@ -566,12 +627,12 @@ void fabc_unpack(const Packed& p, Walks& w, double* ms)
     const int64_t nblk = (p.W + kFabcBlock - 1) / kFabcBlock;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     if (nblk > 0) {
-        UnpackArgs a{p.W, p.L, p.k, (p.L + 7) / 8, p.g->n,
+        UnpackArgs a{p.W, nblk, p.L, p.k, (p.L + 7) / 8, p.g->n,
                      reinterpret_cast<const int32_t*>(base + 32), base + o_bm,
                      reinterpret_cast<const unsigned long long*>(base + o_off),
                      reinterpret_cast<const int32_t*>(base + o_res),
                      (unsigned long long)p.R, w.data.as<int32_t>(), err.as<uint32_t>()};
-        hipLaunchKernelGGL(fabc_unpack_kernel, dim3(nblk), dim3(kFabcBlock), 0, c.stream, a);
+        hipLaunchKernelGGL(fabc_unpack_kernel, dim3((nblk + 3) / 4), dim3(256), 0, c.stream, a);
     }
     FELOG_HIP(hipGetLastError());
     FELOG_HIP(hipEventRecord(c.ev1, c.stream));
