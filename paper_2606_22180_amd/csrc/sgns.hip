@@ -155,17 +155,19 @@ __global__ __launch_bounds__(256) void sgns_prep_kernel(PrepArgs a)
 // Items: the in-touches i (touch i (K+2)) and, in further blocks, the
 // out-touches e (touch (e / (K+1)) (K+2) + 1 + e mod (K+1)).  A first touch
 // (rank 0) lists its row; the scanned values are (entries | chunks << 32),
-// the rows listed, the rows split over chunks and their chunks.
+// the rows listed, the rows split over chunks, their chunks and the out rows
+// touched once (which the forward updates itself).
 constexpr int kScanT = 256, kScanI = 8, kScanSpanS = kScanT * kScanI;
 
 struct ScanArgs {
     const int32_t* touch_row;
     const uint32_t* touch_pos;
     const uint32_t* cnt_in;
-    const uint32_t* cnt_out;
+    uint32_t* cnt_out;             // single-touch rows are reset here
     uint32_t n_in, n_out, nb_in;
     unsigned long long* part_ec;   // per block
-    uint4* part_rm;                // per block: rows, split rows, chunks of split rows
+    uint4* part_rm;                // per block: rows, split rows, chunks of split rows,
+                                   // single-touch out rows
     int32_t* list_in;
     int32_t* list_out;
     int32_t* off_in;
@@ -232,15 +234,21 @@ __device__ __forceinline__ uint4 add4(uint4 a, uint4 b)
     return make_uint4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
 }
 
-__device__ __forceinline__ uint4 split_counts(uint32_t c)
+// An out row with a single touch in the minibatch is read and written by that
+// touch's pair only, so the forward adds its delta in place: it gets no
+// segment entry and no work item.
+__device__ __forceinline__ bool single_out(uint32_t c, bool out) { return out && c == 1u; }
+
+__device__ __forceinline__ uint4 split_counts(uint32_t c, bool out)
 {
     const uint32_t nch = (c + kChunk - 1) / kChunk;
-    return make_uint4(1u, nch > 1 ? 1u : 0u, nch > 1 ? nch : 0u, 0u);
+    return make_uint4(1u, nch > 1 ? 1u : 0u, nch > 1 ? nch : 0u, single_out(c, out) ? 1u : 0u);
 }
 
-__device__ __forceinline__ unsigned long long pack_ec(uint32_t c)
+__device__ __forceinline__ unsigned long long pack_ec(uint32_t c, bool out)
 {
-    return (unsigned long long)c | ((unsigned long long)((c + kChunk - 1) / kChunk) << 32);
+    const uint32_t e = single_out(c, out) ? 0u : c;
+    return (unsigned long long)e | ((unsigned long long)((e + kChunk - 1) / kChunk) << 32);
 }
 
 template <int K, bool BATCH>
@@ -260,8 +268,8 @@ __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
 #pragma unroll
     for (int k = 0; k < kScanI; ++k) {
         if (rows[k] >= 0) {
-            ec += pack_ec(cs[k]);
-            rm = add4(rm, split_counts(cs[k]));
+            ec += pack_ec(cs[k], out);
+            rm = add4(rm, split_counts(cs[k], out));
         }
     }
     s_ec[threadIdx.x] = ec;
@@ -320,8 +328,8 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
 #pragma unroll
     for (int k = 0; k < kScanI; ++k) {
         if (rows[k] >= 0) {
-            mine += pack_ec(cs[k]);
-            mine_rm = add4(mine_rm, split_counts(cs[k]));
+            mine += pack_ec(cs[k], out);
+            mine_rm = add4(mine_rm, split_counts(cs[k], out));
         }
     }
     // block exclusive scans
@@ -341,6 +349,7 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
     uint32_t slot = blk_rm.x + at.x - mine_rm.x;    // list slot
     uint32_t mrow = blk_rm.y + at.y - mine_rm.y;    // split-row index
     uint32_t mchunk = blk_rm.z + at.z - mine_rm.z;  // first chunk of the next split row
+    uint32_t sgl = blk_rm.w + at.w - mine_rm.w;     // single-touch out rows before
     uint32_t entry = (uint32_t)run;
     int32_t* list = out ? a.list_out : a.list_in;
     int32_t* off = out ? a.off_out : a.off_in;
@@ -351,26 +360,35 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
     for (int k = 0; k < kScanI; ++k) {
         if (rows[k] >= 0) {
             const uint32_t c = cs[k];
-            const uint32_t nch = (c + kChunk - 1) / kChunk;
             list[slot] = rows[k];
-            off[rows[k]] = (int32_t)entry;
-            if (nch == 1) {
-                chunks[slot - mrow] = make_int4(rows[k], (int32_t)entry, (int32_t)c, (int32_t)slot);
+            if (single_out(c, out)) {
+                // the forward adds this row's delta; -1 - slot marks it and
+                // carries its list slot
+                off[rows[k]] = -1 - (int32_t)slot;
+                a.cnt_out[rows[k]] = 0u;
+                ++sgl;
             } else {
-                mrows[mrow] = make_int4(rows[k], (int32_t)mchunk, (int32_t)nch, (int32_t)slot);
-                for (uint32_t j = 0; j < nch; ++j)
-                    split[mchunk + j] = make_int4(rows[k], (int32_t)(entry + j * kChunk),
-                                                  (int32_t)min((uint32_t)kChunk, c - j * kChunk),
-                                                  (int32_t)(mchunk + j));
-                ++mrow;
-                mchunk += nch;
+                const uint32_t nch = (c + kChunk - 1) / kChunk;
+                off[rows[k]] = (int32_t)entry;
+                if (nch == 1) {
+                    chunks[slot - mrow - sgl] =
+                        make_int4(rows[k], (int32_t)entry, (int32_t)c, (int32_t)slot);
+                } else {
+                    mrows[mrow] = make_int4(rows[k], (int32_t)mchunk, (int32_t)nch, (int32_t)slot);
+                    for (uint32_t j = 0; j < nch; ++j)
+                        split[mchunk + j] = make_int4(rows[k], (int32_t)(entry + j * kChunk),
+                                                      (int32_t)min((uint32_t)kChunk, c - j * kChunk),
+                                                      (int32_t)(mchunk + j));
+                    ++mrow;
+                    mchunk += nch;
+                }
+                entry += c;
             }
-            entry += c;
             ++slot;
         }
         if (base + k + 1 == n) {   // the table's last item: totals
             a.meta[out ? 1 : 0] = slot;
-            a.meta[out ? 3 : 2] = slot - mrow;   // rows of one chunk
+            a.meta[out ? 3 : 2] = slot - mrow - sgl;   // rows of one chunk
             a.meta[out ? 5 : 4] = mrow;          // split rows
             a.meta[out ? 7 : 6] = mchunk;        // their chunks
         }
@@ -380,7 +398,7 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
 // ---------------------------------------------------------------- forward
 struct FwdArgs {
     const float* __restrict__ tin;
-    const float* __restrict__ tout;
+    float* __restrict__ tout;      // single-touch out rows are updated here
     const int32_t* __restrict__ touch_row;
     const uint32_t* __restrict__ touch_pos;
     const int32_t* __restrict__ off_in;
@@ -393,6 +411,7 @@ struct FwdArgs {
     float* dinp;             // [P][d] sum_k g_k out[t_k] by in-row segment position
     uint32_t* key_in;        // the pair p, same position
     double* loss_part;       // one slot per wave
+    float* cap_out;          // capture != NULL: single-touch out-row deltas to cap_out[slot][d]
 };
 
 // Sum over the L lanes of a lane group (L = 16 or 32).
@@ -424,16 +443,23 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
     const int np = (int)min((uint32_t)a.ppw, a.npairs - q0);
 
     // ---- touch metadata: lane l < np T holds touch l of the wave's pairs and
-    //      its position in its row's segment
+    //      its position in its row's segment, or, for an out row touched once
+    //      in the minibatch, the row's list slot (and a bit in `single`)
     int32_t m_row = -1;
     uint32_t m_pos = 0;
+    bool m_single = false;
     if (lane < np * T) {
         const uint32_t t = q0 * T + lane;
         m_row = a.touch_row[t];
         const uint32_t rk = a.touch_pos[t];
         const bool in = (lane % T) == 0;
-        if (m_row >= 0) m_pos = (uint32_t)(in ? a.off_in : a.off_out)[m_row] + rk;
+        if (m_row >= 0) {
+            const int32_t off = (in ? a.off_in : a.off_out)[m_row];
+            m_single = off < 0;
+            m_pos = m_single ? (uint32_t)(-1 - off) : (uint32_t)off + rk;
+        }
     }
+    const unsigned long long single = __ballot(m_single);
 
     double lacc = 0.0;
     for (int base = 0; base < np; base += G) {
@@ -492,10 +518,34 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
                 }
             if (k <= K && live && tk >= 0) {
                 const uint32_t pos = h == 0 ? my_pos : my_pos_hi;
-                a.ent_out[pos] = make_int2(__float_as_int(gk), ctx);
-                a.key_out[pos] = q * (K + 1) + (uint32_t)k;
+                if (!((single >> (src + 1 + k)) & 1ull)) {
+                    a.ent_out[pos] = make_int2(__float_as_int(gk), ctx);
+                    a.key_out[pos] = q * (K + 1) + (uint32_t)k;
+                }
                 // -log sigma(s0) for the centre, -log sigma(-s_k) for a negative
                 lacc += (double)neg_log_sigmoid(k == 0 ? dk : -dk);
+            }
+        }
+        // out rows touched once: row + g in[ctx], rounded as a one-term sum
+        // added to the row (or the delta alone, when capturing)
+#pragma unroll
+        for (int k = 0; k <= K; ++k) {
+            uint32_t slot = 0;
+            if (a.cap_out) slot = __shfl(m_pos, src + 1 + k);   // uniform branch
+            if (live && t[k] >= 0 && ((single >> (src + 1 + k)) & 1ull)) {
+                float4* dst = reinterpret_cast<float4*>(
+                    a.cap_out ? a.cap_out + (int64_t)slot * D : a.tout + (int64_t)t[k] * D);
+#pragma unroll
+                for (int i = 0; i < V4; ++i) {
+                    float4 d = make_float4(fmaf(g[k], vin[i].x, 0.0f), fmaf(g[k], vin[i].y, 0.0f),
+                                           fmaf(g[k], vin[i].z, 0.0f), fmaf(g[k], vin[i].w, 0.0f));
+                    const float4 base = a.cap_out ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : vo[k][i];
+                    d.x = base.x + d.x;
+                    d.y = base.y + d.y;
+                    d.z = base.z + d.z;
+                    d.w = base.w + d.w;
+                    dst[i * LPP + gl] = d;
+                }
             }
         }
         if (live) {
@@ -882,6 +932,7 @@ static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const Miniba
     fa.touch_pos = mb.touch_pos.as<uint32_t>();
     fa.off_in = mb.off_in.as<int32_t>();
     fa.off_out = mb.off_out.as<int32_t>();
+    fa.cap_out = cap_out;
     if (ev) FELOG_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL((sgns_forward_kernel<D, K>), dim3(ml.fwd_blocks), dim3(256), 0, s, fa);
     if (ev) FELOG_HIP(hipEventRecord(ev[1], s));
