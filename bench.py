@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "SGNS pair-updates/s + walk steps/s at matched link-pred AUC; p99 job latency"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0     # dense BF16 MFMA
-COUNTERS = os.path.join(ROOT, "profiles", "sgns_apply_rmat20_counters.json")
-APPLY_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "sgns_rmat20_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
 
 
 def log(*a):
@@ -44,14 +44,14 @@ def auc_score(emb: np.ndarray, pos: np.ndarray, neg: np.ndarray) -> float:
     return float(roc_auc_score(y, np.r_[sp, sn]))
 
 
-def apply_traffic():
-    """HBM bytes per first apply launch from the committed rocprofv3 counters,
+def kernel_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counters,
     if they were taken on the current kernel source; else None."""
     if not os.path.exists(COUNTERS):
         return None
     rec = json.load(open(COUNTERS))
-    src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != src:
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != src or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
 
@@ -278,7 +278,8 @@ def main():
             tr = felog.felog_train_stats()
             for b0 in range(0, B, args.progress_every):
                 s = M.train_steps(W, rp.train, b0, args.progress_every)
-                for f in ("minibatches", "pairs", "rows_in", "rows_out", "timed_launches"):
+                for f in ("minibatches", "pairs", "rows_in", "rows_out", "rows_out_single",
+                          "timed_launches"):
                     setattr(tr, f, getattr(tr, f) + getattr(s, f))
                 for f in ("loss", "ms", "ms_forward", "ms_apply", "ms_prep", "ms_apply_first"):
                     setattr(tr, f, getattr(tr, f) + getattr(s, f))
@@ -323,7 +324,7 @@ def main():
     pairs = walk_steps = 0
     fwd_ms = apply_ms = prep_ms = apply0_ms = 0.0
     timed = 0
-    mbs = rows = rows_in = rows_out = 0
+    mbs = rows = rows_in = rows_out = rows_single = 0
     ms_walk = 0.0
     for r in range(R):
         tr = st.train[r]
@@ -338,6 +339,7 @@ def main():
         rows += tr.rows_in + tr.rows_out
         rows_in += tr.rows_in
         rows_out += tr.rows_out
+        rows_single += tr.rows_out_single
         ms_walk += st.ms_walk[r]
         rounds.append(dict(active=int(st.active[r]), walks=int(st.walks[r]),
                            walk_steps=int(st.walk_steps[r]), pairs=int(tr.pairs),
@@ -357,16 +359,20 @@ def main():
     log("pairs/step=%d walk_steps/step=%d value=%.4g pairs/s auc=%.4f" % (
         pairs_per_step, walk_steps, value, auc))
 
-    # Roofline of the dominant kernel by time, the first apply launch
-    # (sgns_apply_kernel<d, 0>): the out-rows' sums.  Its algorithmic bytes per
-    # launch: each distinct out row read and written once (d*8 B), each distinct
-    # in row (a pair's context) read once (d*4 B), and 12 B per out touch (its
-    # coefficient, context id and pair-order key).  Rows with more than 16
-    # touches are summed here and written by the second launch; their writes are
-    # counted here.  The forward reads every distinct row once (d*4 B), the
-    # pair's two node ids (8 B) and one 8 B cumulative-weight read per negative.
+    # Roofline of the dominant kernel by time (the events decide): the forward
+    # or the first apply launch.  Algorithmic bytes per launch:
+    #  - forward: every distinct touched row read once (d*4 B), the out rows
+    #    touched once in their minibatch written once (d*4 B; the forward
+    #    applies them), the pair's two node ids (8 B) and one 8 B cumulative
+    #    weight per negative;
+    #  - first apply launch (sgns_apply_kernel<d, 0>, the other out rows' sums):
+    #    those out rows read and written once (d*8 B), each distinct in row (a
+    #    pair's context) read once (d*4 B) and 12 B per out touch it sums (its
+    #    coefficient, context id and pair-order key).  Rows with more than 16
+    #    touches are summed here and written by the second launch; their writes
+    #    are counted here.
     # The whole minibatch update (ids, the destination sort, forward, both apply
-    # launches) also writes each touched row once: rows*d*8 + pairs*(8 + 8K).
+    # launches) reads and writes each touched row once: rows*d*8 + pairs*(8 + 8K).
     # Durations come from HIP events on every timing_every-th minibatch, on the
     # stream the kernels run on; the id work of later minibatches runs
     # concurrently on a second stream, so the durations include that contention.
@@ -374,30 +380,36 @@ def main():
     K = cfg["K"]
     row_bytes = rows * d * 4
     id_bytes = pairs * (8 + 8 * K)
-    per_apply0 = (rows_out * d * 8 + rows_in * d * 4 + pairs * (K + 1) * 12) / max(1, mbs)
-    per_fwd = (row_bytes + id_bytes) / max(1, mbs)
+    multi_out = rows_out - rows_single
+    out_touches = pairs * (K + 1)
+    per_apply0 = (multi_out * d * 8 + rows_in * d * 4 + (out_touches - rows_single) * 12) / max(1, mbs)
+    per_fwd = (row_bytes + rows_single * d * 4 + id_bytes) / max(1, mbs)
     per_update = (2 * row_bytes + id_bytes) / max(1, mbs)
     avg_apply0_s = apply0_ms / 1e3 / max(1, timed)
     avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
     # the next minibatches' ids overlap this one's update, so the update's cost is
     # the training wall time per minibatch
     avg_upd_s = sum(st.train[r].ms for r in range(R)) / 1e3 / max(1, mbs)
-    achieved = per_apply0 / avg_apply0_s / 1e9 if timed else None
-    fwd_achieved = per_fwd / avg_fwd_s / 1e9 if timed else None
+
+    def kernel_roof(name, per, avg_s):
+        ach = per / avg_s / 1e9 if timed else None
+        return {"kernel": name, "algorithmic_bytes_per_launch": per, "avg_launch_us": avg_s * 1e6,
+                "achieved": ach, "frac": (ach / HBM_PEAK_GBS) if ach else None}
+
+    fwd = kernel_roof("sgns_forward_kernel<%d, %d>" % (d, K), per_fwd, avg_fwd_s)
+    ap0 = kernel_roof("sgns_apply_kernel<%d, 0>" % d, per_apply0, avg_apply0_s)
+    dom, other = (fwd, ap0) if avg_fwd_s >= avg_apply0_s else (ap0, fwd)
     upd_achieved = per_update / avg_upd_s / 1e9 if timed else None
-    roof = {"bound": "hbm", "kernel": "sgns_apply_kernel<%d, 0>" % d,
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": apply_traffic(),
-            "algorithmic_bytes_per_launch": per_apply0, "avg_launch_us": avg_apply0_s * 1e6,
-            "timed_launches": timed,
+    roof = {"bound": "hbm", "kernel": dom["kernel"],
+            "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["frac"], "traffic": kernel_traffic(dom["kernel"]),
+            "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
+            "avg_launch_us": dom["avg_launch_us"], "timed_launches": timed,
             "touched_rows_per_minibatch": rows / max(1, mbs),
             "in_rows_per_minibatch": rows_in / max(1, mbs),
             "out_rows_per_minibatch": rows_out / max(1, mbs),
-            "forward": {"kernel": "sgns_forward_kernel<%d, %d>" % (d, K),
-                        "algorithmic_bytes_per_launch": per_fwd,
-                        "avg_launch_us": avg_fwd_s * 1e6, "achieved": fwd_achieved,
-                        "frac": (fwd_achieved / HBM_PEAK_GBS) if fwd_achieved else None},
+            "out_rows_touched_once_per_minibatch": rows_single / max(1, mbs),
+            "other_kernel": other,
             "sgns_update": {"kernels": "prep and scan (second stream), forward, two apply "
                                        "launches",
                             "avg_prep_us": prep_ms / 1e3 / max(1, timed) * 1e6,

@@ -281,6 +281,8 @@ typedef struct felog_train_stats {
                               /* launches that precede each timed forward          */
     double ms_apply_first;    /* summed duration of the first of the timed apply
                                  launches (out rows, chunks of split rows)         */
+    int64_t rows_out_single;  /* of rows_out, the rows touched once in their
+                                 minibatch (updated by the forward launch)          */
 } felog_train_stats;
 
 /* One Train() call: every minibatch of the corpus in order.  Pairs: within each

@@ -168,7 +168,8 @@ struct Model {
     int64_t split_rows_in = 0;    // partial rows reserved for the in-table; the out-table's follow
     DevBuf meta;                  // uint32 [kIdSets][16]: list lengths and counts, by id set
     DevBuf loss_out;              // double [1]
-    DevBuf row_totals;            // uint64 [2]: summed touched-list lengths (in, out)
+    DevBuf row_totals;            // uint64 [3]: summed touched-list lengths (in, out) and
+                                  // out rows touched once
     // shared-negative (BF16) minibatch scratch
     uint32_t bf_P = 0, bf_M = 0;
     DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0;

@@ -86,7 +86,7 @@ static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_param
     while (pow2 < n) pow2 <<= 1;
     uint64_t b = 0;
     b += 8 * (n + 1) + 4 * nnz + 4 * n + 16;                     // CSR, row maxima, check word
-    b += 8 * n * dim + 16 * n + 4 * 16 * kIdSets + 16 + 16;      // tables, counters, offsets
+    b += 8 * n * dim + 16 * n + 4 * 16 * kIdSets + 24 + 16;      // tables, counters, offsets
     b += 4 * n + 8 * n + 8 * (n / 2048 + 2) + 8 * (n + 1) + 4 * std::max<uint64_t>(pow2, 2);
     b += 4 * W * L + 4 * W + 4 * (W / 2048 + 2) + 8 * (W / (1u << 20) + 2);   // walks
     const uint64_t T = P * (K + 2);                              // touches per minibatch

@@ -789,6 +789,7 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
     if (PHASE == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
         a.row_totals[0] += a.meta[0];
         a.row_totals[1] += a.meta[1];
+        a.row_totals[2] += a.meta[1] - a.meta[3] - a.meta[5];   // out rows touched once
     }
 }
 
@@ -865,7 +866,7 @@ void model_alloc_update_state(Model& m)
         FELOG_HIP(hipMemsetAsync(b.cnt_out.ptr, 0, sizeof(uint32_t) * n, c.stream));
     }
     m.meta.alloc(&c, sizeof(uint32_t) * kIdSets * kMetaWords);
-    m.row_totals.alloc(&c, sizeof(uint64_t) * 2);
+    m.row_totals.alloc(&c, sizeof(uint64_t) * 3);
     m.loss_out.alloc(&c, sizeof(double));
     FELOG_HIP(hipMemsetAsync(m.meta.ptr, 0, m.meta.bytes, c.stream));
 }
@@ -1105,7 +1106,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     DevBuf loss_part;
     loss_part.alloc(&c, sizeof(double) * blocks * 4);
     FELOG_HIP(hipMemsetAsync(loss_part.ptr, 0, sizeof(double) * blocks * 4, c.stream));
-    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
+    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
 
     std::vector<int32_t> sl = make_slices(w.L, p.window);
     DevBuf slices;
@@ -1289,7 +1290,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
                                  hipMemcpyDeviceToHost, c.stream));
         FELOG_HIP(hipMemcpyAsync(d_out_host, vout.ptr, sizeof(float) * uo * m.dim,
                                  hipMemcpyDeviceToHost, c.stream));
-        FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 2, c.stream));
+        FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
         c.sync();
         if (n_in) *n_in = ui;
         if (n_out) *n_out = uo;
@@ -1300,7 +1301,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     FELOG_HIP(hipGetLastError());
     FELOG_HIP(hipEventRecord(c.ev1, c.stream));
     double loss = 0.0;
-    unsigned long long rows[2] = {0, 0};
+    unsigned long long rows[3] = {0, 0, 0};
     FELOG_HIP(hipMemcpyAsync(&loss, m.loss_out.ptr, sizeof loss, hipMemcpyDeviceToHost, c.stream));
     FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost,
                              c.stream));
@@ -1319,6 +1320,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         stats->ms = ms;
         stats->rows_in = (int64_t)rows[0];
         stats->rows_out = (int64_t)rows[1];
+        stats->rows_out_single = (int64_t)rows[2];
         stats->timed_launches = timed;
         stats->ms_forward = ms_fwd;
         stats->ms_apply = ms_apply;

@@ -62,7 +62,7 @@ class felog_train_stats(C.Structure):
                 ("rows_in", C.c_int64), ("rows_out", C.c_int64),
                 ("timed_launches", C.c_int64), ("ms_forward", C.c_double),
                 ("ms_apply", C.c_double), ("ms_prep", C.c_double),
-                ("ms_apply_first", C.c_double)]
+                ("ms_apply_first", C.c_double), ("rows_out_single", C.c_int64)]
 
 
 class felog_feedback_params(C.Structure):
