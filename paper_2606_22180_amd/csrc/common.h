@@ -158,6 +158,7 @@ struct Model {
     int32_t guide_bits = 0;
     uint64_t total_weight = 0;
     // minibatch scratch, sized for the largest (pairs, negatives) seen
+    bool counters_dirty = false;  // row counters of the id sets may be non-zero
     int64_t cap_pairs = 0;
     int32_t cap_K = 0;
     MinibatchBufs mb[kIdSets];    // by minibatch index mod kIdSets: ids and sort of one minibatch

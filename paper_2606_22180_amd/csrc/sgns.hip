@@ -163,7 +163,7 @@ struct ScanArgs {
     const int32_t* touch_row;
     const uint32_t* touch_pos;
     const uint32_t* cnt_in;
-    uint32_t* cnt_out;             // single-touch rows are reset here
+    uint32_t* cnt_out;
     uint32_t n_in, n_out, nb_in;
     unsigned long long* part_ec;   // per block
     uint4* part_rm;                // per block: rows, split rows, chunks of split rows,
@@ -179,6 +179,8 @@ struct ScanArgs {
     int4* mrows_in;                // split rows: row, first chunk, chunks, list slot
     int4* mrows_out;
     uint32_t* meta;
+    int32_t reset;                 // zero the counters of the rows done here (else the
+                                   // whole counter arrays are zeroed before the ids)
 };
 
 // Items base .. base + kScanI - 1 of a table (n items): the row each one
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
                 // the forward adds this row's delta; -1 - slot marks it and
                 // carries its list slot
                 off[rows[k]] = -1 - (int32_t)slot;
-                a.cnt_out[rows[k]] = 0u;
+                if (a.reset) a.cnt_out[rows[k]] = 0u;
                 ++sgl;
             } else {
                 const uint32_t nch = (c + kChunk - 1) / kChunk;
@@ -628,6 +630,7 @@ struct ApplyArgs {
     float* cap_out;
     unsigned long long* row_totals;
     double grid_c;                // 1.5 * 2^(floor(log2 lr) + 17)
+    int32_t reset;                // zero the counters of the rows done here
 };
 
 // Adds a row's delta to the table, or stores it in the capture buffer.
@@ -692,7 +695,7 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
 #pragma unroll
             for (int e = 0; e < D / 16; ++e) delta[e] = (float)acc[e];
             put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, m.w, delta, gl);
-            if (gl == 0) (out ? a.cnt_out : a.cnt_in)[m.x] = 0;
+            if (a.reset && gl == 0) (out ? a.cnt_out : a.cnt_in)[m.x] = 0;
             continue;
         }
         // out rows draw on in[ctx] with coefficient g, in rows on the per-pair deltas
@@ -783,7 +786,7 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
                 }
         }
         put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, slot, acc, gl);
-        if (gl == 0) (out ? a.cnt_out : a.cnt_in)[row] = 0;
+        if (a.reset && gl == 0) (out ? a.cnt_out : a.cnt_in)[row] = 0;
     }
     // the second launch counts the minibatch's touched rows
     if (PHASE == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -878,6 +881,8 @@ static int64_t max_split_rows(int64_t touches) { return touches / (kChunk + 1) +
 
 // Largest minibatch whose launches all go to the training stream.
 constexpr int64_t kOneStreamPairs = 2048;
+// Zero the row counters whole when n <= this many times the minibatch's touches.
+constexpr int64_t kZeroWholeRatio = 8;
 static int64_t max_split_chunks(int64_t touches) { return touches / 8 + 1; }
 
 // Launch geometry and per-minibatch values of one minibatch.
@@ -888,14 +893,36 @@ struct MinibatchLaunch {
     int64_t split_in;     // partial-sum rows reserved for the in-table (the out-table's follow)
     double grid_c;        // exact-sum grid constant of this minibatch's learning rate
     bool one_stream;      // ids on the training stream (on the critical path)
+    bool zero_whole;      // zero the row counters whole before the ids (else reset rows)
 };
 
 // Ids, ranks and the destination sort of one minibatch (reads only the walks
 // and the noise table, so it may run ahead of the training of earlier ones).
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t* p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        p[i] = 0u;
+}
+
+static void zero_counters(MinibatchBufs& mb, hipStream_t s)
+{
+    const int64_t n = (int64_t)(mb.cnt_in.bytes / sizeof(uint32_t));
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(256), 0, s, mb.cnt_in.as<uint32_t>(), n);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(256), 0, s, mb.cnt_out.as<uint32_t>(), n);
+}
+
+// When the ids run on a second stream and the table is not much larger than
+// the minibatch's touches, the row counters are zeroed whole before each
+// minibatch's ids (two streaming writes of n words beside the training
+// launches) instead of with one scattered write per touched row on the
+// training stream; otherwise the rows are reset as they are done.
 template <int K>
 static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& ml,
                          uint32_t* meta, hipStream_t s)
 {
+    if (ml.zero_whole) zero_counters(mb, s);
     pa.cnt_in = mb.cnt_in.as<uint32_t>();
     pa.cnt_out = mb.cnt_out.as<uint32_t>();
     pa.touch_row = mb.touch_row.as<int32_t>();
@@ -909,7 +936,7 @@ static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& 
                 mb.list_in.as<int32_t>(), mb.list_out.as<int32_t>(), mb.off_in.as<int32_t>(),
                 mb.off_out.as<int32_t>(), mb.chunks_in.as<int4>(), mb.chunks_out.as<int4>(),
                 mb.split_in.as<int4>(), mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),
-                mb.mrows_out.as<int4>(), meta};
+                mb.mrows_out.as<int4>(), meta, ml.zero_whole ? 0 : 1};
     if (ml.one_stream) {
         hipLaunchKernelGGL((sgns_scan_partials<K, true>), dim3(nb), dim3(256), 0, s, sa);
         hipLaunchKernelGGL((sgns_scan_write<K, true>), dim3(nb), dim3(256), 0, s, sa);
@@ -946,7 +973,8 @@ static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const Miniba
                  mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),  mb.mrows_out.as<int4>(),
                  part_in,                 part_out,                mb.cnt_in.as<uint32_t>(),
                  mb.cnt_out.as<uint32_t>(), meta,                  cap_in,
-                 cap_out,                 m.row_totals.as<unsigned long long>(), ml.grid_c};
+                 cap_out,                 m.row_totals.as<unsigned long long>(), ml.grid_c,
+                 ml.zero_whole ? 0 : 1};
     hipLaunchKernelGGL((sgns_apply_kernel<D, 0>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
     if (ev) FELOG_HIP(hipEventRecord(ev[2], s));
     hipLaunchKernelGGL((sgns_apply_kernel<D, 1>), dim3(ml.reduce_blocks), dim3(256), 0, s, aa);
@@ -1140,6 +1168,14 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     // chains of a few dependent loads each, and waiting on another stream's
     // events costs more than the overlap gains.
     const bool one_stream = P <= kOneStreamPairs;
+    const bool zero_whole = !one_stream && (int64_t)m.g->n <= kZeroWholeRatio * P * (K + 2);
+    // minibatches that reset their rows expect zero counters and leave them
+    // zero; the others zero them first and leave them dirty
+    if (!zero_whole && m.counters_dirty) {
+        for (MinibatchBufs& b : m.mb) zero_counters(b, c.stream);
+        m.counters_dirty = false;
+    }
+    if (zero_whole) m.counters_dirty = true;
     // the launch values of minibatch b
     size_t chunk = 0;
     auto frame = [&](int64_t b, MinibatchLaunch& ml, PrepArgs& a) {
@@ -1161,6 +1197,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         ml.reduce_blocks = (uint32_t)std::max(1, c.num_cus * 8);
         ml.split_in = m.split_rows_in;
         ml.one_stream = one_stream;
+        ml.zero_whole = zero_whole;
         const double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
         const float lr32 = (float)lr;
         ml.grid_c = lr32 > 0.0f ? std::ldexp(1.5, std::ilogb(lr32) + 17) : 1.5;

@@ -247,6 +247,31 @@ def test_sgns_epoch_is_deterministic(fl, ctx, sbm):
         assert out[0][2] == out[1][2]
 
 
+def test_minibatch_size_switch_keeps_counters_clean(fl, ctx, sbm):
+    """Large minibatches zero the row counters before their ids and leave them
+    dirty; small ones reset rows as they go and need clean counters at the
+    start.  Training a model at P = 4096 and then at P = 1024 (and back) gives
+    the same tables as a fresh model given the same tables at each switch."""
+    g = sbm.train
+    _say("counter state across minibatch sizes")
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=10, L=40, seed=5)
+    big = fl.train_params(window=5, negatives=5, minibatch_pairs=4096, seed=2)
+    small = fl.train_params(window=5, negatives=5, minibatch_pairs=1024, seed=2)
+    M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=1)
+    for prm, first, n in ((big, 10, 6), (small, 50, 9), (big, 30, 5), (small, 200, 3)):
+        tin, tout = M.read(fl.TABLE_IN), M.read(fl.TABLE_OUT)
+        F = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=1)
+        F.write(fl.TABLE_IN, tin)
+        F.write(fl.TABLE_OUT, tout)
+        a = M.train_steps(W, prm, first, n)
+        b = F.train_steps(W, prm, first, n)
+        assert a.loss == b.loss and a.rows_out == b.rows_out
+        assert np.array_equal(M.read(fl.TABLE_IN), F.read(fl.TABLE_IN))
+        assert np.array_equal(M.read(fl.TABLE_OUT), F.read(fl.TABLE_OUT))
+        F.close()
+
+
 def test_sgns_epoch_auc_matches_oracle(fl, ctx, orc, sbm):
     """Free-running epoch on sbm1k: AUC within 0.005 of the oracle's."""
     g = sbm.train
