@@ -896,21 +896,28 @@ struct MinibatchLaunch {
     bool zero_whole;      // zero the row counters whole before the ids (else reset rows)
 };
 
-// Ids, ranks and the destination sort of one minibatch (reads only the walks
-// and the noise table, so it may run ahead of the training of earlier ones).
-__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t* p, int64_t n)
+// Zeroes a[0, n) and b[0, n): 16-byte stores, then the tails.
+__global__ __launch_bounds__(256) void zero_counters_kernel(uint32_t* a, uint32_t* b, int64_t n)
 {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256)
-        p[i] = 0u;
+    const int64_t n4 = n / 4;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 2 * n4; i += stride) {
+        uint4* p = reinterpret_cast<uint4*>(i < n4 ? a : b);
+        p[i < n4 ? i : i - n4] = z;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (int)(n - 4 * n4)) {
+        a[4 * n4 + threadIdx.x] = 0u;
+        b[4 * n4 + threadIdx.x] = 0u;
+    }
 }
 
 static void zero_counters(MinibatchBufs& mb, hipStream_t s)
 {
     const int64_t n = (int64_t)(mb.cnt_in.bytes / sizeof(uint32_t));
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(256), 0, s, mb.cnt_in.as<uint32_t>(), n);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(256), 0, s, mb.cnt_out.as<uint32_t>(), n);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n / 2 + 255) / 256, 512));
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(blocks), dim3(256), 0, s,
+                       mb.cnt_in.as<uint32_t>(), mb.cnt_out.as<uint32_t>(), n);
 }
 
 // When the ids run on a second stream and the table is not much larger than
@@ -918,6 +925,8 @@ static void zero_counters(MinibatchBufs& mb, hipStream_t s)
 // minibatch's ids (two streaming writes of n words beside the training
 // launches) instead of with one scattered write per touched row on the
 // training stream; otherwise the rows are reset as they are done.
+// Ids, ranks and the destination sort of one minibatch (reads only the walks
+// and the noise table, so it may run ahead of the training of earlier ones).
 template <int K>
 static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& ml,
                          uint32_t* meta, hipStream_t s)
