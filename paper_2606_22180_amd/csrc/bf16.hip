@@ -15,8 +15,8 @@
 // weighs K/M, so the expected update equals Eq. (2) with K negatives per pair.
 //
 // Kernels per minibatch: gather (rows, transposed copies, positive terms),
-// scores (S and G on 64x64 tiles, 4 waves of 32x32), grads (dC and dN on
-// 32x32 tiles, the shared dimension M or P split over a block's 4 waves,
+// scores (S and G on 32x32 tiles, 4 waves of 16x16), grads (dC and dN on
+// 32x32 tiles, the shared dimension M or P split over a block's 8 waves,
 // added to the masters with FP32 atomics; rows repeat only when a node is
 // drawn twice or is both a centre and a negative).
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds 8 consecutive k of row
@@ -157,77 +157,57 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
     }
 }
 
-// S and G on a 64x64 tile per block; wave w computes rows 32 (w / 2), cols 32 (w % 2).
-// The d / 32 steps are unrolled, so every operand load (and the ids the
-// epilogue needs) is in flight before the first MFMA waits.
+// S and G on a 32x32 tile per block; wave w computes the 16x16 tile at rows
+// 16 (w / 2), cols 16 (w % 2), so that 4096 waves (at P = M = 1024) share the
+// latency of the loads, the MFMAs and the epilogue.  The d / 32 steps are
+// unrolled, so every operand load (and the ids the epilogue needs) is in
+// flight before the first MFMA waits.
 template <int D>
 __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
 {
     constexpr int S = D / 32;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const uint32_t r0 = blockIdx.x * 64 + (wv >> 1) * 32;
-    const uint32_t c0 = blockIdx.y * 64 + (wv & 1) * 32;
+    const uint32_t r0 = blockIdx.x * 32 + (wv >> 1) * 16;
+    const uint32_t c0 = blockIdx.y * 32 + (wv & 1) * 16;
     const int li = lane & 15, lk = lane >> 4;
-    bf16x8 fa[S][2], fb[S][2];
+    bf16x8 fa[S], fb[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k)
+    for (int k = 0; k < S; ++k) {
+        fa[k] = load8(a.C + (int64_t)(r0 + li) * D + 32 * k + 8 * lk);
+        fb[k] = load8(a.N + (int64_t)(c0 + li) * D + 32 * k + 8 * lk);
+    }
+    int32_t ctr[4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            fa[k][i] = load8(a.C + (int64_t)(r0 + 16 * i + li) * D + 32 * k + 8 * lk);
-            fb[k][i] = load8(a.N + (int64_t)(c0 + 16 * i + li) * D + 32 * k + 8 * lk);
-        }
-    int32_t ctr[2][4];
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t row = r0 + 4 * lk + q;
+        ctr[q] = row < a.np ? a.ids[a.P + row] : -2;   // -2: no pair in this row
+    }
+    const uint32_t n = c0 + li;
+    const int32_t neg = a.ids[2 * a.P + n];
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t row = r0 + 16 * i + 4 * lk + q;
-            ctr[i][q] = row < a.np ? a.ids[a.P + row] : -2;   // -2: no pair in this row
-        }
-    int32_t negs[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) negs[j] = a.ids[2 * a.P + c0 + 16 * j + li];
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < S; ++k)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[k][i], fb[k][j], acc[i][j], 0, 0, 0);
+    for (int k = 0; k < S; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[k], fb[k], acc, 0, 0, 0);
     const float wk = -a.lr * (float)a.K / (float)a.M;
     const double lw = (double)a.K / (double)a.M;
     double lacc = 0.0;
+    uint32_t gb[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const uint32_t n = c0 + 16 * j + li;
-        const int32_t neg = negs[j];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            uint32_t gb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t row = r0 + 16 * i + 4 * lk + q;
-                const float s = acc[i][j][q];
-                const bool keep = ctr[i][q] != -2 && ctr[i][q] != neg;
-                float g = 0.0f;
-                if (keep) {
-                    g = wk / (1.0f + expf(-s));
-                    lacc += lw * (double)softplus_f(s);           // -(K/M) log sigma(-s)
-                }
-                gb[q] = bf16_rne(g);
-                a.G[(int64_t)row * a.M + n] = (uint16_t)gb[q];
-            }
-            // rows 4 lk .. 4 lk + 3 of column n are consecutive in G^T
-            *reinterpret_cast<uint2*>(a.Gt + (int64_t)n * a.P + r0 + 16 * i + 4 * lk) =
-                make_uint2(gb[0] | (gb[1] << 16), gb[2] | (gb[3] << 16));
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t row = r0 + 4 * lk + q;
+        const float sc = acc[q];
+        const bool keep = ctr[q] != -2 && ctr[q] != neg;
+        float g = 0.0f;
+        if (keep) {
+            g = wk / (1.0f + expf(-sc));
+            lacc += lw * (double)softplus_f(sc);           // -(K/M) log sigma(-s)
         }
+        gb[q] = bf16_rne(g);
+        a.G[(int64_t)row * a.M + n] = (uint16_t)gb[q];
     }
+    // rows 4 lk .. 4 lk + 3 of column n are consecutive in G^T
+    *reinterpret_cast<uint2*>(a.Gt + (int64_t)n * a.P + r0 + 4 * lk) =
+        make_uint2(gb[0] | (gb[1] << 16), gb[2] | (gb[3] << 16));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lacc += __shfl_xor(lacc, off);
     if (lane == 0) {
@@ -386,7 +366,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         m.bf_Gt.alloc(&c, sizeof(uint16_t) * cp * cm);
         m.bf_g0.alloc(&c, sizeof(float) * cp);
     }
-    const uint32_t score_waves = (P / 64) * (M / 64) * 4;
+    const uint32_t score_waves = (P / 32) * (M / 32) * 4;
     const int64_t nslots = (int64_t)P + M + score_waves;
     DevBuf loss_part;
     loss_part.alloc(&c, sizeof(double) * nslots);
@@ -438,7 +418,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         a.mb = (uint32_t)b;
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
         hipLaunchKernelGGL(bf16_gather_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
-        const dim3 sgrid(P / 64, M / 64);
+        const dim3 sgrid(P / 32, M / 32);
         if (d == 64) hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
         else if (d == 128) hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
         else hipLaunchKernelGGL(bf16_scores_kernel<256>, sgrid, dim3(256), 0, c.stream, a);
