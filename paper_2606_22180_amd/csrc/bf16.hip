@@ -103,6 +103,7 @@ __device__ __forceinline__ float softplus_f(float x)
 }
 
 // One wave per row: waves [0, P) pairs, [P, P + M) negatives.
+template <int D>
 __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
 {
     const int lane = threadIdx.x & 63;
@@ -123,11 +124,20 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
             ctr = a.walks[(int64_t)j * a.W + col];
         }
         float dot = 0.0f;
-        for (int e = lane; e < a.d; e += 64) {
-            uint16_t c = ctx >= 0 ? bf16_rne(a.tin[(int64_t)ctx * a.d + e]) : 0;
-            uint16_t o = ctr >= 0 ? bf16_rne(a.tout[(int64_t)ctr * a.d + e]) : 0;
-            a.C[(int64_t)p * a.d + e] = c;
-            a.O[(int64_t)p * a.d + e] = o;
+        float xc[D / 64], xo[D / 64];
+#pragma unroll
+        for (int u = 0; u < D / 64; ++u) {   // all the row loads first
+            const int e = lane + 64 * u;
+            xc[u] = ctx >= 0 ? a.tin[(int64_t)ctx * D + e] : 0.0f;
+            xo[u] = ctr >= 0 ? a.tout[(int64_t)ctr * D + e] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < D / 64; ++u) {
+            const int e = lane + 64 * u;
+            const uint16_t c = ctx >= 0 ? bf16_rne(xc[u]) : 0;
+            const uint16_t o = ctr >= 0 ? bf16_rne(xo[u]) : 0;
+            a.C[(int64_t)p * D + e] = c;
+            a.O[(int64_t)p * D + e] = o;
             a.Ct[(int64_t)e * a.P + p] = c;
             dot = fmaf(bf16_to_f32(c), bf16_to_f32(o), dot);
         }
@@ -148,9 +158,14 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
         uint32_t lo = (m & 1) ? r.v[2] : r.v[0];
         uint32_t hi = (m & 1) ? r.v[3] : r.v[1];
         const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
-        for (int e = lane; e < a.d; e += 64) {
-            uint16_t x = bf16_rne(a.tout[(int64_t)neg * a.d + e]);
-            a.N[(int64_t)m * a.d + e] = x;
+        float xn[D / 64];
+#pragma unroll
+        for (int u = 0; u < D / 64; ++u) xn[u] = a.tout[(int64_t)neg * D + lane + 64 * u];
+#pragma unroll
+        for (int u = 0; u < D / 64; ++u) {
+            const int e = lane + 64 * u;
+            const uint16_t x = bf16_rne(xn[u]);
+            a.N[(int64_t)m * D + e] = x;
             a.Nt[(int64_t)e * a.M + m] = x;
         }
         if (lane == 0) a.ids[2 * a.P + m] = neg;
@@ -417,7 +432,9 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         a.np = (uint32_t)np;
         a.mb = (uint32_t)b;
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
-        hipLaunchKernelGGL(bf16_gather_kernel, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        if (d == 64) hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        else if (d == 128) hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        else hipLaunchKernelGGL(bf16_gather_kernel<256>, dim3(row_blocks), dim3(256), 0, c.stream, a);
         const dim3 sgrid(P / 32, M / 32);
         if (d == 64) hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
         else if (d == 128) hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
