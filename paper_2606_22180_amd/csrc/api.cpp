@@ -175,6 +175,10 @@ void felog_ctx_destroy(felog_ctx* ctx)
     ctx->make_current();
     (void)hipStreamSynchronize(ctx->stream);
     ctx->release_aux();
+    if (ctx->walk_stream) {
+        (void)hipStreamSynchronize(ctx->walk_stream);
+        (void)hipStreamDestroy(ctx->walk_stream);
+    }
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     for (hipEvent_t e : ctx->timing_pool) (void)hipEventDestroy(e);
@@ -802,6 +806,74 @@ felog_status felog_feedback(felog_model* m, const felog_feedback_params* params,
 }
 
 // --------------------------------------------------------------------- run
+// One round's walks and training with the walks written chunk by chunk on the
+// context's walk stream: the ids of training chunk k wait for the event of
+// walk chunk k only.  *ms_walk is the walk launches' time on their stream.
+static void walk_then_train(Model& m, Walks& w, const felog_walk_params& wp,
+                            const Active* starts, int64_t n_starts,
+                            const felog_train_params& tp, felog_train_stats& ts, double* ms_walk)
+{
+    Ctx& c = *m.ctx;
+    const int64_t chunk = chunk_walks_of(tp);
+    FELOG_REQUIRE(chunk >= 1, "chunk_walks must be >= 1");
+    plan_valid_columns(w, starts, n_starts, chunk);   // needs no walks; one host sync
+    if (!c.walk_stream) FELOG_HIP(hipStreamCreateWithFlags(&c.walk_stream, hipStreamNonBlocking));
+    const int64_t n_chunks = (w.W + chunk - 1) / chunk;
+    hipEvent_t t0 = nullptr, t1 = nullptr, after = nullptr;
+    FELOG_HIP(hipEventCreate(&t0));
+    FELOG_HIP(hipEventCreate(&t1));
+    FELOG_HIP(hipEventCreateWithFlags(&after, hipEventDisableTiming));
+    w.chunk_ready.assign(n_chunks, nullptr);
+    DevBuf cap;
+    struct Cleanup {
+        Ctx& c;
+        Walks& w;
+        hipEvent_t* ev[3];
+        ~Cleanup()
+        {
+            // every walk launch has ended before its events go
+            if (c.walk_stream) (void)hipStreamSynchronize(c.walk_stream);
+            for (hipEvent_t& e : w.chunk_ready)
+                if (e) (void)hipEventDestroy(e);
+            w.chunk_ready.clear();
+            for (hipEvent_t* e : ev)
+                if (*e) (void)hipEventDestroy(*e);
+        }
+    } cleanup{c, w, {&t0, &t1, &after}};
+    for (hipEvent_t& e : w.chunk_ready)
+        FELOG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    unsigned long long* d_capped = nullptr;
+    if (wp.kind != FELOG_WALK_UNIFORM) {
+        cap.alloc(&c, sizeof(unsigned long long));
+        FELOG_HIP(hipMemsetAsync(cap.ptr, 0, sizeof(unsigned long long), c.stream));
+        d_capped = cap.as<unsigned long long>();
+    }
+    // the walks follow everything already queued for the model (start list, tables)
+    FELOG_HIP(hipEventRecord(after, c.stream));
+    FELOG_HIP(hipStreamWaitEvent(c.walk_stream, after, 0));
+    FELOG_HIP(hipEventRecord(t0, c.walk_stream));
+    for (int64_t k = 0; k < n_chunks; ++k) {
+        const int64_t col0 = k * chunk;
+        launch_walk_columns(w, wp, starts, n_starts, col0, std::min(chunk, w.W - col0),
+                            c.walk_stream, d_capped);
+        FELOG_HIP(hipEventRecord(w.chunk_ready[k], c.walk_stream));
+    }
+    FELOG_HIP(hipEventRecord(t1, c.walk_stream));
+    train_minibatches(m, w, tp, 0, -1, true, &ts, nullptr, nullptr, 0, nullptr, nullptr,
+                      nullptr, 0, nullptr);
+    FELOG_HIP(hipEventSynchronize(t1));
+    float ms = 0.0f;
+    FELOG_HIP(hipEventElapsedTime(&ms, t0, t1));
+    *ms_walk = ms;
+    w.capped = 0;
+    if (d_capped) {
+        unsigned long long h = 0;
+        FELOG_HIP(hipMemcpyAsync(&h, d_capped, sizeof h, hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+        w.capped = (int64_t)h;
+    }
+}
+
 felog_status felog_run(felog_model* m, const felog_run_params* p, felog_run_stats* stats)
 {
     return guarded([&] {
@@ -825,24 +897,32 @@ felog_status felog_run(felog_model* m, const felog_run_params* p, felog_run_stat
             w->W = n_active * wp.walks_per_node;
             w->id_base = id_base;
             w->data.alloc(c, sizeof(int32_t) * std::max<int64_t>(w->W * w->L, 1));
-            FELOG_HIP(hipEventRecord(c->ev0, c->stream));
-            launch_walks(*w, wp, act.get(), n_active);
-            FELOG_HIP(hipEventRecord(c->ev1, c->stream));
-            c->sync();
-            float ms = 0;
-            FELOG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-            st.ms_walk[r] = ms;
-            if (!m->have_noise) {
+            felog_train_stats& ts = st.train[r];
+            if (m->have_noise) {
+                // Section 5.3's overlap of sampling and training, on one GPU:
+                // chunk k + 1 of the round's walks is written on a third stream
+                // while the SGNS of chunk k runs.  The walks do not read the
+                // tables, so the result is the same as walking first.
+                check_train_params(m, w.get(), &p->train);
+                walk_then_train(*m, *w, wp, act.get(), n_active, p->train, ts, &st.ms_walk[r]);
+            } else {
+                // the round-1 unigram noise needs the whole corpus first
+                FELOG_HIP(hipEventRecord(c->ev0, c->stream));
+                launch_walks(*w, wp, act.get(), n_active);
+                FELOG_HIP(hipEventRecord(c->ev1, c->stream));
+                c->sync();
+                float ms = 0;
+                FELOG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                st.ms_walk[r] = ms;
                 DevBuf counts;
                 counts.alloc(c, sizeof(uint32_t) * m->g->n);
                 launch_corpus_counts(*w, counts.as<uint32_t>());
                 build_noise_from_counts(*m, counts.as<uint32_t>());
                 c->sync();
+                check_train_params(m, w.get(), &p->train);
+                train_minibatches(*m, *w, p->train, 0, -1, true, &ts, nullptr, nullptr, 0,
+                                  nullptr, nullptr, nullptr, 0, nullptr);
             }
-            check_train_params(m, w.get(), &p->train);
-            felog_train_stats& ts = st.train[r];
-            train_minibatches(*m, *w, p->train, 0, -1, true, &ts, nullptr, nullptr, 0, nullptr,
-                              nullptr, nullptr, 0, nullptr);
             st.active[r] = n_active;
             st.walks[r] = w->W;
             st.walk_steps[r] = w->n_valid * (int64_t)(w->L - 1);
@@ -857,6 +937,7 @@ felog_status felog_run(felog_model* m, const felog_run_params* p, felog_run_stat
             feedback(*m, fp, src, *next, nullptr, 0);
             FELOG_HIP(hipEventRecord(c->ev1, c->stream));
             c->sync();
+            float ms = 0;
             FELOG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
             st.ms_feedback[r] = ms;
             act = std::move(next);

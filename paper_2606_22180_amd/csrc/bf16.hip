@@ -421,8 +421,11 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     int64_t pairs_done = 0;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     size_t chunk = 0;
+    size_t gated = 0;   // walk chunks [0, gated) are known to be written
     for (int64_t b = first_mb; b < end; ++b) {
         while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
+        while (gated <= chunk && gated < w.chunk_ready.size())
+            FELOG_HIP(hipStreamWaitEvent(c.stream, w.chunk_ready[gated++], 0));
         const int64_t local = b - sch.chunk_first_mb[chunk];
         const int64_t first = local * (int64_t)P;
         const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);

@@ -77,6 +77,8 @@ struct Ctx {
     // free, [1 + 2 kIdSets] forward done
     hipStream_t aux = nullptr;
     hipEvent_t pipe_ev[2 + 2 * kIdSets] = {};
+    // third stream: walk chunks of a round beside the training of earlier ones
+    hipStream_t walk_stream = nullptr;
     void make_current() const;
     void sync() const;
     void ensure_aux();
@@ -115,7 +117,17 @@ struct Walks {
     DevBuf valid_cols;       // int32 [n_valid]
     std::vector<int64_t> chunk_valid;   // per chunk of `chunk_for_valid` walks
     int64_t chunk_for_valid = 0;
+    // While the walks are still being written on another stream: event c
+    // completes when the columns of training chunk c are written (chunks of
+    // chunk_for_valid walks).  Training waits for it before reading the chunk.
+    std::vector<hipEvent_t> chunk_ready;
 };
+
+constexpr int64_t kDefaultChunkWalks = (int64_t)1 << 20;   // walks per training chunk
+inline int64_t chunk_walks_of(const felog_train_params& p)
+{
+    return p.chunk_walks ? p.chunk_walks : kDefaultChunkWalks;
+}
 
 // A walk corpus in the FaBC byte format (fabc.hip), in device memory.
 constexpr int kFabcMax = 16;   // most symbols a corpus is packed with
@@ -228,7 +240,14 @@ __device__ __forceinline__ uint32_t scale32(uint32_t x, uint32_t m) { return __u
 void launch_validate_graph(Graph& g, unsigned long long* d_bad);
 void launch_row_wmax(Graph& g);
 void launch_walks(Walks& w, const felog_walk_params& p, const Active* starts, int64_t n_starts);
+// columns [col0, col0 + ncols) of the corpus on stream s; node2vec adds its
+// capped proposals to *d_capped
+void launch_walk_columns(Walks& w, const felog_walk_params& p, const Active* starts,
+                         int64_t n_starts, int64_t col0, int64_t ncols, hipStream_t s,
+                         unsigned long long* d_capped);
 void launch_valid_columns(Walks& w, int64_t chunk);
+// the same columns and counts from the start list, before the walks exist
+void plan_valid_columns(Walks& w, const Active* starts, int64_t n_starts, int64_t chunk);
 void launch_init_tables(Model& m, uint64_t seed);
 void build_noise_from_counts(Model& m, const uint32_t* d_counts);   // counts in device memory
 void launch_degree_counts(Graph& g, uint32_t* d_counts);

@@ -829,7 +829,10 @@ static std::vector<int32_t> make_slices(int32_t L, int32_t w)
 
 static TrainSchedule make_schedule(Walks& w, const felog_train_params& p)
 {
-    int64_t chunk = p.chunk_walks ? p.chunk_walks : (int64_t)1 << 20;
+    const int64_t chunk = chunk_walks_of(p);
+    FELOG_REQUIRE(w.chunk_ready.empty() || w.chunk_for_valid == chunk,
+                  "the corpus is being written in chunks of %lld walks, not %lld",
+                  (long long)w.chunk_for_valid, (long long)chunk);
     launch_valid_columns(w, chunk);
     TrainSchedule s;
     s.nslices = (int64_t)make_slices(w.L, p.window).size();
@@ -1187,6 +1190,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     if (zero_whole) m.counters_dirty = true;
     // the launch values of minibatch b
     size_t chunk = 0;
+    size_t gated = 0;   // walk chunks [0, gated) are known to be written
     auto frame = [&](int64_t b, MinibatchLaunch& ml, PrepArgs& a) {
         while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
         const int64_t first = (b - sch.chunk_first_mb[chunk]) * P;
@@ -1213,6 +1217,11 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         return lr32;
     };
     uint32_t* meta0 = m.meta.as<uint32_t>();
+    // stream s reads the walks of chunk ch next: wait until they are written
+    auto gate = [&](hipStream_t s, size_t ch) {
+        while (gated <= ch && gated < w.chunk_ready.size())
+            FELOG_HIP(hipStreamWaitEvent(s, w.chunk_ready[gated++], 0));
+    };
 
     // sampled timing: [0] before the ids (on the id stream), [1] after them,
     // [2] before the forward, [3] after it, [4] after the first apply launch,
@@ -1267,6 +1276,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
             const int set = (int)(b % kIdSets);
             PrepArgs a = pa;
             lrs[set] = frame(b, mls[set], a);
+            gate(ids_s, chunk);
             // the set's previous minibatch must be done with it
             if (!one_stream && b >= first_mb + kIdSets)
                 FELOG_HIP(hipStreamWaitEvent(ids_s, freed[set], 0));
@@ -1306,6 +1316,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         MinibatchLaunch ml;
         PrepArgs a = pa;
         const float lr = frame(b, ml, a);
+        gate(c.stream, chunk);
         uint32_t* meta = meta0 + kMetaWords * par;
         DevBuf vin, vout;
         vin.alloc(&c, sizeof(float) * (size_t)P * m.dim);

@@ -107,11 +107,11 @@ void launch_row_wmax(Graph& g)
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void walk_uniform_kernel(
     const int64_t* __restrict__ indptr, const int32_t* __restrict__ indices,
-    const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int32_t L, uint64_t seed,
-    int64_t id_base, int32_t* __restrict__ walks)
+    const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int64_t col0,
+    int64_t col_end, int32_t L, uint64_t seed, int64_t id_base, int32_t* __restrict__ walks)
 {
-    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= W) return;
+    int64_t col = col0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= col_end) return;
     int64_t si = col % n_starts;
     int32_t v = starts ? starts[si] : (int32_t)si;
     int64_t wid = id_base + col;
@@ -141,12 +141,13 @@ __global__ __launch_bounds__(256) void walk_uniform_kernel(
 __global__ __launch_bounds__(256) void walk_node2vec_kernel(
     const int64_t* __restrict__ indptr, const int32_t* __restrict__ indices,
     const float* __restrict__ weights, const float* __restrict__ wmax,
-    const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int32_t L, float inv_p,
-    float inv_q, float amax, uint32_t max_attempts, uint64_t seed, int64_t id_base,
-    int32_t* __restrict__ walks, unsigned long long* __restrict__ capped)
+    const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int64_t col0,
+    int64_t col_end, int32_t L, float inv_p, float inv_q, float amax, uint32_t max_attempts,
+    uint64_t seed, int64_t id_base, int32_t* __restrict__ walks,
+    unsigned long long* __restrict__ capped)
 {
-    int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= W) return;
+    int64_t col = col0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= col_end) return;
     int64_t si = col % n_starts;
     int32_t v = starts ? starts[si] : (int32_t)si;
     int32_t prev = -1;
@@ -198,36 +199,49 @@ __global__ __launch_bounds__(256) void walk_node2vec_kernel(
     if (my_capped) atomicAdd(capped, (unsigned long long)my_capped);
 }
 
-void launch_walks(Walks& w, const felog_walk_params& p, const Active* starts, int64_t n_starts)
+void launch_walk_columns(Walks& w, const felog_walk_params& p, const Active* starts,
+                         int64_t n_starts, int64_t col0, int64_t ncols, hipStream_t s,
+                         unsigned long long* d_capped)
 {
     Graph& g = *w.g;
-    Ctx& c = *g.ctx;
+    FELOG_REQUIRE(col0 >= 0 && ncols >= 0 && col0 + ncols <= w.W, "walk columns out of range");
+    if (ncols == 0) return;
     const int32_t* st = starts ? starts->nodes.as<int32_t>() : nullptr;
-    int64_t blocks = (w.W + 255) / 256;
-    w.have_valid = false;
+    const int64_t blocks = (ncols + 255) / 256;
     if (p.kind == FELOG_WALK_UNIFORM) {
-        hipLaunchKernelGGL(walk_uniform_kernel, dim3(blocks), dim3(256), 0, c.stream,
+        hipLaunchKernelGGL(walk_uniform_kernel, dim3(blocks), dim3(256), 0, s,
                            g.indptr.as<int64_t>(), g.indices.as<int32_t>(), st, n_starts, w.W,
-                           w.L, p.seed, w.id_base, w.data.as<int32_t>());
-        FELOG_HIP(hipGetLastError());
-        w.capped = 0;
+                           col0, col0 + ncols, w.L, p.seed, w.id_base, w.data.as<int32_t>());
     } else {
-        DevBuf cap;
-        cap.alloc(&c, sizeof(unsigned long long));
-        FELOG_HIP(hipMemsetAsync(cap.ptr, 0, sizeof(unsigned long long), c.stream));
+        FELOG_REQUIRE(d_capped, "node2vec walks need a device counter for capped proposals");
         float inv_p = 1.0f / p.p, inv_q = 1.0f / p.q;
         float amax = fmaxf(1.0f, fmaxf(inv_p, inv_q));
-        hipLaunchKernelGGL(walk_node2vec_kernel, dim3(blocks), dim3(256), 0, c.stream,
+        hipLaunchKernelGGL(walk_node2vec_kernel, dim3(blocks), dim3(256), 0, s,
                            g.indptr.as<int64_t>(), g.indices.as<int32_t>(),
                            g.weighted ? g.weights.as<float>() : nullptr, g.wmax.as<float>(), st,
-                           n_starts, w.W, w.L, inv_p, inv_q, amax, 1u << 16, p.seed, w.id_base,
-                           w.data.as<int32_t>(), cap.as<unsigned long long>());
-        FELOG_HIP(hipGetLastError());
-        unsigned long long h = 0;
-        FELOG_HIP(hipMemcpyAsync(&h, cap.ptr, sizeof h, hipMemcpyDeviceToHost, c.stream));
-        c.sync();
-        w.capped = (int64_t)h;
+                           n_starts, w.W, col0, col0 + ncols, w.L, inv_p, inv_q, amax, 1u << 16,
+                           p.seed, w.id_base, w.data.as<int32_t>(), d_capped);
     }
+    FELOG_HIP(hipGetLastError());
+}
+
+void launch_walks(Walks& w, const felog_walk_params& p, const Active* starts, int64_t n_starts)
+{
+    Ctx& c = *w.g->ctx;
+    w.have_valid = false;
+    w.capped = 0;
+    if (p.kind == FELOG_WALK_UNIFORM) {
+        launch_walk_columns(w, p, starts, n_starts, 0, w.W, c.stream, nullptr);
+        return;
+    }
+    DevBuf cap;
+    cap.alloc(&c, sizeof(unsigned long long));
+    FELOG_HIP(hipMemsetAsync(cap.ptr, 0, sizeof(unsigned long long), c.stream));
+    launch_walk_columns(w, p, starts, n_starts, 0, w.W, c.stream, cap.as<unsigned long long>());
+    unsigned long long h = 0;
+    FELOG_HIP(hipMemcpyAsync(&h, cap.ptr, sizeof h, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    w.capped = (int64_t)h;
 }
 
 // --------------------------------------------------------------------------
@@ -260,9 +274,10 @@ __global__ void chunk_count_kernel(const int32_t* valid_cols, int64_t n_valid, i
     counts[c] = (unsigned long long)(lower((c + 1) * chunk) - lower(c * chunk));
 }
 
-void launch_valid_columns(Walks& w, int64_t chunk)
+// valid_cols of the columns with pred(col), and their counts per chunk
+template <class Pred>
+static void set_valid_columns(Walks& w, int64_t chunk, Pred pred)
 {
-    if (w.have_valid && w.chunk_for_valid == chunk) return;
     Ctx& c = *w.g->ctx;
     int64_t n_chunks = (w.W + chunk - 1) / chunk;
     w.chunk_valid.assign(n_chunks, 0);
@@ -270,8 +285,7 @@ void launch_valid_columns(Walks& w, int64_t chunk)
         w.n_valid = 0;
         w.valid_cols.alloc(&c, sizeof(int32_t));
     } else {
-        const int32_t* second = w.data.as<int32_t>() + w.W;
-        w.n_valid = compact(c, LongWalk{second}, ColumnId{}, w.W, w.valid_cols);
+        w.n_valid = compact(c, pred, ColumnId{}, w.W, w.valid_cols);
         DevBuf cnt;
         cnt.alloc(&c, sizeof(unsigned long long) * n_chunks);
         hipLaunchKernelGGL(chunk_count_kernel, dim3((n_chunks + 255) / 256), dim3(256), 0,
@@ -286,6 +300,36 @@ void launch_valid_columns(Walks& w, int64_t chunk)
     }
     w.have_valid = true;
     w.chunk_for_valid = chunk;
+}
+
+void launch_valid_columns(Walks& w, int64_t chunk)
+{
+    if (w.have_valid && w.chunk_for_valid == chunk) return;
+    set_valid_columns(w, chunk, LongWalk{w.data.as<int32_t>() + w.W});
+}
+
+// A walk has a second node exactly when its start node has a neighbour: both
+// samplers stop only at a node without neighbours, and node2vec takes its last
+// proposal when every attempt is rejected.  So the columns that yield pairs are
+// known from the start list alone, before any walk is written.
+struct StartHasNeighbour {
+    const int64_t* indptr;
+    const int32_t* starts;    // null: start of column col is col mod n_starts
+    int64_t n_starts;
+    __device__ bool operator()(int64_t col) const
+    {
+        const int64_t si = col % n_starts;
+        const int32_t v = starts ? starts[si] : (int32_t)si;
+        return indptr[v + 1] > indptr[v];
+    }
+};
+
+void plan_valid_columns(Walks& w, const Active* starts, int64_t n_starts, int64_t chunk)
+{
+    const Graph& g = *w.g;
+    set_valid_columns(w, chunk, StartHasNeighbour{g.indptr.as<int64_t>(),
+                                                  starts ? starts->nodes.as<int32_t>() : nullptr,
+                                                  n_starts});
 }
 
 }  // namespace felog
