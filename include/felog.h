@@ -365,7 +365,7 @@ typedef struct felog_run_stats {
     int64_t active[FELOG_MAX_ROUNDS];      /* |V_a| at the start of each round   */
     int64_t walks[FELOG_MAX_ROUNDS];
     int64_t walk_steps[FELOG_MAX_ROUNDS];  /* transitions taken                  */
-    double ms_walk[FELOG_MAX_ROUNDS];
+    double ms_walk[FELOG_MAX_ROUNDS];      /* walk launches, on their stream     */
     double ms_feedback[FELOG_MAX_ROUNDS];
     felog_train_stats train[FELOG_MAX_ROUNDS];
     int64_t final_active;                  /* |V_a| after the last round         */
@@ -374,7 +374,12 @@ typedef struct felog_run_stats {
 /* Algorithm 1: V_a = V; while V_a is not empty and fewer than max_rounds rounds
  * ran: walks from V_a, one training call over them (the unigram noise
  * distribution is set from the first round's corpus if the model asks for it),
- * feedback on V_a (or on V in RECOMPUTE_ALL mode), V_a = result. */
+ * feedback on V_a (or on V in RECOMPUTE_ALL mode), V_a = result.
+ * Sampling overlaps training (Section 5.3): once the noise distribution is
+ * set, a round's walks are written chunk by chunk (train.chunk_walks walks,
+ * default 2^20) on a second stream of the context, and training reads chunk k
+ * as soon as its walks are written.  The results are those of walking first.
+ * Calls on one model must not overlap. */
 felog_status felog_run(felog_model* m, const felog_run_params* params, felog_run_stats* stats);
 
 /* ------------------------------------------------------------------------- */
