@@ -43,6 +43,7 @@ enum {
     FELOG_EDEVICE = -3,       /* a HIP call failed                                 */
     FELOG_ESTATE = -4,        /* handle in the wrong state for this call           */
     FELOG_EUNSUPPORTED = -5,  /* valid request this build does not implement        */
+    FELOG_EIO = -6,           /* a file could not be opened, read or written        */
 };
 
 typedef struct felog_ctx felog_ctx;
@@ -62,6 +63,8 @@ typedef struct felog_model felog_model;
  * FELOG_ENOMEM. */
 felog_status felog_ctx_create(int device, void* hip_stream, uint64_t hbm_budget_bytes,
                               felog_ctx** out);
+/* Every object created on the context (graphs and what is made from them)
+ * must be destroyed before the context. */
 void felog_ctx_destroy(felog_ctx* ctx);
 
 /* Device bytes currently held by handles of this context. */
@@ -241,6 +244,47 @@ felog_status felog_embeddings_read(const felog_model* m, int32_t which, float* h
 /* Same into device memory (e.g. a torch tensor's data pointer) on the context's stream. */
 felog_status felog_embeddings_read_dev(const felog_model* m, int32_t which, void* dev,
                                        int64_t cap);
+/* Shape of a model: nodes, dimension, noise distribution, precision (each
+ * pointer may be NULL). */
+felog_status felog_model_info(const felog_model* m, int32_t* n, int32_t* dim, int32_t* neg_dist,
+                              int32_t* precision);
+
+/* Persist(S, V) of the deployment view (Section 5.4), the V half: the model's
+ * state to a file and back, so that Algorithm 1 can resume at a round.  (The
+ * S half is the walk corpus in the FaBC format: felog_walks_pack and
+ * felog_packed_read give its bytes, felog_packed_from_host takes them back.)
+ *
+ * File layout, little endian:
+ *   header 64 B  u32 magic 0x4D4C6546 ("FeLM"), u32 version 1, i32 n, i32 d,
+ *                i32 neg_dist, i32 precision, u32 round, u32 flags (bit 0:
+ *                noise table present, bit 1: active list present),
+ *                i64 walk_id_base, i64 active count, u64 graph nnz, u64 0
+ *   in table     f32 [n][d] (the FP32 masters of a BF16 model)
+ *   out table    f32 [n][d]
+ *   noise        u64 [n + 1] cumulative weights, when flags bit 0
+ *   active list  i32 [count], strictly increasing, when flags bit 1
+ * `round` and `walk_id_base` are the caller's round metadata (the next round
+ * of Algorithm 1 and the first walk id it uses); they are stored as given.
+ * A BF16 model's copies are rounded from the restored masters when read.
+ * The file is written whole or the call fails with FELOG_EIO (a partial file
+ * may remain); loading checks the header against the graph (n, nnz), the
+ * file size, the noise table (starts at 0, non-decreasing, positive total)
+ * and the active list (sorted, in range) and fails with FELOG_EINVAL or
+ * FELOG_EIO. */
+typedef struct felog_checkpoint_meta {
+    uint32_t round;
+    int64_t walk_id_base;
+} felog_checkpoint_meta;
+
+/* active and meta may be NULL (no list; round 0, id base 0). */
+felog_status felog_model_save(const felog_model* m, const felog_active* active,
+                              const felog_checkpoint_meta* meta, const char* path);
+/* *out: a new model on graph g.  *active (when active is not NULL): the saved
+ * list, or NULL if the file has none.  meta (nullable) receives the round
+ * metadata. */
+felog_status felog_model_load(felog_graph* g, const char* path, felog_model** out,
+                              felog_active** active, felog_checkpoint_meta* meta);
+
 /* Re-initialise the tables as felog_model_create does (in from `seed`,
  * out = 0); a unigram noise distribution is cleared so that the next
  * felog_run sets it again from its first round. */

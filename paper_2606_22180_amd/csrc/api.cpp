@@ -2,8 +2,10 @@
 // lifetimes, host<->device copies and Algorithm 1's round loop.  Every step
 // of the method runs in the kernels of the .hip files.
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -140,6 +142,43 @@ static felog_status guarded(F&& body)
 }
 
 #define NEED(p) FELOG_REQUIRE((p) != nullptr, "%s must not be NULL", #p)
+
+// A model on g with freshly initialised tables (and the degree noise table
+// when asked for); throws on a bad parameter.
+static std::unique_ptr<felog_model> new_model(felog_graph* g, const felog_model_params* p)
+{
+    FELOG_REQUIRE(p->dim == 64 || p->dim == 128 || p->dim == 256,
+                  "dim must be 64, 128 or 256 (got %d)", p->dim);
+    FELOG_REQUIRE(p->neg_dist == FELOG_NEG_DEGREE || p->neg_dist == FELOG_NEG_UNIGRAM,
+                  "unknown noise distribution %d", p->neg_dist);
+    FELOG_REQUIRE(p->precision == FELOG_PREC_FP32 || p->precision == FELOG_PREC_BF16,
+                  "unknown precision %d", p->precision);
+    Ctx* c = g->ctx;
+    auto m = std::make_unique<felog_model>();
+    m->ctx = c;
+    m->g = g;
+    m->dim = p->dim;
+    m->neg_dist = p->neg_dist;
+    m->precision = p->precision;
+    size_t tb = sizeof(float) * (size_t)g->n * p->dim;
+    m->tin.alloc(c, tb);
+    m->tout.alloc(c, tb);
+    model_alloc_update_state(*m);
+    if (p->precision == FELOG_PREC_BF16) {
+        m->bin.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
+        m->bout.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
+    }
+    launch_init_tables(*m, p->seed);
+    if (p->neg_dist == FELOG_NEG_DEGREE) {
+        DevBuf counts;
+        counts.alloc(c, sizeof(uint32_t) * g->n);
+        launch_degree_counts(*g, counts.as<uint32_t>());
+        build_noise_from_counts(*m, counts.as<uint32_t>());
+        c->sync();
+    }
+    c->sync();
+    return m;
+}
 
 extern "C" {
 
@@ -559,37 +598,7 @@ felog_status felog_model_create(felog_graph* g, const felog_model_params* p, fel
         NEED(p);
         NEED(out);
         *out = nullptr;
-        FELOG_REQUIRE(p->dim == 64 || p->dim == 128 || p->dim == 256,
-                      "dim must be 64, 128 or 256 (got %d)", p->dim);
-        FELOG_REQUIRE(p->neg_dist == FELOG_NEG_DEGREE || p->neg_dist == FELOG_NEG_UNIGRAM,
-                      "unknown noise distribution %d", p->neg_dist);
-        FELOG_REQUIRE(p->precision == FELOG_PREC_FP32 || p->precision == FELOG_PREC_BF16,
-                      "unknown precision %d", p->precision);
-        Ctx* c = g->ctx;
-        auto m = std::make_unique<felog_model>();
-        m->ctx = c;
-        m->g = g;
-        m->dim = p->dim;
-        m->neg_dist = p->neg_dist;
-        m->precision = p->precision;
-        size_t tb = sizeof(float) * (size_t)g->n * p->dim;
-        m->tin.alloc(c, tb);
-        m->tout.alloc(c, tb);
-        model_alloc_update_state(*m);
-        if (p->precision == FELOG_PREC_BF16) {
-            m->bin.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
-            m->bout.alloc(c, sizeof(uint16_t) * (size_t)g->n * p->dim);
-        }
-        launch_init_tables(*m, p->seed);
-        if (p->neg_dist == FELOG_NEG_DEGREE) {
-            DevBuf counts;
-            counts.alloc(c, sizeof(uint32_t) * g->n);
-            launch_degree_counts(*g, counts.as<uint32_t>());
-            build_noise_from_counts(*m, counts.as<uint32_t>());
-            c->sync();
-        }
-        c->sync();
-        *out = m.release();
+        *out = new_model(g, p).release();
     });
 }
 
@@ -602,6 +611,183 @@ felog_status felog_model_reset(felog_model* m, uint64_t seed)
         launch_init_tables(*m, seed);
         if (m->neg_dist == FELOG_NEG_UNIGRAM) m->have_noise = false;
         m->ctx->sync();
+    });
+}
+
+felog_status felog_model_info(const felog_model* m, int32_t* n, int32_t* dim, int32_t* neg_dist,
+                              int32_t* precision)
+{
+    return guarded([&] {
+        NEED(m);
+        if (n) *n = m->g->n;
+        if (dim) *dim = m->dim;
+        if (neg_dist) *neg_dist = m->neg_dist;
+        if (precision) *precision = m->precision;
+    });
+}
+
+// ------------------------------------------------------------ checkpoints
+constexpr uint32_t kCheckpointMagic = 0x4D4C6546u;   // "FeLM"
+constexpr uint32_t kCheckpointVersion = 1;
+struct CheckpointHeader {
+    uint32_t magic, version;
+    int32_t n, dim, neg_dist, precision;
+    uint32_t round, flags;
+    int64_t walk_id_base, n_active;
+    uint64_t nnz, zero;
+};
+static_assert(sizeof(CheckpointHeader) == 64, "checkpoint header is 64 bytes");
+
+struct File {
+    std::FILE* f = nullptr;
+    const char* path;
+    File(const char* p, const char* mode) : f(std::fopen(p, mode)), path(p)
+    {
+        if (!f) fail(FELOG_EIO, "cannot open %s: %s", p, std::strerror(errno));
+    }
+    ~File()
+    {
+        if (f) std::fclose(f);
+    }
+    void write(const void* data, size_t bytes)
+    {
+        if (bytes && std::fwrite(data, 1, bytes, f) != bytes)
+            fail(FELOG_EIO, "writing %s failed", path);
+    }
+    void read(void* data, size_t bytes)
+    {
+        if (bytes && std::fread(data, 1, bytes, f) != bytes)
+            fail(FELOG_EIO, "%s ends early (truncated checkpoint)", path);
+    }
+    void close()
+    {
+        const int e = std::fclose(f);
+        f = nullptr;
+        if (e != 0) fail(FELOG_EIO, "closing %s failed", path);
+    }
+};
+
+felog_status felog_model_save(const felog_model* m, const felog_active* active,
+                              const felog_checkpoint_meta* meta, const char* path)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(path);
+        FELOG_REQUIRE(!active || active->g == m->g, "active set belongs to another graph");
+        Ctx* c = m->ctx;
+        const int32_t n = m->g->n;
+        const size_t cnt = (size_t)n * m->dim;
+        CheckpointHeader h{};
+        h.magic = kCheckpointMagic;
+        h.version = kCheckpointVersion;
+        h.n = n;
+        h.dim = m->dim;
+        h.neg_dist = m->neg_dist;
+        h.precision = m->precision;
+        h.round = meta ? meta->round : 0u;
+        h.flags = (m->have_noise ? 1u : 0u) | (active ? 2u : 0u);
+        h.walk_id_base = meta ? meta->walk_id_base : 0;
+        h.n_active = active ? active->count : 0;
+        h.nnz = (uint64_t)m->g->nnz;
+        std::vector<float> tab(std::max<size_t>(cnt, 1));
+        File f(path, "wb");
+        f.write(&h, sizeof h);
+        for (const DevBuf* t : {&m->tin, &m->tout}) {
+            FELOG_HIP(hipMemcpyAsync(tab.data(), t->ptr, sizeof(float) * cnt,
+                                     hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            f.write(tab.data(), sizeof(float) * cnt);
+        }
+        if (m->have_noise) {
+            std::vector<uint64_t> cdf((size_t)n + 1);
+            FELOG_HIP(hipMemcpyAsync(cdf.data(), m->cdf.ptr, sizeof(uint64_t) * (n + 1),
+                                     hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            f.write(cdf.data(), sizeof(uint64_t) * (n + 1));
+        }
+        if (active && active->count) {
+            std::vector<int32_t> nodes(active->count);
+            FELOG_HIP(hipMemcpyAsync(nodes.data(), active->nodes.ptr,
+                                     sizeof(int32_t) * active->count, hipMemcpyDeviceToHost,
+                                     c->stream));
+            c->sync();
+            f.write(nodes.data(), sizeof(int32_t) * active->count);
+        }
+        f.close();
+    });
+}
+
+felog_status felog_model_load(felog_graph* g, const char* path, felog_model** out,
+                              felog_active** active, felog_checkpoint_meta* meta)
+{
+    return guarded([&] {
+        NEED(g);
+        NEED(path);
+        NEED(out);
+        *out = nullptr;
+        if (active) *active = nullptr;
+        File f(path, "rb");
+        CheckpointHeader h{};
+        f.read(&h, sizeof h);
+        FELOG_REQUIRE(h.magic == kCheckpointMagic, "%s is not a model checkpoint", path);
+        FELOG_REQUIRE(h.version == kCheckpointVersion, "checkpoint version %u is not supported",
+                      h.version);
+        FELOG_REQUIRE(h.n == g->n && h.nnz == (uint64_t)g->nnz,
+                      "the checkpoint is of a graph with %d nodes and %llu entries, not %d and "
+                      "%lld", h.n, (unsigned long long)h.nnz, g->n, (long long)g->nnz);
+        FELOG_REQUIRE((h.flags & ~3u) == 0 && h.zero == 0, "unknown checkpoint flags");
+        FELOG_REQUIRE(h.n_active >= 0 && h.n_active <= h.n && ((h.flags & 2u) || !h.n_active),
+                      "bad active count %lld", (long long)h.n_active);
+        const size_t cnt = (size_t)h.n * (size_t)std::max(h.dim, 0);
+        const uint64_t expect = sizeof h + 2 * sizeof(float) * cnt +
+                                ((h.flags & 1u) ? sizeof(uint64_t) * ((uint64_t)h.n + 1) : 0) +
+                                sizeof(int32_t) * (uint64_t)h.n_active;
+        FELOG_REQUIRE(std::fseek(f.f, 0, SEEK_END) == 0, "cannot seek in %s", path);
+        const long size = std::ftell(f.f);
+        FELOG_REQUIRE(size >= 0 && (uint64_t)size == expect,
+                      "%s holds %ld bytes; its header describes %llu", path, size,
+                      (unsigned long long)expect);
+        FELOG_REQUIRE(std::fseek(f.f, (long)sizeof h, SEEK_SET) == 0, "cannot seek in %s", path);
+        felog_model_params prm{h.dim, h.neg_dist, 0, h.precision};
+        std::unique_ptr<felog_model> m = new_model(g, &prm);   // checks d, noise, precision
+        Ctx* c = g->ctx;
+        std::vector<float> tab(std::max<size_t>(cnt, 1));
+        for (DevBuf* t : {&m->tin, &m->tout}) {
+            f.read(tab.data(), sizeof(float) * cnt);
+            FELOG_HIP(hipMemcpyAsync(t->ptr, tab.data(), sizeof(float) * cnt,
+                                     hipMemcpyHostToDevice, c->stream));
+            c->sync();
+        }
+        if (h.flags & 1u) {
+            std::vector<uint64_t> cdf((size_t)h.n + 1);
+            f.read(cdf.data(), sizeof(uint64_t) * cdf.size());
+            set_noise_cdf(*m, cdf.data());
+        } else {
+            m->have_noise = false;
+        }
+        std::unique_ptr<felog_active> a;
+        if (h.flags & 2u) {
+            std::vector<int32_t> nodes(std::max<int64_t>(h.n_active, 1));
+            f.read(nodes.data(), sizeof(int32_t) * h.n_active);
+            for (int64_t i = 0; i < h.n_active; ++i)
+                FELOG_REQUIRE(nodes[i] >= 0 && nodes[i] < g->n && (i == 0 || nodes[i] > nodes[i - 1]),
+                              "the saved active list is not sorted and in range (position %lld)",
+                              (long long)i);
+            a = std::make_unique<felog_active>();
+            a->g = g;
+            a->count = h.n_active;
+            a->nodes.alloc(c, sizeof(int32_t) * std::max<int64_t>(h.n_active, 1));
+            if (h.n_active)
+                FELOG_HIP(hipMemcpyAsync(a->nodes.ptr, nodes.data(), sizeof(int32_t) * h.n_active,
+                                         hipMemcpyHostToDevice, c->stream));
+            c->sync();
+        }
+        if (meta) {
+            meta->round = h.round;
+            meta->walk_id_base = h.walk_id_base;
+        }
+        if (active) *active = a.release();
+        *out = m.release();
     });
 }
 

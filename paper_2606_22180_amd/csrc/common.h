@@ -250,6 +250,7 @@ void launch_valid_columns(Walks& w, int64_t chunk);
 void plan_valid_columns(Walks& w, const Active* starts, int64_t n_starts, int64_t chunk);
 void launch_init_tables(Model& m, uint64_t seed);
 void build_noise_from_counts(Model& m, const uint32_t* d_counts);   // counts in device memory
+void set_noise_cdf(Model& m, const uint64_t* host_cdf);   // a saved table, checked
 void launch_degree_counts(Graph& g, uint32_t* d_counts);
 void launch_corpus_counts(const Walks& w, uint32_t* d_counts);
 void train_minibatches(Model& m, const Walks& w, const felog_train_params& p, int64_t first_mb,

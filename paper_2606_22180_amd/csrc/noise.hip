@@ -182,6 +182,37 @@ __global__ void guide_kernel(const uint64_t* cdf, int32_t n, int32_t bits, uint6
     guide[b] = lo;
 }
 
+// guide table of m.cdf (n + 1 entries, total > 0)
+static void build_guide(Model& m, uint64_t total)
+{
+    Ctx& c = *m.ctx;
+    const int32_t n = m.g->n;
+    int32_t bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
+    m.guide_bits = bits;
+    m.total_weight = total;
+    m.guide.alloc(&c, sizeof(int32_t) * ((size_t)1 << bits));
+    hipLaunchKernelGGL(guide_kernel, dim3((((int64_t)1 << bits) + 255) / 256), dim3(256), 0,
+                       c.stream, m.cdf.as<uint64_t>(), n, bits, total, m.guide.as<int32_t>());
+    FELOG_HIP(hipGetLastError());
+    c.sync();
+    m.have_noise = true;
+}
+
+void set_noise_cdf(Model& m, const uint64_t* host_cdf)
+{
+    Ctx& c = *m.ctx;
+    const int32_t n = m.g->n;
+    FELOG_REQUIRE(host_cdf[0] == 0, "a noise table starts at 0");
+    for (int32_t i = 0; i < n; ++i)
+        FELOG_REQUIRE(host_cdf[i + 1] >= host_cdf[i], "the noise table decreases at node %d", i);
+    FELOG_REQUIRE(host_cdf[n] > 0, "the noise distribution is empty (every weight is zero)");
+    m.cdf.alloc(&c, sizeof(uint64_t) * (n + 1));
+    FELOG_HIP(hipMemcpyAsync(m.cdf.ptr, host_cdf, sizeof(uint64_t) * (n + 1),
+                             hipMemcpyHostToDevice, c.stream));
+    build_guide(m, host_cdf[n]);
+}
+
 void build_noise_from_counts(Model& m, const uint32_t* d_counts)
 {
     Ctx& c = *m.ctx;
@@ -206,16 +237,7 @@ void build_noise_from_counts(Model& m, const uint32_t* d_counts)
                              hipMemcpyDeviceToHost, c.stream));
     c.sync();
     FELOG_REQUIRE(total > 0, "the noise distribution is empty (every count is zero)");
-    int32_t bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
-    m.guide_bits = bits;
-    m.total_weight = total;
-    m.guide.alloc(&c, sizeof(int32_t) * ((size_t)1 << bits));
-    hipLaunchKernelGGL(guide_kernel, dim3((((int64_t)1 << bits) + 255) / 256), dim3(256), 0,
-                       c.stream, m.cdf.as<uint64_t>(), n, bits, total, m.guide.as<int32_t>());
-    FELOG_HIP(hipGetLastError());
-    c.sync();
-    m.have_noise = true;
+    build_guide(m, total);
 }
 
 }  // namespace felog

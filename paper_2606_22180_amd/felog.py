@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libfelog.so")
 
 FELOG_OK, FELOG_EINVAL, FELOG_ENOMEM, FELOG_EDEVICE, FELOG_ESTATE, FELOG_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5
+FELOG_EIO = -6
 WALK_UNIFORM, WALK_NODE2VEC = 0, 1
 NEG_DEGREE, NEG_UNIGRAM = 0, 1
 TABLE_IN, TABLE_OUT = 0, 1
@@ -28,7 +29,7 @@ FABC_MAX_SYMBOLS = 16
 MAX_ROUNDS = 64
 
 _STATUS = {0: "FELOG_OK", -1: "FELOG_EINVAL", -2: "FELOG_ENOMEM", -3: "FELOG_EDEVICE",
-           -4: "FELOG_ESTATE", -5: "FELOG_EUNSUPPORTED"}
+           -4: "FELOG_ESTATE", -5: "FELOG_EUNSUPPORTED", -6: "FELOG_EIO"}
 
 
 class FelogError(RuntimeError):
@@ -68,6 +69,10 @@ class felog_train_stats(C.Structure):
 class felog_feedback_params(C.Structure):
     _fields_ = [("mu", C.c_double), ("k_s", C.c_int32), ("mode", C.c_int32),
                 ("seed", C.c_uint64), ("round", C.c_uint32)]
+
+
+class felog_checkpoint_meta(C.Structure):
+    _fields_ = [("round", C.c_uint32), ("walk_id_base", C.c_int64)]
 
 
 class felog_run_params(C.Structure):
@@ -142,6 +147,10 @@ SIGNATURES = {
     "felog_model_destroy": (None, [_p]),
     "felog_model_set_unigram": (_i32, [_p, _p]),
     "felog_model_read_cdf": (_i32, [_p, _p, _i64]),
+    "felog_model_info": (_i32, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32),
+                                C.POINTER(_i32)]),
+    "felog_model_save": (_i32, [_p, _p, C.POINTER(felog_checkpoint_meta), C.c_char_p]),
+    "felog_model_load": (_i32, [_p, C.c_char_p, _pp, _pp, C.POINTER(felog_checkpoint_meta)]),
     "felog_model_reset": (_i32, [_p, _u64]),
     "felog_embeddings_read": (_i32, [_p, _i32, _p, _i64]),
     "felog_embeddings_read_dev": (_i32, [_p, _i32, _p, _i64]),
@@ -205,6 +214,9 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
         lib = load()
+        self.handle = None
+        self._live = 0                # objects created on this context, not yet destroyed
+        self._close_pending = False
         h = C.c_void_p()
         _check(lib.felog_ctx_create(device, stream, hbm_budget, C.byref(h)))
         self.handle = h
@@ -218,9 +230,23 @@ class Context:
         return b.value
 
     def close(self):
-        if self.handle:
-            load().felog_ctx_destroy(self.handle)
-            self.handle = None
+        """Destroy the context.  The C library needs every object of a context
+        destroyed first; while some are alive (the garbage collector may
+        finalise a context before the objects of the same reference cycle),
+        the destruction waits for the last of them."""
+        if not self.handle:
+            return
+        if self._live > 0:
+            self._close_pending = True
+            return
+        load().felog_ctx_destroy(self.handle)
+        self.handle = None
+
+    def _child_closed(self):
+        self._live -= 1
+        if self._live == 0 and self._close_pending:
+            self._close_pending = False
+            self.close()
 
     def __del__(self):
         try:
@@ -233,13 +259,17 @@ class _Handle:
     _destroy = ""
 
     def __init__(self, handle, owner):
-        self.handle = handle
+        self.handle = None
         self._owner = owner          # keeps the context (and graph) alive
+        self._ctx = owner if isinstance(owner, Context) else owner._ctx
+        self._ctx._live += 1
+        self.handle = handle
 
     def close(self):
         if self.handle:
             getattr(load(), self._destroy)(self.handle)
             self.handle = None
+            self._ctx._child_closed()
 
     def __del__(self):
         try:
@@ -405,6 +435,28 @@ class Model(_Handle):
         m.n = g.n
         m.dim = dim
         return m
+
+    def save(self, path: str, *, active: Active | None = None, round: int = 0,
+             walk_id_base: int = 0):
+        """Tables, noise table, active list and round metadata to `path`."""
+        meta = felog_checkpoint_meta(round, walk_id_base)
+        _check(load().felog_model_save(self.handle, active.handle if active else None,
+                                       C.byref(meta), os.fsencode(path)))
+
+    @classmethod
+    def load(cls, g: Graph, path: str):
+        """(model, active list or None, round, walk_id_base) from a checkpoint."""
+        h, a = C.c_void_p(), C.c_void_p()
+        meta = felog_checkpoint_meta()
+        _check(load().felog_model_load(g.handle, os.fsencode(path), C.byref(h), C.byref(a),
+                                       C.byref(meta)))
+        m = cls(h, g)
+        n, d, neg, prec = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().felog_model_info(m.handle, C.byref(n), C.byref(d), C.byref(neg),
+                                       C.byref(prec)))
+        m.n, m.dim, m.neg_dist, m.precision = n.value, d.value, neg.value, prec.value
+        act = Active(a, g) if a.value else None
+        return m, act, meta.round, meta.walk_id_base
 
     def set_unigram(self, corpus: Walks):
         _check(load().felog_model_set_unigram(self.handle, corpus.handle))

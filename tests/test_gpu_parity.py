@@ -391,3 +391,27 @@ def test_budget_and_bad_params(fl):
     with pytest.raises(fl.FelogError) as e:
         fl.Walks.generate(G, r=0, L=5, seed=1)
     assert e.value.status == fl.FELOG_EINVAL
+
+
+def test_context_closed_before_its_objects(fl):
+    """The C library needs a context's objects destroyed before it; the
+    binding defers a context's destruction until they are gone, whatever
+    order the garbage collector finalises a reference cycle in."""
+    import gc
+    _say("context closed before its objects")
+    g = synth.tiny_graph("k8")
+    c = fl.Context(0)
+    G = fl.Graph.from_csr(c, g.indptr, g.indices)
+    M = fl.Model.create(G, dim=64)
+    W = fl.Walks.generate(G, r=1, L=5, seed=1)
+    c.close()                                    # objects alive: deferred
+    assert c.handle is not None
+    cycle = [c, G, M, W]
+    cycle.append(cycle)
+    del G, M, W, cycle
+    gc.collect()
+    assert c.handle is None                      # destroyed with the last object
+    # no stale HIP error reaches the next calls
+    c2 = fl.Context(0)
+    G2 = fl.Graph.from_csr(c2, g.indptr, g.indices)
+    assert np.array_equal(fl.Walks.generate(G2, r=1, L=5, seed=1).read()[:, 0], np.arange(g.n))
