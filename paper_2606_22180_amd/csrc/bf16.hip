@@ -18,7 +18,8 @@
 // scores (S and G on 32x32 tiles, 4 waves of 16x16), grads (dC and dN on
 // 32x32 tiles, the shared dimension M or P split over a block's 8 waves,
 // added to the masters with FP32 atomics; rows repeat only when a node is
-// drawn twice or is both a centre and a negative).
+// drawn twice or is both a centre and a negative).  The ids (ctx, ctr, neg)
+// of up to 64 minibatches come from one launch before them.
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds 8 consecutive k of row
 // (l mod 16) of A and of column (l mod 16) of B, k chunk l / 16; it receives
 // D[4 (l / 16) + j][l mod 16], j = 0..3.
@@ -102,6 +103,47 @@ __device__ __forceinline__ float softplus_f(float x)
     return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
 }
 
+// The ids of nmb consecutive minibatches of one chunk, mb0 first (their
+// first pair is first0 within the chunk): for each, ctx[P] and ctr[P] (-1
+// past the chunk's last pair) and neg[M], one thread per pair or negative.
+// They read only the walks and the noise table, so one launch draws them for
+// many minibatches and the per-minibatch launches start from the ids.
+constexpr int kIdBatch = 64;
+
+__global__ __launch_bounds__(256) void bf16_ids_kernel(Bf16Args a, uint32_t mb0, uint32_t nmb,
+                                                       uint32_t first0, uint64_t chunk_pairs,
+                                                       int32_t* ids)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t per = a.P + a.M;
+    if (i >= (uint64_t)nmb * per) return;
+    const uint32_t bm = (uint32_t)(i / per), s = (uint32_t)(i - (uint64_t)bm * per);
+    int32_t* out = ids + (size_t)bm * (2 * a.P + a.M);
+    if (s < a.P) {
+        const uint64_t gq64 = (uint64_t)first0 + (uint64_t)bm * a.P + s;   // pair within the chunk
+        int32_t ctx = -1, ctr = -1;
+        if (gq64 < chunk_pairs) {
+            const uint32_t gq = (uint32_t)gq64;
+            const uint32_t sidx = gq / a.Wv;
+            const uint32_t rank = gq - sidx * a.Wv;
+            const int32_t js = a.slices[sidx];
+            const int32_t col = a.vcols[rank];
+            const int32_t j = js >> 8, sl = js & 255;
+            const int32_t off = sl < a.window ? sl - a.window : sl - a.window + 1;
+            ctx = a.walks[(int64_t)(j + off) * a.W + col];
+            ctr = a.walks[(int64_t)j * a.W + col];
+        }
+        out[s] = ctx;
+        out[a.P + s] = ctr;
+    } else {
+        const uint32_t m = s - a.P;
+        Rand4 r = philox4x32(mb0 + bm, a.id_lo, m >> 1, kTagSharedNeg, a.seed);
+        const uint32_t lo = (m & 1) ? r.v[2] : r.v[0];
+        const uint32_t hi = (m & 1) ? r.v[3] : r.v[1];
+        out[2 * a.P + m] = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
+    }
+}
+
 // One wave per row: waves [0, P) pairs, [P, P + M) negatives.
 template <int D>
 __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
@@ -111,18 +153,7 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
     if (w >= a.P + a.M) return;
     if (w < a.P) {
         const uint32_t p = w;
-        int32_t ctx = -1, ctr = -1;
-        if (p < a.np) {
-            uint32_t gq = a.first_pair + p;
-            uint32_t sidx = gq / a.Wv;
-            uint32_t rank = gq - sidx * a.Wv;
-            int32_t js = a.slices[sidx];
-            int32_t col = a.vcols[rank];
-            int32_t j = js >> 8, s = js & 255;
-            int32_t off = s < a.window ? s - a.window : s - a.window + 1;
-            ctx = a.walks[(int64_t)(j + off) * a.W + col];
-            ctr = a.walks[(int64_t)j * a.W + col];
-        }
+        const int32_t ctx = a.ids[p], ctr = a.ids[a.P + p];
         float dot = 0.0f;
         float xc[D / 64], xo[D / 64];
 #pragma unroll
@@ -143,8 +174,6 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
         }
         dot = wave_sum32(dot);
         if (lane == 0) {
-            a.ids[p] = ctx;
-            a.ids[a.P + p] = ctr;
             float g = 0.0f;
             if (ctx >= 0) {
                 g = a.lr * (1.0f - 1.0f / (1.0f + expf(-dot)));
@@ -154,10 +183,7 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
         }
     } else {
         const uint32_t m = w - a.P;
-        Rand4 r = philox4x32(a.mb, a.id_lo, m >> 1, kTagSharedNeg, a.seed);
-        uint32_t lo = (m & 1) ? r.v[2] : r.v[0];
-        uint32_t hi = (m & 1) ? r.v[3] : r.v[1];
-        const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
+        const int32_t neg = a.ids[2 * a.P + m];
         float xn[D / 64];
 #pragma unroll
         for (int u = 0; u < D / 64; ++u) xn[u] = a.tout[(int64_t)neg * D + lane + 64 * u];
@@ -168,7 +194,6 @@ __global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
             a.N[(int64_t)m * D + e] = x;
             a.Nt[(int64_t)e * a.M + m] = x;
         }
-        if (lane == 0) a.ids[2 * a.P + m] = neg;
     }
 }
 
@@ -371,7 +396,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         m.bf_P = std::max(m.bf_P, P);
         m.bf_M = std::max(m.bf_M, M);
         const size_t cp = m.bf_P, cm = m.bf_M;
-        m.bf_ids.alloc(&c, sizeof(int32_t) * (2 * cp + cm));
+        m.bf_ids.alloc(&c, sizeof(int32_t) * (2 * cp + cm) * kIdBatch);
         m.bf_C.alloc(&c, sizeof(uint16_t) * cp * d);
         m.bf_O.alloc(&c, sizeof(uint16_t) * cp * d);
         m.bf_N.alloc(&c, sizeof(uint16_t) * cm * d);
@@ -422,10 +447,10 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     size_t chunk = 0;
     size_t gated = 0;   // walk chunks [0, gated) are known to be written
+    int32_t* const ids0 = m.bf_ids.as<int32_t>();
+    int64_t batch0 = first_mb, batch_end = first_mb;   // minibatches whose ids are drawn
     for (int64_t b = first_mb; b < end; ++b) {
         while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
-        while (gated <= chunk && gated < w.chunk_ready.size())
-            FELOG_HIP(hipStreamWaitEvent(c.stream, w.chunk_ready[gated++], 0));
         const int64_t local = b - sch.chunk_first_mb[chunk];
         const int64_t first = local * (int64_t)P;
         const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
@@ -434,6 +459,21 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         a.first_pair = (uint32_t)first;
         a.np = (uint32_t)np;
         a.mb = (uint32_t)b;
+        if (b == batch_end) {
+            // ids of the next minibatches, up to kIdBatch and the chunk's end
+            while (gated <= chunk && gated < w.chunk_ready.size())
+                FELOG_HIP(hipStreamWaitEvent(c.stream, w.chunk_ready[gated++], 0));
+            int64_t lim = std::min<int64_t>(end, b + kIdBatch);
+            if (chunk + 1 < sch.chunk_first_mb.size())
+                lim = std::min<int64_t>(lim, sch.chunk_first_mb[chunk + 1]);
+            batch0 = b;
+            batch_end = lim;
+            const uint64_t items = (uint64_t)(lim - b) * (P + M);
+            hipLaunchKernelGGL(bf16_ids_kernel, dim3((uint32_t)((items + 255) / 256)), dim3(256),
+                               0, c.stream, a, (uint32_t)b, (uint32_t)(lim - b), (uint32_t)first,
+                               (uint64_t)sch.chunk_pairs[chunk], ids0);
+        }
+        a.ids = ids0 + (size_t)(b - batch0) * (2 * (size_t)P + M);
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
         if (d == 64) hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(256), 0, c.stream, a);
         else if (d == 128) hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(256), 0, c.stream, a);
