@@ -428,12 +428,21 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
-// One pair per group of LPP lanes (32 for d >= 128, so that a lane holds one
-// float4 of each of the pair's K + 2 rows at d = 128), 64 / LPP pairs at a time.
+// One pair per group of LPP lanes, 64 / LPP pairs at a time.  Up to K = 5 at
+// d <= 128, 16 lanes per pair (four pairs' rows in flight per wave) with at
+// least 4 waves per SIMD (at most 128 registers, no spills) was faster at
+// d = 128 than 32 lanes and 5 waves; more negatives or d = 256 take 32 lanes,
+// where 16 would not fit the registers.
 template <int D, int K>
-__global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
+constexpr int fwd_lanes_per_pair() { return (D <= 64 || (D == 128 && K <= 5)) ? 16 : 32; }
+template <int D, int K>
+constexpr int fwd_min_waves() { return (D == 128 && K <= 5) ? 4 : 1; }
+
+template <int D, int K>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fwd_min_waves<D, K>())))
+void sgns_forward_kernel(FwdArgs a)
 {
-    constexpr int LPP = D >= 128 ? 32 : 16;   // lanes per pair
+    constexpr int LPP = fwd_lanes_per_pair<D, K>();   // lanes per pair
     constexpr int G = 64 / LPP;               // pairs in flight per wave
     constexpr int V4 = D / (4 * LPP);         // float4s per lane and row
     constexpr int T = K + 2;                  // touches per pair
