@@ -642,16 +642,29 @@ struct ApplyArgs {
     int32_t reset;                // zero the counters of the rows done here
 };
 
-// Adds a row's delta to the table, or stores it in the capture buffer.
+// The row's current values (zero when capturing), read before the delta is
+// summed so that the read overlaps the summing.
+template <int D>
+__device__ __forceinline__ void get_row(const float* table, const float* cap, int32_t row,
+                                        float4 (&cur)[D / 64], int gl)
+{
+    const float4* s4 = reinterpret_cast<const float4*>(table + (int64_t)row * D);
+#pragma unroll
+    for (int i = 0; i < D / 64; ++i) cur[i] = cap ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : s4[i * 16 + gl];
+}
+
+// Adds a row's delta to its current values (from get_row) in the table, or
+// stores it in the capture buffer.
 template <int D>
 __device__ __forceinline__ void put_row(float* table, float* cap, int32_t row, int32_t slot,
+                                        const float4 (&cur)[D / 64],
                                         const float (&delta)[D / 16], int gl)
 {
     constexpr int V4 = D / 64;
     float4* d4 = reinterpret_cast<float4*>(cap ? cap + (int64_t)slot * D : table + (int64_t)row * D);
 #pragma unroll
     for (int i = 0; i < V4; ++i) {
-        float4 v = cap ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : d4[i * 16 + gl];
+        float4 v = cur[i];
         v.x += delta[4 * i + 0];
         v.y += delta[4 * i + 1];
         v.z += delta[4 * i + 2];
@@ -674,16 +687,32 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
     const uint32_t e2 = e1 + (PHASE == 0 ? a.meta[6] : a.meta[5]);
     const uint32_t e3 = e2 + (PHASE == 0 ? a.meta[3] : a.meta[4]);
     const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4u; base < e3;
-         base += nw * 4u) {
-        const uint32_t c = base + grp;
-        if (c >= e3) continue;
+    // the descriptor of item c: a chunk of a split row, a row of one chunk, or
+    // a split row to merge
+    auto desc_of = [&](uint32_t c) -> int4 {
         const int kind = c < e1 ? 0 : (c < e2 ? 1 : 2);
         const uint32_t ci = kind == 0 ? c : (kind == 1 ? c - e1 : c - e2);
+        const int4* arr = PHASE == 0
+            ? (kind == 0 ? a.split_out : (kind == 1 ? a.split_in : a.chunks_out))
+            : (kind == 0 ? a.chunks_in : (kind == 1 ? a.mrows_out : a.mrows_in));
+        return arr[ci];
+    };
+    const uint32_t stride = nw * 4u;
+    const uint32_t first = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 4u;
+    int4 next = first + grp < e3 ? desc_of(first + grp) : make_int4(0, 0, 0, 0);
+    for (uint32_t base = first; base < e3; base += stride) {
+        const uint32_t c = base + grp;
+        const int4 d = next;
+        // the next item's descriptor is in flight while this one is done
+        if (c + stride < e3) next = desc_of(c + stride);
+        if (c >= e3) continue;
+        const int kind = c < e1 ? 0 : (c < e2 ? 1 : 2);
         if (PHASE == 1 && kind > 0) {
             // merge of a split row: its chunks' exact sums in chunk order
             const bool out = kind == 1;
-            const int4 m = (out ? a.mrows_out : a.mrows_in)[ci];
+            const int4 m = d;
+            float4 cur[V4];
+            get_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, cur, gl);
             const double* partial = out ? a.partial_out : a.partial_in;
             double acc[D / 16];
 #pragma unroll
@@ -703,15 +732,13 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
             float delta[D / 16];
 #pragma unroll
             for (int e = 0; e < D / 16; ++e) delta[e] = (float)acc[e];
-            put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, m.w, delta, gl);
+            put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, m.w, cur, delta, gl);
             if (a.reset && gl == 0) (out ? a.cnt_out : a.cnt_in)[m.x] = 0;
             continue;
         }
         // out rows draw on in[ctx] with coefficient g, in rows on the per-pair deltas
         const bool split = PHASE == 0 && kind < 2;
         const bool out = PHASE == 0 ? kind != 1 : false;
-        const int4 d = split ? (out ? a.split_out : a.split_in)[ci]
-                             : (out ? a.chunks_out : a.chunks_in)[ci];
         const int32_t row = d.x, start = d.y, len = d.z, slot = d.w;
         const float* src = out ? a.tin : a.dinp;
         float my_g = 1.0f;
@@ -764,6 +791,8 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
             continue;
         }
         // a row of at most kChunk touches: sum in pair order
+        float4 cur[V4];
+        get_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, cur, gl);
         uint32_t key = gl < len ? (out ? a.key_out : a.key_in)[start + gl] : 0xffffffffu;
         sort16(key, my_g, my_src, gl);
         float acc[D / 16];
@@ -794,7 +823,7 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
                     acc[4 * i + 3] = fmaf(gg[u], x[u][i].w, acc[4 * i + 3]);
                 }
         }
-        put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, slot, acc, gl);
+        put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, slot, cur, acc, gl);
         if (a.reset && gl == 0) (out ? a.cnt_out : a.cnt_in)[row] = 0;
     }
     // the second launch counts the minibatch's touched rows
@@ -1147,7 +1176,9 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         m.partial.alloc(&c, sizeof(double) * (m.split_rows_in + max_split_chunks(touches_out)) *
                                 m.dim);
     }
-    const int ppw_max = std::max(1, std::min(8, 64 / (K + 2)));
+    // pairs per forward wave: 4 (more, shorter waves) ran 1.4 us per minibatch
+    // faster than 8 at 65,536 pairs, d = 128, K = 5
+    const int ppw_max = std::max(1, std::min(4, 64 / (K + 2)));
     const int ppw = (int)std::min<int64_t>(ppw_max,
                                            std::max<int64_t>(1, P / ((int64_t)c.num_cus * 32)));
     const int64_t waves = (P + ppw - 1) / ppw;
