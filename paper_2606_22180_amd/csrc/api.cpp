@@ -1017,8 +1017,15 @@ static void walk_then_train(Model& m, Walks& w, const felog_walk_params& wp,
         hipEvent_t* ev[3];
         ~Cleanup()
         {
-            // every walk launch has ended before its events go
-            if (c.walk_stream) (void)hipStreamSynchronize(c.walk_stream);
+            // every walk launch has ended before its events and stream go; the
+            // stream is not kept, since every stream a process holds takes one
+            // of the device's few hardware queues (streams beyond them share
+            // queues and lose their concurrency)
+            if (c.walk_stream) {
+                (void)hipStreamSynchronize(c.walk_stream);
+                (void)hipStreamDestroy(c.walk_stream);
+                c.walk_stream = nullptr;
+            }
             for (hipEvent_t& e : w.chunk_ready)
                 if (e) (void)hipEventDestroy(e);
             w.chunk_ready.clear();
