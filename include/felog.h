@@ -421,9 +421,9 @@ typedef struct felog_run_stats {
  * feedback on V_a (or on V in RECOMPUTE_ALL mode), V_a = result.
  * Sampling overlaps training (Section 5.3): once the noise distribution is
  * set, a round's walks are written chunk by chunk (train.chunk_walks walks,
- * default 2^20) on a second stream of the context, and training reads chunk k
- * as soon as its walks are written.  The results are those of walking first.
- * Calls on one model must not overlap. */
+ * default 2^20) on a stream the call creates and releases, beside the
+ * training, which reads chunk k as soon as its walks are written.  The
+ * results are those of walking first.  Calls on one model must not overlap. */
 felog_status felog_run(felog_model* m, const felog_run_params* params, felog_run_stats* stats);
 
 /* ------------------------------------------------------------------------- */
