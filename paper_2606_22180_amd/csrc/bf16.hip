@@ -144,56 +144,91 @@ __global__ __launch_bounds__(256) void bf16_ids_kernel(Bf16Args a, uint32_t mb0,
     }
 }
 
-// One wave per row: waves [0, P) pairs, [P, P + M) negatives.
+// 16 rows per block, one per wave: blocks [0, P / 16) take pairs, the rest
+// negatives (P and M are multiples of 64).  The rows are written as they are
+// (C, O, N) and, through an LDS tile, transposed (C^T, N^T) as 16-byte runs
+// of 8 consecutive rows.
+constexpr int kGatherRows = 16;
+
 template <int D>
-__global__ __launch_bounds__(256) void bf16_gather_kernel(Bf16Args a)
+__global__ __launch_bounds__(64 * kGatherRows) void bf16_gather_kernel(Bf16Args a)
 {
-    const int lane = threadIdx.x & 63;
-    const uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= a.P + a.M) return;
-    if (w < a.P) {
-        const uint32_t p = w;
-        const int32_t ctx = a.ids[p], ctr = a.ids[a.P + p];
-        float dot = 0.0f;
-        float xc[D / 64], xo[D / 64];
+    constexpr int RW = 1;                 // rows per wave
+    constexpr int U = D / 64;             // elements per lane and row
+    __shared__ __align__(16) uint16_t tile[D][kGatherRows + 8];   // [e][row of the block]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t r0 = blockIdx.x * kGatherRows;
+    const bool pairs = r0 < a.P;
+    if (pairs) {
+        int32_t ctx[RW], ctr[RW];
+        float xc[RW][U], xo[RW][U];
 #pragma unroll
-        for (int u = 0; u < D / 64; ++u) {   // all the row loads first
-            const int e = lane + 64 * u;
-            xc[u] = ctx >= 0 ? a.tin[(int64_t)ctx * D + e] : 0.0f;
-            xo[u] = ctr >= 0 ? a.tout[(int64_t)ctr * D + e] : 0.0f;
+        for (int j = 0; j < RW; ++j) {
+            const uint32_t p = r0 + wv * RW + j;
+            ctx[j] = a.ids[p];
+            ctr[j] = a.ids[a.P + p];
         }
 #pragma unroll
-        for (int u = 0; u < D / 64; ++u) {
-            const int e = lane + 64 * u;
-            const uint16_t c = ctx >= 0 ? bf16_rne(xc[u]) : 0;
-            const uint16_t o = ctr >= 0 ? bf16_rne(xo[u]) : 0;
-            a.C[(int64_t)p * D + e] = c;
-            a.O[(int64_t)p * D + e] = o;
-            a.Ct[(int64_t)e * a.P + p] = c;
-            dot = fmaf(bf16_to_f32(c), bf16_to_f32(o), dot);
-        }
-        dot = wave_sum32(dot);
-        if (lane == 0) {
-            float g = 0.0f;
-            if (ctx >= 0) {
-                g = a.lr * (1.0f - 1.0f / (1.0f + expf(-dot)));
-                a.loss_part[w] += (double)softplus_f(-dot);       // -log sigma(s0)
+        for (int j = 0; j < RW; ++j)        // all the row loads first
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + 64 * u;
+                xc[j][u] = ctx[j] >= 0 ? a.tin[(int64_t)ctx[j] * D + e] : 0.0f;
+                xo[j][u] = ctr[j] >= 0 ? a.tout[(int64_t)ctr[j] * D + e] : 0.0f;
             }
-            a.g0[p] = g;
+#pragma unroll
+        for (int j = 0; j < RW; ++j) {
+            const uint32_t p = r0 + wv * RW + j;
+            float dot = 0.0f;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + 64 * u;
+                const uint16_t c = ctx[j] >= 0 ? bf16_rne(xc[j][u]) : 0;
+                const uint16_t o = ctr[j] >= 0 ? bf16_rne(xo[j][u]) : 0;
+                a.C[(int64_t)p * D + e] = c;
+                a.O[(int64_t)p * D + e] = o;
+                tile[e][wv * RW + j] = c;
+                dot = fmaf(bf16_to_f32(c), bf16_to_f32(o), dot);
+            }
+            dot = wave_sum32(dot);
+            if (lane == 0) {
+                float g = 0.0f;
+                if (ctx[j] >= 0) {
+                    g = a.lr * (1.0f - 1.0f / (1.0f + expf(-dot)));
+                    a.loss_part[p] += (double)softplus_f(-dot);       // -log sigma(s0)
+                }
+                a.g0[p] = g;
+            }
         }
     } else {
-        const uint32_t m = w - a.P;
-        const int32_t neg = a.ids[2 * a.P + m];
-        float xn[D / 64];
+        int32_t neg[RW];
+        float xn[RW][U];
 #pragma unroll
-        for (int u = 0; u < D / 64; ++u) xn[u] = a.tout[(int64_t)neg * D + lane + 64 * u];
+        for (int j = 0; j < RW; ++j) neg[j] = a.ids[2 * a.P + (r0 - a.P) + wv * RW + j];
 #pragma unroll
-        for (int u = 0; u < D / 64; ++u) {
-            const int e = lane + 64 * u;
-            const uint16_t x = bf16_rne(xn[u]);
-            a.N[(int64_t)m * D + e] = x;
-            a.Nt[(int64_t)e * a.M + m] = x;
+        for (int j = 0; j < RW; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) xn[j][u] = a.tout[(int64_t)neg[j] * D + lane + 64 * u];
+#pragma unroll
+        for (int j = 0; j < RW; ++j) {
+            const uint32_t m = (r0 - a.P) + wv * RW + j;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = lane + 64 * u;
+                const uint16_t x = bf16_rne(xn[j][u]);
+                a.N[(int64_t)m * D + e] = x;
+                tile[e][wv * RW + j] = x;
+            }
         }
+    }
+    __syncthreads();
+    uint16_t* T = pairs ? a.Ct : a.Nt;
+    const uint32_t ld = pairs ? a.P : a.M;
+    const uint32_t c0 = pairs ? r0 : r0 - a.P;
+    for (int i = threadIdx.x; i < D * (kGatherRows / 8); i += blockDim.x) {
+        const int e = i / (kGatherRows / 8), q = i % (kGatherRows / 8);
+        *reinterpret_cast<uint4*>(T + (int64_t)e * ld + c0 + 8 * q) =
+            *reinterpret_cast<const uint4*>(&tile[e][8 * q]);
     }
 }
 
@@ -440,7 +475,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     a.cap_out = cap_out;
 
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
-    const uint32_t row_blocks = (P + M + 3) / 4;
+    const uint32_t row_blocks = (P + M) / kGatherRows;
     const uint32_t te = d / 32;
     const uint32_t grad_blocks = (P / 32) * te + (M / 32) * te;
     int64_t pairs_done = 0;
@@ -475,9 +510,9 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         }
         a.ids = ids0 + (size_t)(b - batch0) * (2 * (size_t)P + M);
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
-        if (d == 64) hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(256), 0, c.stream, a);
-        else if (d == 128) hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(256), 0, c.stream, a);
-        else hipLaunchKernelGGL(bf16_gather_kernel<256>, dim3(row_blocks), dim3(256), 0, c.stream, a);
+        if (d == 64) hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
+        else if (d == 128) hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
+        else hipLaunchKernelGGL(bf16_gather_kernel<256>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
         const dim3 sgrid(P / 32, M / 32);
         if (d == 64) hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
         else if (d == 128) hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
