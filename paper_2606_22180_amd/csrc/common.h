@@ -60,6 +60,7 @@ struct DevBuf {
 };
 
 constexpr int kIdSets = 3;   // minibatch id buffer sets: ids run kIdSets - 1 minibatches ahead
+constexpr int kScanSpanMin = 512;   // fewest touches a block of the SGNS scan passes takes
 constexpr int kTimingEvents = 6;   // events per timed minibatch
 
 struct Ctx {

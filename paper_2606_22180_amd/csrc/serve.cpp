@@ -92,7 +92,7 @@ static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_param
     const uint64_t T = P * (K + 2);                              // touches per minibatch
     const uint64_t sc = P / 8 + 1 + P * (K + 1) / 8 + 1;         // chunks of split rows
     const uint64_t sr = P / 17 + 1 + P * (K + 1) / 17 + 1;       // split rows
-    const uint64_t nbs = P / 2048 + 1 + P * (K + 1) / 2048 + 1;  // scan blocks
+    const uint64_t nbs = P / kScanSpanMin + 1 + P * (K + 1) / kScanSpanMin + 1;  // scan blocks
     b += 16 * n * (kIdSets - 1);                                 // more sets of counters, offsets
     b += kIdSets * (8 * T + 4 * T + 16 * T + 16 * sc + 16 * sr + 24 * nbs);   // id/sort sets
     b += 8 * P * (K + 1) + 4 * T + 4 * P * dim + 8 * sc * dim;   // outputs, keys, split sums

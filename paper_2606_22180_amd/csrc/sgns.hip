@@ -173,8 +173,16 @@ __global__ __launch_bounds__(256) void sgns_prep_kernel(PrepArgs a)
 // out-touches e (touch (e / (K+1)) (K+2) + 1 + e mod (K+1)).  A first touch
 // (rank 0) lists its row; the scanned values are (entries | chunks << 32),
 // the rows listed, the rows split over chunks, their chunks and the out rows
-// touched once (which the forward updates itself).
-constexpr int kScanT = 256, kScanI = 8, kScanSpanS = kScanT * kScanI;
+// touched once (which the forward updates itself).  A thread takes I items:
+// 2 up to 65,536 pairs per minibatch (shorter chains of dependent loads per
+// thread and more blocks than with 8; on R-MAT 2^20, d = 128, K = 5:
+// 39.5 -> 34.0 us per minibatch at P = 1,024, 73.2 -> 64.7 at 16,384,
+// 146.3 -> 142.7 at 65,536), 8 above, where every block's sum over the
+// partials of the blocks before it (quadratic in their number) would grow.
+constexpr int kScanT = 256;
+constexpr int kScanISmall = 2, kScanILarge = 8;
+constexpr int64_t kScanSmallPairs = 65536;
+static_assert(kScanT * kScanISmall == kScanSpanMin, "fewest items per scan block");
 
 struct ScanArgs {
     const int32_t* touch_row;
@@ -200,39 +208,39 @@ struct ScanArgs {
                                    // whole counter arrays are zeroed before the ids)
 };
 
-// Items base .. base + kScanI - 1 of a table (n items): the row each one
+// Items base .. base + I - 1 of a table (n items): the row each one
 // lists (-1 if none) and the row's touch count.  BATCH issues the loads of
 // all the items before it uses any (indices past the end clamped, their
-// values dropped): two round trips to memory instead of 2 kScanI, for when
+// values dropped): two round trips to memory instead of 2 I, for when
 // the scan is on the minibatch's critical path.  Otherwise each item's loads
 // wait for the previous item, which leaves more bandwidth to the launches
 // that run beside the scan.
-template <int K, bool BATCH>
+template <int K, bool BATCH, int I>
 __device__ __forceinline__ void scan_items(const ScanArgs& a, bool out, uint32_t base, uint32_t n,
-                                           int32_t (&rows)[kScanI], uint32_t (&cs)[kScanI])
+                                           int32_t (&rows)[I], uint32_t (&cs)[I])
 {
     const uint32_t* cnt = out ? a.cnt_out : a.cnt_in;
     if (BATCH) {
         const uint32_t last = n > 0 ? n - 1 : 0;
-        uint32_t pos[kScanI];
+        uint32_t pos[I];
 #pragma unroll
-        for (int k = 0; k < kScanI; ++k) {
+        for (int k = 0; k < I; ++k) {
             const uint32_t i = min(base + k, last);
             const uint32_t t = out ? (i / (K + 1)) * (K + 2) + 1 + i % (K + 1) : i * (K + 2);
             rows[k] = a.touch_row[t];
             pos[k] = a.touch_pos[t];
         }
 #pragma unroll
-        for (int k = 0; k < kScanI; ++k) {
+        for (int k = 0; k < I; ++k) {
             const bool first = base + k < n && rows[k] >= 0 && pos[k] == 0u;
             rows[k] = first ? rows[k] : -1;
             cs[k] = cnt[first ? rows[k] : 0];
         }
 #pragma unroll
-        for (int k = 0; k < kScanI; ++k) cs[k] = rows[k] >= 0 ? cs[k] : 0u;
+        for (int k = 0; k < I; ++k) cs[k] = rows[k] >= 0 ? cs[k] : 0u;
     } else {
 #pragma unroll
-        for (int k = 0; k < kScanI; ++k) {
+        for (int k = 0; k < I; ++k) {
             rows[k] = -1;
             cs[k] = 0u;
             if (base + k < n) {
@@ -270,7 +278,7 @@ __device__ __forceinline__ unsigned long long pack_ec(uint32_t c, bool out)
     return (unsigned long long)e | ((unsigned long long)((e + kChunk - 1) / kChunk) << 32);
 }
 
-template <int K, bool BATCH>
+template <int K, bool BATCH, int I>
 __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
 {
     __shared__ unsigned long long s_ec[kScanT];
@@ -278,14 +286,14 @@ __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
     const bool out = blockIdx.x >= a.nb_in;
     const uint32_t nb = out ? blockIdx.x - a.nb_in : blockIdx.x;
     const uint32_t n = out ? a.n_out : a.n_in;
-    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
+    const uint32_t base = nb * (kScanT * I) + threadIdx.x * I;
     unsigned long long ec = 0;
     uint4 rm = make_uint4(0u, 0u, 0u, 0u);
-    int32_t rows[kScanI];
-    uint32_t cs[kScanI];
-    scan_items<K, BATCH>(a, out, base, n, rows, cs);
+    int32_t rows[I];
+    uint32_t cs[I];
+    scan_items<K, BATCH, I>(a, out, base, n, rows, cs);
 #pragma unroll
-    for (int k = 0; k < kScanI; ++k) {
+    for (int k = 0; k < I; ++k) {
         if (rows[k] >= 0) {
             ec += pack_ec(cs[k], out);
             rm = add4(rm, split_counts(cs[k], out));
@@ -307,7 +315,7 @@ __global__ __launch_bounds__(256) void sgns_scan_partials(ScanArgs a)
     }
 }
 
-template <int K, bool BATCH>
+template <int K, bool BATCH, int I>
 __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
 {
     __shared__ unsigned long long s_ec[kScanT];
@@ -337,15 +345,15 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
     const uint4 blk_rm = s_rm[0];
     __syncthreads();
 
-    const uint32_t base = nb * kScanSpanS + threadIdx.x * kScanI;
+    const uint32_t base = nb * (kScanT * I) + threadIdx.x * I;
     // (entries scanned in the low word; the chunk count in the high word is unused here)
-    int32_t rows[kScanI];
-    uint32_t cs[kScanI];
+    int32_t rows[I];
+    uint32_t cs[I];
     unsigned long long mine = 0;
     uint4 mine_rm = make_uint4(0u, 0u, 0u, 0u);
-    scan_items<K, BATCH>(a, out, base, n, rows, cs);
+    scan_items<K, BATCH, I>(a, out, base, n, rows, cs);
 #pragma unroll
-    for (int k = 0; k < kScanI; ++k) {
+    for (int k = 0; k < I; ++k) {
         if (rows[k] >= 0) {
             mine += pack_ec(cs[k], out);
             mine_rm = add4(mine_rm, split_counts(cs[k], out));
@@ -376,7 +384,7 @@ __global__ __launch_bounds__(256) void sgns_scan_write(ScanArgs a)
     int4* split = out ? a.split_out : a.split_in;      // chunks of the split rows
     int4* mrows = out ? a.mrows_out : a.mrows_in;
 #pragma unroll
-    for (int k = 0; k < kScanI; ++k) {
+    for (int k = 0; k < I; ++k) {
         if (rows[k] >= 0) {
             const uint32_t c = cs[k];
             list[slot] = rows[k];
@@ -948,6 +956,7 @@ struct MinibatchLaunch {
     uint32_t npairs;
     int dim, K;
     uint32_t prep_blocks, fwd_blocks, nb_in, nb_out, reduce_blocks;
+    int scan_i;           // scan items per thread (kScanISmall or kScanILarge)
     int64_t split_in;     // partial-sum rows reserved for the in-table (the out-table's follow)
     double grid_c;        // exact-sum grid constant of this minibatch's learning rate
     bool one_stream;      // ids on the training stream (on the critical path)
@@ -1004,12 +1013,19 @@ static void launch_ids_t(MinibatchBufs& mb, PrepArgs pa, const MinibatchLaunch& 
                 mb.off_out.as<int32_t>(), mb.chunks_in.as<int4>(), mb.chunks_out.as<int4>(),
                 mb.split_in.as<int4>(), mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),
                 mb.mrows_out.as<int4>(), meta, ml.zero_whole ? 0 : 1};
-    if (ml.one_stream) {
-        hipLaunchKernelGGL((sgns_scan_partials<K, true>), dim3(nb), dim3(256), 0, s, sa);
-        hipLaunchKernelGGL((sgns_scan_write<K, true>), dim3(nb), dim3(256), 0, s, sa);
+    const bool small = ml.scan_i == kScanISmall;
+    if (ml.one_stream && small) {
+        hipLaunchKernelGGL((sgns_scan_partials<K, true, kScanISmall>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_write<K, true, kScanISmall>), dim3(nb), dim3(256), 0, s, sa);
+    } else if (ml.one_stream) {
+        hipLaunchKernelGGL((sgns_scan_partials<K, true, kScanILarge>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_write<K, true, kScanILarge>), dim3(nb), dim3(256), 0, s, sa);
+    } else if (small) {
+        hipLaunchKernelGGL((sgns_scan_partials<K, false, kScanISmall>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_write<K, false, kScanISmall>), dim3(nb), dim3(256), 0, s, sa);
     } else {
-        hipLaunchKernelGGL((sgns_scan_partials<K, false>), dim3(nb), dim3(256), 0, s, sa);
-        hipLaunchKernelGGL((sgns_scan_write<K, false>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_partials<K, false, kScanILarge>), dim3(nb), dim3(256), 0, s, sa);
+        hipLaunchKernelGGL((sgns_scan_write<K, false, kScanILarge>), dim3(nb), dim3(256), 0, s, sa);
     }
     FELOG_HIP(hipGetLastError());
 }
@@ -1170,8 +1186,8 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         m.cap_K = std::max(m.cap_K, K);
         const int64_t cp = m.cap_pairs, ck = m.cap_K;
         const int64_t touches_out = cp * (ck + 1);
-        const int64_t nbmax = (cp + kScanSpanS - 1) / kScanSpanS +
-                              (touches_out + kScanSpanS - 1) / kScanSpanS;
+        const int64_t nbmax = (cp + kScanSpanMin - 1) / kScanSpanMin +
+                              (touches_out + kScanSpanMin - 1) / kScanSpanMin;
         for (MinibatchBufs& b : m.mb) {
             b.touch_row.alloc(&c, sizeof(int32_t) * cp * (ck + 2));
             b.touch_pos.alloc(&c, sizeof(uint32_t) * cp * (ck + 2));
@@ -1262,8 +1278,10 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         ml.npairs = (uint32_t)np;
         ml.prep_blocks = (uint32_t)std::min<int64_t>((int64_t)c.num_cus * 4, (np * (K + 2) + 255) / 256);
         ml.fwd_blocks = (uint32_t)(((np + ppw - 1) / ppw + 3) / 4);
-        ml.nb_in = (uint32_t)((np + kScanSpanS - 1) / kScanSpanS);
-        ml.nb_out = (uint32_t)((np * (K + 1) + kScanSpanS - 1) / kScanSpanS);
+        ml.scan_i = P <= kScanSmallPairs ? kScanISmall : kScanILarge;
+        const int64_t span = (int64_t)kScanT * ml.scan_i;
+        ml.nb_in = (uint32_t)((np + span - 1) / span);
+        ml.nb_out = (uint32_t)((np * (K + 1) + span - 1) / span);
         // 16 blocks per CU (faster than 6, 8 or 32 at 65,536 pairs on 2^20 rows),
         // but no more than the items can use: at most one row per touch and per
         // table row, plus the chunks of split rows, 16 items per block at a time
