@@ -1276,10 +1276,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
         ml.dim = m.dim;
         ml.K = K;
         ml.npairs = (uint32_t)np;
-        // prep runs beside the training launches: 2 blocks per CU (grid-stride)
-        // leave them more of the chip than 4 or 8 (145.7, 146.7, 150.0 us per
-        // minibatch at 65,536 pairs on R-MAT 2^20)
-        ml.prep_blocks = (uint32_t)std::min<int64_t>((int64_t)c.num_cus * 2, (np * (K + 2) + 255) / 256);
+        ml.prep_blocks = (uint32_t)std::min<int64_t>((int64_t)c.num_cus * 4, (np * (K + 2) + 255) / 256);
         ml.fwd_blocks = (uint32_t)(((np + ppw - 1) / ppw + 3) / 4);
         ml.scan_i = P <= kScanSmallPairs ? kScanISmall : kScanILarge;
         const int64_t span = (int64_t)kScanT * ml.scan_i;
