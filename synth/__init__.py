@@ -14,19 +14,24 @@ Stand-ins for the paper's data:
     the inner product of embeddings, measure AUC) is kept, with a 10% holdout
     and one split per seed.
 
-Every generator takes an explicit seed and uses numpy's PCG64, so the same
-call returns the same arrays on every machine.
+Every generator takes an explicit seed.  The R-MAT graphs, CSR assembly, edge
+weights and link-prediction splits come from graphgen.cpp (C++ with OpenMP,
+built in-tree by ``build()``), whose random numbers are counter based, so a
+call returns the same arrays on every machine and for any thread count; the
+SBM and the serving mix use numpy's PCG64.
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import math
+import os
+import subprocess
 
 import numpy as np
-import pandas as pd
 
 __all__ = [
-    "Graph", "sbm_edges", "rmat_edges", "csr_from_edges", "edge_weights",
+    "Graph", "sbm_edges", "rmat_edges", "csr_from_edges", "edge_weights", "edge_weight_hash",
     "holdout_split", "LinkSplit", "build_graph", "tiny_graph", "job_mix",
     "CONFIGS",
 ]
@@ -84,51 +89,95 @@ def sbm_edges(n: int = 1000, blocks: int = 4, p_in: float = 0.035,
     return np.stack([iu[keep], ju[keep]], axis=1).astype(np.int64)
 
 
-def rmat_edges(scale: int, n_edges: int, a: float = 0.57, b: float = 0.19,
-               c: float = 0.19, seed: int = 1, batch: int = 1 << 22,
-               permute: bool = True) -> np.ndarray:
-    """R-MAT edge list with ``n_edges`` unique undirected edges (u < v).
+_LIB_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib")
+_LIB = os.path.join(_LIB_DIR, "libgraphgen.so")
+_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "graphgen.cpp")
+_lib_handle = None
 
-    Edges are drawn in batches by recursive quadrant choice with probabilities
-    (a, b, c, 1-a-b-c); self loops and duplicates are dropped and the first
-    ``n_edges`` unique edges in generation order are kept. A seeded random
-    vertex permutation is applied at the end (the Graph500 convention) so
-    that vertex id does not encode degree.
+
+def build(force: bool = False) -> str:
+    """Compile the graph-input library (g++, OpenMP) in-tree."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        os.makedirs(_LIB_DIR, exist_ok=True)
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("g++ failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _gg():
+    global _lib_handle
+    if _lib_handle is None:
+        lib = ctypes.CDLL(build())
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.gg_rmat.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, i64p, i64p]
+        lib.gg_rmat.restype = ctypes.c_int
+        lib.gg_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, i64p, i64p, i64p,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                               ctypes.c_uint64]
+        lib.gg_csr.restype = ctypes.c_int
+        lib.gg_holdout.argtypes = [ctypes.c_int64, ctypes.c_int64, i64p, i64p, ctypes.c_int64,
+                                   ctypes.c_uint64, i64p, i64p, i64p]
+        lib.gg_holdout.restype = ctypes.c_int
+        lib.gg_edge_weight.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64]
+        lib.gg_edge_weight.restype = ctypes.c_float
+        _lib_handle = lib
+    return _lib_handle
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def rmat_edges(scale: int, n_edges: int, a: float = 0.57, b: float = 0.19,
+               c: float = 0.19, seed: int = 1, permute: bool = True) -> np.ndarray:
+    """R-MAT edge list with ``n_edges`` distinct undirected edges (u < v),
+    sorted by (u, v).
+
+    Each candidate edge takes ``scale`` quadrant choices with probabilities
+    (a, b, c, 1-a-b-c), each from a 16-bit uniform draw (the probabilities are
+    rounded to multiples of 2^-16).  Self loops are dropped; candidates are
+    made until the distinct edges number at least ``n_edges`` and the surplus
+    is dropped uniformly at random.  A seeded random vertex permutation is
+    applied at the end (the Graph500 convention), so that vertex id does not
+    encode degree.  All draws are counter based (graphgen.cpp), so the graph
+    depends on the arguments alone.
     """
-    n = 1 << scale
-    rng = np.random.Generator(np.random.PCG64(seed))
-    ab = a + b
-    abc = a + b + c
-    keys_all = []
-    have = 0
-    uniq = None
-    while True:
-        src = np.zeros(batch, dtype=np.int64)
-        dst = np.zeros(batch, dtype=np.int64)
-        for lvl in range(scale):
-            r = rng.random(batch, dtype=np.float32)
-            bit = np.int64(1) << (scale - 1 - lvl)
-            right = ((r >= a) & (r < ab)) | (r >= abc)
-            down = r >= ab
-            src |= np.where(down, bit, 0)
-            dst |= np.where(right, bit, 0)
-        u, v = _canon(src, dst)
-        keys_all.append(u * n + v)
-        have += u.shape[0]
-        if have >= n_edges:
-            # distinct keys in order of first appearance (a hash pass)
-            keys = pd.unique(np.concatenate(keys_all))
-            if keys.shape[0] >= n_edges:
-                keys = keys[:n_edges]
-                break
-            keys_all = [keys]
-    u = keys // n
-    v = keys % n
-    if permute:
-        perm = rng.permutation(n).astype(np.int64)
-        u, v = perm[u], perm[v]
-        u, v = np.minimum(u, v), np.maximum(u, v)
+    ta, tab, tabc = (int(round(x * 65536)) for x in (a, a + b, a + b + c))
+    u = np.empty(n_edges, dtype=np.int64)
+    v = np.empty(n_edges, dtype=np.int64)
+    rc = _gg().gg_rmat(scale, n_edges, ta, tab, tabc, seed & (2**64 - 1), int(permute),
+                       _ptr(u, ctypes.c_int64), _ptr(v, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError("rmat_edges: scale %d with %d edges is out of range" % (scale, n_edges))
     return np.stack([u, v], axis=1)
+
+
+def _splitmix64(z):
+    z = z + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def edge_weight_hash(u: np.ndarray, v: np.ndarray, seed: int) -> np.ndarray:
+    """Weight of undirected edge {u, v}, uniform on (0, 1] with 2^-24 spacing,
+    as a function of the edge alone, so that both directions and every subset
+    of the edges agree without an array riding along: ((h >> 40) + 1) 2^-24,
+    h = word 0 of the SplitMix64 stream of the edge key (min << 32 | max), as
+    graphgen.cpp computes it."""
+    with np.errstate(over="ignore"):
+        a = np.minimum(u, v).astype(np.uint64)
+        b = np.maximum(u, v).astype(np.uint64)
+        key = (a << np.uint64(32)) | b
+        s = _splitmix64(np.uint64(seed & (2**64 - 1)) ^ np.uint64(0xD1B54A32D192ED03))
+        h = _splitmix64(s ^ (key * np.uint64(16)))
+    k = (h >> np.uint64(40)).astype(np.int64) + 1
+    return (k.astype(np.float64) * 2.0 ** -24).astype(np.float32)
 
 
 def edge_weights(n_edges: int, seed: int) -> np.ndarray:
@@ -138,24 +187,37 @@ def edge_weights(n_edges: int, seed: int) -> np.ndarray:
     return (k.astype(np.float64) * 2.0 ** -24).astype(np.float32)
 
 
-def csr_from_edges(n: int, edges: np.ndarray,
-                   weights: np.ndarray | None = None) -> Graph:
-    """Symmetric CSR from an undirected edge list (u < v, unique)."""
+def csr_from_edges(n: int, edges: np.ndarray, weights: np.ndarray | None = None,
+                   weight_seed: int | None = None) -> Graph:
+    """Symmetric CSR from an undirected edge list (u != v, no repeated edge).
+
+    Weights: ``weights`` aligned with ``edges`` (one per undirected edge), or
+    ``weight_seed`` for the per-edge hash weights of ``edge_weight_hash`` (a
+    function of the edge, so no array rides along with the sort), or neither
+    for an unweighted graph.
+    """
+    m = edges.shape[0]
+    if weights is None:
+        u = np.ascontiguousarray(edges[:, 0], dtype=np.int64)
+        v = np.ascontiguousarray(edges[:, 1], dtype=np.int64)
+        indptr = np.empty(n + 1, dtype=np.int64)
+        indices = np.empty(2 * m, dtype=np.int32)
+        w = None if weight_seed is None else np.empty(2 * m, dtype=np.float32)
+        rc = _gg().gg_csr(n, m, _ptr(u, ctypes.c_int64), _ptr(v, ctypes.c_int64),
+                          _ptr(indptr, ctypes.c_int64), _ptr(indices, ctypes.c_int32),
+                          None if w is None else _ptr(w, ctypes.c_float),
+                          0 if weight_seed is None else weight_seed & (2**64 - 1))
+        if rc != 0:
+            raise ValueError("csr_from_edges: an edge is a self loop or leaves [0, n)")
+        return Graph(n=n, indptr=indptr, indices=indices, weights=w)
     u = edges[:, 0].astype(np.int64)
     v = edges[:, 1].astype(np.int64)
     src = np.concatenate([u, v])
     dst = np.concatenate([v, u])
-    key = src * n + dst
-    w = None
-    if weights is None:
-        key = np.sort(key)   # keys are distinct: no order among equals to keep
-        src = key // n
-        dst = key - src * n
-    else:
-        order = np.argsort(key)
-        src = src[order]
-        dst = dst[order]
-        w = np.concatenate([weights, weights])[order].astype(np.float32)
+    order = np.argsort(src * n + dst)
+    src = src[order]
+    dst = dst[order]
+    w = np.concatenate([weights, weights])[order].astype(np.float32)
     counts = np.bincount(src, minlength=n)
     indptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=indptr[1:])
@@ -163,42 +225,30 @@ def csr_from_edges(n: int, edges: np.ndarray,
 
 
 def holdout_split(n: int, edges: np.ndarray, frac: float = 0.1, seed: int = 7,
-                  weights: np.ndarray | None = None) -> LinkSplit:
-    """Hide ``frac`` of the undirected edges (uniformly) for link prediction.
-
-    Test negatives: as many node pairs (u < v) as held-out edges, uniform over
-    pairs that are not edges of the *full* graph, drawn without replacement.
-    """
-    rng = np.random.Generator(np.random.PCG64(seed))
+                  weights: np.ndarray | None = None,
+                  weight_seed: int | None = None) -> LinkSplit:
+    """Hide ``frac`` of the undirected edges (uniformly, without replacement)
+    for link prediction.  Test negatives: as many distinct node pairs (u < v)
+    as held-out edges, uniform over the pairs that are not edges of the *full*
+    graph.  Draws are counter based (graphgen.cpp)."""
     m = edges.shape[0]
     n_test = int(round(frac * m))
-    perm = rng.permutation(m)
-    test_idx = np.sort(perm[:n_test])
+    u = np.ascontiguousarray(edges[:, 0], dtype=np.int64)
+    v = np.ascontiguousarray(edges[:, 1], dtype=np.int64)
+    test_idx = np.empty(n_test, dtype=np.int64)
+    nu = np.empty(n_test, dtype=np.int64)
+    nv = np.empty(n_test, dtype=np.int64)
+    rc = _gg().gg_holdout(n, m, _ptr(u, ctypes.c_int64), _ptr(v, ctypes.c_int64), n_test,
+                          seed & (2**64 - 1), _ptr(test_idx, ctypes.c_int64),
+                          _ptr(nu, ctypes.c_int64), _ptr(nv, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError("holdout_split: %d test pairs do not fit a graph on %d nodes" % (n_test, n))
     train_mask = np.ones(m, dtype=bool)
     train_mask[test_idx] = False
-    full_keys = edges[:, 0].astype(np.int64) * n + edges[:, 1]
-    full_sorted = np.sort(full_keys)
-    neg = np.zeros((0, 2), dtype=np.int64)
-    seen = np.zeros(0, dtype=np.int64)
-    while neg.shape[0] < n_test:
-        want = (n_test - neg.shape[0]) * 2 + 16
-        a = rng.integers(0, n, size=want, dtype=np.int64)
-        b = rng.integers(0, n, size=want, dtype=np.int64)
-        a, b = _canon(a, b)
-        k = a * n + b
-        pos = np.searchsorted(full_sorted, k)
-        pos = np.minimum(pos, full_sorted.shape[0] - 1)
-        ok = full_sorted[pos] != k
-        k = k[ok]
-        k = pd.unique(k)   # distinct, in order of first appearance
-        k = k[~np.isin(k, seen)]
-        seen = np.concatenate([seen, k])
-        take = k[: n_test - neg.shape[0]]
-        neg = np.concatenate([neg, np.stack([take // n, take % n], axis=1)])
     tw = None if weights is None else weights[train_mask]
-    train = csr_from_edges(n, edges[train_mask], tw)
+    train = csr_from_edges(n, edges[train_mask], tw, weight_seed=weight_seed)
     return LinkSplit(train=train, test_pos=edges[test_idx].astype(np.int64),
-                     test_neg=neg.astype(np.int64))
+                     test_neg=np.stack([nu, nv], axis=1))
 
 
 def tiny_graph(kind: str = "path") -> Graph:
@@ -257,8 +307,9 @@ def build_graph(name: str, scale_override: int | None = None,
         ne = edges_override or cfg["edges"]
         n = 1 << scale
         e = rmat_edges(scale, ne, seed=cfg["seed"])
-        w = edge_weights(e.shape[0], cfg["seed"] + 100) if cfg.get("weighted") else None
-    return holdout_split(n, e, cfg["holdout"], seed=cfg["seed"] + 7, weights=w)
+        ws = cfg["seed"] + 100 if cfg.get("weighted") else None
+        return holdout_split(n, e, cfg["holdout"], seed=cfg["seed"] + 7, weight_seed=ws)
+    return holdout_split(n, e, cfg["holdout"], seed=cfg["seed"] + 7)
 
 
 def job_mix(n_jobs: int, seed: int = 4, n_min: int = 200, n_max: int = 200_000):
@@ -310,7 +361,10 @@ def job_graph(job: dict) -> Graph:
         e = np.stack([k // n, k % n], axis=1)
     else:
         scale = max(1, math.ceil(math.log2(n)))
-        e = rmat_edges(scale, m * 2, seed=2000 + job["seed"], batch=max(1024, m * 4),
-                       permute=False)
-        e = e[(e[:, 0] < n) & (e[:, 1] < n)][:m]
+        cap = (1 << scale) * ((1 << scale) - 1) // 2
+        e = rmat_edges(scale, min(m * 2, cap), seed=2000 + job["seed"], permute=False)
+        e = e[(e[:, 0] < n) & (e[:, 1] < n)]
+        if e.shape[0] > m:
+            rng = np.random.Generator(np.random.PCG64(3000 + job["seed"]))
+            e = e[np.sort(rng.choice(e.shape[0], m, replace=False))]
     return csr_from_edges(n, e.astype(np.int64))

@@ -69,3 +69,44 @@ def test_job_mix_ranges():
     assert set(j["dim"] for j in jobs) == {64, 128}
     g = synth.job_graph(jobs[0])
     _check_csr(g)
+
+
+def test_edge_weight_hash_matches_library():
+    """The numpy and C++ forms of the per-edge hash weight agree, and a weight
+    does not depend on the direction of the edge."""
+    rng = np.random.default_rng(0)
+    u = rng.integers(0, 1 << 23, 2000)
+    v = rng.integers(0, 1 << 23, 2000)
+    w = synth.edge_weight_hash(u, v, 103)
+    lib = synth._gg()
+    assert all(lib.gg_edge_weight(int(a), int(b), 103) == x for a, b, x in zip(u, v, w))
+    assert np.array_equal(w, synth.edge_weight_hash(v, u, 103))
+    assert w.min() > 0 and w.max() <= 1
+
+
+def test_rmat_independent_of_thread_count():
+    """Counter-based draws: one thread and all threads give the same graph."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import synth, hashlib; "
+            "sp = synth.holdout_split(1 << 14, synth.rmat_edges(14, 1 << 17, seed=9), 0.1, seed=3, "
+            "weight_seed=4); g = sp.train; "
+            "print(hashlib.sha256(g.indptr.tobytes() + g.indices.tobytes() + g.weights.tobytes() "
+            "+ sp.test_pos.tobytes() + sp.test_neg.tobytes()).hexdigest())"
+            % __import__("os").path.dirname(__import__("os").path.dirname(__file__)))
+    out = []
+    for threads in ("1", "8"):
+        env = dict(__import__("os").environ, OMP_NUM_THREADS=threads)
+        out.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                                  text=True, check=True).stdout.strip())
+    assert out[0] == out[1]
+
+
+def test_holdout_weighted_split_keeps_mirrored_weights():
+    sp = synth.holdout_split(1 << 12, synth.rmat_edges(12, 20000, seed=5), 0.1, seed=2,
+                             weight_seed=11)
+    g = sp.train
+    _check_csr(g)
+    src = np.repeat(np.arange(g.n), np.diff(g.indptr))
+    assert np.array_equal(g.weights, synth.edge_weight_hash(src, g.indices.astype(np.int64), 11))
+    assert sp.test_pos.shape == sp.test_neg.shape == (2000, 2)
