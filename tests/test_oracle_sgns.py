@@ -291,3 +291,100 @@ def test_sbm_epoch_learns(orc):
                     cdf=cdf)
     assert probe_loss(tin, tout) < before
     assert orc.link_auc(tin, sp) > max(0.70, auc0 + 0.1)
+
+
+def _noise_case():
+    rng = np.random.default_rng(17)
+    counts = rng.integers(1, 80, 24).astype(np.uint64)
+    counts[4] = 3000                                   # one heavy node
+    p = counts.astype(np.float64) ** 0.75
+    return counts, p / p.sum()
+
+
+def _mass_groups(p, groups=4):
+    """Nodes grouped into `groups` classes of roughly equal noise mass (for
+    contingency tables with well-filled cells)."""
+    order = np.argsort(-p)
+    cls = np.zeros(p.shape[0], np.int64)
+    acc, g = 0.0, 0
+    for i in order:
+        cls[i] = g
+        acc += p[i]
+        if acc >= (g + 1) / groups and g < groups - 1:
+            g += 1
+    return cls
+
+
+def _draw_negatives_raw(orc, wid, j, slot, K, seed, cdf):
+    n = cdf.shape[0] - 1
+    out = np.zeros((wid.shape[0], K), np.int32)
+    orc.lib().orc_draw_negatives(wid.shape[0], orc._ptr(np.ascontiguousarray(wid, np.int64)),
+                                 orc._ptr(np.ascontiguousarray(j, np.int32)),
+                                 orc._ptr(np.ascontiguousarray(slot, np.int32)), K, seed, n,
+                                 orc._ptr(cdf), orc._ptr(out))
+    return out
+
+
+def test_pair_negatives_marginal_and_independent(orc):
+    """Negatives of Eq. (2): each of a pair's K draws is an independent draw
+    from Pn(u) ~ c^0.75.  Marginals by chi-square per slot k; independence by
+    chi-square on the joint class counts of every (k, k') of a pair, of the
+    same k across the two window slots of one (walk, j), and across walks at
+    the same (j, slot).  A plausible wiring mistake (two k sharing words, the
+    slot or the walk left out of the counter) makes a joint table diagonal."""
+    from scipy.stats import chi2_contingency
+    counts, p = _noise_case()
+    cdf = orc.neg_cdf(counts)
+    cls = _mass_groups(p)
+    K = 6
+    n_pairs = 200_000
+    rng = np.random.default_rng(5)
+    wid = rng.integers(0, 2 ** 40, n_pairs, dtype=np.int64)
+    j = rng.integers(0, 80, n_pairs).astype(np.int32)
+    slot = rng.integers(0, 19, n_pairs).astype(np.int32)
+    neg = _draw_negatives_raw(orc, wid, j, slot, K, 123, cdf)
+    for k in range(K):
+        obs = np.bincount(neg[:, k], minlength=p.shape[0])
+        assert chisquare(obs, p * n_pairs).pvalue > 1e-4, k
+    pooled = np.bincount(neg.ravel(), minlength=p.shape[0])
+    assert chisquare(pooled, p * neg.size).pvalue > 1e-4
+
+    def independent(a, b, what):
+        tab = np.zeros((4, 4))
+        np.add.at(tab, (cls[a], cls[b]), 1)
+        assert chi2_contingency(tab).pvalue > 1e-4, (what, tab)
+
+    for k in range(K):
+        for k2 in range(k + 1, K):
+            independent(neg[:, k], neg[:, k2], ("k", k, k2))
+    # the next window slot of the same (walk, j), and the next walk
+    neg_s = _draw_negatives_raw(orc, wid, j, slot + 1, K, 123, cdf)
+    neg_w = _draw_negatives_raw(orc, wid + 1, j, slot, K, 123, cdf)
+    neg_j = _draw_negatives_raw(orc, wid, j + 1, slot, K, 123, cdf)
+    for k in (0, 1, K - 1):
+        independent(neg[:, k], neg_s[:, k], ("slot", k))
+        independent(neg[:, k], neg_w[:, k], ("walk", k))
+        independent(neg[:, k], neg_j[:, k], ("j", k))
+
+
+def test_shared_negatives_marginal_and_independent(orc):
+    """The shared-negative form's M draws per minibatch: marginally c^0.75,
+    independent between neighbouring draws m, m+1 (which share one Philox
+    call) and between minibatches."""
+    from scipy.stats import chi2_contingency
+    counts, p = _noise_case()
+    cdf = orc.neg_cdf(counts)
+    cls = _mass_groups(p)
+    M = 1024
+    draws = np.stack([orc.shared_negatives(b, 0, M, 31, cdf) for b in range(400)])
+    obs = np.bincount(draws.ravel(), minlength=p.shape[0])
+    assert chisquare(obs, p * draws.size).pvalue > 1e-4
+    for what, a, b in (("m, m+1", draws[:, 0::2], draws[:, 1::2]),
+                       ("m, m+2", draws[:, 0:-2:4], draws[:, 2::4]),
+                       ("b, b+1", draws[:-1], draws[1:])):
+        tab = np.zeros((4, 4))
+        np.add.at(tab, (cls[a.ravel()], cls[b.ravel()]), 1)
+        assert chi2_contingency(tab).pvalue > 1e-4, (what, tab)
+    # another round gives other draws
+    other = orc.shared_negatives(0, 1, M, 31, cdf)
+    assert not np.array_equal(other, draws[0])
