@@ -44,7 +44,7 @@ def build(force: bool = False) -> str:
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                                "-ffp-contract=off", "-fno-fast-math",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)

@@ -24,7 +24,12 @@
  * entry; comparisons that decide an integer (node2vec acceptance) use the FP32
  * operations that define them.
  *
- * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fno-fast-math
+ * Loops over independent items (table rows, walks, scored nodes, the
+ * coefficients of a minibatch's pairs) run under OpenMP; every value is
+ * computed as in a one-thread run, and every sum keeps its order, so the
+ * results do not depend on the number of threads.
+ *
+ * Build: gcc -O2 -fopenmp -fPIC -shared -ffp-contract=off -fno-fast-math
  */
 #include <math.h>
 #include <stdint.h>
@@ -87,11 +92,14 @@ void orc_philox_batch(int64_t count, const uint32_t* ctrs, uint64_t seed, uint32
 /* ------------------------------------------------------------------ */
 void orc_init_tables(int64_t n, int d, uint64_t seed, float* in, float* out)
 {
+    /* rows are independent; one Philox call serves columns 4m .. 4m+3 */
+#pragma omp parallel for schedule(static)
     for (int64_t v = 0; v < n; ++v) {
+        uint32_t r[4];
         for (int c = 0; c < d; ++c) {
-            uint32_t r[4];
-            philox_u64key((uint32_t)v, (uint32_t)(v >> 32), (uint32_t)(c / 4),
-                          (uint32_t)TAG_INIT << 24, seed, r);
+            if (c % 4 == 0)
+                philox_u64key((uint32_t)v, (uint32_t)(v >> 32), (uint32_t)(c / 4),
+                              (uint32_t)TAG_INIT << 24, seed, r);
             float u = (float)(r[c % 4] >> 8) * (1.0f / 16777216.0f);  /* [0,1), 24 bits */
             in[v * d + c] = (u - 0.5f) / (float)d;
             out[v * d + c] = 0.0f;
@@ -151,6 +159,8 @@ void orc_walks_uniform(int64_t n, const int64_t* indptr, const int32_t* indices,
 {
     (void)n;
     int64_t W = n_starts * (int64_t)r;
+    /* walks are independent */
+#pragma omp parallel for schedule(dynamic, 1024)
     for (int64_t wi = 0; wi < W; ++wi) {
         int32_t* out = walks + wi * L;
         int64_t wid = id_base + wi;
@@ -208,6 +218,8 @@ int64_t orc_walks_node2vec(int64_t n, const int64_t* indptr, const int32_t* indi
     }
     int64_t capped = 0;
     int64_t W = n_starts * (int64_t)r;
+    /* walks are independent */
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : capped)
     for (int64_t wi = 0; wi < W; ++wi) {
         int32_t* out = walks + wi * L;
         int64_t wid = id_base + wi;
@@ -421,19 +433,34 @@ double NAME(T* in, T* out, int64_t n, int d, int64_t np,                        
     }                                                                               \
     int64_t ui = 0, uo = 0;                                                         \
     double loss = 0.0;                                                              \
-    double* g = (double*)malloc(sizeof(double) * (size_t)(K + 1));                 \
+    /* coefficients and loss terms of every pair, from the tables at the start:    \
+       pairs are independent here */                                                \
+    double* gall = (double*)malloc(sizeof(double) * (size_t)(np * (K + 1) + 1));    \
+    double* lall = (double*)malloc(sizeof(double) * (size_t)(np * (K + 1) + 1));    \
+    _Pragma("omp parallel for schedule(static)")                                    \
+    for (int64_t p = 0; p < np; ++p) {                                              \
+        int32_t c = ctx[p];                                                         \
+        for (int k = 0; k <= K; ++k) {                                              \
+            int32_t t = k == 0 ? ctr[p] : neg[p * K + (k - 1)];                     \
+            double* gk = gall + p * (K + 1) + k;                                    \
+            double* lk = lall + p * (K + 1) + k;                                    \
+            if (k > 0 && t == ctr[p]) { *gk = 0.0; *lk = 0.0; continue; }           \
+            double s = 0.0;                                                         \
+            for (int e = 0; e < d; ++e)                                             \
+                s += (double)in[(int64_t)c * d + e] * (double)out[(int64_t)t * d + e]; \
+            if (k == 0) { *gk = lr * (1.0 - orc_sigmoid(s)); *lk = orc_log_sigmoid(s); } \
+            else { *gk = -lr * orc_sigmoid(s); *lk = orc_log_sigmoid(-s); }         \
+        }                                                                           \
+    }                                                                               \
     int32_t* tk = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K + 1));             \
     for (int64_t p = 0; p < np; ++p) {                                              \
         int32_t c = ctx[p];                                                         \
+        const double* g = gall + p * (K + 1);                                       \
         tk[0] = ctr[p];                                                             \
         for (int k = 1; k <= K; ++k) tk[k] = neg[p * K + (k - 1)];                  \
         for (int k = 0; k <= K; ++k) {                                              \
-            if (k > 0 && tk[k] == tk[0]) { g[k] = 0.0; continue; }                  \
-            double s = 0.0;                                                         \
-            for (int e = 0; e < d; ++e)                                             \
-                s += (double)in[(int64_t)c * d + e] * (double)out[(int64_t)tk[k] * d + e]; \
-            if (k == 0) { g[k] = lr * (1.0 - orc_sigmoid(s)); loss -= orc_log_sigmoid(s); } \
-            else { g[k] = -lr * orc_sigmoid(s); loss -= orc_log_sigmoid(-s); }      \
+            if (k > 0 && tk[k] == tk[0]) continue;                                  \
+            loss -= lall[p * (K + 1) + k];                                          \
         }                                                                           \
         if (slot_in[c] < 0) {                                                       \
             slot_in[c] = (int32_t)ui; rows_in[ui] = c;                              \
@@ -471,7 +498,7 @@ double NAME(T* in, T* out, int64_t n, int d, int64_t np,                        
     if (n_in) *n_in = ui;                                                           \
     if (n_out) *n_out = uo;                                                         \
     if (own) { free(rows_in); free(d_in); free(rows_out); free(d_out); }            \
-    free(g); free(tk); free(slot_in); free(slot_out);                               \
+    free(gall); free(lall); free(tk); free(slot_in); free(slot_out);                \
     return loss;                                                                    \
 }
 
@@ -541,21 +568,26 @@ void orc_psi(const float* in, int d, const int64_t* indptr, const int32_t* indic
              const int32_t* nodes, int64_t count, int k_s, uint64_t seed, uint32_t round,
              double* psi)
 {
-    /* the subset never holds more than k_s entries */
-    int64_t* pick = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k_s > 0 ? k_s : 1));
-    for (int64_t i = 0; i < count; ++i) {
-        int32_t v = nodes[i];
-        int64_t deg = indptr[v + 1] - indptr[v];
-        if (deg == 0) { psi[i] = NAN; continue; }
-        int m = orc_neighbour_subset(indptr, v, k_s, seed, round, pick);
-        double acc = 0.0;
-        for (int j = 0; j < m; ++j) {
-            int32_t u = indices[indptr[v] + pick[j]];
-            acc += cosine(in + (int64_t)v * d, in + (int64_t)u * d, d);
+    /* nodes are independent */
+#pragma omp parallel
+    {
+        /* the subset never holds more than k_s entries */
+        int64_t* pick = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k_s > 0 ? k_s : 1));
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < count; ++i) {
+            int32_t v = nodes[i];
+            int64_t deg = indptr[v + 1] - indptr[v];
+            if (deg == 0) { psi[i] = NAN; continue; }
+            int m = orc_neighbour_subset(indptr, v, k_s, seed, round, pick);
+            double acc = 0.0;
+            for (int j = 0; j < m; ++j) {
+                int32_t u = indices[indptr[v] + pick[j]];
+                acc += cosine(in + (int64_t)v * d, in + (int64_t)u * d, d);
+            }
+            psi[i] = acc / (double)m;
         }
-        psi[i] = acc / (double)m;
+        free(pick);
     }
-    free(pick);
 }
 
 /* ------------------------------------------------------------------ */

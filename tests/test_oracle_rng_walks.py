@@ -200,3 +200,36 @@ def test_node2vec_isolated_and_cap(orc):
     for row in w1:
         for a, b in zip(row[:-1], row[1:]):
             assert (int(a), int(b)) in edges
+
+
+def test_oracle_independent_of_thread_count():
+    """The oracle's loops over independent items run under OpenMP; tables,
+    walks, Psi and a training epoch are bit-identical with one thread and
+    with several."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r'''
+import sys, hashlib; sys.path.insert(0, %r)
+import numpy as np, oracle, synth
+g = synth.build_graph("sbm1k").train
+tin, tout = oracle.init_tables(g.n, 64, 3)
+w = oracle.walks_uniform(g, np.arange(g.n), 2, 20, 5)
+gw = synth.csr_from_edges(1 << 10, synth.rmat_edges(10, 1 << 12, seed=41), weight_seed=42)
+w2, c2 = oracle.walks_node2vec(gw, np.arange(gw.n), 2, 20, 0.5, 2.0, 5)
+cdf = oracle.neg_cdf(g.degrees().astype(np.uint64))
+r = oracle.train_epoch(tin, tout, w, window=3, K=5, lr0=0.025, lr_end=1e-4, P=1024, seed=9,
+                       cdf=cdf, mb_end=60)
+ps = oracle.psi(tin, g, np.arange(g.n), 10, 4, 0)
+h = hashlib.sha256()
+for a in (tin, tout, w, w2, ps, np.array([r.loss, c2])):
+    h.update(np.ascontiguousarray(a).tobytes())
+print(h.hexdigest())
+''' % root
+    out = []
+    for threads in ("1", "4"):
+        env = dict(os.environ, OMP_NUM_THREADS=threads)
+        out.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                                  text=True, check=True).stdout.strip())
+    assert out[0] == out[1]
