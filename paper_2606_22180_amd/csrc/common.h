@@ -175,9 +175,11 @@ struct Model {
     int64_t cap_pairs = 0;
     int32_t cap_K = 0;
     MinibatchBufs mb[kIdSets];    // by minibatch index mod kIdSets: ids and sort of one minibatch
-    DevBuf ent_out;               // int2 [P(K+1)]: (g, ctx) of each out-touch, by row segment
-    DevBuf key_in, key_out;       // uint32: pair-order key of each segment position
-    DevBuf dinp;                  // float [P][d]: sum_k g_k out[t_k] of each pair, by row segment
+    DevBuf ent_out;               // int4 [P(K+1)]: (FP64 g, ctx, pair-order key) of each
+                                  // out-touch, by row segment
+    DevBuf key_in;                // uint32 [P]: pair of each in-row segment position
+    DevBuf dinp;                  // float [P][d]: sum_k g_k out[t_k] of each pair (FP64 sum,
+                                  // rounded once), by row segment
     DevBuf partial;               // double [chunks of split rows][d]: each chunk's exact sums
     int64_t split_rows_in = 0;    // partial rows reserved for the in-table; the out-table's follow
     DevBuf meta;                  // uint32 [kIdSets][16]: list lengths and counts, by id set

@@ -68,6 +68,11 @@ __device__ __forceinline__ void store_nt(int2* p, const int2& v)
     __builtin_nontemporal_store(nt_i2{v.x, v.y}, reinterpret_cast<nt_i2*>(p));
 }
 __device__ __forceinline__ void store_nt(uint32_t* p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_nt(int4* p, const int4& v)
+{
+    typedef int nt_i4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(nt_i4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_i4*>(p));
+}
 
 constexpr int kChunk = 16;                // touches per reduction work item (one per lane of a group)
 constexpr int kMetaWords = 16;            // per minibatch parity
@@ -85,13 +90,36 @@ __device__ __forceinline__ double wave_sum_f64(double x)
     return x;
 }
 
-__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+// sigma(x) = 1 / (1 + exp(-x)) in FP64, without clipping (Eq. (2)).
+__device__ __forceinline__ double sigmoid_d(double x) { return 1.0 / (1.0 + exp(-x)); }
 
-// -log sigma(x) = log(1 + exp(-x)), evaluated without overflow.  The dot x is
-// FP32, so is the term; the terms are summed in FP64.
+// -log sigma(x) = log(1 + exp(-x)), without overflow.  A loss term is
+// evaluated in FP32 from the FP64 dot (relative error ~1e-7 per term) and the
+// terms are summed in FP64.
 __device__ __forceinline__ float neg_log_sigmoid(float x)
 {
     return fmaxf(-x, 0.0f) + log1pf(expf(-fabsf(x)));
+}
+
+__device__ __forceinline__ double dot4d(float4 a, float4 b, double acc)
+{
+    acc = fma((double)a.x, (double)b.x, acc);
+    acc = fma((double)a.y, (double)b.y, acc);
+    acc = fma((double)a.z, (double)b.z, acc);
+    return fma((double)a.w, (double)b.w, acc);
+}
+
+// The FP64 coefficient g and the pair-order key of an out-touch, with the
+// context row its delta draws on, in one 16-byte entry.
+__device__ __forceinline__ int4 pack_entry(double g, int32_t ctx, uint32_t key)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(g);
+    return make_int4((int32_t)(uint32_t)b, (int32_t)(uint32_t)(b >> 32), ctx, (int32_t)key);
+}
+__device__ __forceinline__ double entry_g(int4 e)
+{
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)e.y << 32) |
+                                            (uint32_t)e.x));
 }
 
 template <int D>
@@ -433,9 +461,10 @@ struct FwdArgs {
     uint32_t npairs;
     int32_t ppw;             // pairs per wave, ppw (K + 2) <= 64
     float lr;
-    int2* ent_out;           // (g bits, ctx) by out-row segment position
-    uint32_t* key_out;       // the touch's pair-order key p (K+1) + k, same position
-    float* dinp;             // [P][d] sum_k g_k out[t_k] by in-row segment position
+    int4* ent_out;           // (FP64 g, ctx, pair-order key p (K+1) + k) by out-row
+                             // segment position
+    float* dinp;             // [P][d] sum_k g_k out[t_k] (FP64 sum, rounded once) by
+                             // in-row segment position
     uint32_t* key_in;        // the pair p, same position
     double* loss_part;       // one slot per wave
     float* cap_out;          // capture != NULL: single-touch out-row deltas to cap_out[slot][d]
@@ -453,6 +482,17 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
+template <int L>
+__device__ __forceinline__ double group_sum_d(double x)
+{
+    if (L > 16) x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 8);
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 2);
+    x += __shfl_xor(x, 1);
+    return x;
+}
+
 // One pair per group of LPP lanes, 64 / LPP pairs at a time.  Up to K = 5 at
 // d <= 128, 16 lanes per pair (four pairs' rows in flight per wave) with at
 // least 4 waves per SIMD (at most 128 registers, no spills) was faster at
@@ -461,7 +501,7 @@ __device__ __forceinline__ float group_sum(float x)
 template <int D, int K>
 constexpr int fwd_lanes_per_pair() { return (D <= 64 || (D == 128 && K <= 5)) ? 16 : 32; }
 template <int D, int K>
-constexpr int fwd_min_waves() { return (D == 128 && K <= 5) ? 4 : 1; }
+constexpr int fwd_min_waves() { return 1; }
 
 template <int D, int K>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fwd_min_waves<D, K>())))
@@ -526,44 +566,41 @@ void sgns_forward_kernel(FwdArgs a)
             for (int i = 0; i < V4; ++i)
                 vo[k][i] = ok ? ro[i * LPP + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
-        float dot[K + 1];
+        // dots, sigma and coefficients in FP64 over the FP32 entries; lane
+        // k mod LPP of the group takes touch k's loss term, -log sigma(s0) for
+        // the centre and -log sigma(-s_k) for a negative
+        const double lr = (double)a.lr;
+        double g[K + 1];
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
-            float acc = 0.0f;
+            double acc = 0.0;
 #pragma unroll
-            for (int i = 0; i < V4; ++i) acc = dot4(vin[i], vo[k][i], acc);
-            dot[k] = group_sum<LPP>(acc);
+            for (int i = 0; i < V4; ++i) acc = dot4d(vin[i], vo[k][i], acc);
+            const double dk = group_sum_d<LPP>(acc);
+            const bool ok = k == 0 || t[k] >= 0;
+            g[k] = k == 0 ? lr * (1.0 - sigmoid_d(dk)) : (ok ? -lr * sigmoid_d(dk) : 0.0);
+            if (live && ok && gl == k % LPP) lacc += (double)neg_log_sigmoid((float)(k == 0 ? dk : -dk));
         }
-        float g[K + 1];
-        g[0] = a.lr * (1.0f - sigmoidf_(dot[0]));
-#pragma unroll
-        for (int k = 1; k <= K; ++k) g[k] = t[k] >= 0 ? -a.lr * sigmoidf_(dot[k]) : 0.0f;
 
-        // lane j of the group writes touch k = j (and j + 16) and takes its loss term
+        // lane j of the group writes the entry of touch k = j (and j + 16)
 #pragma unroll
         for (int h = 0; h < (K + LPP) / LPP; ++h) {
             const int k = gl + h * LPP;
-            float gk = g[0], dk = dot[0];
+            double gk = g[0];
             int32_t tk = t[0];
 #pragma unroll
             for (int j = 1; j <= K; ++j)
                 if (k == j) {
                     gk = g[j];
-                    dk = dot[j];
                     tk = t[j];
                 }
-            if (k <= K && live && tk >= 0) {
+            if (k <= K && live && tk >= 0 && !((single >> (src + 1 + k)) & 1ull)) {
                 const uint32_t pos = h == 0 ? my_pos : my_pos_hi;
-                if (!((single >> (src + 1 + k)) & 1ull)) {
-                    store_nt(&a.ent_out[pos], make_int2(__float_as_int(gk), ctx));
-                    store_nt(&a.key_out[pos], q * (K + 1) + (uint32_t)k);
-                }
-                // -log sigma(s0) for the centre, -log sigma(-s_k) for a negative
-                lacc += (double)neg_log_sigmoid(k == 0 ? dk : -dk);
+                store_nt(&a.ent_out[pos], pack_entry(gk, ctx, q * (K + 1) + (uint32_t)k));
             }
         }
-        // out rows touched once: row + g in[ctx], rounded as a one-term sum
-        // added to the row (or the delta alone, when capturing)
+        // out rows touched once: row + g in[ctx] in FP64, rounded once (or the
+        // delta alone, when capturing)
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
             uint32_t slot = 0;
@@ -573,13 +610,12 @@ void sgns_forward_kernel(FwdArgs a)
                     a.cap_out ? a.cap_out + (int64_t)slot * D : a.tout + (int64_t)t[k] * D);
 #pragma unroll
                 for (int i = 0; i < V4; ++i) {
-                    float4 d = make_float4(fmaf(g[k], vin[i].x, 0.0f), fmaf(g[k], vin[i].y, 0.0f),
-                                           fmaf(g[k], vin[i].z, 0.0f), fmaf(g[k], vin[i].w, 0.0f));
                     const float4 base = a.cap_out ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : vo[k][i];
-                    d.x = base.x + d.x;
-                    d.y = base.y + d.y;
-                    d.z = base.z + d.z;
-                    d.w = base.w + d.w;
+                    const float4 d = make_float4(
+                        (float)fma(g[k], (double)vin[i].x, (double)base.x),
+                        (float)fma(g[k], (double)vin[i].y, (double)base.y),
+                        (float)fma(g[k], (double)vin[i].z, (double)base.z),
+                        (float)fma(g[k], (double)vin[i].w, (double)base.w));
                     store_nt(&dst[i * LPP + gl], d);
                 }
             }
@@ -589,15 +625,15 @@ void sgns_forward_kernel(FwdArgs a)
             float4* dp = reinterpret_cast<float4*>(a.dinp + (int64_t)pos_in * D);
 #pragma unroll
             for (int i = 0; i < V4; ++i) {
-                float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
 #pragma unroll
                 for (int k = 0; k <= K; ++k) {
-                    acc.x = fmaf(g[k], vo[k][i].x, acc.x);
-                    acc.y = fmaf(g[k], vo[k][i].y, acc.y);
-                    acc.z = fmaf(g[k], vo[k][i].z, acc.z);
-                    acc.w = fmaf(g[k], vo[k][i].w, acc.w);
+                    ax = fma(g[k], (double)vo[k][i].x, ax);
+                    ay = fma(g[k], (double)vo[k][i].y, ay);
+                    az = fma(g[k], (double)vo[k][i].z, az);
+                    aw = fma(g[k], (double)vo[k][i].w, aw);
                 }
-                store_nt(&dp[i * LPP + gl], acc);
+                store_nt(&dp[i * LPP + gl], make_float4((float)ax, (float)ay, (float)az, (float)aw));
             }
         }
     }
@@ -615,14 +651,14 @@ void sgns_forward_kernel(FwdArgs a)
 // touches (their membership follows the atomics' order) get exact sums
 // instead, which a merge adds in chunk order.
 // Sort (key, a, b) ascending over the 16 lanes of a group.
-__device__ __forceinline__ void sort16(uint32_t& key, float& va, int32_t& vb, int gl)
+__device__ __forceinline__ void sort16(uint32_t& key, double& va, int32_t& vb, int gl)
 {
 #pragma unroll
     for (int k = 2; k <= 16; k <<= 1)
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             const uint32_t pk = __shfl_xor(key, j);
-            const float pa = __shfl_xor(va, j);
+            const double pa = __shfl_xor(va, j);
             const int32_t pb = __shfl_xor(vb, j);
             const bool up = (gl & k) == 0;        // this pair of lanes sorts ascending
             const bool low = (gl & j) == 0;       // this lane keeps the smaller key
@@ -645,8 +681,7 @@ __device__ __forceinline__ void sort16(uint32_t& key, float& va, int32_t& vb, in
 struct ApplyArgs {
     float* tin;
     float* tout;
-    const int2* ent_out;          // (g, ctx) by out segment position
-    const uint32_t* key_out;      // pair-order key by out segment position
+    const int4* ent_out;          // (FP64 g, ctx, pair-order key) by out segment position
     const float* dinp;            // in-row delta of each pair, by in segment position
     const uint32_t* key_in;       // pair by in segment position
     const int4* chunks_in;        // rows of at most kChunk touches
@@ -678,22 +713,23 @@ __device__ __forceinline__ void get_row(const float* table, const float* cap, in
     for (int i = 0; i < D / 64; ++i) cur[i] = cap ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : s4[i * 16 + gl];
 }
 
-// Adds a row's delta to its current values (from get_row) in the table, or
-// stores it in the capture buffer.
+// Adds a row's FP64 delta to its current values (from get_row) and rounds
+// once to FP32 into the table, or stores the delta rounded to FP32 in the
+// capture buffer.
 template <int D>
 __device__ __forceinline__ void put_row(float* table, float* cap, int32_t row, int32_t slot,
                                         const float4 (&cur)[D / 64],
-                                        const float (&delta)[D / 16], int gl)
+                                        const double (&delta)[D / 16], int gl)
 {
     constexpr int V4 = D / 64;
     float4* d4 = reinterpret_cast<float4*>(cap ? cap + (int64_t)slot * D : table + (int64_t)row * D);
 #pragma unroll
     for (int i = 0; i < V4; ++i) {
-        float4 v = cur[i];
-        v.x += delta[4 * i + 0];
-        v.y += delta[4 * i + 1];
-        v.z += delta[4 * i + 2];
-        v.w += delta[4 * i + 3];
+        const float4 c = cur[i];
+        const float4 v = make_float4((float)((double)c.x + delta[4 * i + 0]),
+                                     (float)((double)c.y + delta[4 * i + 1]),
+                                     (float)((double)c.z + delta[4 * i + 2]),
+                                     (float)((double)c.w + delta[4 * i + 3]));
         store_nt(&d4[i * 16 + gl], v);
     }
 }
@@ -754,10 +790,7 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
                     acc[4 * i + 3] += v.y;
                 }
             }
-            float delta[D / 16];
-#pragma unroll
-            for (int e = 0; e < D / 16; ++e) delta[e] = (float)acc[e];
-            put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, m.w, cur, delta, gl);
+            put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, m.x, m.w, cur, acc, gl);
             if (a.reset && gl == 0) (out ? a.cnt_out : a.cnt_in)[m.x] = 0;
             continue;
         }
@@ -766,12 +799,18 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
         const bool out = PHASE == 0 ? kind != 1 : false;
         const int32_t row = d.x, start = d.y, len = d.z, slot = d.w;
         const float* src = out ? a.tin : a.dinp;
-        float my_g = 1.0f;
+        double my_g = 1.0;
         int32_t my_src = start + gl;
-        if (out && gl < len) {
-            const int2 e = a.ent_out[start + gl];
-            my_g = __int_as_float(e.x);
-            my_src = e.y;
+        uint32_t my_key = 0xffffffffu;
+        if (gl < len) {
+            if (out) {
+                const int4 e = a.ent_out[start + gl];
+                my_g = entry_g(e);
+                my_src = e.z;
+                my_key = (uint32_t)e.w;
+            } else {
+                my_key = a.key_in[start + gl];
+            }
         }
         if (split) {
             // exact sums, stored for the merge
@@ -780,13 +819,13 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
             for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
             const double gc = a.grid_c;
             for (int32_t i0 = 0; i0 < len; i0 += kRowsS) {
-                float gg[kRowsS];
+                double gg[kRowsS];
                 float4 x[kRowsS][V4];
 #pragma unroll
                 for (int u = 0; u < kRowsS; ++u) {
                     const int32_t idx = min(i0 + u, kChunk - 1);
                     const bool ok = i0 + u < len;
-                    gg[u] = ok ? __shfl(my_g, g0 + idx) : 0.0f;
+                    gg[u] = ok ? __shfl(my_g, g0 + idx) : 0.0;
                     const int32_t rr = __shfl(my_src, g0 + idx);
                     const float4* rp = row4<D>(src, ok ? rr : 0);
 #pragma unroll
@@ -795,8 +834,8 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
                 }
 #pragma unroll
                 for (int u = 0; u < kRowsS; ++u) {
-                    // g * x is exact in FP64 (two 24-bit significands)
-                    const double gd = (double)gg[u];
+                    // each FP64 term g * x is rounded once more, onto the grid
+                    const double gd = gg[u];
 #pragma unroll
                     for (int i = 0; i < V4; ++i) {
                         acc[4 * i + 0] += on_grid(gd * (double)x[u][i].x, gc);
@@ -815,16 +854,16 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
             }
             continue;
         }
-        // a row of at most kChunk touches: sum in pair order
+        // a row of at most kChunk touches: FP64 sum in pair order
         float4 cur[V4];
         get_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, cur, gl);
-        uint32_t key = gl < len ? (out ? a.key_out : a.key_in)[start + gl] : 0xffffffffu;
+        uint32_t key = my_key;
         sort16(key, my_g, my_src, gl);
-        float acc[D / 16];
+        double acc[D / 16];
 #pragma unroll
-        for (int e = 0; e < D / 16; ++e) acc[e] = 0.0f;
+        for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
         for (int32_t i0 = 0; i0 < len; i0 += kRows) {
-            float gg[kRows];
+            double gg[kRows];
             float4 x[kRows][V4];
 #pragma unroll
             for (int u = 0; u < kRows; ++u) {
@@ -842,10 +881,10 @@ __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
 #pragma unroll
                 for (int i = 0; i < V4; ++i) {
                     // in rows: g = 1, and 1 * x + acc is exactly x + acc
-                    acc[4 * i + 0] = fmaf(gg[u], x[u][i].x, acc[4 * i + 0]);
-                    acc[4 * i + 1] = fmaf(gg[u], x[u][i].y, acc[4 * i + 1]);
-                    acc[4 * i + 2] = fmaf(gg[u], x[u][i].z, acc[4 * i + 2]);
-                    acc[4 * i + 3] = fmaf(gg[u], x[u][i].w, acc[4 * i + 3]);
+                    acc[4 * i + 0] = fma(gg[u], (double)x[u][i].x, acc[4 * i + 0]);
+                    acc[4 * i + 1] = fma(gg[u], (double)x[u][i].y, acc[4 * i + 1]);
+                    acc[4 * i + 2] = fma(gg[u], (double)x[u][i].z, acc[4 * i + 2]);
+                    acc[4 * i + 3] = fma(gg[u], (double)x[u][i].w, acc[4 * i + 3]);
                 }
         }
         put_row<D>(out ? a.tout : a.tin, out ? a.cap_out : a.cap_in, row, slot, cur, acc, gl);
@@ -1051,7 +1090,7 @@ static void launch_train_t(Model& m, MinibatchBufs& mb, FwdArgs fa, const Miniba
     double* part_in = m.partial.as<double>();
     double* part_out = part_in + ml.split_in * D;
     ApplyArgs aa{m.tin.as<float>(),       m.tout.as<float>(),      fa.ent_out,
-                 fa.key_out,              fa.dinp,                 fa.key_in,
+                 fa.dinp,                 fa.key_in,
                  mb.chunks_in.as<int4>(), mb.chunks_out.as<int4>(), mb.split_in.as<int4>(),
                  mb.split_out.as<int4>(), mb.mrows_in.as<int4>(),  mb.mrows_out.as<int4>(),
                  part_in,                 part_out,                mb.cnt_in.as<uint32_t>(),
@@ -1201,8 +1240,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
             b.mrows_out.alloc(&c, sizeof(int4) * max_split_rows(touches_out));
             b.partials.alloc(&c, (sizeof(uint4) + sizeof(unsigned long long)) * nbmax);
         }
-        m.ent_out.alloc(&c, sizeof(int2) * touches_out);
-        m.key_out.alloc(&c, sizeof(uint32_t) * touches_out);
+        m.ent_out.alloc(&c, sizeof(int4) * touches_out);
         m.dinp.alloc(&c, sizeof(float) * cp * m.dim);
         m.key_in.alloc(&c, sizeof(uint32_t) * cp);
         m.split_rows_in = max_split_chunks(cp);
@@ -1242,8 +1280,7 @@ void train_minibatches(Model& m, const Walks& wc, const felog_train_params& p, i
     fa.tin = m.tin.as<float>();
     fa.tout = m.tout.as<float>();
     fa.ppw = ppw;
-    fa.ent_out = m.ent_out.as<int2>();
-    fa.key_out = m.key_out.as<uint32_t>();
+    fa.ent_out = m.ent_out.as<int4>();
     fa.dinp = m.dinp.as<float>();
     fa.key_in = m.key_in.as<uint32_t>();
     fa.loss_part = loss_part.as<double>();

@@ -152,12 +152,18 @@ def _mass(tin, tout, ctx_, ctr, neg, lr, orc):
 
 
 def _check_delta(gpu, ref, mass, what):
+    """The per-step bar: every row's delta within 1e-5 of the oracle's in
+    norm, plus 1e-12 absolute.  (mass, the row's sum of |term| vectors, is
+    printed as the scale of the FP rounding the bar leaves room for.)"""
     num = np.linalg.norm(gpu - ref, axis=1)
-    tol = 1e-5 * np.linalg.norm(ref, axis=1) + 2 ** -20 * np.linalg.norm(mass, axis=1)
-    bad = np.nonzero(num > tol + 1e-30)[0]
-    rel = num / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
-    _say("%s: rows=%d max rel=%.3e bad=%d" % (what, int((np.abs(ref).sum(1) > 0).sum()),
-                                              rel.max(), len(bad)))
+    nref = np.linalg.norm(ref, axis=1)
+    tol = 1e-5 * nref + 1e-12
+    bad = np.nonzero(num > tol)[0]
+    rel = num / np.maximum(nref, 1e-30)
+    canc = np.linalg.norm(mass, axis=1) / np.maximum(nref, 1e-30)
+    _say("%s: rows=%d max rel=%.3e misses of 1e-5|d|+1e-12: %d (max |mass|/|d| %.1f)"
+         % (what, int((np.abs(ref).sum(1) > 0).sum()), rel.max(), len(bad),
+            canc[nref > 0].max() if (nref > 0).any() else 0.0))
     assert len(bad) == 0, (what, bad[:5], num[bad[:5]], tol[bad[:5]])
 
 
@@ -325,10 +331,76 @@ def test_psi_and_active_set(fl, ctx, orc, sbm):
     assert np.array_equal(act.read(), orc.next_active(nodes, opsi, 0.01))
 
 
-def test_run_algorithm1_matches_oracle(fl, ctx, orc, sbm):
-    """Algorithm 1 end to end on sbm1k (3 rounds, mu = 0.7): the same active
-    sets round by round, up to decisions within the FP32 drift of the free-
-    running tables, the same pairs, and AUC within 0.005."""
+def _algorithm1_guard_band(fl, ctx, orc, split, *, mode, mu, rounds, d=64, r=10, L=40,
+                           window=5, K=5, P=1024, k_s=10, seeds=(1, 2, 3, 4)):
+    """Algorithm 1 round by round on both sides (Eq. (4)-(5)), free-running
+    tables.  Each round starts both sides from the same active list (the
+    oracle's, handed to the library through felog_active_from_host), so walks
+    and pair counts must be equal; the next active sets may differ only by
+    nodes whose oracle score lies within 1e-3 of mu.  Returns the per-round
+    flip counts."""
+    g = split.train
+    seed_walk, seed_model, seed_train, seed_psi = seeds
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    M = fl.Model.create(G, dim=d, neg_dist=fl.NEG_DEGREE, seed=seed_model)
+    prm = fl.train_params(window=window, negatives=K, minibatch_pairs=P, seed=seed_train)
+    tin, tout = orc.init_tables(g.n, d, seed_model)
+    cdf = orc.neg_cdf(g.degrees().astype(np.uint64))
+    gmode = fl.FEEDBACK_MONOTONE if mode == "monotone" else fl.FEEDBACK_RECOMPUTE_ALL
+    active = np.arange(g.n, dtype=np.int32)
+    id_base = 0
+    flips = []
+    for rnd in range(rounds):
+        if active.shape[0] == 0:
+            break
+        starts = None if rnd == 0 else fl.Active.from_host(G, active)
+        W = fl.Walks.generate(G, r=r, L=L, seed=seed_walk, id_base=id_base, starts=starts)
+        ow = orc.walks_uniform(g, active, r, L, seed_walk, id_base)
+        assert np.array_equal(W.read(), ow), ("walks", rnd)
+        st = M.train_epoch(W, prm)
+        tr = orc.train_epoch(tin, tout, ow, window=window, K=K, lr0=prm.lr_start,
+                             lr_end=prm.lr_end, P=P, seed=seed_train, cdf=cdf, id_base=id_base)
+        assert st.pairs == tr.pairs, ("pairs", rnd)
+        assert abs(st.loss - tr.loss) <= 1e-5 * abs(tr.loss), ("loss", rnd, st.loss, tr.loss)
+        id_base += ow.shape[0]
+        cand = active if mode == "monotone" else np.arange(g.n, dtype=np.int32)
+        nxt, _ = M.feedback(mu=mu, k_s=k_s, seed=seed_psi, round=rnd, mode=gmode,
+                            active=starts, want_psi=True)
+        ps = orc.psi(tin, g, cand, k_s, seed_psi, rnd)
+        o_next = orc.next_active(cand, ps, mu)
+        g_next = nxt.read()
+        diff = np.setxor1d(g_next, o_next)
+        band = np.abs(ps[np.searchsorted(cand, diff)] - mu)
+        _say("round %d (%s): active %d, next gpu %d oracle %d, flips %d (max |psi-mu| %.2e)"
+             % (rnd, mode, active.shape[0], g_next.shape[0], o_next.shape[0], diff.shape[0],
+                band.max() if diff.shape[0] else 0.0))
+        assert np.all(band <= 1e-3), ("flip outside the guard band", rnd, diff[band > 1e-3])
+        flips.append(int(diff.shape[0]))
+        active = o_next
+    a_gpu = link_auc_of(M.read(fl.TABLE_IN), split)
+    a_orc = orc.link_auc(tin, split)
+    _say("AUC gpu=%.5f oracle=%.5f" % (a_gpu, a_orc))
+    assert abs(a_gpu - a_orc) <= 0.005
+    return flips
+
+
+def test_algorithm1_guard_band_monotone(fl, ctx, orc, sbm):
+    """Algorithm 1 on sbm1k, MONOTONE (Eq. (5)), mu = 0.7, 3 rounds."""
+    _say("algorithm 1 guard band sbm1k monotone mu=0.7")
+    _algorithm1_guard_band(fl, ctx, orc, sbm, mode="monotone", mu=0.7, rounds=3)
+
+
+def test_algorithm1_guard_band_recompute_all(fl, ctx, orc, sbm):
+    """The same with every node rescored each round (RECOMPUTE_ALL, the
+    reactivation reading of Section 5.1), mu = 0.7, 3 rounds."""
+    _say("algorithm 1 guard band sbm1k recompute-all mu=0.7")
+    _algorithm1_guard_band(fl, ctx, orc, sbm, mode="recompute_all", mu=0.7, rounds=3)
+
+
+def test_run_matches_separate_calls(fl, ctx, orc, sbm):
+    """felog_run (walks beside training on their own stream) against the
+    oracle's Algorithm 1 on sbm1k: the same active sets round by round up to
+    guard-band flips, the same pairs, and AUC within 0.005."""
     g = sbm.train
     _say("felog_run sbm1k 3 rounds mu=0.7")
     G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
@@ -350,10 +422,12 @@ def test_run_algorithm1_matches_oracle(fl, ctx, orc, sbm):
     assert st.rounds == len(ostats) == 3
     assert gpu_act[0] == orc_act[0] == 1000
     for r in range(st.rounds):
-        assert abs(gpu_act[r] - orc_act[r]) <= max(2, orc_act[r] // 100)
+        # a flip within the guard band (checked node by node in the lockstep
+        # tests) carries into the next round here
+        assert abs(gpu_act[r] - orc_act[r]) <= 2
         if gpu_act[r] == orc_act[r]:
             assert st.train[r].pairs == ostats[r].pairs
-            assert abs(st.train[r].loss - ostats[r].loss) <= 1e-3 * ostats[r].loss
+            assert abs(st.train[r].loss - ostats[r].loss) <= 1e-5 * ostats[r].loss
     a_gpu = link_auc_of(M.read(fl.TABLE_IN), sbm)
     a_orc = orc.link_auc(tin, sbm)
     _say("AUC gpu=%.5f oracle=%.5f" % (a_gpu, a_orc))
