@@ -1,18 +1,40 @@
 """Benchmark of the FeLoG hot path on one MI355X.
 
-One step = Algorithm 1 end to end on the R-MAT 2^20 workload: walks from the
-active set, one SGNS training call per round, the Psi feedback and the
-active-set compaction, until the active set is empty or 4 rounds ran.  The
-graph is resident in HBM before the timed region; each step re-initialises the
-embedding tables so that every step does the same work.
+Headline workload (timed steps): second-order node2vec walks (p = 0.5,
+q = 2) on a weighted R-MAT graph with 2^23 nodes and 2^27 undirected edges
+(10% held out), feeding FP32 skip-gram with negative sampling at d = 128,
+window 10, 5 negatives from unigram^0.75, 1,024 pairs per minibatch.  This is
+the largest single-GPU configuration of the method's benchmark set.
 
-Prints one JSON line (see the keys below).  `--gpus N` with N > 1 is refused:
-this build measures one GPU.
+One step is a fixed slice of that workload's epoch: the node2vec walks of one
+2^20-walk chunk of the corpus (chunk s mod 80 at step s, the same walk ids
+and start nodes as in the full corpus), then the first --mb-per-step
+minibatches (default 16,384, i.e. 16.8M pair-updates) of that chunk's pairs.
+The graph, the model and the unigram noise distribution (from the whole
+r = 10 corpus, walked once before the timed region) are resident in HBM
+before the timed region; nothing inside a step is skipped or cached.  Every
+library call returns after its stream completes, so the timed region is
+bracketed by device synchronisations.
+
+After the timed steps the JSON line also carries, measured outside them:
+  - roofline: the dominant SGNS kernel by HIP-event time, algorithmic bytes
+    per launch over its average launch duration, against 8 TB/s;
+  - c2_algorithm1: Algorithm 1 end to end on R-MAT 2^20 (uniform walks,
+    P = 65,536, FeeST mu = 0.65, at most 4 rounds): per-round active set,
+    pairs, walk steps/s, and link-prediction AUC;
+  - c3_forms: FP32 per-pair against BF16 shared-negative minibatches
+    (P = M = 1,024) on R-MAT 2^22, their error against the FP64 oracle on one
+    minibatch, and the AUC of both forms after one epoch on the small SBM;
+  - walk_codec, serving: the FaBC corpus codec and the serving loop's latency
+    sample;
+  - cpu_baseline: the CPU oracle on a bounded sample of the headline
+    workload, at one thread and at all host cores.
+
+`--gpus N` with N > 1 is refused: this build measures one GPU.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,12 +48,27 @@ sys.path.insert(0, ROOT)
 METRIC = "SGNS pair-updates/s + walk steps/s at matched link-pred AUC; p99 job latency"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0     # dense BF16 MFMA
-COUNTERS = os.path.join(ROOT, "profiles", "sgns_rmat20_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2606_22180_amd", "csrc", "sgns.hip")
+CHUNK = 1 << 20               # walks per training chunk
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def host_info():
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cores, model
 
 
 def auc_score(emb: np.ndarray, pos: np.ndarray, neg: np.ndarray) -> float:
@@ -44,41 +81,256 @@ def auc_score(emb: np.ndarray, pos: np.ndarray, neg: np.ndarray) -> float:
     return float(roc_auc_score(y, np.r_[sp, sn]))
 
 
-def kernel_traffic(kernel: str):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counters,
-    if they were taken on the current kernel source; else None."""
-    if not os.path.exists(COUNTERS):
-        return None
-    rec = json.load(open(COUNTERS))
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != src or rec.get("kernel") != kernel:
-        return None
-    return rec.get("bytes_per_launch")
-
-
-def cpu_baseline(g, cfg, n_walks: int, n_mb: int):
-    """The CPU oracle as it stands, on a bounded sample of the same workload:
-    the first n_walks walks of round 1 and the first n_mb minibatches of SGNS
-    over that sub-corpus.  Single-threaded C."""
+# ----------------------------------------------------------------- CPU oracle
+def cpu_baseline(g, cfg, n_walks: int, n_mb: int, cores: int, model: str):
+    """The CPU oracle as it stands, on a bounded sample of the headline
+    workload: node2vec walks 0 .. n_walks-1 of the corpus, then the first n_mb
+    minibatches of SGNS over those walks (unigram^0.75 noise of the sample),
+    once with one thread and once with every host core (the oracle's OpenMP
+    loops run over independent walks and over a minibatch's pair
+    coefficients; its row sums stay sequential)."""
     import oracle
+    oracle.build()
+    out = {"unit": "pair-updates/s", "kind": "oracle", "cpu_model": model, "nproc": cores}
+    legs = {}
+    tin0 = None
+    for threads in (1, cores):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        walks, _ = oracle.walks_node2vec(g, np.arange(n_walks, dtype=np.int32), 1, cfg["L"],
+                                         cfg["p"], cfg["q"], cfg["seed_walk"], 0)
+        t_walk = time.perf_counter() - t0
+        steps = int((walks[:, 1:] >= 0).sum())
+        if tin0 is None:
+            cdf = oracle.neg_cdf(oracle.corpus_counts(walks, g.n))
+            tin0, tout0 = oracle.init_tables(g.n, cfg["dim"], cfg["seed_model"])
+        tin, tout = tin0.copy(), tout0.copy()
+        t1 = time.perf_counter()
+        tr = oracle.train_epoch(tin, tout, walks, window=cfg["window"], K=cfg["K"],
+                                lr0=float(np.float32(cfg["lr0"])),
+                                lr_end=float(np.float32(cfg["lr_end"])), P=cfg["minibatch"],
+                                seed=cfg["seed_train"], cdf=cdf, mb_end=n_mb)
+        t_train = time.perf_counter() - t1
+        legs[threads] = {"pair_updates_per_s": tr.pairs / t_train,
+                         "walk_steps_per_s": steps / t_walk, "threads": threads,
+                         "walk_s": t_walk, "train_s": t_train, "pairs": int(tr.pairs),
+                         "walk_steps": steps}
+        log("cpu oracle, %d thread(s): %.3g walk steps/s, %.3g pair-updates/s"
+            % (threads, steps / t_walk, tr.pairs / t_train))
+        del tin, tout
+    oracle.set_threads(cores)
+    allc = legs[cores]
+    out.update({"value": allc["pair_updates_per_s"], "cores": cores,
+                "walk_steps_per_s": allc["walk_steps_per_s"],
+                "single_thread": legs[1], "all_cores": allc,
+                "sample": "node2vec walks 0..%d of the weighted R-MAT 2^23 corpus (%d steps) and "
+                          "the first %d minibatches of %d pairs over them (%d pairs); unigram "
+                          "noise of the sample; at 1 thread and at %d threads (%s)"
+                          % (n_walks - 1, allc["walk_steps"], n_mb, cfg["minibatch"],
+                             allc["pairs"], cores, model)})
+    return out
+
+
+# --------------------------------------------------------------- side legs
+def c2_algorithm1(felog, max_rounds: int):
+    """Algorithm 1 end to end on R-MAT 2^20 (the feedback-loop workload)."""
+    import synth
+    pre = synth.CONFIGS["rmat20"]
+    t = time.perf_counter()
+    split = synth.build_graph("rmat20")
+    g = split.train
+    log("c2: graph n=%d nnz=%d (%.1f s)" % (g.n, g.nnz, time.perf_counter() - t))
+    ctx = felog.Context(0)
+    G = felog.Graph.from_csr(ctx, g.indptr, g.indices)
+    M = felog.Model.create(G, dim=pre["dim"], neg_dist=felog.NEG_UNIGRAM, seed=2)
+    rp = felog.felog_run_params()
+    rp.walk = felog.felog_walk_params(felog.WALK_UNIFORM, pre["r"], pre["L"], 1.0, 1.0, 1, 0)
+    rp.train = felog.train_params(window=pre["window"], negatives=pre["K"], lr_start=pre["lr0"],
+                                  lr_end=pre["lr_end"], minibatch_pairs=pre["minibatch"], seed=3)
+    rp.feedback = felog.felog_feedback_params(pre["mu"], pre["k_s"], felog.FEEDBACK_MONOTONE,
+                                              4, 0)
+    rp.max_rounds = max_rounds
     t0 = time.perf_counter()
-    walks = oracle.walks_uniform(g, np.arange(n_walks, dtype=np.int32), 1, cfg["L"], cfg["seed_walk"])
-    t_walk = time.perf_counter() - t0
-    steps = int((walks[:, 1:] >= 0).sum())
-    cdf = oracle.neg_cdf(oracle.corpus_counts(walks, g.n))
-    tin, tout = oracle.init_tables(g.n, cfg["dim"], cfg["seed_model"])
-    t1 = time.perf_counter()
-    tr = oracle.train_epoch(tin, tout, walks, window=cfg["window"], K=cfg["K"],
-                            lr0=float(np.float32(cfg["lr0"])), lr_end=float(np.float32(cfg["lr_end"])),
-                            P=cfg["minibatch"], seed=cfg["seed_train"], cdf=cdf, mb_end=n_mb)
-    t_train = time.perf_counter() - t1
-    return {
-        "value": tr.pairs / t_train, "unit": "pair-updates/s", "cores": 1, "kind": "oracle",
-        "walk_steps_per_s": steps / t_walk,
-        "sample": "first %d round-1 walks (%d steps, %.1f s) and the first %d minibatches "
-                  "of %d pairs over that sub-corpus (%d pairs, %.1f s), single thread"
-                  % (n_walks, steps, t_walk, n_mb, cfg["minibatch"], tr.pairs, t_train),
-    }
+    st = M.run(rp)
+    wall = time.perf_counter() - t0
+    auc = auc_score(M.read(felog.TABLE_IN), split.test_pos, split.test_neg)
+    rounds = []
+    pairs = steps = 0
+    walk_ms = 0.0
+    for r in range(st.rounds):
+        tr = st.train[r]
+        pairs += tr.pairs
+        steps += st.walk_steps[r]
+        walk_ms += st.ms_walk[r]
+        rounds.append(dict(active=int(st.active[r]), walks=int(st.walks[r]),
+                           walk_steps=int(st.walk_steps[r]), pairs=int(tr.pairs),
+                           loss_per_pair=tr.loss / max(1, tr.pairs), ms_walk=st.ms_walk[r],
+                           ms_train=tr.ms, ms_feedback=st.ms_feedback[r],
+                           minibatches=int(tr.minibatches)))
+    out = {"workload": "R-MAT scale 20 (a,b,c = .57,.19,.19), 2^24 undirected edges, 10% held "
+                       "out; uniform walks r=10 L=80; SGNS d=128 w=10 K=5 unigram^0.75 P=65536; "
+                       "FeeST mu=0.65 k_s=10 monotone, at most %d rounds" % max_rounds,
+           "rounds": rounds, "final_active": int(st.final_active), "wall_s": wall,
+           "pair_updates_per_s": pairs / wall, "pairs": int(pairs),
+           "walk_steps_per_s": steps / (walk_ms / 1e3) if walk_ms > 0 else None,
+           "link_pred_auc": auc}
+    log("c2: %d rounds, active %s, %.2f s, %.3g pair-updates/s, AUC %.4f"
+        % (st.rounds, [r["active"] for r in rounds], wall, pairs / wall, auc))
+    W = felog.Walks.generate(G, r=pre["r"], L=pre["L"], seed=1)
+    out_codec = codec_sample(felog, W)
+    W.close()
+    M.close()
+    G.close()
+    return out, out_codec
+
+
+def codec_sample(felog, W, reps: int = 3):
+    """The FaBC walk-corpus codec (Section 5.2.2) on a round-1 corpus: profile,
+    the Eq. (8) target set, pack and unpack on the device, best of reps, with a
+    sampled round-trip check."""
+    n_walks, L, _ = W.info()
+    raw = 4 * n_walks * L
+    best = None
+    for _ in range(reps):
+        k, sym, cnt, total = W.fabc_profile()
+        P = W.pack(sym[:k])
+        U = P.unpack()
+        by, _, _, _, R = P.info()
+        for first in (0, n_walks // 2, max(0, n_walks - 4096)):
+            c = min(4096, n_walks - first)
+            assert np.array_equal(U.read_range(first, c), W.read_range(first, c))
+        pack_ms = P.ms[0] + P.ms[1]
+        if best is None or pack_ms + U.unpack_ms < best[0] + best[1]:
+            best = (pack_ms, U.unpack_ms, P.ms)
+        U.close()
+        P.close()
+    F = float(cnt[:k].sum()) / total
+    moved = raw + by
+    pack_gbs = moved / (best[0] * 1e-3) / 1e9
+    unpack_gbs = moved / (best[1] * 1e-3) / 1e9
+    out = {"walks": int(n_walks), "length": int(L), "k": int(k),
+           "symbols": [int(x) for x in sym[:k]], "top_shares": [float(c) / total for c in cnt[:4]],
+           "raw_bytes": int(raw), "packed_bytes": int(by), "residuals": int(R),
+           "ratio": by / raw, "g_eq7": 1.0 - F + k / L + k / 32.0,
+           "pack_ms": best[0], "unpack_ms": best[1], "pack_gbs": pack_gbs,
+           "unpack_gbs": unpack_gbs, "pack_frac": pack_gbs / HBM_PEAK_GBS,
+           "unpack_frac": unpack_gbs / HBM_PEAK_GBS}
+    log("codec: k=%d, %.3f of raw, pack %.2f ms, unpack %.2f ms"
+        % (k, by / raw, best[0], best[1]))
+    return out
+
+
+def c3_forms(felog, n_mb: int):
+    """FP32 per-pair against BF16 shared-negative minibatches at P = M = 1,024
+    (d = 128, K = 5, w = 10, degree^0.75 noise) on R-MAT 2^22: time per
+    minibatch over n_mb minibatches from the middle of the first 2^20-walk
+    chunk; each form's error against the FP64 oracle on one minibatch from the
+    same teacher-forced state; and the AUC of both forms after one epoch on
+    the small SBM graph (the R-MAT epoch is 62.5G pairs)."""
+    import oracle
+    import synth
+    t = time.perf_counter()
+    split = synth.build_graph("rmat22")
+    g = split.train
+    log("c3: graph n=%d nnz=%d (%.1f s)" % (g.n, g.nnz, time.perf_counter() - t))
+    ctx = felog.Context(0)
+    G = felog.Graph.from_csr(ctx, g.indptr, g.indices)
+    starts = felog.Active.from_host(G, np.arange(CHUNK, dtype=np.int32))
+    W = felog.Walks.generate(G, r=1, L=80, seed=1, starts=starts)
+    out = {"workload": "R-MAT scale 22, 2^26 undirected edges, 10% held out; uniform walks "
+                       "L=80; SGNS d=128 w=10 K=5 degree^0.75; P = M = 1024",
+           "minibatches": n_mb}
+    first = 300000
+    for prec, msh, name in ((felog.PREC_FP32, 0, "fp32_per_pair"),
+                            (felog.PREC_BF16, 1024, "bf16_shared_negative")):
+        M = felog.Model.create(G, dim=128, neg_dist=felog.NEG_DEGREE, seed=2, precision=prec)
+        prm = felog.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=3,
+                                 shared_negatives=msh)
+        M.train_steps(W, prm, first - 200, 200)
+        st = M.train_steps(W, prm, first, n_mb)
+        us = st.ms / st.minibatches * 1e3
+        r = {"us_per_minibatch": us, "pair_updates_per_s": st.pairs / (st.ms / 1e3)}
+        if msh:
+            flops = 3 * 2 * 1024 * 1024 * 128   # S = C N^T, dC = G N, dN = G^T C
+            r["mfma_tflops"] = flops / (us * 1e-6) / 1e12
+            r["mfma_frac"] = r["mfma_tflops"] / BF16_PEAK_TFLOPS
+        out[name] = r
+        log("c3 %s: %.1f us/minibatch" % (name, us))
+        M.close()
+    out["bf16_speedup"] = (out["fp32_per_pair"]["us_per_minibatch"]
+                           / out["bf16_shared_negative"]["us_per_minibatch"])
+    # error of each form against the FP64 oracle, one minibatch, same state
+    oracle.build()
+    ow = oracle.walks_uniform(g, np.arange(CHUNK, dtype=np.int32), 1, 80, 1, 0)
+    assert np.array_equal(W.read_range(0, 4096), ow[:4096])
+    cdf = oracle.neg_cdf(g.degrees().astype(np.uint64))
+    tin, tout = oracle.init_tables(g.n, 128, 2)
+    tout += np.random.default_rng(4).normal(0, 0.05, tout.shape).astype(np.float32)
+    b = first
+    mb = oracle.minibatch_pairs(ow, 10, 1024, b)
+    lr = 0.0125
+    errs = {}
+    for prec, msh, name in ((felog.PREC_FP32, 0, "fp32_per_pair"),
+                            (felog.PREC_BF16, 1024, "bf16_shared_negative")):
+        M = felog.Model.create(G, dim=128, neg_dist=felog.NEG_DEGREE, seed=2, precision=prec)
+        M.write(felog.TABLE_IN, tin)
+        M.write(felog.TABLE_OUT, tout)
+        prm = felog.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=3,
+                                 shared_negatives=msh, lr_start=lr, lr_end=lr)
+        ri, di, ro, do, loss = M.train_delta(W, prm, b)
+        M.close()
+        if msh:
+            neg = oracle.shared_negatives(b, 0, 1024, 3, cdf)
+            dctx, dneg, dctr, oloss = oracle.shared_neg_step(tin, tout, mb.ctx, mb.ctr, neg, 5,
+                                                             lr, bf16=False)
+            rows_in, inv_in = np.unique(mb.ctx, return_inverse=True)
+            ref_in = np.zeros((rows_in.shape[0], 128))
+            np.add.at(ref_in, inv_in, dctx)
+            outs = np.concatenate([neg, mb.ctr])
+            rows_out, inv_out = np.unique(outs, return_inverse=True)
+            ref_out = np.zeros((rows_out.shape[0], 128))
+            np.add.at(ref_out, inv_out, np.concatenate([dneg, dctr]))
+        else:
+            ng = oracle.draw_negatives(mb, 0, 5, 3, cdf)
+            ref = oracle.sgns_step(tin.copy(), tout.copy(), mb.ctx, mb.ctr, ng, lr, apply=False)
+            o = np.argsort(ref.rows_in)
+            rows_in, ref_in = ref.rows_in[o], ref.d_in[o]
+            o = np.argsort(ref.rows_out)
+            rows_out, ref_out = ref.rows_out[o], ref.d_out[o]
+            oloss = ref.loss
+        rel = []
+        for gr, gd, rr, rd in ((ri, di, rows_in, ref_in), (ro, do, rows_out, ref_out)):
+            assert np.array_equal(np.sort(gr), rr)
+            gv = gd[np.argsort(gr)].astype(np.float64)
+            rel.append(np.linalg.norm(gv - rd, axis=1) / np.maximum(np.linalg.norm(rd, axis=1),
+                                                                  1e-30))
+        rel = np.concatenate(rel)
+        errs[name] = {"rows": int(rel.shape[0]), "median_rel_err": float(np.median(rel)),
+                      "p99_rel_err": float(np.percentile(rel, 99)),
+                      "max_rel_err": float(rel.max()),
+                      "loss_rel_err": abs(loss - oloss) / abs(oloss)}
+        log("c3 %s vs FP64 oracle: median %.2e, max %.2e" % (name, np.median(rel), rel.max()))
+    out["error_vs_fp64_oracle"] = errs
+    W.close()
+    starts.close()
+    G.close()
+    # AUC of both forms after one epoch on the small SBM (d = 128)
+    sbm = synth.build_graph("sbm1k")
+    Gs = felog.Graph.from_csr(ctx, sbm.train.indptr, sbm.train.indices)
+    Ws = felog.Walks.generate(Gs, r=10, L=40, seed=11)
+    aucs = {}
+    for prec, msh, name in ((felog.PREC_FP32, 0, "fp32_per_pair"),
+                            (felog.PREC_BF16, 1024, "bf16_shared_negative")):
+        M = felog.Model.create(Gs, dim=128, neg_dist=felog.NEG_DEGREE, seed=0, precision=prec)
+        M.train_epoch(Ws, felog.train_params(window=5, negatives=5, minibatch_pairs=1024,
+                                             seed=3, shared_negatives=msh))
+        aucs[name] = auc_score(M.read(felog.TABLE_IN), sbm.test_pos, sbm.test_neg)
+        M.close()
+    out["sbm_epoch_auc"] = aucs
+    out["sbm_auc_delta"] = aucs["bf16_shared_negative"] - aucs["fp32_per_pair"]
+    log("c3: sbm epoch AUC fp32 %.4f bf16 %.4f" % (aucs["fp32_per_pair"],
+                                                    aucs["bf16_shared_negative"]))
+    return out
 
 
 def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
@@ -89,8 +341,7 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
     t0 = time.perf_counter()
     mix = synth.job_mix(n_jobs, seed=seed)
     graphs = [synth.job_graph(j) for j in mix]
-    log("serving: %d jobs, n = %s (graphs %.1f s)" % (n_jobs, [j["n"] for j in mix],
-                                                     time.perf_counter() - t0))
+    log("serving: %d jobs (graphs %.1f s)" % (n_jobs, time.perf_counter() - t0))
 
     def submit(S, j, g, at=0.0):
         return S.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
@@ -104,7 +355,6 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
         pairs.append(st.pairs)
     S.close()
     capacity = 1.0 / float(np.mean(service))
-    log("serving: mean service %.3f s, capacity %.3f jobs/s" % (1.0 / capacity, capacity))
     out = {"jobs": n_jobs, "slots": slots, "capacity_jobs_per_s": capacity,
            "mean_service_s": 1.0 / capacity, "pairs_per_job": float(np.mean(pairs)), "rates": []}
     rng = np.random.Generator(np.random.PCG64(seed + 1))
@@ -122,104 +372,33 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
         S.close()
         lat = np.array([s.t_done - s.t_arrive for s in states])
         span = max(s.t_done for s in states) - (base + arrivals[0])
-        r = {"load": frac, "arrival_rate_jobs_per_s": lam, "p50_latency_s": float(np.percentile(lat, 50)),
+        r = {"load": frac, "arrival_rate_jobs_per_s": lam,
+             "p50_latency_s": float(np.percentile(lat, 50)),
              "p99_latency_s": float(np.percentile(lat, 99)), "jobs_per_s": n_jobs / span,
              "pair_updates_per_s": float(np.sum(pairs)) / span}
-        log("serving: load %.2f p50 %.3f s p99 %.3f s" % (frac, r["p50_latency_s"], r["p99_latency_s"]))
+        log("serving: load %.2f p50 %.3f s p99 %.3f s" % (frac, r["p50_latency_s"],
+                                                          r["p99_latency_s"]))
         out["rates"].append(r)
     return out
 
 
-def small_minibatch_sample(felog, G, n_mb: int, seed: int = 3):
-    """The FP32 per-pair form against the BF16 shared-negative form at P = M = 1024
-    (d = 128, K = 5, w = 10, degree noise) on the bench graph: time per minibatch
-    over n_mb minibatches from the middle of the corpus."""
-    W = felog.Walks.generate(G, r=10, L=80, seed=1)
-    out = {"minibatch_pairs": 1024, "shared_negatives": 1024, "dim": 128, "negatives": 5,
-           "window": 10, "minibatches": n_mb}
-    for prec, msh, name in ((felog.PREC_FP32, 0, "fp32_per_pair"),
-                            (felog.PREC_BF16, 1024, "bf16_shared_negative")):
-        M = felog.Model.create(G, dim=128, neg_dist=felog.NEG_DEGREE, seed=2, precision=prec)
-        prm = felog.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=seed,
-                                 shared_negatives=msh)
-        M.train_steps(W, prm, 0, 200)
-        st = M.train_steps(W, prm, 300000, n_mb)
-        us = st.ms / st.minibatches * 1e3
-        r = {"us_per_minibatch": us, "pair_updates_per_s": st.pairs / (st.ms / 1e3)}
-        if msh:
-            flops = 3 * 2 * 1024 * 1024 * 128   # S, dC and dN
-            r["mfma_tflops"] = flops / (us * 1e-6) / 1e12
-            r["mfma_frac"] = r["mfma_tflops"] / BF16_PEAK_TFLOPS
-        out[name] = r
-        log("%s at P=1024: %.1f us/minibatch" % (name, us))
-        M.close()
-    W.close()
-    return out
-
-
-def codec_sample(felog, G, reps: int = 3):
-    """The FaBC walk-corpus codec (Section 5.2.2) on the round-1 corpus of the
-    bench graph (r = 10, L = 80): profile, the Eq. (8) target set, pack and
-    unpack on the device, best of reps, with a sampled round-trip check."""
-    W = felog.Walks.generate(G, r=10, L=80, seed=1)
-    n_walks, L, _ = W.info()
-    raw = 4 * n_walks * L
-    best = None
-    for _ in range(reps):
-        k, sym, cnt, total = W.fabc_profile()
-        P = W.pack(sym[:k])
-        U = P.unpack()
-        by, _, _, _, R = P.info()
-        for first in (0, n_walks // 2, max(0, n_walks - 4096)):
-            c = min(4096, n_walks - first)
-            assert np.array_equal(U.read_range(first, c), W.read_range(first, c))
-        pack_ms = P.ms[0] + P.ms[1]
-        if best is None or pack_ms + U.unpack_ms < best[0] + best[1]:
-            best = (pack_ms, U.unpack_ms, P.ms)
-        U.close()
-        P.close()
-    W.close()
-    F = float(cnt[:k].sum()) / total
-    moved = raw + by                      # read the corpus once, write the packed bytes
-    pack_gbs = moved / (best[0] * 1e-3) / 1e9
-    unpack_gbs = moved / (best[1] * 1e-3) / 1e9
-    out = {"walks": int(n_walks), "length": int(L), "k": int(k),
-           "symbols": [int(x) for x in sym[:k]], "top_shares": [float(c) / total for c in cnt[:4]],
-           "raw_bytes": int(raw), "packed_bytes": int(by), "residuals": int(R),
-           "ratio": by / raw, "g_eq7": 1.0 - F + k / L + k / 32.0,
-           "pack_ms": best[0], "pack_count_ms": best[2][0], "pack_write_ms": best[2][1],
-           "unpack_ms": best[1], "pack_gbs": pack_gbs, "unpack_gbs": unpack_gbs,
-           "pack_frac": pack_gbs / HBM_PEAK_GBS, "unpack_frac": unpack_gbs / HBM_PEAK_GBS}
-    log("codec: k=%d, %d of %d bytes (%.3f; Eq. (7) g = %.3f), pack %.2f ms, unpack %.2f ms" % (
-        k, by, raw, by / raw, out["g_eq7"], best[0], best[1]))
-    return out
-
-
+# ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--max-rounds", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mb-per-step", type=int, default=16384,
+                    help="minibatches of a walk chunk's pairs per step")
     ap.add_argument("--timing-every", type=int, default=16,
-                    help="time every n-th forward/apply launch with HIP events")
+                    help="time every n-th minibatch's launches with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walks", type=int, default=1 << 17)
-    ap.add_argument("--cpu-minibatches", type=int, default=30)
-    ap.add_argument("--progress-every", type=int, default=0,
-                    help="drive the rounds from Python (same ABI calls and kernels as "
-                         "felog_run) and print a line every N minibatches; for profiler runs")
-    ap.add_argument("--serving-jobs", type=int, default=8,
-                    help="jobs in the serving-latency sample (0: skip)")
+    ap.add_argument("--cpu-walks", type=int, default=1 << 15)
+    ap.add_argument("--cpu-minibatches", type=int, default=12)
+    ap.add_argument("--c2-rounds", type=int, default=4, help="0 skips the Algorithm 1 leg")
+    ap.add_argument("--c3-minibatches", type=int, default=20000, help="0 skips the C3 leg")
+    ap.add_argument("--serving-jobs", type=int, default=8, help="0 skips the serving sample")
     ap.add_argument("--serving-slots", type=int, default=4)
-    ap.add_argument("--no-codec", action="store_true",
-                    help="skip the walk-corpus codec sample")
-    ap.add_argument("--small-minibatches", type=int, default=20000,
-                    help="minibatches of the FP32 vs BF16 comparison at P = 1024 (0 = skip)")
-    ap.add_argument("--calibrate", action="store_true",
-                    help="after the run, build a BF16 model once: its two table conversions "
-                         "read n*d*4 and write n*d*2 bytes each (known sizes, for HBM "
-                         "counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
@@ -227,220 +406,155 @@ def main():
         sys.exit(2)
 
     import synth
+    cores, cpu_model = host_info()
+    cfg = dict(L=80, r=10, p=0.5, q=2.0, window=10, K=5, dim=128, minibatch=1024, lr0=0.025,
+               lr_end=1e-4, seed_walk=1, seed_model=2, seed_train=3)
+    t = time.perf_counter()
+    split = synth.build_graph("rmat23w")
+    g = split.train
+    deg = g.degrees()
+    log("graph n=%d nnz=%d isolated=%d (%.1f s)" % (g.n, g.nnz, int((deg == 0).sum()),
+                                                   time.perf_counter() - t))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched
+        cpu = cpu_baseline(g, cfg, args.cpu_walks, args.cpu_minibatches, cores, cpu_model)
+
     from paper_2606_22180_amd import build as hipbuild
-    from paper_2606_22180_amd import felog
     if not os.path.exists(hipbuild.LIB):
         hipbuild.build()
-
-    preset = synth.CONFIGS["rmat20"]
-    cfg = dict(L=preset["L"], r=preset["r"], window=preset["window"], K=preset["K"],
-               dim=preset["dim"], minibatch=preset["minibatch"], lr0=preset["lr0"],
-               lr_end=preset["lr_end"], mu=preset["mu"], k_s=preset["k_s"],
-               r_max=args.max_rounds, seed_walk=1, seed_model=2, seed_train=3, seed_psi=4)
-    t = time.perf_counter()
-    split = synth.build_graph("rmat20")
-    g = split.train
-    log("graph n=%d nnz=%d isolated=%d (%.1f s)" % (g.n, g.nnz, int((g.degrees() == 0).sum()),
-                                                   time.perf_counter() - t))
-
+    from paper_2606_22180_amd import felog
     ctx = felog.Context(0)
-    G = felog.Graph.from_csr(ctx, g.indptr, g.indices)
+    G = felog.Graph.from_csr(ctx, g.indptr, g.indices, g.weights)
     M = felog.Model.create(G, dim=cfg["dim"], neg_dist=felog.NEG_UNIGRAM, seed=cfg["seed_model"])
-    rp = felog.felog_run_params()
-    rp.walk = felog.felog_walk_params(felog.WALK_UNIFORM, cfg["r"], cfg["L"], 1.0, 1.0,
-                                      cfg["seed_walk"], 0)
-    rp.train = felog.train_params(window=cfg["window"], negatives=cfg["K"], lr_start=cfg["lr0"],
-                                  lr_end=cfg["lr_end"], minibatch_pairs=cfg["minibatch"],
-                                  seed=cfg["seed_train"])
-    rp.feedback = felog.felog_feedback_params(cfg["mu"], cfg["k_s"], felog.FEEDBACK_MONOTONE,
-                                              cfg["seed_psi"], 0)
-    rp.max_rounds = cfg["r_max"]
+    t = time.perf_counter()
+    Wf = felog.Walks.generate(G, r=cfg["r"], L=cfg["L"], seed=cfg["seed_walk"],
+                              kind=felog.WALK_NODE2VEC, p=cfg["p"], q=cfg["q"])
+    full_walks = Wf.info()[0]
+    full_s = time.perf_counter() - t
+    capped = Wf.capped()
+    M.set_unigram(Wf)
+    Wf.close()
+    full_steps = cfg["r"] * (cfg["L"] - 1) * int((deg > 0).sum())
+    log("full node2vec corpus: %d walks, %d steps in %.3f s, capped %d; unigram table set"
+        % (full_walks, full_steps, full_s, capped))
+    n_chunks = full_walks // CHUNK
+    offsets = {}
+    prm = felog.train_params(window=cfg["window"], negatives=cfg["K"], lr_start=cfg["lr0"],
+                             lr_end=cfg["lr_end"], minibatch_pairs=cfg["minibatch"],
+                             seed=cfg["seed_train"])
 
-    deg = g.degrees()
-
-    def run_rounds_python():
-        """Algorithm 1 through the separate ABI calls (what felog_run does), with a
-        progress line every --progress-every minibatches."""
-        st = felog.felog_run_stats()
-        act = None
-        n_active = g.n
-        id_base = 0
-        for r in range(cfg["r_max"]):
-            if n_active == 0:
-                break
-            t0 = time.perf_counter()
-            W = felog.Walks.generate(G, r=cfg["r"], L=cfg["L"], seed=cfg["seed_walk"],
-                                     id_base=id_base, starts=act)
-            if r == 0:
-                M.set_unigram(W)
-            st.ms_walk[r] = (time.perf_counter() - t0) * 1e3
-            B = M.train_steps(W, rp.train, 0, 0).minibatches_total
-            tr = felog.felog_train_stats()
-            for b0 in range(0, B, args.progress_every):
-                s = M.train_steps(W, rp.train, b0, args.progress_every)
-                for f in ("minibatches", "pairs", "rows_in", "rows_out", "rows_out_single",
-                          "timed_launches"):
-                    setattr(tr, f, getattr(tr, f) + getattr(s, f))
-                for f in ("loss", "ms", "ms_forward", "ms_apply", "ms_prep", "ms_apply_first"):
-                    setattr(tr, f, getattr(tr, f) + getattr(s, f))
-                log("round %d: minibatches %d/%d" % (r, min(B, b0 + args.progress_every), B))
-            st.train[r] = tr
-            st.active[r] = n_active
-            st.walks[r] = W.info()[0]
-            starts = np.arange(g.n) if act is None else act.read()
-            st.walk_steps[r] = int(cfg["r"] * (cfg["L"] - 1) * (deg[starts] > 0).sum())
-            id_base += st.walks[r]
-            t1 = time.perf_counter()
-            act = M.feedback(mu=cfg["mu"], k_s=cfg["k_s"], seed=cfg["seed_psi"], round=r,
-                             active=act)
-            st.ms_feedback[r] = (time.perf_counter() - t1) * 1e3
-            n_active = act.count()
-            st.rounds = r + 1
-        st.final_active = n_active
-        return st
-
-    def step():
-        M.reset(cfg["seed_model"])
+    def step(s):
+        c = s % n_chunks
+        first = c * CHUNK
+        off = first % g.n
+        if off not in offsets:
+            offsets[off] = felog.Active.from_host(G, np.arange(off, off + CHUNK, dtype=np.int32))
         t0 = time.perf_counter()
-        st = run_rounds_python() if args.progress_every else M.run(rp)
-        return st, time.perf_counter() - t0
+        W = felog.Walks.generate(G, r=1, L=cfg["L"], seed=cfg["seed_walk"], id_base=first,
+                                 kind=felog.WALK_NODE2VEC, p=cfg["p"], q=cfg["q"],
+                                 starts=offsets[off])
+        t1 = time.perf_counter()
+        st = M.train_steps(W, prm, 0, args.mb_per_step)
+        W.close()
+        steps = (cfg["L"] - 1) * int((deg[off:off + CHUNK] > 0).sum())
+        return st, t1 - t0, steps
 
     for i in range(args.warmup):
-        st, dt = step()
-        log("warmup %d: %.2f s, rounds=%d" % (i, dt, st.rounds))
-
+        st, _, _ = step(i)
+        log("warmup %d: %d minibatches" % (i, st.minibatches))
     ctx.set_timing(args.timing_every)
-    times = []
-    st = None
+    walk_s = 0.0
+    walk_steps = pairs = 0
+    sts = []
+    t0 = time.perf_counter()
     for i in range(args.steps):
-        st, dt = step()
-        times.append(dt)
-        log("step %d: %.2f s, rounds=%d active=%s" % (i, dt, st.rounds,
-                                                       list(st.active[:st.rounds])))
+        st, ws, steps = step(args.warmup + i)
+        walk_s += ws
+        walk_steps += steps
+        pairs += st.pairs
+        sts.append(st)
+    total = time.perf_counter() - t0
     ctx.set_timing(0)
-    total = float(np.sum(times))
-    R = st.rounds
-    rounds = []
-    pairs = walk_steps = 0
-    fwd_ms = apply_ms = prep_ms = apply0_ms = 0.0
-    timed = 0
-    mbs = rows = rows_in = rows_out = rows_single = 0
-    ms_walk = 0.0
-    for r in range(R):
-        tr = st.train[r]
-        pairs += tr.pairs
-        walk_steps += st.walk_steps[r]
-        fwd_ms += tr.ms_forward
-        apply_ms += tr.ms_apply
-        prep_ms += tr.ms_prep
-        apply0_ms += tr.ms_apply_first
-        timed += tr.timed_launches
-        mbs += tr.minibatches
-        rows += tr.rows_in + tr.rows_out
-        rows_in += tr.rows_in
-        rows_out += tr.rows_out
-        rows_single += tr.rows_out_single
-        ms_walk += st.ms_walk[r]
-        rounds.append(dict(active=int(st.active[r]), walks=int(st.walks[r]),
-                           walk_steps=int(st.walk_steps[r]), pairs=int(tr.pairs),
-                           loss_per_pair=tr.loss / max(1, tr.pairs), ms_walk=st.ms_walk[r],
-                           ms_train=tr.ms, ms_feedback=st.ms_feedback[r],
-                           minibatches=int(tr.minibatches)))
-    pairs_per_step = pairs
-    value = pairs_per_step * len(times) / total
-    if args.calibrate:
-        Mb = felog.Model.create(G, dim=cfg["dim"], neg_dist=felog.NEG_DEGREE,
-                                seed=cfg["seed_model"], precision=felog.PREC_BF16)
-        log("calibration: 2 conversions of %d bytes read, %d bytes written" % (
-            g.n * cfg["dim"] * 4, g.n * cfg["dim"] * 2))
-        Mb.close()
-    emb = M.read(felog.TABLE_IN)
-    auc = auc_score(emb, split.test_pos, split.test_neg)
-    log("pairs/step=%d walk_steps/step=%d value=%.4g pairs/s auc=%.4f" % (
-        pairs_per_step, walk_steps, value, auc))
+    value = pairs / total
+    log("timed: %d steps, %.3f s, %.4g pair-updates/s, walks %.3g steps/s"
+        % (args.steps, total, value, walk_steps / walk_s))
 
-    # Roofline of the dominant kernel by time (the events decide): the forward
-    # or the first apply launch.  Algorithmic bytes per launch:
-    #  - forward: every distinct touched row read once (d*4 B), the out rows
-    #    touched once in their minibatch written once (d*4 B; the forward
-    #    applies them), the pair's two node ids (8 B) and one 8 B cumulative
-    #    weight per negative;
-    #  - first apply launch (sgns_apply_kernel<d, 0>, the other out rows' sums):
-    #    those out rows read and written once (d*8 B), each distinct in row (a
-    #    pair's context) read once (d*4 B) and 12 B per out touch it sums (its
-    #    coefficient, context id and pair-order key).  Rows with more than 16
-    #    touches are summed here and written by the second launch; their writes
-    #    are counted here.
-    # The whole minibatch update (ids, the destination sort, forward, both apply
-    # launches) reads and writes each touched row once: rows*d*8 + pairs*(8 + 8K).
-    # Durations come from HIP events on every timing_every-th minibatch, on the
-    # stream the kernels run on; the id work of later minibatches runs
-    # concurrently on a second stream, so the durations include that contention.
-    d = cfg["dim"]
-    K = cfg["K"]
-    row_bytes = rows * d * 4
-    id_bytes = pairs * (8 + 8 * K)
-    multi_out = rows_out - rows_single
+    # Roofline of the dominant SGNS kernel by HIP-event time (every
+    # timing_every-th minibatch, events on the training stream).
+    d, K = cfg["dim"], cfg["K"]
+    mbs = sum(s.minibatches for s in sts)
+    timed = sum(s.timed_launches for s in sts)
+    rows_in = sum(s.rows_in for s in sts)
+    rows_out = sum(s.rows_out for s in sts)
+    single = sum(s.rows_out_single for s in sts)
+    multi_out = rows_out - single
     out_touches = pairs * (K + 1)
-    per_apply0 = (multi_out * d * 8 + rows_in * d * 4 + (out_touches - rows_single) * 12) / max(1, mbs)
-    per_fwd = (row_bytes + rows_single * d * 4 + id_bytes) / max(1, mbs)
-    per_update = (2 * row_bytes + id_bytes) / max(1, mbs)
-    avg_apply0_s = apply0_ms / 1e3 / max(1, timed)
-    avg_fwd_s = fwd_ms / 1e3 / max(1, timed)
-    # the next minibatches' ids overlap this one's update, so the update's cost is
-    # the training wall time per minibatch
-    avg_upd_s = sum(st.train[r].ms for r in range(R)) / 1e3 / max(1, mbs)
-
-    def kernel_roof(name, per, avg_s):
-        ach = per / avg_s / 1e9 if timed else None
-        return {"kernel": name, "algorithmic_bytes_per_launch": per, "avg_launch_us": avg_s * 1e6,
-                "achieved": ach, "frac": (ach / HBM_PEAK_GBS) if ach else None}
-
-    fwd = kernel_roof("sgns_forward_kernel<%d, %d>" % (d, K), per_fwd, avg_fwd_s)
-    ap0 = kernel_roof("sgns_apply_kernel<%d, 0>" % d, per_apply0, avg_apply0_s)
-    dom, other = (fwd, ap0) if avg_fwd_s >= avg_apply0_s else (ap0, fwd)
-    upd_achieved = per_update / avg_upd_s / 1e9 if timed else None
-    roof = {"bound": "hbm", "kernel": dom["kernel"],
-            "achieved": dom["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom["frac"], "traffic": kernel_traffic(dom["kernel"]),
-            "algorithmic_bytes_per_launch": dom["algorithmic_bytes_per_launch"],
-            "avg_launch_us": dom["avg_launch_us"], "timed_launches": timed,
-            "touched_rows_per_minibatch": rows / max(1, mbs),
-            "in_rows_per_minibatch": rows_in / max(1, mbs),
-            "out_rows_per_minibatch": rows_out / max(1, mbs),
-            "out_rows_touched_once_per_minibatch": rows_single / max(1, mbs),
-            "other_kernel": other,
-            "sgns_update": {"kernels": "prep and scan (second stream), forward, two apply "
-                                       "launches",
-                            "avg_prep_us": prep_ms / 1e3 / max(1, timed) * 1e6,
-                            "avg_reduce_us": apply_ms / 1e3 / max(1, timed) * 1e6,
-                            "algorithmic_bytes": per_update, "avg_us": avg_upd_s * 1e6,
-                            "achieved": upd_achieved,
-                            "frac": (upd_achieved / HBM_PEAK_GBS) if upd_achieved else None}}
+    per = {
+        # every distinct touched row read once, out rows touched once written,
+        # the pair's ids and one 8-byte cumulative weight per negative
+        "sgns_forward_kernel<%d, %d>" % (d, K):
+            ((rows_in + rows_out) * d * 4 + single * d * 4 + pairs * (8 + 8 * K)) / mbs,
+        # other out rows read and written, each context row read, 16-byte
+        # entries of the out-touches it sums
+        "sgns_apply_kernel<%d, 0>" % d:
+            (multi_out * d * 8 + rows_in * d * 4 + (out_touches - single) * 16) / mbs,
+        # in rows read and written, each pair's in-row delta read
+        "sgns_apply_kernel<%d, 1>" % d: (rows_in * d * 8 + pairs * d * 4) / mbs,
+    }
+    ms = {
+        "sgns_forward_kernel<%d, %d>" % (d, K): sum(s.ms_forward for s in sts),
+        "sgns_apply_kernel<%d, 0>" % d: sum(s.ms_apply_first for s in sts),
+        "sgns_apply_kernel<%d, 1>" % d: sum(s.ms_apply - s.ms_apply_first for s in sts),
+    }
+    kern = {}
+    for name in per:
+        avg = ms[name] / 1e3 / max(1, timed)
+        ach = per[name] / avg / 1e9 if avg > 0 else None
+        kern[name] = {"algorithmic_bytes_per_launch": per[name], "avg_launch_us": avg * 1e6,
+                      "achieved_gbs": ach, "frac": ach / HBM_PEAK_GBS if ach else None}
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_us"])
+    upd_bytes = ((rows_in + rows_out) * d * 8 + pairs * (8 + 8 * K)) / mbs
+    upd_us = sum(s.ms for s in sts) / mbs * 1e3
+    roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["achieved_gbs"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern[dom]["frac"], "traffic": None,
+            "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes_per_launch"],
+            "avg_launch_us": kern[dom]["avg_launch_us"], "timed_minibatches": timed,
+            "kernels": kern, "ids_us_per_minibatch": sum(s.ms_prep for s in sts) / max(1, timed) * 1e3,
+            "touched_rows_per_minibatch": (rows_in + rows_out) / mbs,
+            "sgns_update": {"algorithmic_bytes": upd_bytes, "us_per_minibatch": upd_us,
+                            "achieved_gbs": upd_bytes / upd_us / 1e3,
+                            "frac": upd_bytes / upd_us / 1e3 / HBM_PEAK_GBS}}
 
     out = {
         "metric": METRIC, "value": value, "unit": "pair-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / len(times) * 1e3,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "rmat20: R-MAT scale 20 (a,b,c = .57,.19,.19), 2^24 undirected "
-                               "edges with 10%% held out, uniform walks r=10 L=80, SGNS d=128 "
-                               "w=10 K=5 unigram^0.75 minibatch 65536, FeeST mu=0.65 k_s=10 "
-                               "monotone, at most %d rounds" % cfg["r_max"],
-                   "nodes": g.n, "csr_entries": g.nnz},
-        "walk_steps_per_s": walk_steps * len(times) / (ms_walk / 1e3 * len(times)),
-        "walk_steps_per_step": int(walk_steps), "pairs_per_step": int(pairs_per_step),
-        "link_pred_auc": auc, "rounds": rounds, "roofline": roof,
+        "config": {"workload": "weighted R-MAT scale 23 (a,b,c = .57,.19,.19), 2^27 undirected "
+                               "edges, 10% held out, weights U(0,1]; node2vec p=0.5 q=2, "
+                               "r=10 L=80; SGNS FP32 d=128 w=10 K=5 unigram^0.75, minibatch "
+                               "1024; one step = the walks of one 2^20-walk chunk + its first "
+                               "%d minibatches" % args.mb_per_step,
+                   "nodes": g.n, "csr_entries": g.nnz, "minibatches_per_step": args.mb_per_step},
+        "walk_steps_per_s": walk_steps / walk_s,
+        "walk_steps_per_s_full_corpus": full_steps / full_s,
+        "pairs_per_step": pairs / args.steps, "node2vec_capped": int(capped),
+        "roofline": roof,
     }
-    if not args.no_codec:
-        out["walk_codec"] = codec_sample(felog, G)
-    if args.small_minibatches > 0:
-        out["small_minibatch_forms"] = small_minibatch_sample(felog, G, args.small_minibatches)
+    G.close()
+    M.close()
+    for a in offsets.values():
+        a.close()
+    if args.c2_rounds > 0:
+        out["c2_algorithm1"], out["walk_codec"] = c2_algorithm1(felog, args.c2_rounds)
+    if args.c3_minibatches > 0:
+        out["c3_forms"] = c3_forms(felog, args.c3_minibatches)
     if args.serving_jobs > 0:
         out["serving"] = serving_sample(felog, args.serving_jobs, args.serving_slots)
-        out["p99_job_latency_s"] = out["serving"]["rates"][1]["p99_latency_s"]   # at 0.8 x capacity
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, cfg, args.cpu_walks, args.cpu_minibatches)
+        out["p99_job_latency_s"] = out["serving"]["rates"][1]["p99_latency_s"]
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

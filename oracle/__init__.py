@@ -68,6 +68,8 @@ def lib():
     if _lib is None:
         L = ctypes.CDLL(build())
         sig = {
+            "orc_set_threads": (None, [_int]),
+            "orc_max_threads": (_int, []),
             "orc_philox": (None, [_p, _p, _p]),
             "orc_philox_batch": (None, [_i64, _p, _u64, _p]),
             "orc_init_tables": (None, [_i64, _int, _u64, _p, _p]),
@@ -121,6 +123,15 @@ def _c(a, dtype):
 # --------------------------------------------------------------------------
 # Random numbers: Philox4x32-10 (Salmon et al., SC'11)
 # --------------------------------------------------------------------------
+def set_threads(k: int) -> None:
+    """Threads of the oracle's OpenMP loops (independent items only)."""
+    lib().orc_set_threads(int(k))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
 def philox(ctr, key) -> np.ndarray:
     c = _c(ctr, np.uint32)
     k = _c(key, np.uint32)

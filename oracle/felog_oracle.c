@@ -32,9 +32,14 @@
  * Build: gcc -O2 -fopenmp -fPIC -shared -ffp-contract=off -fno-fast-math
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the OpenMP loops (for the CPU-baseline timings). */
+void orc_set_threads(int k) { omp_set_num_threads(k > 0 ? k : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10, SC'11: multipliers and Weyl key increments.          */
