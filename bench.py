@@ -167,7 +167,7 @@ def c2_algorithm1(felog, max_rounds: int):
                            loss_per_pair=tr.loss / max(1, tr.pairs), ms_walk=st.ms_walk[r],
                            ms_train=tr.ms, ms_feedback=st.ms_feedback[r],
                            minibatches=int(tr.minibatches)))
-    out = {"workload": "R-MAT scale 20 (a,b,c = .57,.19,.19), 2^24 undirected edges, 10% held "
+    out = {"workload": "R-MAT scale 20 (a,b,c = .57,.19,.19), 2^24 undirected edges, 10%% held "
                        "out; uniform walks r=10 L=80; SGNS d=128 w=10 K=5 unigram^0.75 P=65536; "
                        "FeeST mu=0.65 k_s=10 monotone, at most %d rounds" % max_rounds,
            "rounds": rounds, "final_active": int(st.final_active), "wall_s": wall,
@@ -382,6 +382,77 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
     return out
 
 
+# ----------------------------------------------------------------- roofline
+def sgns_roofline(sts, d: int, K: int, pairs: int):
+    """Roofline of the dominant SGNS kernel by HIP-event time.
+
+    Algorithmic bytes of a minibatch: each touched row read once and written
+    once (d * 4 bytes each way), the pair's ids and one 8-byte cumulative
+    weight per negative draw, and the 8-byte touch descriptor the update
+    reads per touch.  Intermediates that a kernel writes and reads back
+    (entries, per-pair deltas, context copies) are not counted.
+
+    Persistent path (stats.path == 1): every plan and update launch is timed;
+    a launch covers timed_minibatches / timed_launches minibatches.
+    Per-minibatch launches (path 0): every timing_every-th minibatch's
+    forward and two apply launches are timed."""
+    mbs = sum(s.minibatches for s in sts)
+    timed = sum(s.timed_launches for s in sts)
+    rows_in = sum(s.rows_in for s in sts)
+    rows_out = sum(s.rows_out for s in sts)
+    single = sum(s.rows_out_single for s in sts)
+    touches = pairs * (K + 2)
+    row_bytes = (rows_in + rows_out) * d * 4
+    upd_bytes = (2 * row_bytes + pairs * (8 + 8 * K)) / mbs
+    upd_us = sum(s.ms for s in sts) / mbs * 1e3
+    kern = {}
+    if sts[0].path == 1:
+        tmb = sum(s.timed_minibatches for s in sts)
+        per_launch_mb = tmb / max(1, timed)
+        per_mb_update = (2 * row_bytes + touches * 8) / mbs
+        per_mb_plan = (pairs * (8 + 8 * K) + touches * 8) / mbs
+        for name, per, ms in (("sgns_small_update_kernel<%d, %d>" % (d, K), per_mb_update,
+                               sum(s.ms_update for s in sts)),
+                              ("sgns_plan_kernel<%d>" % K, per_mb_plan,
+                               sum(s.ms_prep for s in sts))):
+            avg = ms / 1e3 / max(1, timed)
+            byt = per * per_launch_mb
+            ach = byt / avg / 1e9 if avg > 0 else None
+            kern[name] = {"algorithmic_bytes_per_launch": byt, "avg_launch_us": avg * 1e6,
+                          "minibatches_per_launch": per_launch_mb,
+                          "us_per_minibatch": avg * 1e6 / max(1e-30, per_launch_mb),
+                          "achieved_gbs": ach, "frac": ach / HBM_PEAK_GBS if ach else None}
+        blocks = sts[0].update_blocks
+    else:
+        multi_out = rows_out - single
+        out_touches = pairs * (K + 1)
+        per = {"sgns_forward_kernel<%d, %d>" % (d, K):
+                   (row_bytes + single * d * 4 + pairs * (8 + 8 * K)) / mbs,
+               "sgns_apply_kernel<%d, 0>" % d:
+                   (multi_out * d * 8 + rows_in * d * 4 + (out_touches - single) * 16) / mbs,
+               "sgns_apply_kernel<%d, 1>" % d: (rows_in * d * 8 + pairs * d * 4) / mbs}
+        ms = {"sgns_forward_kernel<%d, %d>" % (d, K): sum(s.ms_forward for s in sts),
+              "sgns_apply_kernel<%d, 0>" % d: sum(s.ms_apply_first for s in sts),
+              "sgns_apply_kernel<%d, 1>" % d: sum(s.ms_apply - s.ms_apply_first for s in sts)}
+        for name in per:
+            avg = ms[name] / 1e3 / max(1, timed)
+            ach = per[name] / avg / 1e9 if avg > 0 else None
+            kern[name] = {"algorithmic_bytes_per_launch": per[name], "avg_launch_us": avg * 1e6,
+                          "achieved_gbs": ach, "frac": ach / HBM_PEAK_GBS if ach else None}
+        blocks = None
+    dom = max(kern, key=lambda k: kern[k]["avg_launch_us"])
+    return {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["achieved_gbs"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern[dom]["frac"], "traffic": None,
+            "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes_per_launch"],
+            "avg_launch_us": kern[dom]["avg_launch_us"], "timed_launches": timed,
+            "update_path": "persistent" if sts[0].path == 1 else "per-minibatch launches",
+            "update_blocks": blocks, "kernels": kern,
+            "touched_rows_per_minibatch": (rows_in + rows_out) / mbs,
+            "sgns_update": {"algorithmic_bytes": upd_bytes, "us_per_minibatch": upd_us,
+                            "achieved_gbs": upd_bytes / upd_us / 1e3,
+                            "frac": upd_bytes / upd_us / 1e3 / HBM_PEAK_GBS}}
+
+
 # ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -480,59 +551,14 @@ def main():
     log("timed: %d steps, %.3f s, %.4g pair-updates/s, walks %.3g steps/s"
         % (args.steps, total, value, walk_steps / walk_s))
 
-    # Roofline of the dominant SGNS kernel by HIP-event time (every
-    # timing_every-th minibatch, events on the training stream).
-    d, K = cfg["dim"], cfg["K"]
-    mbs = sum(s.minibatches for s in sts)
-    timed = sum(s.timed_launches for s in sts)
-    rows_in = sum(s.rows_in for s in sts)
-    rows_out = sum(s.rows_out for s in sts)
-    single = sum(s.rows_out_single for s in sts)
-    multi_out = rows_out - single
-    out_touches = pairs * (K + 1)
-    per = {
-        # every distinct touched row read once, out rows touched once written,
-        # the pair's ids and one 8-byte cumulative weight per negative
-        "sgns_forward_kernel<%d, %d>" % (d, K):
-            ((rows_in + rows_out) * d * 4 + single * d * 4 + pairs * (8 + 8 * K)) / mbs,
-        # other out rows read and written, each context row read, 16-byte
-        # entries of the out-touches it sums
-        "sgns_apply_kernel<%d, 0>" % d:
-            (multi_out * d * 8 + rows_in * d * 4 + (out_touches - single) * 16) / mbs,
-        # in rows read and written, each pair's in-row delta read
-        "sgns_apply_kernel<%d, 1>" % d: (rows_in * d * 8 + pairs * d * 4) / mbs,
-    }
-    ms = {
-        "sgns_forward_kernel<%d, %d>" % (d, K): sum(s.ms_forward for s in sts),
-        "sgns_apply_kernel<%d, 0>" % d: sum(s.ms_apply_first for s in sts),
-        "sgns_apply_kernel<%d, 1>" % d: sum(s.ms_apply - s.ms_apply_first for s in sts),
-    }
-    kern = {}
-    for name in per:
-        avg = ms[name] / 1e3 / max(1, timed)
-        ach = per[name] / avg / 1e9 if avg > 0 else None
-        kern[name] = {"algorithmic_bytes_per_launch": per[name], "avg_launch_us": avg * 1e6,
-                      "achieved_gbs": ach, "frac": ach / HBM_PEAK_GBS if ach else None}
-    dom = max(kern, key=lambda k: kern[k]["avg_launch_us"])
-    upd_bytes = ((rows_in + rows_out) * d * 8 + pairs * (8 + 8 * K)) / mbs
-    upd_us = sum(s.ms for s in sts) / mbs * 1e3
-    roof = {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["achieved_gbs"],
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern[dom]["frac"], "traffic": None,
-            "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes_per_launch"],
-            "avg_launch_us": kern[dom]["avg_launch_us"], "timed_minibatches": timed,
-            "kernels": kern, "ids_us_per_minibatch": sum(s.ms_prep for s in sts) / max(1, timed) * 1e3,
-            "touched_rows_per_minibatch": (rows_in + rows_out) / mbs,
-            "sgns_update": {"algorithmic_bytes": upd_bytes, "us_per_minibatch": upd_us,
-                            "achieved_gbs": upd_bytes / upd_us / 1e3,
-                            "frac": upd_bytes / upd_us / 1e3 / HBM_PEAK_GBS}}
-
+    roof = sgns_roofline(sts, cfg["dim"], cfg["K"], pairs)
     out = {
         "metric": METRIC, "value": value, "unit": "pair-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "weighted R-MAT scale 23 (a,b,c = .57,.19,.19), 2^27 undirected "
-                               "edges, 10% held out, weights U(0,1]; node2vec p=0.5 q=2, "
+                               "edges, 10%% held out, weights U(0,1]; node2vec p=0.5 q=2, "
                                "r=10 L=80; SGNS FP32 d=128 w=10 K=5 unigram^0.75, minibatch "
                                "1024; one step = the walks of one 2^20-walk chunk + its first "
                                "%d minibatches" % args.mb_per_step,

@@ -75,6 +75,16 @@ felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes);
  * summed durations in felog_train_stats (0 = off, the default). */
 felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every);
 
+/* SGNS update path of the FP32 form.  path 0 (the default): minibatches of
+ * P (K + 2) <= 8192 touches run as plan launches (ids and a sort of each
+ * minibatch's touches by row, many minibatches per launch) and one persistent
+ * cooperative update launch per group of minibatches; larger ones run
+ * per-minibatch launches.  path 1: per-minibatch launches always.  Both give
+ * bit-identical tables.  blocks: workgroups of the persistent launch (0 = one
+ * per compute unit; capped at what can be resident at once).  With timing on
+ * (felog_ctx_set_timing), every plan and update launch of path 0 is timed. */
+felog_status felog_ctx_set_sgns_path(felog_ctx* ctx, int32_t path, int32_t blocks);
+
 /* Message for the calling thread's last failed call ("" if none). */
 const char* felog_last_error(void);
 
@@ -327,6 +337,12 @@ typedef struct felog_train_stats {
                                  launches (out rows, chunks of split rows)         */
     int64_t rows_out_single;  /* of rows_out, the rows touched once in their
                                  minibatch (updated by the forward launch)          */
+    int32_t path;             /* update path the call took: 0 per-minibatch launches,
+                                 1 the persistent small-minibatch update             */
+    int32_t update_blocks;    /* path 1: workgroups of the persistent launch         */
+    int64_t timed_minibatches;/* path 1: minibatches covered by the timed launches   */
+    double ms_update;         /* path 1: summed duration of the timed persistent
+                                 update launches (ms_prep: their plan launches)      */
 } felog_train_stats;
 
 /* One Train() call: every minibatch of the corpus in order.  Pairs: within each

@@ -18,8 +18,8 @@ OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libfelog.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.cpp", "walks.hip", "noise.hip", "sgns.hip", "feedback.hip", "bf16.hip", "fabc.hip",
-           "serve.cpp"]
+SOURCES = ["api.cpp", "walks.hip", "noise.hip", "sgns.hip", "sgns_small.hip", "feedback.hip",
+           "bf16.hip", "fabc.hip", "serve.cpp"]
 
 ARCH = os.environ.get("FELOG_OFFLOAD_ARCH", "gfx950")
 

@@ -238,6 +238,17 @@ felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every)
     });
 }
 
+felog_status felog_ctx_set_sgns_path(felog_ctx* ctx, int32_t path, int32_t blocks)
+{
+    return guarded([&] {
+        NEED(ctx);
+        FELOG_REQUIRE(path == 0 || path == 1, "path must be 0 or 1");
+        FELOG_REQUIRE(blocks >= 0 && blocks <= 65536, "blocks out of range");
+        ctx->sgns_path = path;
+        ctx->sgns_blocks = blocks;
+    });
+}
+
 felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes)
 {
     return guarded([&] {

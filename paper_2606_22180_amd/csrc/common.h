@@ -80,6 +80,11 @@ struct Ctx {
     hipEvent_t pipe_ev[2 + 2 * kIdSets] = {};
     // third stream: walk chunks of a round beside the training of earlier ones
     hipStream_t walk_stream = nullptr;
+    // SGNS update path: 0 = the persistent small-minibatch update where it
+    // applies, 1 = per-minibatch launches always; workgroups of the persistent
+    // launch (0 = one per compute unit)
+    int32_t sgns_path = 0;
+    int32_t sgns_blocks = 0;
     void make_current() const;
     void sync() const;
     void ensure_aux();
@@ -186,6 +191,12 @@ struct Model {
     DevBuf loss_out;              // double [1]
     DevBuf row_totals;            // uint64 [3]: summed touched-list lengths (in, out) and
                                   // out rows touched once
+    // small-minibatch update scratch (sgns_small.hip): per launch, each
+    // minibatch's touch info, segments and counts; per minibatch, the
+    // out-touch entries, in-row deltas and context copies
+    int64_t sm_tmax = 0, sm_G = 0;
+    int32_t sm_dim = 0;
+    DevBuf sm_tinfo, sm_segs, sm_meta, sm_ent, sm_dinp, sm_ctxc;
     // shared-negative (BF16) minibatch scratch
     uint32_t bf_P = 0, bf_M = 0;
     DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0;
@@ -271,6 +282,12 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
                             int64_t end, float* cap_in, float* cap_out, felog_train_stats* stats);
 void bf16_refresh_all(Model& m);
+// The persistent small-minibatch FP32 update (P (K + 2) <= 8192 touches).
+bool small_path_applies(const Model& m, const felog_train_params& p);
+void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
+                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
+                             int64_t end, felog_train_stats* stats);
+void launch_loss_reduce(const double* part, int64_t n, double* out, hipStream_t s);
 void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
               double* psi_host, int64_t psi_cap);
 // Order-preserving compaction of nodes[i] where flags[i] != 0; returns the count.

@@ -1,0 +1,748 @@
+// Skip-gram with negative sampling for small minibatches (Train of
+// Algorithm 1; Eq. (1)-(2)): P (K + 2) <= 8192 touches per minibatch, the
+// shape of the 1,024-pair configurations.
+//
+// At that size a minibatch moves a few MB, so the per-minibatch launch chain
+// of sgns.hip (ids, two scan passes, forward, two apply launches) is bound by
+// launch and cache-flush latency, not by HBM.  Here the work splits in two:
+//
+//   plan    one workgroup per minibatch, many minibatches per launch.  It
+//           draws the minibatch's node ids (walk reads, noise draws), sorts
+//           its touches by (table, row, touch) with a bitonic network in LDS
+//           and lists the rows' segments.  Sorting by touch index within a
+//           row is pair order (pair, then slot), so no atomics and no
+//           per-row counters are needed.  Plans depend only on the walks and
+//           the noise table, never on the embeddings.
+//   update  one persistent cooperative launch for those minibatches.  Per
+//           minibatch: the forward (gathers, FP64 dots, sigma, coefficients;
+//           each out-touch's entry at its sorted position; each pair's
+//           context row copied; out rows touched once updated in place),
+//           a grid barrier, the apply (one 16-lane group per segment sums
+//           the row's terms and adds them once), and a grid barrier.  The
+//           apply reads the context copies, not the in-table, so in and out
+//           rows are applied together.
+//
+// The arithmetic is that of sgns.hip term for term: rows of at most kChunk
+// touches sum their FP64 terms sequentially in pair order, longer rows sum
+// terms rounded onto the exact-sum grid, every stored value is rounded once.
+// The two paths therefore give bit-identical tables.
+//
+// The grid barrier is a two-level counter (groups of kBarGroup workgroups,
+// then the groups) with a bounded wait: a wait that exceeds kSpinLimit polls
+// raises an abort flag that every workgroup checks at its next barrier, so
+// every wave leaves the kernel, and the host reports the failure.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "noise.h"
+#include "sgns_device.h"
+
+namespace felog {
+
+// Values of one minibatch that the plan and update launches read.
+struct MbDesc {
+    int64_t vcol_base;     // offset of the minibatch's chunk in valid_cols
+    uint32_t Wv;           // valid columns of the chunk
+    uint32_t first_pair;   // first pair of the minibatch in its chunk
+    uint32_t npairs;
+    float lr;
+    double grid_c;         // exact-sum grid constant of lr
+};
+static_assert(sizeof(MbDesc) == 32, "descriptor layout shared by host and device");
+
+constexpr int kPlanThreads = 512;
+constexpr int kPlanMaxTouches = 8192;   // touches a plan sorts in LDS (64 KB of keys)
+constexpr int32_t kPosMask = (1 << 30) - 1;
+constexpr int32_t kSingleBit = 1 << 30;  // out row touched once: the forward updates it
+constexpr int kBarGroup = 16;            // workgroups per first-level barrier counter
+constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a barrier wait gives up (seconds)
+constexpr int kUpdThreads = 256;
+
+// ------------------------------------------------------------------- plan
+struct PlanArgs {
+    const int32_t* walks;          // step-major [L][W]
+    int64_t W;
+    const int32_t* vcols;
+    const int32_t* slices;         // (j << 8) | slot
+    int64_t id_base;
+    int32_t window;
+    uint64_t seed;
+    NoiseTable noise;
+    const MbDesc* desc;            // [minibatches of the launch]
+    int32_t tmax;                  // touch slots per minibatch, P (K + 2)
+    int2* tinfo;                   // [mb][tmax]: (row, sorted position | kSingleBit), -1 skipped
+    int4* segs;                    // [mb][tmax]: (row, first position, touches, table)
+    uint32_t* meta;                // [mb][4]: applied segments, in segments, out rows,
+                                   // out rows touched once
+    unsigned long long* row_totals;// [3]: in rows, out rows, out rows touched once
+};
+
+// Exclusive scan of one value per thread over the workgroup; *total gets the sum.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32_t* total)
+{
+    constexpr int NW = kPlanThreads / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) tmp[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < NW; ++i) {
+            const uint32_t c = tmp[i];
+            tmp[i] = run;
+            run += c;
+        }
+        tmp[NW] = run;
+    }
+    __syncthreads();
+    const uint32_t excl = tmp[w] + x - v;
+    *total = tmp[NW];
+    __syncthreads();
+    return excl;
+}
+
+template <int K>
+__global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
+{
+    constexpr int T = K + 2;
+    __shared__ unsigned long long keys[kPlanMaxTouches];
+    __shared__ uint16_t seg_first[kPlanMaxTouches + 1];
+    __shared__ uint32_t tmp[kPlanThreads / 64 + 1];
+    __shared__ uint32_t counts[3];
+    const MbDesc d = a.desc[blockIdx.x];
+    const uint32_t nt = d.npairs * T;
+    uint32_t N = 64;
+    while (N < nt) N <<= 1;                 // nt <= kPlanMaxTouches (checked on the host)
+    int2* tinfo = a.tinfo + (int64_t)blockIdx.x * a.tmax;
+    int4* segs = a.segs + (int64_t)blockIdx.x * a.tmax;
+    const int32_t* vcols = a.vcols + d.vcol_base;
+    if (threadIdx.x < 3) counts[threadIdx.x] = 0;
+
+    // 1. each touch's row and sort key (table << 62 | row << 16 | touch)
+    for (uint32_t t = threadIdx.x; t < N; t += kPlanThreads) {
+        unsigned long long key = ~0ull;
+        if (t < nt) {
+            const uint32_t p = t / T, r = t - p * T;
+            const uint32_t gq = d.first_pair + p;
+            const uint32_t sidx = gq / d.Wv;
+            const uint32_t rank = gq - sidx * d.Wv;
+            const int32_t js = a.slices[sidx];
+            const int32_t col = vcols[rank];
+            const int32_t j = js >> 8, s = js & 255;
+            const int32_t ctr = a.walks[(int64_t)j * a.W + col];
+            int32_t row;
+            if (r == 0) {
+                const int32_t off = s < a.window ? s - a.window : s - a.window + 1;
+                row = a.walks[(int64_t)(j + off) * a.W + col];
+            } else if (r == 1) {
+                row = ctr;
+            } else {
+                // negative k = r - 2: Philox(walk id, (j << 8) | slot, NEG | k / 2), words
+                // 2 (k mod 2) and 2 (k mod 2) + 1
+                const uint32_t k = r - 2;
+                const int64_t wid = a.id_base + col;
+                const Rand4 x = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)js,
+                                           kTagNeg | (k >> 1), a.seed);
+                const uint32_t lo = (k & 1) ? x.v[2] : x.v[0];
+                const uint32_t hi = (k & 1) ? x.v[3] : x.v[1];
+                const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
+                row = neg != ctr ? neg : -1;   // a negative equal to the centre is skipped
+            }
+            if (row >= 0)
+                key = ((unsigned long long)(r != 0) << 62) | ((unsigned long long)row << 16) | t;
+            else
+                tinfo[t] = make_int2(-1, -1);
+        }
+        keys[t] = key;
+    }
+    __syncthreads();
+
+    // 2. bitonic sort, ascending
+    for (uint32_t k = 2; k <= N; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < N; i += kPlanThreads) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const unsigned long long x = keys[i], y = keys[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        keys[i] = y;
+                        keys[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+    // 3. segments: a position starts one where (table, row) changes; each
+    //    thread takes a contiguous run of positions
+    const uint32_t per = (N + kPlanThreads - 1) / kPlanThreads;
+    const uint32_t lo = min(N, threadIdx.x * per), hi = min(N, lo + per);
+    uint32_t nstart = 0, nvalid = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const unsigned long long x = keys[i];
+        if (x == ~0ull) continue;
+        ++nvalid;
+        if (i == 0 || (keys[i - 1] >> 16) != (x >> 16)) ++nstart;
+    }
+    uint32_t nseg, nv;
+    uint32_t s = block_scan(nstart, tmp, &nseg);
+    block_scan(nvalid, tmp, &nv);
+    for (uint32_t i = lo; i < hi; ++i) {
+        const unsigned long long x = keys[i];
+        if (x != ~0ull && (i == 0 || (keys[i - 1] >> 16) != (x >> 16))) seg_first[s++] = (uint16_t)i;
+    }
+    if (threadIdx.x == 0) seg_first[nseg] = (uint16_t)nv;
+    __syncthreads();
+
+    // 4. per segment: length; in segments and out segments of two or more
+    //    touches go to the apply list (in segments first: they sort first);
+    //    every touch's sorted position
+    const uint32_t sper = (nseg + kPlanThreads - 1) / kPlanThreads;
+    const uint32_t s_lo = min(nseg, threadIdx.x * sper), s_hi = min(nseg, s_lo + sper);
+    uint32_t napply = 0, nin = 0, nsingle = 0;
+    for (uint32_t q = s_lo; q < s_hi; ++q) {
+        const uint32_t f = seg_first[q], len = seg_first[q + 1] - f;
+        const bool out = (keys[f] >> 62) != 0;
+        napply += (!out || len > 1) ? 1u : 0u;
+        nin += out ? 0u : 1u;
+        nsingle += (out && len == 1) ? 1u : 0u;
+    }
+    uint32_t n_apply;
+    uint32_t slot = block_scan(napply, tmp, &n_apply);
+    atomicAdd(&counts[0], nin);
+    atomicAdd(&counts[1], nsingle);
+    for (uint32_t q = s_lo; q < s_hi; ++q) {
+        const uint32_t f = seg_first[q], len = seg_first[q + 1] - f;
+        const unsigned long long x = keys[f];
+        const int32_t out = (int32_t)(x >> 62);
+        const int32_t row = (int32_t)((x >> 16) & 0x7FFFFFFFull);
+        const bool single = out && len == 1;
+        if (!single) segs[slot++] = make_int4(row, (int32_t)f, (int32_t)len, out);
+        for (uint32_t i = f; i < f + len; ++i)
+            tinfo[keys[i] & 0xFFFF] = make_int2(row, (int32_t)i | (single ? kSingleBit : 0));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t* m = a.meta + (int64_t)blockIdx.x * 4;
+        m[0] = n_apply;
+        m[1] = counts[0];
+        m[2] = nseg - counts[0];
+        m[3] = counts[1];
+        atomicAdd(&a.row_totals[0], (unsigned long long)counts[0]);
+        atomicAdd(&a.row_totals[1], (unsigned long long)(nseg - counts[0]));
+        atomicAdd(&a.row_totals[2], (unsigned long long)counts[1]);
+    }
+}
+
+// ----------------------------------------------------------------- update
+struct UpdArgs {
+    float* tin;
+    float* tout;
+    const MbDesc* desc;            // [nmb]
+    const int2* tinfo;             // [nmb][tmax]
+    const int4* segs;              // [nmb][tmax]
+    const uint32_t* meta;          // [nmb][4]
+    int32_t tmax;
+    int32_t nmb;
+    int4* ent;                     // [tmax]: (FP64 g, pair) of each out-touch, by sorted position
+    float* dinp;                   // [P][D]: each pair's in-row delta, by sorted position
+    float* ctxc;                   // [P][D]: each pair's context row at the minibatch start
+    double* loss_part;             // [waves]
+    uint32_t* bar;                 // [1 + groups]: barrier counters, zero at the call's start
+    uint32_t epoch0;               // barriers passed by earlier launches of the call
+    int32_t* abort;
+};
+
+// Grid barrier with release/acquire at agent scope.  Returns false when the
+// launch is aborting (a wait exceeded its bound somewhere).
+__device__ __forceinline__ bool grid_sync(const UpdArgs& a, uint32_t& epoch)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    ++epoch;
+    if (threadIdx.x == 0) {
+        const uint32_t nb = gridDim.x;
+        const uint32_t grp = blockIdx.x / kBarGroup;
+        const uint32_t ngrp = (nb + kBarGroup - 1) / kBarGroup;
+        const uint32_t gsize = min((uint32_t)kBarGroup, nb - grp * kBarGroup);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t old = __hip_atomic_fetch_add(&a.bar[1 + grp], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == epoch * gsize)   // the group's last arrival carries it up
+            __hip_atomic_fetch_add(&a.bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        uint32_t polls = 0;
+        while (__hip_atomic_load(&a.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               epoch * ngrp) {
+            if (++polls > kSpinLimit) {
+                __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            if ((polls & 255) == 0 &&
+                __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs a)
+{
+    constexpr int LPP = fwd_lanes_per_pair<D, K>();   // lanes per pair in the forward
+    constexpr int G = 64 / LPP;                         // pairs in flight per wave
+    constexpr int V4 = D / (4 * LPP);                   // float4s per lane and row
+    constexpr int T = K + 2;
+    constexpr int AV4 = D / 64;                         // float4s per lane and row (apply)
+    constexpr int kRows = 4;                            // rows in flight per apply group
+    const int lane = threadIdx.x & 63;
+    const int grp = lane / LPP, gl = lane % LPP;
+    const int g16 = lane >> 4, l16 = lane & 15;
+    const uint32_t nw = gridDim.x * (blockDim.x >> 6);
+    const uint32_t gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    uint32_t epoch = a.epoch0;
+    double lacc = 0.0;
+
+    for (int m = 0; m < a.nmb; ++m) {
+        const MbDesc dsc = a.desc[m];
+        const int2* ti = a.tinfo + (int64_t)m * a.tmax;
+        const uint32_t np = dsc.npairs;
+        const double lr = (double)dsc.lr;
+
+        // ---- forward: G pairs per wave at a time
+        for (uint32_t q0 = gw * G; q0 < np; q0 += nw * G) {
+            const int npw = (int)min((uint32_t)G, np - q0);
+            int32_t m_row = -1, m_code = -1;
+            if (lane < npw * T) {
+                const int2 x = ti[(int64_t)q0 * T + lane];
+                m_row = x.x;
+                m_code = x.y;
+            }
+            const unsigned long long single = __ballot(m_code >= 0 && (m_code & kSingleBit));
+            const int p = grp;
+            const bool live = p < npw;
+            const uint32_t q = q0 + (uint32_t)p;
+            const int src = (live ? p : 0) * T;
+            const int32_t ctx = __shfl(m_row, src);
+            const int32_t pos_in = __shfl(m_code, src) & kPosMask;
+            int32_t t[K + 1];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) t[k] = __shfl(m_row, src + 1 + k);
+            const int32_t my_code = __shfl(m_code, src + 1 + (gl <= K ? gl : 0));
+            int32_t my_code_hi = 0;
+            if (LPP == 16 && K >= 16) my_code_hi = __shfl(m_code, src + 1 + (gl + 16 <= K ? gl + 16 : 0));
+
+            float4 vin[V4];
+            float4 vo[K + 1][V4];
+            const float4* ri = reinterpret_cast<const float4*>(a.tin + (int64_t)(live ? ctx : 0) * D);
+#pragma unroll
+            for (int i = 0; i < V4; ++i) vin[i] = ri[i * LPP + gl];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
+                const bool ok = live && t[k] >= 0;
+                const float4* ro = reinterpret_cast<const float4*>(a.tout + (int64_t)(ok ? t[k] : 0) * D);
+#pragma unroll
+                for (int i = 0; i < V4; ++i)
+                    vo[k][i] = ok ? ro[i * LPP + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+            double g[K + 1];
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < V4; ++i) acc = dot4d(vin[i], vo[k][i], acc);
+                const double dk = group_sum_d<LPP>(acc);
+                const bool ok = k == 0 || t[k] >= 0;
+                g[k] = k == 0 ? lr * (1.0 - sigmoid_d(dk)) : (ok ? -lr * sigmoid_d(dk) : 0.0);
+                if (live && ok && gl == k % LPP)
+                    lacc += (double)neg_log_sigmoid((float)(k == 0 ? dk : -dk));
+            }
+            // entries of the out-touches (not the rows touched once)
+#pragma unroll
+            for (int h = 0; h < (K + LPP) / LPP; ++h) {
+                const int k = gl + h * LPP;
+                double gk = g[0];
+                int32_t tk = t[0];
+#pragma unroll
+                for (int jj = 1; jj <= K; ++jj)
+                    if (k == jj) {
+                        gk = g[jj];
+                        tk = t[jj];
+                    }
+                if (k <= K && live && tk >= 0 && !((single >> (src + 1 + k)) & 1ull)) {
+                    const int32_t code = h == 0 ? my_code : my_code_hi;
+                    a.ent[code & kPosMask] = pack_entry(gk, (int32_t)q, 0u);
+                }
+            }
+            // out rows touched once: row + g in[ctx] in FP64, rounded once
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
+                if (live && t[k] >= 0 && ((single >> (src + 1 + k)) & 1ull)) {
+                    float4* dst = reinterpret_cast<float4*>(a.tout + (int64_t)t[k] * D);
+#pragma unroll
+                    for (int i = 0; i < V4; ++i) {
+                        const float4 b = vo[k][i];
+                        dst[i * LPP + gl] = make_float4((float)fma(g[k], (double)vin[i].x, (double)b.x),
+                                                        (float)fma(g[k], (double)vin[i].y, (double)b.y),
+                                                        (float)fma(g[k], (double)vin[i].z, (double)b.z),
+                                                        (float)fma(g[k], (double)vin[i].w, (double)b.w));
+                    }
+                }
+            }
+            if (live) {
+                float4* cc = reinterpret_cast<float4*>(a.ctxc + (int64_t)q * D);
+                float4* dp = reinterpret_cast<float4*>(a.dinp + (int64_t)pos_in * D);
+#pragma unroll
+                for (int i = 0; i < V4; ++i) {
+                    cc[i * LPP + gl] = vin[i];
+                    double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
+#pragma unroll
+                    for (int k = 0; k <= K; ++k) {
+                        ax = fma(g[k], (double)vo[k][i].x, ax);
+                        ay = fma(g[k], (double)vo[k][i].y, ay);
+                        az = fma(g[k], (double)vo[k][i].z, az);
+                        aw = fma(g[k], (double)vo[k][i].w, aw);
+                    }
+                    dp[i * LPP + gl] = make_float4((float)ax, (float)ay, (float)az, (float)aw);
+                }
+            }
+        }
+        if (!grid_sync(a, epoch)) break;
+
+        // ---- apply: one 16-lane group per segment, in and out rows together
+        const uint32_t* mt = a.meta + (int64_t)m * 4;
+        const uint32_t nseg = mt[0], nin = mt[1];
+        const int4* sg = a.segs + (int64_t)m * a.tmax;
+        const double gc = dsc.grid_c;
+        for (uint32_t sidx = gw * 4 + (uint32_t)g16; sidx < nseg; sidx += nw * 4) {
+            const int4 sd = sg[sidx];
+            const bool out = sidx >= nin;
+            const int32_t row = sd.x, start = sd.y, len = sd.z;
+            float* table = out ? a.tout : a.tin;
+            const float* srcb = out ? a.ctxc : a.dinp;
+            float4 cur[AV4];
+            const float4* r4 = reinterpret_cast<const float4*>(table + (int64_t)row * D);
+#pragma unroll
+            for (int i = 0; i < AV4; ++i) cur[i] = r4[i * 16 + l16];
+            double acc[D / 16];
+#pragma unroll
+            for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
+            const bool exact = len > kChunk;
+            // touches in batches of 16, one descriptor per lane
+            for (int32_t b0 = 0; b0 < len; b0 += 16) {
+                const int32_t nb = min(16, len - b0);
+                double my_g = 1.0;
+                int32_t my_src = start + b0 + l16;
+                if (out && l16 < nb) {
+                    const int4 e = a.ent[start + b0 + l16];
+                    my_g = entry_g(e);
+                    my_src = e.z;
+                }
+                for (int32_t i0 = 0; i0 < nb; i0 += kRows) {
+                    double gg[kRows];
+                    float4 x[kRows][AV4];
+#pragma unroll
+                    for (int u = 0; u < kRows; ++u) {
+                        const bool ok = i0 + u < nb;
+                        const int32_t idx = min(i0 + u, 15);
+                        gg[u] = __shfl(my_g, (g16 << 4) + idx);
+                        const int32_t rr = __shfl(my_src, (g16 << 4) + idx);
+                        const float4* rp = reinterpret_cast<const float4*>(srcb + (int64_t)(ok ? rr : 0) * D);
+#pragma unroll
+                        for (int i = 0; i < AV4; ++i)
+                            x[u][i] = ok ? rp[i * 16 + l16] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        if (!ok) gg[u] = 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kRows; ++u) {
+                        if (i0 + u >= nb) break;
+#pragma unroll
+                        for (int i = 0; i < AV4; ++i) {
+                            if (exact) {
+                                // order-free: each term rounded onto the grid, sums exact
+                                acc[4 * i + 0] += on_grid(gg[u] * (double)x[u][i].x, gc);
+                                acc[4 * i + 1] += on_grid(gg[u] * (double)x[u][i].y, gc);
+                                acc[4 * i + 2] += on_grid(gg[u] * (double)x[u][i].z, gc);
+                                acc[4 * i + 3] += on_grid(gg[u] * (double)x[u][i].w, gc);
+                            } else {
+                                // in rows: g = 1, and 1 * x + acc is exactly x + acc
+                                acc[4 * i + 0] = fma(gg[u], (double)x[u][i].x, acc[4 * i + 0]);
+                                acc[4 * i + 1] = fma(gg[u], (double)x[u][i].y, acc[4 * i + 1]);
+                                acc[4 * i + 2] = fma(gg[u], (double)x[u][i].z, acc[4 * i + 2]);
+                                acc[4 * i + 3] = fma(gg[u], (double)x[u][i].w, acc[4 * i + 3]);
+                            }
+                        }
+                    }
+                }
+            }
+            float4* d4 = reinterpret_cast<float4*>(table + (int64_t)row * D);
+#pragma unroll
+            for (int i = 0; i < AV4; ++i) {
+                const float4 c = cur[i];
+                d4[i * 16 + l16] = make_float4((float)((double)c.x + acc[4 * i + 0]),
+                                               (float)((double)c.y + acc[4 * i + 1]),
+                                               (float)((double)c.z + acc[4 * i + 2]),
+                                               (float)((double)c.w + acc[4 * i + 3]));
+            }
+        }
+        if (!grid_sync(a, epoch)) break;
+    }
+    lacc = wave_sum_f64(lacc);
+    if (lane == 0) a.loss_part[gw] += lacc;
+}
+
+__global__ void zero_words_kernel(uint32_t* p, int32_t n)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+bool small_path_applies(const Model& m, const felog_train_params& p)
+{
+    return m.precision == FELOG_PREC_FP32 && m.ctx->sgns_path == 0 &&
+           p.minibatch_pairs * (p.negatives + 2) <= kPlanMaxTouches && p.negatives <= 20;
+}
+
+static int64_t small_minibatches_per_launch(int64_t P) { return P >= 512 ? 256 : 512; }
+
+template <int D, int K>
+static void* update_kernel_ptr()
+{
+    return reinterpret_cast<void*>(&sgns_small_update_kernel<D, K>);
+}
+
+template <int D>
+static void* update_kernel_d(int K)
+{
+    switch (K) {
+#define FELOG_CASE(k) \
+    case k: return update_kernel_ptr<D, k>();
+        FELOG_CASE(1) FELOG_CASE(2) FELOG_CASE(3) FELOG_CASE(4) FELOG_CASE(5) FELOG_CASE(6)
+        FELOG_CASE(7) FELOG_CASE(8) FELOG_CASE(9) FELOG_CASE(10) FELOG_CASE(11) FELOG_CASE(12)
+        FELOG_CASE(13) FELOG_CASE(14) FELOG_CASE(15) FELOG_CASE(16) FELOG_CASE(17)
+        FELOG_CASE(18) FELOG_CASE(19) FELOG_CASE(20)
+#undef FELOG_CASE
+        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", K);
+    }
+}
+
+static void* update_kernel(int D, int K)
+{
+    if (D == 64) return update_kernel_d<64>(K);
+    if (D == 128) return update_kernel_d<128>(K);
+    return update_kernel_d<256>(K);
+}
+
+static void launch_plan(int K, int nmb, const PlanArgs& pa, hipStream_t s)
+{
+    switch (K) {
+#define FELOG_CASE(k)                                                                      \
+    case k:                                                                                \
+        hipLaunchKernelGGL((sgns_plan_kernel<k>), dim3(nmb), dim3(kPlanThreads), 0, s, pa); \
+        break;
+        FELOG_CASE(1) FELOG_CASE(2) FELOG_CASE(3) FELOG_CASE(4) FELOG_CASE(5) FELOG_CASE(6)
+        FELOG_CASE(7) FELOG_CASE(8) FELOG_CASE(9) FELOG_CASE(10) FELOG_CASE(11) FELOG_CASE(12)
+        FELOG_CASE(13) FELOG_CASE(14) FELOG_CASE(15) FELOG_CASE(16) FELOG_CASE(17)
+        FELOG_CASE(18) FELOG_CASE(19) FELOG_CASE(20)
+#undef FELOG_CASE
+        default: fail(FELOG_EUNSUPPORTED, "negatives = %d not supported", K);
+    }
+    FELOG_HIP(hipGetLastError());
+}
+
+void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
+                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
+                             int64_t end, felog_train_stats* stats)
+{
+    Ctx& c = *m.ctx;
+    const int K = p.negatives;
+    const int D = m.dim;
+    const int64_t P = p.minibatch_pairs;
+    const int32_t tmax = (int32_t)(P * (K + 2));
+    FELOG_REQUIRE(tmax <= kPlanMaxTouches, "minibatch of %lld pairs is too large for the "
+                  "small-minibatch update", (long long)P);
+    FELOG_REQUIRE(D == 64 || D == 128 || D == 256, "dim %d not supported", D);
+    const int64_t G = small_minibatches_per_launch(P);
+    void* kern = update_kernel(D, K);
+
+    // workgroups of the persistent launch: all co-resident (cooperative)
+    int per_cu = 0;
+    FELOG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kUpdThreads, 0));
+    FELOG_REQUIRE(per_cu >= 1, "the update kernel does not fit a compute unit");
+    const int64_t max_blocks = (int64_t)per_cu * c.num_cus;
+    const int64_t want = c.sgns_blocks > 0 ? c.sgns_blocks : c.num_cus;
+    const int nblocks = (int)std::max<int64_t>(1, std::min(want, max_blocks));
+    const int nwaves = nblocks * (kUpdThreads / 64);
+    const int ngroups = (nblocks + kBarGroup - 1) / kBarGroup;
+
+    // buffers (model-owned, grown on demand)
+    if (m.sm_tmax < tmax || m.sm_G < G) {
+        m.sm_tmax = std::max<int64_t>(m.sm_tmax, tmax);
+        m.sm_G = std::max<int64_t>(m.sm_G, G);
+        m.sm_tinfo.alloc(&c, sizeof(int2) * m.sm_tmax * m.sm_G);
+        m.sm_segs.alloc(&c, sizeof(int4) * m.sm_tmax * m.sm_G);
+        m.sm_meta.alloc(&c, sizeof(uint32_t) * 4 * m.sm_G);
+        m.sm_ent.alloc(&c, sizeof(int4) * m.sm_tmax);
+        m.sm_dinp.alloc(&c, sizeof(float) * m.sm_tmax * D);   // P rows suffice; tmax >= P
+        m.sm_ctxc.alloc(&c, sizeof(float) * m.sm_tmax * D);
+    }
+    if (m.sm_dim != D) {
+        m.sm_dinp.alloc(&c, sizeof(float) * m.sm_tmax * D);
+        m.sm_ctxc.alloc(&c, sizeof(float) * m.sm_tmax * D);
+        m.sm_dim = D;
+    }
+    DevBuf ctl;   // barrier counters [1 + groups], abort flag, loss partials [waves]
+    const int64_t ctl_words = 2 + ngroups + 1;
+    ctl.alloc(&c, sizeof(uint32_t) * ctl_words + sizeof(double) * nwaves + 16);
+    uint32_t* bar = ctl.as<uint32_t>();
+    int32_t* abort = reinterpret_cast<int32_t*>(bar + 1 + ngroups);
+    double* loss_part = reinterpret_cast<double*>(
+        reinterpret_cast<char*>(ctl.ptr) + ((sizeof(uint32_t) * ctl_words + 15) / 16) * 16);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, c.stream, bar,
+                       (int32_t)(ctl.bytes / sizeof(uint32_t)));
+    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
+
+    PlanArgs pa{};
+    pa.walks = w.data.as<int32_t>();
+    pa.W = w.W;
+    pa.vcols = w.valid_cols.as<int32_t>();
+    pa.slices = d_slices;
+    pa.id_base = w.id_base;
+    pa.window = p.window;
+    pa.seed = p.seed;
+    pa.noise = NoiseTable{m.cdf.as<uint64_t>(), m.guide.as<int32_t>(), m.total_weight,
+                          m.guide_bits};
+    pa.tmax = tmax;
+    pa.tinfo = m.sm_tinfo.as<int2>();
+    pa.segs = m.sm_segs.as<int4>();
+    pa.meta = m.sm_meta.as<uint32_t>();
+    pa.row_totals = m.row_totals.as<unsigned long long>();
+
+    // every minibatch's descriptor, uploaded once for the call
+    const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
+    std::vector<MbDesc> desc((size_t)std::max<int64_t>(1, end - first_mb));
+    std::vector<size_t> last_chunk;   // chunk of the last minibatch of each launch
+    int64_t pairs = 0;
+    {
+        size_t chunk = 0;
+        for (int64_t b = first_mb; b < end; ++b) {
+            while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b)
+                ++chunk;
+            const int64_t first = (b - sch.chunk_first_mb[chunk]) * P;
+            const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
+            MbDesc& d = desc[(size_t)(b - first_mb)];
+            d.vcol_base = sch.chunk_valid_base[chunk];
+            d.Wv = (uint32_t)w.chunk_valid[chunk];
+            d.first_pair = (uint32_t)first;
+            d.npairs = (uint32_t)np;
+            const double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
+            d.lr = (float)lr;
+            d.grid_c = d.lr > 0.0f ? std::ldexp(1.5, std::ilogb(d.lr) + 17) : 1.5;
+            pairs += np;
+            if ((b - first_mb) % G == G - 1 || b == end - 1) last_chunk.push_back(chunk);
+        }
+    }
+    DevBuf ddesc;
+    ddesc.alloc(&c, sizeof(MbDesc) * desc.size());
+    FELOG_HIP(hipMemcpyAsync(ddesc.ptr, desc.data(), sizeof(MbDesc) * desc.size(),
+                             hipMemcpyHostToDevice, c.stream));
+
+    UpdArgs ua{};
+    ua.tin = m.tin.as<float>();
+    ua.tout = m.tout.as<float>();
+    ua.tinfo = pa.tinfo;
+    ua.segs = pa.segs;
+    ua.meta = pa.meta;
+    ua.tmax = tmax;
+    ua.ent = m.sm_ent.as<int4>();
+    ua.dinp = m.sm_dinp.as<float>();
+    ua.ctxc = m.sm_ctxc.as<float>();
+    ua.loss_part = loss_part;
+    ua.bar = bar;
+    ua.abort = abort;
+
+    size_t gated = 0;
+    const bool timing = c.timing_every > 0;
+    double ms_plan = 0.0, ms_update = 0.0;
+    int64_t timed = 0, timed_mb = 0;
+    uint32_t epoch = 0;
+    FELOG_HIP(hipEventRecord(c.ev0, c.stream));
+    for (int64_t g0 = first_mb, li = 0; g0 < end; g0 += G, ++li) {
+        const int64_t g1 = std::min(end, g0 + G);
+        const int nmb = (int)(g1 - g0);
+        // the walks of the launch's chunks must be written
+        while (gated <= last_chunk[(size_t)li] && gated < w.chunk_ready.size())
+            FELOG_HIP(hipStreamWaitEvent(c.stream, w.chunk_ready[gated++], 0));
+        pa.desc = ddesc.as<MbDesc>() + (g0 - first_mb);
+        ua.desc = pa.desc;
+        hipEvent_t* e = nullptr;
+        if (timing && !c.timing_pool.empty()) e = &c.timing_pool[0];
+        if (e) FELOG_HIP(hipEventRecord(e[0], c.stream));
+        launch_plan(K, nmb, pa, c.stream);
+        if (e) FELOG_HIP(hipEventRecord(e[1], c.stream));
+        ua.nmb = nmb;
+        ua.epoch0 = epoch;
+        void* args[] = {&ua};
+        FELOG_HIP(hipLaunchCooperativeKernel(kern, dim3(nblocks), dim3(kUpdThreads), args, 0,
+                                             c.stream));
+        epoch += 2u * (uint32_t)nmb;
+        if (e) {
+            FELOG_HIP(hipEventRecord(e[2], c.stream));
+            FELOG_HIP(hipEventSynchronize(e[2]));
+            float a0 = 0.0f, a1 = 0.0f;
+            FELOG_HIP(hipEventElapsedTime(&a0, e[0], e[1]));
+            FELOG_HIP(hipEventElapsedTime(&a1, e[1], e[2]));
+            ms_plan += a0;
+            ms_update += a1;
+            ++timed;
+            timed_mb += nmb;
+        }
+    }
+    launch_loss_reduce(loss_part, nwaves, m.loss_out.as<double>(), c.stream);
+    FELOG_HIP(hipEventRecord(c.ev1, c.stream));
+    double loss = 0.0;
+    unsigned long long rows[3] = {0, 0, 0};
+    int32_t aborted = 0;
+    FELOG_HIP(hipMemcpyAsync(&loss, m.loss_out.ptr, sizeof loss, hipMemcpyDeviceToHost, c.stream));
+    FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost, c.stream));
+    FELOG_HIP(hipMemcpyAsync(&aborted, abort, sizeof aborted, hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+    FELOG_REQUIRE(!aborted, "small-minibatch update: a grid barrier wait exceeded its bound");
+    float ms = 0.0f;
+    FELOG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    if (stats) {
+        *stats = felog_train_stats{};
+        stats->minibatches = end - first_mb;
+        stats->pairs = pairs;
+        stats->minibatches_total = sch.B;
+        stats->loss = loss;
+        stats->ms = ms;
+        stats->rows_in = (int64_t)rows[0];
+        stats->rows_out = (int64_t)rows[1];
+        stats->rows_out_single = (int64_t)rows[2];
+        stats->path = 1;
+        stats->timed_launches = timed;
+        stats->timed_minibatches = timed_mb;
+        stats->ms_prep = ms_plan;
+        stats->ms_update = ms_update;
+        stats->update_blocks = nblocks;
+    }
+}
+
+}  // namespace felog

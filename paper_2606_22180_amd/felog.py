@@ -63,7 +63,9 @@ class felog_train_stats(C.Structure):
                 ("rows_in", C.c_int64), ("rows_out", C.c_int64),
                 ("timed_launches", C.c_int64), ("ms_forward", C.c_double),
                 ("ms_apply", C.c_double), ("ms_prep", C.c_double),
-                ("ms_apply_first", C.c_double), ("rows_out_single", C.c_int64)]
+                ("ms_apply_first", C.c_double), ("rows_out_single", C.c_int64),
+                ("path", C.c_int32), ("update_blocks", C.c_int32),
+                ("timed_minibatches", C.c_int64), ("ms_update", C.c_double)]
 
 
 class felog_feedback_params(C.Structure):
@@ -119,6 +121,7 @@ SIGNATURES = {
     "felog_ctx_destroy": (None, [_p]),
     "felog_ctx_bytes_in_use": (_i32, [_p, C.POINTER(_u64)]),
     "felog_ctx_set_timing": (_i32, [_p, _i32]),
+    "felog_ctx_set_sgns_path": (_i32, [_p, _i32, _i32]),
     "felog_last_error": (C.c_char_p, []),
     "felog_graph_load_csr": (_i32, [_p, _i32, _i64, _p, _p, _p, _pp]),
     "felog_graph_destroy": (None, [_p]),
@@ -223,6 +226,11 @@ class Context:
 
     def set_timing(self, every: int):
         _check(load().felog_ctx_set_timing(self.handle, every))
+
+    def set_sgns_path(self, path: int, blocks: int = 0):
+        """0: persistent small-minibatch update where it applies; 1: per-minibatch
+        launches always.  blocks: workgroups of the persistent launch (0 = one per CU)."""
+        _check(load().felog_ctx_set_sgns_path(self.handle, path, blocks))
 
     def bytes_in_use(self) -> int:
         b = C.c_uint64()
