@@ -194,7 +194,7 @@ struct Model {
     // small-minibatch update scratch (sgns_small.hip): per launch, each
     // minibatch's touch info, segments and counts; per minibatch, the
     // out-touch entries, in-row deltas and context copies
-    int64_t sm_tmax = 0, sm_G = 0;
+    int64_t sm_tmax = 0, sm_G = 0, sm_pairs = 0;
     int32_t sm_dim = 0;
     DevBuf sm_tinfo, sm_segs, sm_meta, sm_ent, sm_dinp, sm_ctxc;
     // shared-negative (BF16) minibatch scratch
@@ -288,6 +288,8 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
                              const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
                              int64_t end, felog_train_stats* stats);
 void launch_loss_reduce(const double* part, int64_t n, double* out, hipStream_t s);
+int64_t small_minibatches_per_launch();
+uint64_t small_path_bytes(int64_t P, int K, int d, int64_t B, int num_cus);
 void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
               double* psi_host, int64_t psi_cap);
 // Order-preserving compaction of nodes[i] where flags[i] != 0; returns the count.

@@ -111,6 +111,11 @@ static void run_job(Server& s, Job& job)
     hipDeviceProp_t prop;
     FELOG_HIP(hipGetDeviceProperties(&prop, s.device));
     ctx.num_cus = prop.multiProcessorCount;
+    // Jobs run side by side on their own streams.  Two persistent cooperative
+    // launches that are each only partly resident would wait for each other
+    // (until their bounded barrier waits gave up), so jobs take the
+    // per-minibatch launches.
+    ctx.sgns_path = 1;
     FELOG_HIP(hipEventCreate(&ctx.ev0));
     FELOG_HIP(hipEventCreate(&ctx.ev1));
     struct StreamGuard {
