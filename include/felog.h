@@ -407,6 +407,29 @@ felog_status felog_feedback(felog_model* m, const felog_feedback_params* params,
                             const felog_active* in, felog_active** out, double* psi_host,
                             int64_t psi_cap);
 
+/* The feedback step with no device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same scores and decisions as
+ * felog_feedback.  All buffers are the caller's device memory:
+ *   in_nodes_dev   int32 [count], strictly increasing node ids (checked), the
+ *                  scored list of the MONOTONE mode; NULL = all nodes (count
+ *                  must then be n).  RECOMPUTE_ALL ignores it and scores all n.
+ *   out_nodes_dev  int32 [out_cap]: the kept nodes {v : Psi(v) < mu}, in list
+ *                  order; out_cap >= the number of scored nodes.
+ *   psi_dev        double [psi_cap]: Psi of every scored node, in list order
+ *                  (NaN for nodes without neighbours); psi_cap >= scored.
+ *   *out_count     (host) number of kept nodes.
+ * At most 2^24 nodes are scored per call (FELOG_EINVAL beyond).  The only
+ * scratch is a fixed array of about 33 KB that each device holds from its
+ * first context until the process ends; calls that overlap on one device
+ * share it and race, so they must be serialised (one stream, or one call at
+ * a time).  Work runs on the model's context stream; the call returns after
+ * it completes. */
+felog_status felog_feedback_noalloc(felog_model* m, const felog_feedback_params* params,
+                                    const int32_t* in_nodes_dev, int64_t count,
+                                    int32_t* out_nodes_dev, int64_t out_cap, double* psi_dev,
+                                    int64_t psi_cap, int64_t* out_count);
+
 /* ------------------------------------------------------------------------- */
 /* Algorithm 1 end to end                                                      */
 /* ------------------------------------------------------------------------- */

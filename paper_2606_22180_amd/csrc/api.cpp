@@ -202,6 +202,7 @@ felog_status felog_ctx_create(int device, void* hip_stream, uint64_t hbm_budget_
         c->stream = static_cast<hipStream_t>(hip_stream);
         c->budget = hbm_budget_bytes;
         c->num_cus = prop.multiProcessorCount;
+        noalloc_scratch_init(device);
         FELOG_HIP(hipEventCreate(&c->ev0));
         FELOG_HIP(hipEventCreate(&c->ev1));
         *out = c.release();
@@ -999,6 +1000,24 @@ felog_status felog_feedback(felog_model* m, const felog_feedback_params* params,
         const Active* src = params->mode == FELOG_FEEDBACK_RECOMPUTE_ALL ? nullptr : in;
         feedback(*m, *params, src, *a, psi_host, psi_cap);
         *out = a.release();
+    });
+}
+
+felog_status felog_feedback_noalloc(felog_model* m, const felog_feedback_params* params,
+                                    const int32_t* in_nodes_dev, int64_t count,
+                                    int32_t* out_nodes_dev, int64_t out_cap, double* psi_dev,
+                                    int64_t psi_cap, int64_t* out_count)
+{
+    return guarded([&] {
+        NEED(m);
+        NEED(out_count);
+        *out_count = 0;
+        check_feedback_params(params);
+        FELOG_REQUIRE(count >= 0, "count must be >= 0");
+        FELOG_REQUIRE(in_nodes_dev || params->mode == FELOG_FEEDBACK_RECOMPUTE_ALL ||
+                      count == m->g->n, "in_nodes_dev NULL means all nodes: count must be n");
+        feedback_noalloc(*m, *params, in_nodes_dev, count, out_nodes_dev, out_cap, psi_dev,
+                         psi_cap, out_count);
     });
 }
 

@@ -292,6 +292,14 @@ int64_t small_minibatches_per_launch();
 uint64_t small_path_bytes(int64_t P, int K, int d, int64_t B, int num_cus);
 void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
               double* psi_host, int64_t psi_cap);
+// The feedback step with no device allocation: Psi into the caller's psi[],
+// the kept ids into out_nodes[]; scratch is a fixed per-device array whose
+// address noalloc_scratch_init (called once per device, from context
+// creation) looks up.
+void noalloc_scratch_init(int device);
+void feedback_noalloc(Model& m, const felog_feedback_params& p, const int32_t* in_nodes,
+                      int64_t count, int32_t* out_nodes, int64_t out_cap, double* psi,
+                      int64_t psi_cap, int64_t* out_count);
 // Order-preserving compaction of nodes[i] where flags[i] != 0; returns the count.
 int64_t compact_nodes(Ctx& ctx, const int32_t* d_nodes, const uint8_t* d_flags, int64_t count,
                       DevBuf& out);

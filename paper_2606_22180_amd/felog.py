@@ -167,6 +167,8 @@ SIGNATURES = {
                                  _p, _p, _i64, C.POINTER(_i64), _p, _p, _i64, C.POINTER(_i64),
                                  C.POINTER(_f64)]),
     "felog_feedback": (_i32, [_p, C.POINTER(felog_feedback_params), _p, _pp, _p, _i64]),
+    "felog_feedback_noalloc": (_i32, [_p, C.POINTER(felog_feedback_params), _p, _i64, _p, _i64,
+                                      _p, _i64, C.POINTER(_i64)]),
     "felog_run": (_i32, [_p, C.POINTER(felog_run_params), C.POINTER(felog_run_stats)]),
     "felog_server_create": (_i32, [C.c_int, _u64, C.POINTER(felog_server_params), _pp]),
     "felog_server_submit": (_i32, [_p, C.POINTER(felog_job_desc), C.POINTER(_u64)]),
@@ -535,6 +537,18 @@ class Model(_Handle):
                                      psi.shape[0] if want_psi else 0))
         nxt = Active(h, self._owner)
         return (nxt, psi[:n_scored]) if want_psi else nxt
+
+    def feedback_noalloc(self, *, mu: float, k_s: int, seed: int, round: int,
+                         in_nodes_dev: int | None, count: int, out_nodes_dev: int, out_cap: int,
+                         psi_dev: int, psi_cap: int, mode: int = FEEDBACK_MONOTONE) -> int:
+        """felog_feedback_noalloc on caller-owned device buffers (raw device
+        addresses); returns the number of kept nodes."""
+        prm = felog_feedback_params(mu, k_s, mode, seed, round)
+        n = C.c_int64()
+        _check(load().felog_feedback_noalloc(self.handle, C.byref(prm), in_nodes_dev, count,
+                                             out_nodes_dev, out_cap, psi_dev, psi_cap,
+                                             C.byref(n)))
+        return n.value
 
     def run(self, prm: felog_run_params) -> felog_run_stats:
         st = felog_run_stats()
