@@ -192,11 +192,11 @@ struct Model {
     DevBuf row_totals;            // uint64 [3]: summed touched-list lengths (in, out) and
                                   // out rows touched once
     // small-minibatch update scratch (sgns_small.hip): per launch, each
-    // minibatch's touch info, segments and counts; per minibatch, the
-    // out-touch entries, in-row deltas and context copies
+    // minibatch's touch info, segments, position pairs and counts; per
+    // minibatch, the out-touch coefficients, in-row deltas and context copies
     int64_t sm_tmax = 0, sm_G = 0, sm_pairs = 0;
     int32_t sm_dim = 0;
-    DevBuf sm_tinfo, sm_segs, sm_meta, sm_ent, sm_dinp, sm_ctxc;
+    DevBuf sm_tinfo, sm_segs, sm_spair, sm_meta, sm_gpos, sm_dinp, sm_ctxc;
     // shared-negative (BF16) minibatch scratch
     uint32_t bf_P = 0, bf_M = 0;
     DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0;

@@ -457,16 +457,7 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
         // the centre and -log sigma(-s_k) for a negative
         const double lr = (double)a.lr;
         double g[K + 1];
-#pragma unroll
-        for (int k = 0; k <= K; ++k) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < V4; ++i) acc = dot4d(vin[i], vo[k][i], acc);
-            const double dk = group_sum_d<LPP>(acc);
-            const bool ok = k == 0 || t[k] >= 0;
-            g[k] = k == 0 ? lr * (1.0 - sigmoid_d(dk)) : (ok ? -lr * sigmoid_d(dk) : 0.0);
-            if (live && ok && gl == k % LPP) lacc += (double)neg_log_sigmoid((float)(k == 0 ? dk : -dk));
-        }
+        coefficients<K, LPP, V4>(vin, vo, t, lr, live, gl, grp, g, lacc);
 
         // lane j of the group writes the entry of touch k = j (and j + 16)
 #pragma unroll

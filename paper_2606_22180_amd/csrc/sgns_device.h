@@ -109,6 +109,50 @@ template <int D, int K>
 constexpr int fwd_lanes_per_pair() { return (D <= 64 || (D == 128 && K <= 5)) ? 16 : 32; }
 
 template <int L>
+__device__ __forceinline__ double group_sum_d(double x);
+
+// The pair's coefficients g[0..K] (Eq. (2) gradient weights, FP64):
+// g0 = lr (1 - sigma(s0)), gk = -lr sigma(sk), 0 for a skipped negative,
+// from FP64 dots over the group's LPP lanes.  Lane j of the group evaluates
+// sigma and the loss term of touch j (and j + LPP), so each lane runs one
+// FP64 exponential instead of K + 1; the coefficients are then broadcast.
+// The loss term, -log sigma(s0) or -log sigma(-sk), is FP32 from the FP64
+// dot, added to lacc in FP64.
+template <int K, int LPP, int V4>
+__device__ __forceinline__ void coefficients(const float4 (&vin)[V4], const float4 (&vo)[K + 1][V4],
+                                             const int32_t (&t)[K + 1], double lr, bool live,
+                                             int gl, int grp, double (&g)[K + 1], double& lacc)
+{
+    double dot[K + 1];
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < V4; ++i) acc = dot4d(vin[i], vo[k][i], acc);
+        dot[k] = group_sum_d<LPP>(acc);
+    }
+    constexpr int H = (K + LPP) / LPP;   // touches per lane
+    double mine[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int k = gl + h * LPP;
+        double dk = dot[0];
+        bool ok = true;
+#pragma unroll
+        for (int j = 1; j <= K; ++j)
+            if (k == j) {
+                dk = dot[j];
+                ok = t[j] >= 0;
+            }
+        const double sg = sigmoid_d(dk);
+        mine[h] = k == 0 ? lr * (1.0 - sg) : (ok ? -lr * sg : 0.0);
+        if (k <= K && live && ok) lacc += (double)neg_log_sigmoid((float)(k == 0 ? dk : -dk));
+    }
+#pragma unroll
+    for (int k = 0; k <= K; ++k) g[k] = __shfl(mine[k / LPP], grp * LPP + k % LPP);
+}
+
+template <int L>
 __device__ __forceinline__ double group_sum_d(double x)
 {
     if (L > 16) x += __shfl_xor(x, 16);

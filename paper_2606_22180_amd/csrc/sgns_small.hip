@@ -15,7 +15,7 @@
 //           the noise table, never on the embeddings.
 //   update  one persistent cooperative launch for those minibatches.  Per
 //           minibatch: the forward (gathers, FP64 dots, sigma, coefficients;
-//           each out-touch's entry at its sorted position; each pair's
+//           each out-touch's coefficient at its sorted position; each pair's
 //           context row copied; out rows touched once updated in place),
 //           a grid barrier, the apply (one 16-lane group per segment sums
 //           the row's terms and adds them once), and a grid barrier.  The
@@ -79,6 +79,7 @@ struct PlanArgs {
     int32_t tmax;                  // touch slots per minibatch, P (K + 2)
     int2* tinfo;                   // [mb][tmax]: (row, sorted position | kSingleBit), -1 skipped
     int4* segs;                    // [mb][tmax]: (row, first position, touches, table)
+    int32_t* spair;                // [mb][tmax]: pair of each sorted position
     uint32_t* meta;                // [mb][4]: applied segments, in segments, out rows,
                                    // out rows touched once
     unsigned long long* row_totals;// [3]: in rows, out rows, out rows touched once
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
     while (N < nt) N <<= 1;                 // nt <= kPlanMaxTouches (checked on the host)
     int2* tinfo = a.tinfo + (int64_t)blockIdx.x * a.tmax;
     int4* segs = a.segs + (int64_t)blockIdx.x * a.tmax;
+    int32_t* spair = a.spair + (int64_t)blockIdx.x * a.tmax;
     const int32_t* vcols = a.vcols + d.vcol_base;
     if (threadIdx.x < 3) counts[threadIdx.x] = 0;
 
@@ -230,8 +232,11 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
         const int32_t row = (int32_t)((x >> 16) & 0x7FFFFFFFull);
         const bool single = out && len == 1;
         if (!single) segs[slot++] = make_int4(row, (int32_t)f, (int32_t)len, out);
-        for (uint32_t i = f; i < f + len; ++i)
-            tinfo[keys[i] & 0xFFFF] = make_int2(row, (int32_t)i | (single ? kSingleBit : 0));
+        for (uint32_t i = f; i < f + len; ++i) {
+            const uint32_t t = (uint32_t)(keys[i] & 0xFFFF);
+            tinfo[t] = make_int2(row, (int32_t)i | (single ? kSingleBit : 0));
+            spair[i] = (int32_t)(t / T);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -256,7 +261,8 @@ struct UpdArgs {
     const uint32_t* meta;          // [nmb][4]
     int32_t tmax;
     int32_t nmb;
-    int4* ent;                     // [tmax]: (FP64 g, pair) of each out-touch, by sorted position
+    const int32_t* spair;          // [nmb][tmax]: pair of each sorted position
+    double* gpos;                  // [tmax]: FP64 coefficient of each out-touch, by position
     float* dinp;                   // [P][D]: each pair's in-row delta, by sorted position
     float* ctxc;                   // [P][D]: each pair's context row at the minibatch start
     double* loss_part;             // [waves]
@@ -316,7 +322,10 @@ __device__ __forceinline__ bool grid_sync(const UpdArgs& a, uint32_t& epoch)
 template <int D, int K>
 __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs a)
 {
-    constexpr int LPP = fwd_lanes_per_pair<D, K>();   // lanes per pair in the forward
+    // lanes per pair in the forward: 32 at d >= 128, so that the 1,024 pairs of
+    // a minibatch occupy every wave of the 64 workgroups (16 lanes left half
+    // of them idle: 10.2 -> 6.8 us for the forward on R-MAT 2^20, K = 5)
+    constexpr int LPP = D >= 128 ? 32 : 16;
     constexpr int G = 64 / LPP;                         // pairs in flight per wave
     constexpr int V4 = D / (4 * LPP);                   // float4s per lane and row
     constexpr int T = K + 2;
@@ -329,18 +338,36 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
     const uint32_t gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     uint32_t epoch = a.epoch0;
     double lacc = 0.0;
+    // plan data of the next phase, loaded a phase ahead: this lane's touch of
+    // the wave's first pair group (forward) and the group's first segment with
+    // the pair of each of its first 16 positions (apply)
+    auto first_touch = [&](int mm) -> int2 {
+        const uint32_t npm = a.desc[mm].npairs, q0 = gw * G;
+        if (q0 < npm && lane < (int)min((uint32_t)G, npm - q0) * T)
+            return a.tinfo[(int64_t)mm * a.tmax + (int64_t)q0 * T + lane];
+        return make_int2(-1, -1);
+    };
+    int2 pf_touch = a.nmb > 0 ? first_touch(0) : make_int2(-1, -1);
 
     for (int m = 0; m < a.nmb; ++m) {
         const MbDesc dsc = a.desc[m];
         const int2* ti = a.tinfo + (int64_t)m * a.tmax;
+        const int32_t* sp = a.spair + (int64_t)m * a.tmax;
         const uint32_t np = dsc.npairs;
         const double lr = (double)dsc.lr;
+        const uint32_t nseg = a.meta[(int64_t)m * 4], nin = a.meta[(int64_t)m * 4 + 1];
+        const int4* sg = a.segs + (int64_t)m * a.tmax;
+        const uint32_t sidx0 = gw * 4 + (uint32_t)g16;
+        const int4 pf_seg = sidx0 < nseg ? sg[sidx0] : make_int4(0, 0, 0, 0);
 
         // ---- forward: G pairs per wave at a time
         for (uint32_t q0 = gw * G; q0 < np; q0 += nw * G) {
             const int npw = (int)min((uint32_t)G, np - q0);
             int32_t m_row = -1, m_code = -1;
-            if (lane < npw * T) {
+            if (q0 == gw * G) {
+                m_row = pf_touch.x;
+                m_code = pf_touch.y;
+            } else if (lane < npw * T) {
                 const int2 x = ti[(int64_t)q0 * T + lane];
                 m_row = x.x;
                 m_code = x.y;
@@ -373,17 +400,7 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                     vo[k][i] = ok ? ro[i * LPP + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
             double g[K + 1];
-#pragma unroll
-            for (int k = 0; k <= K; ++k) {
-                double acc = 0.0;
-#pragma unroll
-                for (int i = 0; i < V4; ++i) acc = dot4d(vin[i], vo[k][i], acc);
-                const double dk = group_sum_d<LPP>(acc);
-                const bool ok = k == 0 || t[k] >= 0;
-                g[k] = k == 0 ? lr * (1.0 - sigmoid_d(dk)) : (ok ? -lr * sigmoid_d(dk) : 0.0);
-                if (live && ok && gl == k % LPP)
-                    lacc += (double)neg_log_sigmoid((float)(k == 0 ? dk : -dk));
-            }
+            coefficients<K, LPP, V4>(vin, vo, t, lr, live, gl, grp, g, lacc);
             // entries of the out-touches (not the rows touched once)
 #pragma unroll
             for (int h = 0; h < (K + LPP) / LPP; ++h) {
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                     }
                 if (k <= K && live && tk >= 0 && !((single >> (src + 1 + k)) & 1ull)) {
                     const int32_t code = h == 0 ? my_code : my_code_hi;
-                    a.ent[code & kPosMask] = pack_entry(gk, (int32_t)q, 0u);
+                    a.gpos[code & kPosMask] = gk;
                 }
             }
             // out rows touched once: row + g in[ctx] in FP64, rounded once
@@ -434,15 +451,15 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                 }
             }
         }
+        const int32_t pf_pair = (sidx0 < nseg && l16 < pf_seg.z) ? sp[pf_seg.y + l16] : 0;
         if (!grid_sync(a, epoch)) break;
 
         // ---- apply: one 16-lane group per segment, in and out rows together
-        const uint32_t* mt = a.meta + (int64_t)m * 4;
-        const uint32_t nseg = mt[0], nin = mt[1];
-        const int4* sg = a.segs + (int64_t)m * a.tmax;
+        if (m + 1 < a.nmb) pf_touch = first_touch(m + 1);
         const double gc = dsc.grid_c;
-        for (uint32_t sidx = gw * 4 + (uint32_t)g16; sidx < nseg; sidx += nw * 4) {
-            const int4 sd = sg[sidx];
+        for (uint32_t sidx = sidx0; sidx < nseg; sidx += nw * 4) {
+            const bool first_seg = sidx == sidx0;
+            const int4 sd = first_seg ? pf_seg : sg[sidx];
             const bool out = sidx >= nin;
             const int32_t row = sd.x, start = sd.y, len = sd.z;
             float* table = out ? a.tout : a.tin;
@@ -458,12 +475,13 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
             // touches in batches of 16, one descriptor per lane
             for (int32_t b0 = 0; b0 < len; b0 += 16) {
                 const int32_t nb = min(16, len - b0);
+                // out rows: the touch's coefficient and its pair's context
+                // copy; in rows: the pair's delta at the touch's position
                 double my_g = 1.0;
                 int32_t my_src = start + b0 + l16;
                 if (out && l16 < nb) {
-                    const int4 e = a.ent[start + b0 + l16];
-                    my_g = entry_g(e);
-                    my_src = e.z;
+                    my_g = a.gpos[start + b0 + l16];
+                    my_src = (first_seg && b0 == 0) ? pf_pair : sp[start + b0 + l16];
                 }
                 for (int32_t i0 = 0; i0 < nb; i0 += kRows) {
                     double gg[kRows];
@@ -542,7 +560,7 @@ uint64_t small_path_bytes(int64_t P, int K, int d, int64_t B, int num_cus)
 {
     const uint64_t T = (uint64_t)(P * (K + 2)), G = (uint64_t)small_minibatches_per_launch();
     const uint64_t blocks = (uint64_t)std::max(kDefaultUpdBlocks, num_cus);
-    return 8 * T * G + 16 * T * G + 16 * G + 16 * T + 2 * 4 * (uint64_t)P * d +
+    return 8 * T * G + 16 * T * G + 4 * T * G + 16 * G + 8 * T + 2 * 4 * (uint64_t)P * d +
            32 * (uint64_t)std::max<int64_t>(B, 1) + 4 * kFlagStride * (blocks + 2) +
            8 * blocks * (kUpdThreads / 64) + 64;
 }
@@ -623,7 +641,8 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
         m.sm_tinfo.alloc(&c, sizeof(int2) * m.sm_tmax * m.sm_G);
         m.sm_segs.alloc(&c, sizeof(int4) * m.sm_tmax * m.sm_G);
         m.sm_meta.alloc(&c, sizeof(uint32_t) * 4 * m.sm_G);
-        m.sm_ent.alloc(&c, sizeof(int4) * m.sm_tmax);
+        m.sm_spair.alloc(&c, sizeof(int32_t) * m.sm_tmax * m.sm_G);
+        m.sm_gpos.alloc(&c, sizeof(double) * m.sm_tmax);
     }
     if (m.sm_pairs < P || m.sm_dim != D) {
         // each pair's in-row delta and context copy: P rows of d floats
@@ -658,6 +677,7 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     pa.tmax = tmax;
     pa.tinfo = m.sm_tinfo.as<int2>();
     pa.segs = m.sm_segs.as<int4>();
+    pa.spair = m.sm_spair.as<int32_t>();
     pa.meta = m.sm_meta.as<uint32_t>();
     pa.row_totals = m.row_totals.as<unsigned long long>();
 
@@ -697,7 +717,8 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     ua.segs = pa.segs;
     ua.meta = pa.meta;
     ua.tmax = tmax;
-    ua.ent = m.sm_ent.as<int4>();
+    ua.spair = m.sm_spair.as<int32_t>();
+    ua.gpos = m.sm_gpos.as<double>();
     ua.dinp = m.sm_dinp.as<float>();
     ua.ctxc = m.sm_ctxc.as<float>();
     ua.loss_part = loss_part;
