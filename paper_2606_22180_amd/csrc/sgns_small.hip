@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
 {
     constexpr int T = K + 2;
     __shared__ unsigned long long keys[kPlanMaxTouches];
-    __shared__ uint16_t seg_first[kPlanMaxTouches + 1];
+    // segment starts (step 3); before that, the pairs' centres (step 1)
+    __shared__ __align__(16) uint16_t seg_first[kPlanMaxTouches + 1];
     __shared__ uint32_t tmp[kPlanThreads / 64 + 1];
     __shared__ uint32_t counts[3];
     const MbDesc d = a.desc[blockIdx.x];
@@ -132,42 +133,48 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
     const int32_t* vcols = a.vcols + d.vcol_base;
     if (threadIdx.x < 3) counts[threadIdx.x] = 0;
 
-    // 1. each touch's row and sort key (table << 62 | row << 16 | touch)
-    for (uint32_t t = threadIdx.x; t < N; t += kPlanThreads) {
-        unsigned long long key = ~0ull;
-        if (t < nt) {
-            const uint32_t p = t / T, r = t - p * T;
-            const uint32_t gq = d.first_pair + p;
-            const uint32_t sidx = gq / d.Wv;
-            const uint32_t rank = gq - sidx * d.Wv;
-            const int32_t js = a.slices[sidx];
-            const int32_t col = vcols[rank];
-            const int32_t j = js >> 8, s = js & 255;
-            const int32_t ctr = a.walks[(int64_t)j * a.W + col];
-            int32_t row;
-            if (r == 0) {
-                const int32_t off = s < a.window ? s - a.window : s - a.window + 1;
-                row = a.walks[(int64_t)(j + off) * a.W + col];
-            } else if (r == 1) {
-                row = ctr;
-            } else {
-                // negative k = r - 2: Philox(walk id, (j << 8) | slot, NEG | k / 2), words
-                // 2 (k mod 2) and 2 (k mod 2) + 1
-                const uint32_t k = r - 2;
-                const int64_t wid = a.id_base + col;
-                const Rand4 x = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)js,
-                                           kTagNeg | (k >> 1), a.seed);
-                const uint32_t lo = (k & 1) ? x.v[2] : x.v[0];
-                const uint32_t hi = (k & 1) ? x.v[3] : x.v[1];
-                const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
-                row = neg != ctr ? neg : -1;   // a negative equal to the centre is skipped
-            }
-            if (row >= 0)
-                key = ((unsigned long long)(r != 0) << 62) | ((unsigned long long)row << 16) | t;
-            else
-                tinfo[t] = make_int2(-1, -1);
-        }
-        keys[t] = key;
+    // 1. each touch's row and sort key (table << 62 | row << 16 | touch).  A
+    //    pair's walk reads are made once: its context and centre first (one
+    //    thread per pair), then the negatives (one thread per negative),
+    //    which read the centre from LDS; every thread's loads are independent
+    //    of its earlier items', so they overlap.
+    for (uint32_t t = threadIdx.x; t < N; t += kPlanThreads) keys[t] = ~0ull;
+    __syncthreads();
+    int32_t* ctr_of = reinterpret_cast<int32_t*>(seg_first);   // [P] centres, until step 3
+    for (uint32_t p = threadIdx.x; p < d.npairs; p += kPlanThreads) {
+        const uint32_t gq = d.first_pair + p;
+        const uint32_t sidx = gq / d.Wv;
+        const uint32_t rank = gq - sidx * d.Wv;
+        const int32_t js = a.slices[sidx];
+        const int32_t col = vcols[rank];
+        const int32_t j = js >> 8, s = js & 255;
+        const int32_t off = s < a.window ? s - a.window : s - a.window + 1;
+        const int32_t ctr = a.walks[(int64_t)j * a.W + col];
+        const int32_t ctx = a.walks[(int64_t)(j + off) * a.W + col];
+        ctr_of[p] = ctr;
+        keys[p * T] = ((unsigned long long)ctx << 16) | (p * T);
+        keys[p * T + 1] = (1ull << 62) | ((unsigned long long)ctr << 16) | (p * T + 1);
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < d.npairs * K; e += kPlanThreads) {
+        // negative k of pair p: Philox(walk id, (j << 8) | slot, NEG | k / 2), words
+        // 2 (k mod 2) and 2 (k mod 2) + 1
+        const uint32_t p = e / K, k = e - p * K;
+        const uint32_t gq = d.first_pair + p;
+        const uint32_t sidx = gq / d.Wv;
+        const uint32_t rank = gq - sidx * d.Wv;
+        const int32_t js = a.slices[sidx];
+        const int64_t wid = a.id_base + vcols[rank];
+        const Rand4 x = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)js,
+                                   kTagNeg | (k >> 1), a.seed);
+        const uint32_t lo = (k & 1) ? x.v[2] : x.v[0];
+        const uint32_t hi = (k & 1) ? x.v[3] : x.v[1];
+        const int32_t neg = noise_draw(a.noise, ((uint64_t)hi << 32) | lo);
+        const uint32_t t = p * T + 2 + k;
+        if (neg != ctr_of[p])
+            keys[t] = (1ull << 62) | ((unsigned long long)neg << 16) | t;
+        else
+            tinfo[t] = make_int2(-1, -1);   // a negative equal to the centre is skipped
     }
     __syncthreads();
 
@@ -560,7 +567,7 @@ uint64_t small_path_bytes(int64_t P, int K, int d, int64_t B, int num_cus)
 {
     const uint64_t T = (uint64_t)(P * (K + 2)), G = (uint64_t)small_minibatches_per_launch();
     const uint64_t blocks = (uint64_t)std::max(kDefaultUpdBlocks, num_cus);
-    return 8 * T * G + 16 * T * G + 4 * T * G + 16 * G + 8 * T + 2 * 4 * (uint64_t)P * d +
+    return 2 * (8 * T * G + 16 * T * G + 4 * T * G + 16 * G) + 8 * T + 2 * 4 * (uint64_t)P * d +
            32 * (uint64_t)std::max<int64_t>(B, 1) + 4 * kFlagStride * (blocks + 2) +
            8 * blocks * (kUpdThreads / 64) + 64;
 }
@@ -635,9 +642,11 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     const int nwaves = nblocks * (kUpdThreads / 64);
 
     // buffers (model-owned, grown on demand)
-    if (m.sm_tmax < tmax || m.sm_G < G) {
+    // two sets of plan buffers: the plans of launch group i + 1 are written
+    // (on the second stream) while the update of group i reads set i mod 2
+    if (m.sm_tmax < tmax || m.sm_G < 2 * G) {
         m.sm_tmax = std::max<int64_t>(m.sm_tmax, tmax);
-        m.sm_G = std::max<int64_t>(m.sm_G, G);
+        m.sm_G = std::max<int64_t>(m.sm_G, 2 * G);
         m.sm_tinfo.alloc(&c, sizeof(int2) * m.sm_tmax * m.sm_G);
         m.sm_segs.alloc(&c, sizeof(int4) * m.sm_tmax * m.sm_G);
         m.sm_meta.alloc(&c, sizeof(uint32_t) * 4 * m.sm_G);
@@ -717,7 +726,6 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     ua.segs = pa.segs;
     ua.meta = pa.meta;
     ua.tmax = tmax;
-    ua.spair = m.sm_spair.as<int32_t>();
     ua.gpos = m.sm_gpos.as<double>();
     ua.dinp = m.sm_dinp.as<float>();
     ua.ctxc = m.sm_ctxc.as<float>();
@@ -725,43 +733,81 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     ua.flags = flags;
     ua.abort = abort;
 
+    // Plans run on the context's second stream one launch group ahead of the
+    // updates: plan(i) waits for update(i - 2) (its buffer set), update(i)
+    // waits for plan(i).  pipe_ev: [0] start, [1 + set] plan done,
+    // [3 + set] update done.
+    c.ensure_aux();
+    hipStream_t ps = c.aux;
+    FELOG_HIP(hipEventRecord(c.pipe_ev[0], c.stream));
+    FELOG_HIP(hipStreamWaitEvent(ps, c.pipe_ev[0], 0));
     size_t gated = 0;
-    const bool timing = c.timing_every > 0;
+    const bool timing = c.timing_every > 0 && !c.timing_pool.empty();
+    const size_t tslots = c.timing_pool.size() / 4;
+    std::vector<int64_t> slot_nmb(tslots, 0);
     double ms_plan = 0.0, ms_update = 0.0;
     int64_t timed = 0, timed_mb = 0;
+    auto harvest = [&](size_t slot) {
+        hipEvent_t* e = &c.timing_pool[4 * slot];
+        FELOG_HIP(hipEventSynchronize(e[3]));
+        float a0 = 0.0f, a1 = 0.0f;
+        FELOG_HIP(hipEventElapsedTime(&a0, e[0], e[1]));
+        FELOG_HIP(hipEventElapsedTime(&a1, e[2], e[3]));
+        ms_plan += a0;
+        ms_update += a1;
+        ++timed;
+        timed_mb += slot_nmb[slot];
+        slot_nmb[slot] = 0;
+    };
     uint32_t epoch = 0;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     for (int64_t g0 = first_mb, li = 0; g0 < end; g0 += G, ++li) {
         const int64_t g1 = std::min(end, g0 + G);
         const int nmb = (int)(g1 - g0);
+        const int set = (int)(li & 1);
+        hipEvent_t* e = nullptr;
+        if (timing) {
+            const size_t slot = (size_t)(li % (int64_t)tslots);
+            if (slot_nmb[slot]) harvest(slot);
+            slot_nmb[slot] = nmb;
+            e = &c.timing_pool[4 * slot];
+        }
+        // plan of group li, on the second stream
+        if (li >= 2) FELOG_HIP(hipStreamWaitEvent(ps, c.pipe_ev[3 + set], 0));
         // the walks of the launch's chunks must be written
         while (gated <= last_chunk[(size_t)li] && gated < w.chunk_ready.size())
-            FELOG_HIP(hipStreamWaitEvent(c.stream, w.chunk_ready[gated++], 0));
-        pa.desc = ddesc.as<MbDesc>() + (g0 - first_mb);
-        ua.desc = pa.desc;
-        hipEvent_t* e = nullptr;
-        if (timing && !c.timing_pool.empty()) e = &c.timing_pool[0];
-        if (e) FELOG_HIP(hipEventRecord(e[0], c.stream));
-        launch_plan(K, nmb, pa, c.stream);
-        if (e) FELOG_HIP(hipEventRecord(e[1], c.stream));
-        ua.nmb = nmb;
-        ua.epoch0 = epoch;
-        void* args[] = {&ua};
+            FELOG_HIP(hipStreamWaitEvent(ps, w.chunk_ready[gated++], 0));
+        PlanArgs pl = pa;
+        pl.desc = ddesc.as<MbDesc>() + (g0 - first_mb);
+        pl.tinfo = pa.tinfo + (int64_t)set * G * tmax;
+        pl.segs = pa.segs + (int64_t)set * G * tmax;
+        pl.spair = pa.spair + (int64_t)set * G * tmax;
+        pl.meta = pa.meta + (int64_t)set * G * 4;
+        if (e) FELOG_HIP(hipEventRecord(e[0], ps));
+        launch_plan(K, nmb, pl, ps);
+        if (e) FELOG_HIP(hipEventRecord(e[1], ps));
+        FELOG_HIP(hipEventRecord(c.pipe_ev[1 + set], ps));
+        // update of group li, on the context's stream
+        FELOG_HIP(hipStreamWaitEvent(c.stream, c.pipe_ev[1 + set], 0));
+        UpdArgs u = ua;
+        u.desc = pl.desc;
+        u.tinfo = pl.tinfo;
+        u.segs = pl.segs;
+        u.spair = pl.spair;
+        u.meta = pl.meta;
+        u.nmb = nmb;
+        u.epoch0 = epoch;
+        void* args[] = {&u};
+        if (e) FELOG_HIP(hipEventRecord(e[2], c.stream));
         FELOG_HIP(hipLaunchCooperativeKernel(kern, dim3(nblocks), dim3(kUpdThreads), args, 0,
                                              c.stream));
+        if (e) FELOG_HIP(hipEventRecord(e[3], c.stream));
+        FELOG_HIP(hipEventRecord(c.pipe_ev[3 + set], c.stream));
         epoch += 2u * (uint32_t)nmb;
-        if (e) {
-            FELOG_HIP(hipEventRecord(e[2], c.stream));
-            FELOG_HIP(hipEventSynchronize(e[2]));
-            float a0 = 0.0f, a1 = 0.0f;
-            FELOG_HIP(hipEventElapsedTime(&a0, e[0], e[1]));
-            FELOG_HIP(hipEventElapsedTime(&a1, e[1], e[2]));
-            ms_plan += a0;
-            ms_update += a1;
-            ++timed;
-            timed_mb += nmb;
-        }
     }
+    if (timing)
+        for (size_t slot = 0; slot < tslots; ++slot)
+            if (slot_nmb[slot]) harvest(slot);
     launch_loss_reduce(loss_part, nwaves, m.loss_out.as<double>(), c.stream);
     FELOG_HIP(hipEventRecord(c.ev1, c.stream));
     double loss = 0.0;
@@ -771,6 +817,7 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost, c.stream));
     FELOG_HIP(hipMemcpyAsync(&aborted, abort, sizeof aborted, hipMemcpyDeviceToHost, c.stream));
     c.sync();
+    FELOG_HIP(hipStreamSynchronize(ps));
     FELOG_REQUIRE(!aborted, "small-minibatch update: a grid barrier wait exceeded its bound");
     float ms = 0.0f;
     FELOG_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
