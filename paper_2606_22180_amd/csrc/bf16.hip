@@ -16,14 +16,24 @@
 //
 // Kernels per minibatch: gather (rows, transposed copies, positive terms),
 // scores (S and G on 32x32 tiles, 4 waves of 16x16), grads (dC and dN on
-// 32x32 tiles, the shared dimension M or P split over a block's 8 waves,
-// added to the masters with FP32 atomics; rows repeat only when a node is
-// drawn twice or is both a centre and a negative).  The ids (ctx, ctr, neg)
-// of up to 64 minibatches come from one launch before them.
+// 32x32 tiles, the shared dimension M or P split over a block's 8 waves; each
+// touch's FP32 term stored as a row of a delta buffer), apply (one wave per
+// touched row sums its touches' terms in FP64, in touch order, and adds the
+// sum to the master with one rounding).  A row repeats when a node is the
+// context of several pairs, the centre of several, a negative drawn twice, or
+// both a centre and a negative; summing its terms in a fixed order instead of
+// with atomics makes the tables bit-reproducible.  The touches' order comes
+// from a plan that sorts them by (table, row, touch): in LDS, one workgroup
+// per minibatch for up to 64 minibatches per launch, when 2P + M <= 8192,
+// else a radix sort per minibatch (stable, so equal rows keep touch order).
+// The ids (ctx, ctr, neg) of up to 64 minibatches come from one launch
+// before them.
 // MFMA: v_mfma_f32_16x16x32_bf16.  Lane l holds 8 consecutive k of row
 // (l mod 16) of A and of column (l mod 16) of B, k chunk l / 16; it receives
 // D[4 (l / 16) + j][l mod 16], j = 0..3.
 #include <algorithm>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 #include "noise.h"
@@ -86,8 +96,7 @@ struct Bf16Args {
     uint16_t* Gt;         // [M][P]
     float* g0;            // [P]
     double* loss_part;    // [P + M] gather slots, then one per scores wave
-    float* cap_in;        // capture (dense [n][d]) instead of updating masters
-    float* cap_out;
+    float* delta;         // [2P + M][d]: each touch's term (ctx, ctr, neg rows in touch order)
 };
 
 __device__ __forceinline__ float wave_sum32(float x)
@@ -295,9 +304,8 @@ __global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
 // kGradWaves waves per 32x32 output tile.  The waves take contiguous parts of
 // the shared dimension (M or P), loading up to kGradBatch steps of operands
 // before their MFMAs; the parts meet in LDS and every thread adds two
-// elements' parts in wave order and applies them: in[ctx] += dC + g0 O and
-// out[ctr] += g0 C for a pair's row, out[neg] += dN for a negative's, with
-// FP32 atomics on the masters (or the capture tables).
+// elements' parts in wave order and stores the touches' terms: dC + g0 O for
+// a pair's context, g0 C for its centre, dN for a negative.
 constexpr int kGradWaves = 8, kGradBatch = 4;
 
 __global__ __launch_bounds__(64 * kGradWaves) void bf16_grads_kernel(Bf16Args a)
@@ -362,27 +370,129 @@ __global__ __launch_bounds__(64 * kGradWaves) void bf16_grads_kernel(Bf16Args a)
         for (int w = 1; w < kGradWaves; ++w) x += part[w][row][col + h];
         v[h] = x;
     }
-    float* tin = a.cap_in ? a.cap_in : a.tin;
-    float* tout = a.cap_out ? a.cap_out : a.tout;
     const uint32_t r = r0 + row, e = e0 + col;
     if (isC) {
-        const int32_t ctx = a.ids[r];
-        if (ctx < 0) return;                    // no pair in this row
-        const int32_t ctr = a.ids[a.P + r];
+        if (a.ids[r] < 0) return;               // no pair in this row
         const float g = a.g0[r];
         const uint32_t o2 = *reinterpret_cast<const uint32_t*>(a.O + (int64_t)r * a.d + e);
         const uint32_t c2 = *reinterpret_cast<const uint32_t*>(a.C + (int64_t)r * a.d + e);
+        float din[2], dout[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const float o = bf16_to_f32((uint16_t)(o2 >> (16 * h)));
             const float c = bf16_to_f32((uint16_t)(c2 >> (16 * h)));
-            unsafeAtomicAdd(&tin[(int64_t)ctx * a.d + e + h], v[h] + g * o);
-            unsafeAtomicAdd(&tout[(int64_t)ctr * a.d + e + h], g * c);
+            din[h] = v[h] + g * o;
+            dout[h] = g * c;
         }
+        *reinterpret_cast<float2*>(a.delta + (int64_t)r * a.d + e) = make_float2(din[0], din[1]);
+        *reinterpret_cast<float2*>(a.delta + (int64_t)(a.P + r) * a.d + e) =
+            make_float2(dout[0], dout[1]);
     } else {
-        const int32_t neg = a.ids[2 * a.P + r];
+        *reinterpret_cast<float2*>(a.delta + (int64_t)(2 * a.P + r) * a.d + e) =
+            make_float2(v[0], v[1]);
+    }
+}
+
+// ------------------------------------------------------------------ apply
+// Touch t of a minibatch: t < P the context of pair t (in table), P <= t < 2P
+// the centre of pair t - P, 2P <= t the negative t - 2P (out table).  Its
+// sort key is (table << rb) | row with n < 2^rb; a pair past the chunk's end
+// has key (2 << rb) - 1, which sorts after every real touch.
+__device__ __forceinline__ uint32_t touch_key(int32_t row, uint32_t t, uint32_t P, uint32_t rb)
+{
+    if (row < 0) return (uint32_t)((2ull << rb) - 1);
+    return ((t >= P ? 1u : 0u) << rb) | (uint32_t)row;
+}
+
+// Plan of up to 64 minibatches with 2P + M <= kBfPlanMax, one workgroup per
+// minibatch: keys (key << 16 | t) in LDS, bitonic sort ascending, then the
+// sorted keys and touches.
+constexpr int kBfPlanThreads = 512;
+constexpr uint32_t kBfPlanMax = 8192;
+
+__global__ __launch_bounds__(kBfPlanThreads) void bf16_plan_kernel(const int32_t* ids, uint32_t P,
+                                                                   uint32_t M, uint32_t rb,
+                                                                   uint32_t* skey, uint32_t* stouch)
+{
+    __shared__ unsigned long long keys[kBfPlanMax];
+    const uint32_t nt = 2 * P + M;
+    uint32_t N = 64;
+    while (N < nt) N <<= 1;
+    const int32_t* id = ids + (size_t)blockIdx.x * nt;
+    for (uint32_t t = threadIdx.x; t < N; t += kBfPlanThreads)
+        keys[t] = t < nt ? ((unsigned long long)touch_key(id[t], t, P, rb) << 16) | t : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= N; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < N; i += kBfPlanThreads) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const unsigned long long x = keys[i], y = keys[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        keys[i] = y;
+                        keys[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    uint32_t* sk = skey + (size_t)blockIdx.x * nt;
+    uint32_t* st = stouch + (size_t)blockIdx.x * nt;
+    for (uint32_t i = threadIdx.x; i < nt; i += kBfPlanThreads) {
+        const unsigned long long x = keys[i];
+        sk[i] = (uint32_t)(x >> 16);
+        st[i] = (uint32_t)(x & 0xFFFF);
+    }
+}
+
+// Sort input of one large minibatch: key and touch per touch.
+__global__ void bf16_keys_kernel(const int32_t* ids, uint32_t P, uint32_t M, uint32_t rb,
+                                 uint32_t* kin, uint32_t* vin)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * P + M) return;
+    kin[t] = touch_key(ids[t], t, P, rb);
+    vin[t] = t;
+}
+
+// One wave per sorted position; the wave at the first position of a row sums
+// the terms of the row's touches in FP64, in sorted (touch) order, 64 keys
+// at a time, and adds the sum to the row with one rounding.
+template <int D>
+__global__ __launch_bounds__(256) void bf16_apply_kernel(const uint32_t* skey,
+                                                         const uint32_t* stouch, uint32_t nt,
+                                                         uint32_t rb, const float* delta,
+                                                         float* tin, float* tout)
+{
+    constexpr int U = D / 64;
+    const int lane = threadIdx.x & 63;
+    const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nt) return;
+    const uint32_t key = skey[i];
+    if (key == (uint32_t)((2ull << rb) - 1) || (i > 0 && skey[i - 1] == key)) return;
+    double acc[U];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) unsafeAtomicAdd(&tout[(int64_t)neg * a.d + e + h], v[h]);
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    for (uint32_t j0 = i;; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const bool same = j < nt && skey[j] == key;
+        const unsigned long long ends = __ballot(!same);
+        const int len = ends ? __ffsll((long long)ends) - 1 : 64;
+        const uint32_t mine = same ? stouch[j] : 0u;
+#pragma unroll 4
+        for (int q = 0; q < len; ++q) {
+            const uint32_t t = __shfl(mine, q);
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[u] += (double)delta[(int64_t)t * D + lane + 64 * u];
+        }
+        if (len < 64) break;
+    }
+    const uint32_t row = key & ((1u << rb) - 1);
+    float* T = (key >> rb) ? tout : tin;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float* x = T + (int64_t)row * D + lane + 64 * u;
+        *x = (float)((double)*x + acc[u]);
     }
 }
 
@@ -426,12 +536,16 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
 {
     Ctx& c = *m.ctx;
     const uint32_t P = (uint32_t)p.minibatch_pairs, M = (uint32_t)p.shared_negatives;
+    const uint32_t nt = 2 * P + M;               // touches per minibatch
+    const bool lds_plan = nt <= kBfPlanMax;
     const int d = m.dim;
+    uint32_t rb = 1;
+    while (((int64_t)1 << rb) <= m.g->n) ++rb;   // n < 2^rb
     if (m.bf_P < P || m.bf_M < M) {
         m.bf_P = std::max(m.bf_P, P);
         m.bf_M = std::max(m.bf_M, M);
-        const size_t cp = m.bf_P, cm = m.bf_M;
-        m.bf_ids.alloc(&c, sizeof(int32_t) * (2 * cp + cm) * kIdBatch);
+        const size_t cp = m.bf_P, cm = m.bf_M, ct = 2 * cp + cm;
+        m.bf_ids.alloc(&c, sizeof(int32_t) * ct * kIdBatch);
         m.bf_C.alloc(&c, sizeof(uint16_t) * cp * d);
         m.bf_O.alloc(&c, sizeof(uint16_t) * cp * d);
         m.bf_N.alloc(&c, sizeof(uint16_t) * cm * d);
@@ -440,6 +554,24 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         m.bf_G.alloc(&c, sizeof(uint16_t) * cp * cm);
         m.bf_Gt.alloc(&c, sizeof(uint16_t) * cp * cm);
         m.bf_g0.alloc(&c, sizeof(float) * cp);
+        m.bf_delta.alloc(&c, sizeof(float) * ct * d);
+        // a launch group's LDS plans or one large minibatch's sorted touches
+        const size_t sorted = std::max(ct, (size_t)kIdBatch * std::min<size_t>(ct, kBfPlanMax));
+        m.bf_skey.alloc(&c, sizeof(uint32_t) * sorted);
+        m.bf_stouch.alloc(&c, sizeof(uint32_t) * sorted);
+        m.bf_kin.release();
+        m.bf_vin.release();
+        m.bf_sort_tmp.release();
+    }
+    if (!lds_plan && !m.bf_sort_tmp.ptr) {
+        const size_t ct = 2 * (size_t)m.bf_P + m.bf_M;
+        m.bf_kin.alloc(&c, sizeof(uint32_t) * ct);
+        m.bf_vin.alloc(&c, sizeof(uint32_t) * ct);
+        size_t tmp = 0;
+        FELOG_HIP(rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t*)nullptr,
+                                            (uint32_t*)nullptr, (const uint32_t*)nullptr,
+                                            (uint32_t*)nullptr, (uint32_t)ct, 0u, 32u, c.stream));
+        m.bf_sort_tmp.alloc(&c, std::max<size_t>(tmp, 256));
     }
     const uint32_t score_waves = (P / 32) * (M / 32) * 4;
     const int64_t nslots = (int64_t)P + M + score_waves;
@@ -471,8 +603,10 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     a.Gt = m.bf_Gt.as<uint16_t>();
     a.g0 = m.bf_g0.as<float>();
     a.loss_part = loss_part.as<double>();
-    a.cap_in = cap_in;
-    a.cap_out = cap_out;
+    a.delta = m.bf_delta.as<float>();
+    // capture: the sums go to dense zeroed tables instead of the masters
+    float* const dst_in = cap_in ? cap_in : m.tin.as<float>();
+    float* const dst_out = cap_out ? cap_out : m.tout.as<float>();
 
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
     const uint32_t row_blocks = (P + M) / kGatherRows;
@@ -483,6 +617,8 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     size_t chunk = 0;
     size_t gated = 0;   // walk chunks [0, gated) are known to be written
     int32_t* const ids0 = m.bf_ids.as<int32_t>();
+    uint32_t* const skey0 = m.bf_skey.as<uint32_t>();
+    uint32_t* const stouch0 = m.bf_stouch.as<uint32_t>();
     int64_t batch0 = first_mb, batch_end = first_mb;   // minibatches whose ids are drawn
     for (int64_t b = first_mb; b < end; ++b) {
         while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
@@ -495,7 +631,8 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         a.np = (uint32_t)np;
         a.mb = (uint32_t)b;
         if (b == batch_end) {
-            // ids of the next minibatches, up to kIdBatch and the chunk's end
+            // ids (and, when they fit in LDS, plans) of the next minibatches,
+            // up to kIdBatch and the chunk's end
             while (gated <= chunk && gated < w.chunk_ready.size())
                 FELOG_HIP(hipStreamWaitEvent(c.stream, w.chunk_ready[gated++], 0));
             int64_t lim = std::min<int64_t>(end, b + kIdBatch);
@@ -507,18 +644,50 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
             hipLaunchKernelGGL(bf16_ids_kernel, dim3((uint32_t)((items + 255) / 256)), dim3(256),
                                0, c.stream, a, (uint32_t)b, (uint32_t)(lim - b), (uint32_t)first,
                                (uint64_t)sch.chunk_pairs[chunk], ids0);
+            if (lds_plan)
+                hipLaunchKernelGGL(bf16_plan_kernel, dim3((uint32_t)(lim - b)),
+                                   dim3(kBfPlanThreads), 0, c.stream, ids0, P, M, rb, skey0,
+                                   stouch0);
         }
-        a.ids = ids0 + (size_t)(b - batch0) * (2 * (size_t)P + M);
+        a.ids = ids0 + (size_t)(b - batch0) * nt;
+        const uint32_t* skey = skey0;
+        const uint32_t* stouch = stouch0;
+        if (lds_plan) {
+            skey += (size_t)(b - batch0) * nt;
+            stouch += (size_t)(b - batch0) * nt;
+        } else {
+            hipLaunchKernelGGL(bf16_keys_kernel, dim3((nt + 255) / 256), dim3(256), 0, c.stream,
+                               a.ids, P, M, rb, m.bf_kin.as<uint32_t>(), m.bf_vin.as<uint32_t>());
+            size_t tmp = m.bf_sort_tmp.bytes;
+            FELOG_HIP(rocprim::radix_sort_pairs(m.bf_sort_tmp.ptr, tmp,
+                                                (const uint32_t*)m.bf_kin.as<uint32_t>(), skey0,
+                                                (const uint32_t*)m.bf_vin.as<uint32_t>(), stouch0,
+                                                nt, 0u, rb + 1, c.stream));
+        }
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
-        if (d == 64) hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
-        else if (d == 128) hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
-        else hipLaunchKernelGGL(bf16_gather_kernel<256>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
         const dim3 sgrid(P / 32, M / 32);
-        if (d == 64) hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
-        else if (d == 128) hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
-        else hipLaunchKernelGGL(bf16_scores_kernel<256>, sgrid, dim3(256), 0, c.stream, a);
+        const dim3 agrid((nt + 3) / 4);
+        if (d == 64) {
+            hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
+            hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
+        } else if (d == 128) {
+            hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
+            hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
+        } else {
+            hipLaunchKernelGGL(bf16_gather_kernel<256>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
+            hipLaunchKernelGGL(bf16_scores_kernel<256>, sgrid, dim3(256), 0, c.stream, a);
+        }
         hipLaunchKernelGGL(bf16_grads_kernel, dim3(grad_blocks), dim3(64 * kGradWaves), 0,
                            c.stream, a);
+        if (d == 64)
+            hipLaunchKernelGGL(bf16_apply_kernel<64>, agrid, dim3(256), 0, c.stream, skey, stouch,
+                               nt, rb, (const float*)a.delta, dst_in, dst_out);
+        else if (d == 128)
+            hipLaunchKernelGGL(bf16_apply_kernel<128>, agrid, dim3(256), 0, c.stream, skey, stouch,
+                               nt, rb, (const float*)a.delta, dst_in, dst_out);
+        else
+            hipLaunchKernelGGL(bf16_apply_kernel<256>, agrid, dim3(256), 0, c.stream, skey, stouch,
+                               nt, rb, (const float*)a.delta, dst_in, dst_out);
         FELOG_HIP(hipGetLastError());
         pairs_done += np;
     }

@@ -200,6 +200,10 @@ struct Model {
     // shared-negative (BF16) minibatch scratch
     uint32_t bf_P = 0, bf_M = 0;
     DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0;
+    // per-touch update terms and the touches sorted by (table, row): plans of
+    // a launch group (small minibatches) or one minibatch with its sort input
+    // and radix-sort storage (large ones)
+    DevBuf bf_delta, bf_skey, bf_stouch, bf_kin, bf_vin, bf_sort_tmp;
 };
 
 // Minibatch schedule of one training call over a corpus.

@@ -87,11 +87,14 @@ def _agg(n, d, rows, vals):
     return out
 
 
-@pytest.mark.parametrize("dim,pre", [(64, 0), (128, 300), (256, 50)])
-def test_bf16_step_parity(fl, ctx, orc, sbm, dim, pre):
+@pytest.mark.parametrize("dim,pre,P,M", [(64, 0, 1024, 1024), (128, 300, 1024, 1024),
+                                         (256, 50, 1024, 1024), (128, 20, 4096, 1024)])
+def test_bf16_step_parity(fl, ctx, orc, sbm, dim, pre, P, M):
+    """P = 4096, M = 1024: 9,216 touches, more than an LDS plan sorts, so the
+    rows are grouped by the radix-sort plan."""
     g = sbm.train
-    P, M, K = 1024, 1024, 5
-    _say("bf16 step parity sbm1k d=%d after %d minibatches" % (dim, pre))
+    K = 5
+    _say("bf16 step parity sbm1k d=%d P=%d M=%d after %d minibatches" % (dim, P, M, pre))
     G, W, Mo, prm = _setup(fl, ctx, g, dim=dim, P=P, M=M, K=K)
     walks = orc.walks_uniform(g, np.arange(g.n), 10, 40, 11)
     assert np.array_equal(W.read(), walks)
@@ -169,3 +172,29 @@ def test_bf16_epoch_auc(fl, ctx, orc, sbm):
         a16, a32, st.ms, st32.ms))
     assert st.pairs == st32.pairs
     assert abs(a16 - a32) <= 0.01
+
+
+@pytest.mark.parametrize("P,M", [(1024, 1024), (4096, 1024), (64, 4096)])
+def test_bf16_bit_reproducible(fl, ctx, sbm, P, M):
+    """The same minibatches from the same state give bit-identical masters:
+    every row's terms are summed in touch order, never with atomics.  sbm1k
+    has 1,000 nodes, so a minibatch touches most rows several times (hub rows
+    dozens of times) through contexts, centres and negatives alike.  P = 4096
+    takes the radix-sort plan, the others the LDS plan; (64, 4096) has far
+    more negatives than pairs."""
+    g = sbm.train
+    tabs = []
+    for run in range(2):
+        G, W, Mo, prm = _setup(fl, ctx, g, dim=128, P=P, M=M, K=5)
+        st = Mo.train_steps(W, prm, 0, 60)
+        tabs.append((Mo.read(fl.TABLE_IN), Mo.read(fl.TABLE_OUT), st.loss))
+        Mo.close()
+        W.close()
+        G.close()
+    (i0, o0, l0), (i1, o1, l1) = tabs
+    di = int((i0.view(np.uint32) != i1.view(np.uint32)).sum())
+    do = int((o0.view(np.uint32) != o1.view(np.uint32)).sum())
+    _say("bf16 P=%d M=%d, 60 minibatches twice: differing words in %d out %d, loss %.9e %.9e"
+         % (P, M, di, do, l0, l1))
+    assert di == 0 and do == 0
+    assert l0 == l1
