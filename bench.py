@@ -453,6 +453,99 @@ def sgns_roofline(sts, d: int, K: int, pairs: int):
                             "frac": upd_bytes / upd_us / 1e3 / HBM_PEAK_GBS}}
 
 
+# --------------------------------------------------------------- counters
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "sgns_small_update_rmat23w_counters.md")
+COUNTER_SOURCES = ("paper_2606_22180_amd/csrc/sgns_small.hip",
+                   "paper_2606_22180_amd/csrc/sgns_device.h", "paper_2606_22180_amd/csrc/noise.h",
+                   "paper_2606_22180_amd/csrc/common.h")
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 over the sources the persistent update kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per persistent update launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters' reading of
+    a copy of known size), or None when the summary is missing or was taken
+    on other kernel sources."""
+    try:
+        with open(COUNTER_SUMMARY) as f:
+            kv = dict(line.split(":", 1) for line in f.read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:",
+                                          "minibatches_per_launch:")))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_digest():
+        return None
+    return {"bytes": float(kv["traffic_bytes_per_launch"]),
+            "minibatches_per_launch": float(kv["minibatches_per_launch"])}
+
+
+def counter_workload(args):
+    """A short single-stream run of the headline kernels for counter passes
+    (rocprofv3 --pmc takes one dispatch at a time): a 1 GiB elementwise copy
+    (torch.neg, 1 GiB read + 1 GiB written) that calibrates the counters,
+    then on the weighted R-MAT 2^23 graph with the unigram table of the full
+    node2vec corpus, three persistent-update launch groups (192 minibatches
+    of 1,024 pairs, d = 128, K = 5) and 64 BF16 shared-negative minibatches
+    (P = M = 1,024).  The graph is cached at --graph-cache when given."""
+    import synth
+    import torch
+    path = args.graph_cache
+    t = time.perf_counter()
+    if path and os.path.exists(path):
+        z = np.load(path)
+        g = synth.Graph(n=int(z["n"]), indptr=z["indptr"], indices=z["indices"],
+                        weights=z["weights"])
+    else:
+        g = synth.build_graph("rmat23w").train
+        if path:
+            np.savez(path, n=g.n, indptr=g.indptr, indices=g.indices, weights=g.weights)
+    log("counters: graph n=%d nnz=%d (%.1f s)" % (g.n, g.nnz, time.perf_counter() - t))
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    log("counters: calibration copies done (3 x 1 GiB read + 1 GiB written)")
+    from paper_2606_22180_amd import felog
+    ctx = felog.Context(0)
+    ctx.set_single_stream(True)
+    G = felog.Graph.from_csr(ctx, g.indptr, g.indices, g.weights)
+    M = felog.Model.create(G, dim=128, neg_dist=felog.NEG_UNIGRAM, seed=2)
+    Mb = felog.Model.create(G, dim=128, neg_dist=felog.NEG_UNIGRAM, seed=2,
+                            precision=felog.PREC_BF16)
+    Wf = felog.Walks.generate(G, r=10, L=80, seed=1, kind=felog.WALK_NODE2VEC, p=0.5, q=2.0)
+    M.set_unigram(Wf)
+    Mb.set_unigram(Wf)
+    Wf.close()
+    starts = felog.Active.from_host(G, np.arange(CHUNK, dtype=np.int32))
+    W = felog.Walks.generate(G, r=1, L=80, seed=1, kind=felog.WALK_NODE2VEC, p=0.5, q=2.0,
+                             starts=starts)
+    log("counters: corpus, unigram table and one 2^20-walk chunk ready")
+    prm = felog.train_params(window=10, negatives=5, lr_start=0.025, lr_end=1e-4,
+                             minibatch_pairs=1024, seed=3)
+    st = M.train_steps(W, prm, 0, 192)
+    log("counters: fp32 persistent update, %d minibatches, path %d" % (st.minibatches,
+                                                                         st.path))
+    prm16 = felog.train_params(window=10, negatives=5, lr_start=0.025, lr_end=1e-4,
+                               minibatch_pairs=1024, seed=3, shared_negatives=1024)
+    st = Mb.train_steps(W, prm16, 0, 64)
+    log("counters: bf16 shared-negative form, %d minibatches" % st.minibatches)
+    for o in (W, starts, Mb, M, G, ctx):
+        o.close()
+    print(json.dumps({"counter_workload": "done", "kernel_sources_sha256":
+                      kernel_sources_digest()}), flush=True)
+
+
 # ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -470,11 +563,17 @@ def main():
     ap.add_argument("--c3-minibatches", type=int, default=20000, help="0 skips the C3 leg")
     ap.add_argument("--serving-jobs", type=int, default=8, help="0 skips the serving sample")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--counters", action="store_true",
+                    help="run the short single-stream workload for counter passes instead")
+    ap.add_argument("--graph-cache", default=None, help="--counters: graph cache file (.npz)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported by this build" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.counters:
+        counter_workload(args)
+        return
 
     import synth
     cores, cpu_model = host_info()
@@ -552,6 +651,12 @@ def main():
         % (args.steps, total, value, walk_steps / walk_s))
 
     roof = sgns_roofline(sts, cfg["dim"], cfg["K"], pairs)
+    tr = measured_traffic()
+    if tr is not None and roof["kernel"].startswith("sgns_small_update_kernel"):
+        # counters were taken on launches of tr["minibatches_per_launch"] minibatches
+        roof["traffic"] = tr["bytes"] / tr["minibatches_per_launch"] * \
+            roof["kernels"][roof["kernel"]]["minibatches_per_launch"]
+        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
     out = {
         "metric": METRIC, "value": value, "unit": "pair-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,

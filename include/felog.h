@@ -80,10 +80,20 @@ felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every);
  * minibatch's touches by row, many minibatches per launch) and one persistent
  * cooperative update launch per group of minibatches; larger ones run
  * per-minibatch launches.  path 1: per-minibatch launches always.  Both give
- * bit-identical tables.  blocks: workgroups of the persistent launch (0 = one
- * per compute unit; capped at what can be resident at once).  With timing on
- * (felog_ctx_set_timing), every plan and update launch of path 0 is timed. */
+ * bit-identical tables.  blocks: workgroups of the persistent launch (0 = the
+ * default, 64; capped at what can be resident at once).  With timing on
+ * (felog_ctx_set_timing), every plan and update launch of path 0 is timed.
+ * Errors: path not 0 or 1, blocks outside [0, 65536]. */
 felog_status felog_ctx_set_sgns_path(felog_ctx* ctx, int32_t path, int32_t blocks);
+
+/* on = 1: every launch of the context goes to its one stream.  The plans of
+ * later minibatches, the ids of the large-minibatch path and the walks that
+ * felog_run writes beside training then run in issue order after the
+ * launches they would overlap; results are unchanged.  For tools that follow
+ * one stream (profilers, stream capture).  on = 0 (the default) restores the
+ * second and third streams.  Waits for the context's second stream first.
+ * Errors: on not 0 or 1. */
+felog_status felog_ctx_set_single_stream(felog_ctx* ctx, int32_t on);
 
 /* Message for the calling thread's last failed call ("" if none). */
 const char* felog_last_error(void);

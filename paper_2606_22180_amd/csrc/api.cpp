@@ -101,7 +101,10 @@ void Ctx::ensure_aux()
 {
     if (aux) return;
     make_current();
-    FELOG_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+    if (single_stream)
+        aux = stream;
+    else
+        FELOG_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
     for (hipEvent_t& e : pipe_ev) FELOG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
@@ -114,7 +117,7 @@ void Ctx::release_aux()
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
     }
-    (void)hipStreamDestroy(aux);
+    if (aux != stream) (void)hipStreamDestroy(aux);
     aux = nullptr;
 }
 
@@ -247,6 +250,16 @@ felog_status felog_ctx_set_sgns_path(felog_ctx* ctx, int32_t path, int32_t block
         FELOG_REQUIRE(blocks >= 0 && blocks <= 65536, "blocks out of range");
         ctx->sgns_path = path;
         ctx->sgns_blocks = blocks;
+    });
+}
+
+felog_status felog_ctx_set_single_stream(felog_ctx* ctx, int32_t on)
+{
+    return guarded([&] {
+        NEED(ctx);
+        FELOG_REQUIRE(on == 0 || on == 1, "on must be 0 or 1");
+        ctx->release_aux();   // waits for the second stream's work
+        ctx->single_stream = on != 0;
     });
 }
 
@@ -1033,7 +1046,9 @@ static void walk_then_train(Model& m, Walks& w, const felog_walk_params& wp,
     const int64_t chunk = chunk_walks_of(tp);
     FELOG_REQUIRE(chunk >= 1, "chunk_walks must be >= 1");
     plan_valid_columns(w, starts, n_starts, chunk);   // needs no walks; one host sync
-    if (!c.walk_stream) FELOG_HIP(hipStreamCreateWithFlags(&c.walk_stream, hipStreamNonBlocking));
+    if (!c.walk_stream && !c.single_stream)
+        FELOG_HIP(hipStreamCreateWithFlags(&c.walk_stream, hipStreamNonBlocking));
+    const hipStream_t ws = c.single_stream ? c.stream : c.walk_stream;
     const int64_t n_chunks = (w.W + chunk - 1) / chunk;
     hipEvent_t t0 = nullptr, t1 = nullptr, after = nullptr;
     FELOG_HIP(hipEventCreate(&t0));
@@ -1073,15 +1088,15 @@ static void walk_then_train(Model& m, Walks& w, const felog_walk_params& wp,
     }
     // the walks follow everything already queued for the model (start list, tables)
     FELOG_HIP(hipEventRecord(after, c.stream));
-    FELOG_HIP(hipStreamWaitEvent(c.walk_stream, after, 0));
-    FELOG_HIP(hipEventRecord(t0, c.walk_stream));
+    FELOG_HIP(hipStreamWaitEvent(ws, after, 0));
+    FELOG_HIP(hipEventRecord(t0, ws));
     for (int64_t k = 0; k < n_chunks; ++k) {
         const int64_t col0 = k * chunk;
-        launch_walk_columns(w, wp, starts, n_starts, col0, std::min(chunk, w.W - col0),
-                            c.walk_stream, d_capped);
-        FELOG_HIP(hipEventRecord(w.chunk_ready[k], c.walk_stream));
+        launch_walk_columns(w, wp, starts, n_starts, col0, std::min(chunk, w.W - col0), ws,
+                            d_capped);
+        FELOG_HIP(hipEventRecord(w.chunk_ready[k], ws));
     }
-    FELOG_HIP(hipEventRecord(t1, c.walk_stream));
+    FELOG_HIP(hipEventRecord(t1, ws));
     train_minibatches(m, w, tp, 0, -1, true, &ts, nullptr, nullptr, 0, nullptr, nullptr,
                       nullptr, 0, nullptr);
     FELOG_HIP(hipEventSynchronize(t1));

@@ -85,6 +85,8 @@ struct Ctx {
     // launch (0 = one per compute unit)
     int32_t sgns_path = 0;
     int32_t sgns_blocks = 0;
+    // every launch on `stream`: the second and third streams are `stream` itself
+    bool single_stream = false;
     void make_current() const;
     void sync() const;
     void ensure_aux();

@@ -122,6 +122,7 @@ SIGNATURES = {
     "felog_ctx_bytes_in_use": (_i32, [_p, C.POINTER(_u64)]),
     "felog_ctx_set_timing": (_i32, [_p, _i32]),
     "felog_ctx_set_sgns_path": (_i32, [_p, _i32, _i32]),
+    "felog_ctx_set_single_stream": (_i32, [_p, _i32]),
     "felog_last_error": (C.c_char_p, []),
     "felog_graph_load_csr": (_i32, [_p, _i32, _i64, _p, _p, _p, _pp]),
     "felog_graph_destroy": (None, [_p]),
@@ -231,8 +232,13 @@ class Context:
 
     def set_sgns_path(self, path: int, blocks: int = 0):
         """0: persistent small-minibatch update where it applies; 1: per-minibatch
-        launches always.  blocks: workgroups of the persistent launch (0 = one per CU)."""
+        launches always.  blocks: workgroups of the persistent launch (0 = the
+        default, 64)."""
         _check(load().felog_ctx_set_sgns_path(self.handle, path, blocks))
+
+    def set_single_stream(self, on: bool):
+        """Every launch of the context on its one stream (for profilers)."""
+        _check(load().felog_ctx_set_single_stream(self.handle, 1 if on else 0))
 
     def bytes_in_use(self) -> int:
         b = C.c_uint64()

@@ -150,3 +150,29 @@ def test_small_update_matches_oracle(fl, orc, sbm):
         _say("oracle, 8 minibatches, %s rows changed %d, max rel %.2e, misses %d"
              % (what, int((nref > 0).sum()), (num / np.maximum(nref, 1e-30)).max(), bad))
         assert bad == 0, what
+
+
+def test_single_stream_identical(fl, sbm):
+    """One stream for every launch (plans in issue order after the updates
+    they would overlap) gives the same tables and loss as two streams, on the
+    persistent path and on the per-minibatch launches."""
+    g = sbm.train
+    for path in (0, 1):
+        res = []
+        for single in (False, True):
+            ctx = fl.Context(0)
+            ctx.set_sgns_path(path)
+            ctx.set_single_stream(single)
+            G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+            W = fl.Walks.generate(G, r=10, L=40, seed=11)
+            M = fl.Model.create(G, dim=128, neg_dist=fl.NEG_DEGREE, seed=5)
+            prm = fl.train_params(window=5, negatives=5, minibatch_pairs=1024, seed=3)
+            st = M.train_steps(W, prm, 0, 200)
+            res.append((M.read(fl.TABLE_IN), M.read(fl.TABLE_OUT), st.loss))
+            for o in (M, W, G, ctx):
+                o.close()
+        (i0, o0, l0), (i1, o1, l1) = res
+        _say("path %d: one stream vs two, tables equal %s, loss %.9e %.9e"
+             % (path, np.array_equal(i0, i1) and np.array_equal(o0, o1), l0, l1))
+        assert np.array_equal(i0, i1) and np.array_equal(o0, o1)
+        assert l0 == l1
