@@ -375,9 +375,13 @@ felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
  * in[ctx], N = BF16 rows of out[neg], O = BF16 rows of out[ctr]:
  *   S = C N^T (MFMA, FP32 accumulation),  G = bf16(-lr (K/M) sigma(S) o mask),
  *   delta in[ctx] += G N + g0 O,  delta out[neg] += G^T C,  delta out[ctr] += g0 C,
- * g0 = lr (1 - sigma(rowwise C.O)); the FP32 masters take the deltas.  The
- * BF16 rows of a minibatch are its masters at the minibatch's start, rounded
- * to nearest even. */
+ * g0 = lr (1 - sigma(rowwise C.O)); sigma of S from the hardware exp2, rcp and
+ * log2 (a few FP32 ulps before the BF16 rounding of G).  Each touch's term is
+ * FP32; every touched row sums its terms in FP64 in touch order (contexts,
+ * then centres, then negatives) and the FP32 master takes the sum with one
+ * rounding, so the tables are bit-reproducible.  The BF16 rows of a
+ * minibatch are its masters at the minibatch's start, rounded to nearest
+ * even. */
 
 /* Minibatches [first_mb, first_mb + n_mb) of the same schedule (the tables must
  * hold the state at the start of first_mb). */

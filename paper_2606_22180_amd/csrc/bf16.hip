@@ -92,11 +92,11 @@ struct Bf16Args {
     uint16_t* N;          // [M][d]
     uint16_t* Ct;         // [d][P]
     uint16_t* Nt;         // [d][M]
-    uint16_t* G;          // [P][M]
-    uint16_t* Gt;         // [M][P]
     float* g0;            // [P]
-    double* loss_part;    // [P + M] gather slots, then one per scores wave
-    float* delta;         // [2P + M][d]: each touch's term (ctx, ctr, neg rows in touch order)
+    double* loss_part;    // [P + M] gather slots, then one per pair block of the fused launch
+    float* delta;         // [split][2P + M][d]: each touch's term (ctx, ctr, neg rows in
+                          // touch order), as `split` partial sums over the shared dimension
+    uint32_t split;       // blocks per panel of the fused launch (1, 2 or 4)
 };
 
 __device__ __forceinline__ float wave_sum32(float x)
@@ -110,6 +110,16 @@ __device__ __forceinline__ float wave_sum32(float x)
 __device__ __forceinline__ float softplus_f(float x)
 {
     return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+}
+
+// sigma(x) and log(1 + exp(-|x|)) from one hardware exp2, one reciprocal and
+// one log2 (a few FP32 ulps; the fused launch rounds G to BF16 right after)
+__device__ __forceinline__ void sigma_fast(float x, float& sig, float& l1p)
+{
+    const float e = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    sig = x >= 0.0f ? r : e * r;
+    l1p = __builtin_amdgcn_logf(1.0f + e) * 0.6931471805599453f;
 }
 
 // The ids of nmb consecutive minibatches of one chunk, mb0 first (their
@@ -241,155 +251,163 @@ __global__ __launch_bounds__(64 * kGatherRows) void bf16_gather_kernel(Bf16Args 
     }
 }
 
-// S and G on a 32x32 tile per block; wave w computes the 16x16 tile at rows
-// 16 (w / 2), cols 16 (w % 2), so that 4096 waves (at P = M = 1024) share the
-// latency of the loads, the MFMAs and the epilogue.  The d / 32 steps are
-// unrolled, so every operand load (and the ids the epilogue needs) is in
-// flight before the first MFMA waits.
+// Scores and gradients in one launch, G never stored.  A block owns a panel
+// of 16 rows of one side and streams the other side in chunks of 32 rows:
+//   panels [0, P/16):       panel = 16 pairs,      streamed = negatives,
+//                           out = dC = G N  (16 x d)
+//   panels [P/16, +M/16):   panel = 16 negatives,  streamed = pairs,
+//                           out = dN = G^T C (16 x d)
+// Each panel has `split` blocks (block = s * panels + panel), so that small
+// minibatches still fill the chip; the chunks form 8 * split contiguous
+// parts, and wave w of block s takes part (8 s + w + panel) mod 8 split, so
+// that blocks of different panels read different chunks at a time.  Block s
+// stores its partial sum as the touches' rows of delta part s; the apply
+// adds the parts in order.
+// Per chunk a wave computes the 32 x 16 score tile Y X^T (Y the streamed
+// rows, X the panel) as two 16x16 MFMA tiles, so that lane l holds the
+// scores of panel row l mod 16 against streamed rows 4 (l / 16) + j and
+// 16 + 4 (l / 16) + j (j < 4).  Those 8 G values are exactly an A operand of
+// the output contraction for panel row l mod 16 if the contraction's k index
+// runs over the chunk's streamed rows in that order (any order of k gives
+// the same sum's terms); the B operand takes the same rows from the
+// transposed copy Y^T.  So G goes from the score accumulators to the next
+// MFMA in registers.  The waves' partial outputs meet in LDS and are added
+// in wave order; every element's terms are then stored as the touches'
+// rows of the delta buffer: dC + g0 O and g0 C for a pair, dN for a negative.
+// Pair blocks also sum the negative loss terms, one slot per block.
+constexpr int kFusedWaves = 8;
+
 template <int D>
-__global__ __launch_bounds__(256) void bf16_scores_kernel(Bf16Args a)
+__global__ __launch_bounds__(64 * kFusedWaves) void bf16_fused_kernel(Bf16Args a)
 {
-    constexpr int S = D / 32;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const uint32_t r0 = blockIdx.x * 32 + (wv >> 1) * 16;
-    const uint32_t c0 = blockIdx.y * 32 + (wv & 1) * 16;
-    const int li = lane & 15, lk = lane >> 4;
-    bf16x8 fa[S], fb[S];
+    constexpr int KS = D / 32;   // k steps of a score tile
+    constexpr int ET = D / 16;   // 16-wide output tiles
+    __shared__ float part[kFusedWaves][16][D + 4];
+    __shared__ double lred[kFusedWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, q = lane >> 4;
+    const uint32_t npb = a.P / 16;
+    const uint32_t panels = npb + a.M / 16;
+    const uint32_t sp = blockIdx.x / panels, panel = blockIdx.x - sp * panels;
+    const bool isC = panel < npb;
+    const uint32_t x0 = (isC ? panel : panel - npb) * 16;
+    const uint16_t* X = isC ? a.C : a.N;
+    const uint16_t* Y = isC ? a.N : a.C;
+    const uint16_t* Yt = isC ? a.Nt : a.Ct;
+    const uint32_t ny = isC ? a.M : a.P;
+    // ids: a pair's centre (-1 past the chunk's end), a negative's node; a
+    // term is kept when both are real and differ
+    const int32_t* yid = isC ? a.ids + 2 * a.P : a.ids + a.P;
+    const int32_t pv = isC ? a.ids[a.P + x0 + li] : a.ids[2 * a.P + x0 + li];
+    bf16x8 xf[KS];
 #pragma unroll
-    for (int k = 0; k < S; ++k) {
-        fa[k] = load8(a.C + (int64_t)(r0 + li) * D + 32 * k + 8 * lk);
-        fb[k] = load8(a.N + (int64_t)(c0 + li) * D + 32 * k + 8 * lk);
-    }
-    int32_t ctr[4];
+    for (int s = 0; s < KS; ++s) xf[s] = load8(X + (int64_t)(x0 + li) * D + 32 * s + 8 * q);
+    f32x4 acc[ET];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t row = r0 + 4 * lk + q;
-        ctr[q] = row < a.np ? a.ids[a.P + row] : -2;   // -2: no pair in this row
-    }
-    const uint32_t n = c0 + li;
-    const int32_t neg = a.ids[2 * a.P + n];
-    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < S; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[k], fb[k], acc, 0, 0, 0);
+    for (int t = 0; t < ET; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const float wk = -a.lr * (float)a.K / (float)a.M;
     const double lw = (double)a.K / (double)a.M;
     double lacc = 0.0;
-    uint32_t gb[4];
+    const uint32_t chunks = ny / 32;
+    const uint32_t nparts = kFusedWaves * a.split;
+    const uint32_t part_id = (sp * kFusedWaves + wv + panel) % nparts;
+    const uint32_t c0 = (uint32_t)((uint64_t)chunks * part_id / nparts);
+    const uint32_t c1 = (uint32_t)((uint64_t)chunks * (part_id + 1) / nparts);
+    for (uint32_t ch = c0; ch < c1; ++ch) {
+        const uint32_t y0 = ch * 32;
+        bf16x8 yf[2][KS];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t row = r0 + 4 * lk + q;
-        const float sc = acc[q];
-        const bool keep = ctr[q] != -2 && ctr[q] != neg;
-        float g = 0.0f;
-        if (keep) {
-            g = wk / (1.0f + expf(-sc));
-            lacc += lw * (double)softplus_f(sc);           // -(K/M) log sigma(-s)
-        }
-        gb[q] = bf16_rne(g);
-        a.G[(int64_t)row * a.M + n] = (uint16_t)gb[q];
-    }
-    // rows 4 lk .. 4 lk + 3 of column n are consecutive in G^T
-    *reinterpret_cast<uint2*>(a.Gt + (int64_t)n * a.P + r0 + 4 * lk) =
-        make_uint2(gb[0] | (gb[1] << 16), gb[2] | (gb[3] << 16));
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) lacc += __shfl_xor(lacc, off);
-    if (lane == 0) {
-        const uint32_t slot = a.P + a.M + (blockIdx.y * gridDim.x + blockIdx.x) * 4 + wv;
-        a.loss_part[slot] += lacc;
-    }
-}
-
-// dC = G N (tiles [0, P/32 * d/32)) and dN = G^T C (the rest): one block of
-// kGradWaves waves per 32x32 output tile.  The waves take contiguous parts of
-// the shared dimension (M or P), loading up to kGradBatch steps of operands
-// before their MFMAs; the parts meet in LDS and every thread adds two
-// elements' parts in wave order and stores the touches' terms: dC + g0 O for
-// a pair's context, g0 C for its centre, dN for a negative.
-constexpr int kGradWaves = 8, kGradBatch = 4;
-
-__global__ __launch_bounds__(64 * kGradWaves) void bf16_grads_kernel(Bf16Args a)
-{
-    __shared__ float part[kGradWaves][32][33];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const uint32_t t = blockIdx.x;
-    const uint32_t te = a.d / 32;
-    const uint32_t tiles_c = (a.P / 32) * te;
-    const bool isC = t < tiles_c;
-    const uint32_t tt = isC ? t : t - tiles_c;
-    const uint32_t r0 = (tt / te) * 32, e0 = (tt % te) * 32;
-    const uint16_t* A = isC ? a.G : a.Gt;       // rows r, k over the shared dimension
-    const uint16_t* B = isC ? a.Nt : a.Ct;      // rows e, k over the shared dimension
-    const uint32_t kdim = isC ? a.M : a.P;
-    const uint32_t steps = kdim / 32;
-    const uint32_t s0 = steps * wv / kGradWaves, s1 = steps * (wv + 1) / kGradWaves;
-    const int li = lane & 15, lk = lane >> 4;
-    f32x4 acc[2][2];
+            for (int s = 0; s < KS; ++s)
+                yf[h][s] = load8(Y + (int64_t)(y0 + 16 * h + li) * D + 32 * s + 8 * q);
+        int4 ids2[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t sb = s0; sb < s1; sb += kGradBatch) {
-        bf16x8 fa[kGradBatch][2], fb[kGradBatch][2];
-#pragma unroll
-        for (int u = 0; u < kGradBatch; ++u) {
-            const uint32_t k0 = min(sb + u, s1 - 1) * 32;   // past the end: reloads the last step
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                fa[u][i] = load8(A + (int64_t)(r0 + 16 * i + li) * kdim + k0 + 8 * lk);
-                fb[u][i] = load8(B + (int64_t)(e0 + 16 * i + li) * kdim + k0 + 8 * lk);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kGradBatch; ++u) {
-            if (sb + u >= s1) break;
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[u][i], fb[u][j],
-                                                                        acc[i][j], 0, 0, 0);
-        }
-    }
-    // acc[i][j][q] is element (16 i + 4 lk + q, 16 j + li) of the tile
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) part[wv][16 * i + 4 * lk + q][16 * j + li] = acc[i][j][q];
-    __syncthreads();
-    const int row = threadIdx.x >> 4;            // 32 rows of 16 threads, two elements each
-    const int col = (threadIdx.x & 15) * 2;
-    float v[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        float x = part[0][row][col + h];
-#pragma unroll
-        for (int w = 1; w < kGradWaves; ++w) x += part[w][row][col + h];
-        v[h] = x;
-    }
-    const uint32_t r = r0 + row, e = e0 + col;
-    if (isC) {
-        if (a.ids[r] < 0) return;               // no pair in this row
-        const float g = a.g0[r];
-        const uint32_t o2 = *reinterpret_cast<const uint32_t*>(a.O + (int64_t)r * a.d + e);
-        const uint32_t c2 = *reinterpret_cast<const uint32_t*>(a.C + (int64_t)r * a.d + e);
-        float din[2], dout[2];
+        for (int h = 0; h < 2; ++h)
+            ids2[h] = *reinterpret_cast<const int4*>(yid + y0 + 16 * h + 4 * q);
+        f32x4 sc[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const float o = bf16_to_f32((uint16_t)(o2 >> (16 * h)));
-            const float c = bf16_to_f32((uint16_t)(c2 >> (16 * h)));
-            din[h] = v[h] + g * o;
-            dout[h] = g * c;
+            sc[h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+                sc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yf[h][s], xf[s], sc[h], 0, 0, 0);
         }
-        *reinterpret_cast<float2*>(a.delta + (int64_t)r * a.d + e) = make_float2(din[0], din[1]);
-        *reinterpret_cast<float2*>(a.delta + (int64_t)(a.P + r) * a.d + e) =
-            make_float2(dout[0], dout[1]);
-    } else {
-        *reinterpret_cast<float2*>(a.delta + (int64_t)(2 * a.P + r) * a.d + e) =
-            make_float2(v[0], v[1]);
+        uint32_t gw[4];   // G as 8 BF16 values, streamed rows 4q + j then 16 + 4q + j
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int32_t iv[4] = {ids2[h].x, ids2[h].y, ids2[h].z, ids2[h].w};
+            uint32_t gb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float x = sc[h][j];
+                const int32_t sv = iv[j];
+                float g = 0.0f;
+                if (pv >= 0 && sv >= 0 && pv != sv) {
+                    float sig, l1p;
+                    sigma_fast(x, sig, l1p);
+                    g = wk * sig;
+                    // -(K/M) log sigma(-s) = (K/M) (max(s, 0) + log(1 + exp(-|s|)))
+                    if (isC) lacc += lw * (double)(fmaxf(x, 0.0f) + l1p);
+                }
+                gb[j] = bf16_rne(g);
+            }
+            gw[2 * h] = gb[0] | (gb[1] << 16);
+            gw[2 * h + 1] = gb[2] | (gb[3] << 16);
+        }
+        const bf16x8 ga = __builtin_bit_cast(bf16x8, make_uint4(gw[0], gw[1], gw[2], gw[3]));
+        // B operands of the output contraction, loaded after the scores: with
+        // them in flight beside the score operands the kernel needs more than
+        // 128 VGPRs, which halves the resident blocks (measured slower)
+#pragma unroll
+        for (int t = 0; t < ET; ++t) {
+            uint2 bt[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                bt[h] = *reinterpret_cast<const uint2*>(Yt + (int64_t)(16 * t + li) * ny + y0 +
+                                                        16 * h + 4 * q);
+            const bf16x8 b =
+                __builtin_bit_cast(bf16x8, make_uint4(bt[0].x, bt[0].y, bt[1].x, bt[1].y));
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga, b, acc[t], 0, 0, 0);
+        }
+    }
+    // acc[t][j] is element (4q + j, 16 t + li) of the block's 16 x D output
+#pragma unroll
+    for (int t = 0; t < ET; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[wv][4 * q + j][16 * t + li] = acc[t][j];
+    if (isC) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lacc += __shfl_xor(lacc, off);
+        if (lane == 0) lred[wv] = lacc;
+    }
+    __syncthreads();
+    if (isC && threadIdx.x == 0) {
+        double l = 0.0;
+        for (int w = 0; w < kFusedWaves; ++w) l += lred[w];
+        a.loss_part[a.P + a.M + sp * npb + panel] += l;
+    }
+    float* const dpart = a.delta + (size_t)sp * (2 * a.P + a.M) * D;
+    for (int i = threadIdx.x; i < 16 * D; i += 64 * kFusedWaves) {
+        const int row = i / D, e = i % D;
+        float v = part[0][row][e];
+#pragma unroll
+        for (int w = 1; w < kFusedWaves; ++w) v += part[w][row][e];
+        const uint32_t r = x0 + row;
+        if (isC) {
+            if (a.ids[r] < 0) continue;          // no pair in this row
+            if (sp == 0) {                       // the positive terms go with part 0
+                const float g = a.g0[r];
+                const float o = bf16_to_f32(a.O[(int64_t)r * D + e]);
+                const float c = bf16_to_f32(a.C[(int64_t)r * D + e]);
+                dpart[(int64_t)r * D + e] = v + g * o;
+                dpart[(int64_t)(a.P + r) * D + e] = g * c;
+            } else {
+                dpart[(int64_t)r * D + e] = v;
+            }
+        } else {
+            dpart[(int64_t)(2 * a.P + r) * D + e] = v;
+        }
     }
 }
 
@@ -456,13 +474,15 @@ __global__ void bf16_keys_kernel(const int32_t* ids, uint32_t P, uint32_t M, uin
 }
 
 // One wave per sorted position; the wave at the first position of a row sums
-// the terms of the row's touches in FP64, in sorted (touch) order, 64 keys
-// at a time, and adds the sum to the row with one rounding.
+// the terms of the row's touches in FP64, in sorted (touch) order and part
+// order within a touch (a centre's term has part 0 only), 64 keys at a time,
+// and adds the sum to the row with one rounding.
 template <int D>
 __global__ __launch_bounds__(256) void bf16_apply_kernel(const uint32_t* skey,
                                                          const uint32_t* stouch, uint32_t nt,
-                                                         uint32_t rb, const float* delta,
-                                                         float* tin, float* tout)
+                                                         uint32_t rb, uint32_t P, uint32_t split,
+                                                         const float* delta, float* tin,
+                                                         float* tout)
 {
     constexpr int U = D / 64;
     const int lane = threadIdx.x & 63;
@@ -482,8 +502,12 @@ __global__ __launch_bounds__(256) void bf16_apply_kernel(const uint32_t* skey,
 #pragma unroll 4
         for (int q = 0; q < len; ++q) {
             const uint32_t t = __shfl(mine, q);
+            const uint32_t parts = (t >= P && t < 2 * P) ? 1u : split;
+            for (uint32_t s = 0; s < parts; ++s) {
+                const float* row = delta + ((size_t)s * nt + t) * D;
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc[u] += (double)delta[(int64_t)t * D + lane + 64 * u];
+                for (int u = 0; u < U; ++u) acc[u] += (double)row[lane + 64 * u];
+            }
         }
         if (len < 64) break;
     }
@@ -551,10 +575,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         m.bf_N.alloc(&c, sizeof(uint16_t) * cm * d);
         m.bf_Ct.alloc(&c, sizeof(uint16_t) * cp * d);
         m.bf_Nt.alloc(&c, sizeof(uint16_t) * cm * d);
-        m.bf_G.alloc(&c, sizeof(uint16_t) * cp * cm);
-        m.bf_Gt.alloc(&c, sizeof(uint16_t) * cp * cm);
         m.bf_g0.alloc(&c, sizeof(float) * cp);
-        m.bf_delta.alloc(&c, sizeof(float) * ct * d);
         // a launch group's LDS plans or one large minibatch's sorted touches
         const size_t sorted = std::max(ct, (size_t)kIdBatch * std::min<size_t>(ct, kBfPlanMax));
         m.bf_skey.alloc(&c, sizeof(uint32_t) * sorted);
@@ -563,6 +584,12 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
         m.bf_vin.release();
         m.bf_sort_tmp.release();
     }
+    // blocks per panel of the fused launch: at least 512 blocks where 4 suffice
+    const uint32_t panels = P / 16 + M / 16;
+    uint32_t split = 1;
+    while (split < 4 && panels * split < 512) split *= 2;
+    if (m.bf_delta.bytes < sizeof(float) * split * (size_t)nt * d)
+        m.bf_delta.alloc(&c, sizeof(float) * split * (size_t)nt * d);
     if (!lds_plan && !m.bf_sort_tmp.ptr) {
         const size_t ct = 2 * (size_t)m.bf_P + m.bf_M;
         m.bf_kin.alloc(&c, sizeof(uint32_t) * ct);
@@ -573,8 +600,7 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
                                             (uint32_t*)nullptr, (uint32_t)ct, 0u, 32u, c.stream));
         m.bf_sort_tmp.alloc(&c, std::max<size_t>(tmp, 256));
     }
-    const uint32_t score_waves = (P / 32) * (M / 32) * 4;
-    const int64_t nslots = (int64_t)P + M + score_waves;
+    const int64_t nslots = (int64_t)P + M + (int64_t)split * (P / 16);
     DevBuf loss_part;
     loss_part.alloc(&c, sizeof(double) * nslots);
     FELOG_HIP(hipMemsetAsync(loss_part.ptr, 0, sizeof(double) * nslots, c.stream));
@@ -599,19 +625,17 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
     a.N = m.bf_N.as<uint16_t>();
     a.Ct = m.bf_Ct.as<uint16_t>();
     a.Nt = m.bf_Nt.as<uint16_t>();
-    a.G = m.bf_G.as<uint16_t>();
-    a.Gt = m.bf_Gt.as<uint16_t>();
     a.g0 = m.bf_g0.as<float>();
     a.loss_part = loss_part.as<double>();
     a.delta = m.bf_delta.as<float>();
+    a.split = split;
     // capture: the sums go to dense zeroed tables instead of the masters
     float* const dst_in = cap_in ? cap_in : m.tin.as<float>();
     float* const dst_out = cap_out ? cap_out : m.tout.as<float>();
 
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
     const uint32_t row_blocks = (P + M) / kGatherRows;
-    const uint32_t te = d / 32;
-    const uint32_t grad_blocks = (P / 32) * te + (M / 32) * te;
+    const uint32_t fused_blocks = panels * split;
     int64_t pairs_done = 0;
     FELOG_HIP(hipEventRecord(c.ev0, c.stream));
     size_t chunk = 0;
@@ -665,29 +689,27 @@ void train_minibatches_bf16(Model& m, Walks& w, const felog_train_params& p,
                                                 nt, 0u, rb + 1, c.stream));
         }
         a.lr = (float)(lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1));
-        const dim3 sgrid(P / 32, M / 32);
         const dim3 agrid((nt + 3) / 4);
+        const dim3 fgrid(fused_blocks), fblock(64 * kFusedWaves);
         if (d == 64) {
             hipLaunchKernelGGL(bf16_gather_kernel<64>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
-            hipLaunchKernelGGL(bf16_scores_kernel<64>, sgrid, dim3(256), 0, c.stream, a);
+            hipLaunchKernelGGL(bf16_fused_kernel<64>, fgrid, fblock, 0, c.stream, a);
         } else if (d == 128) {
             hipLaunchKernelGGL(bf16_gather_kernel<128>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
-            hipLaunchKernelGGL(bf16_scores_kernel<128>, sgrid, dim3(256), 0, c.stream, a);
+            hipLaunchKernelGGL(bf16_fused_kernel<128>, fgrid, fblock, 0, c.stream, a);
         } else {
             hipLaunchKernelGGL(bf16_gather_kernel<256>, dim3(row_blocks), dim3(64 * kGatherRows), 0, c.stream, a);
-            hipLaunchKernelGGL(bf16_scores_kernel<256>, sgrid, dim3(256), 0, c.stream, a);
+            hipLaunchKernelGGL(bf16_fused_kernel<256>, fgrid, fblock, 0, c.stream, a);
         }
-        hipLaunchKernelGGL(bf16_grads_kernel, dim3(grad_blocks), dim3(64 * kGradWaves), 0,
-                           c.stream, a);
         if (d == 64)
             hipLaunchKernelGGL(bf16_apply_kernel<64>, agrid, dim3(256), 0, c.stream, skey, stouch,
-                               nt, rb, (const float*)a.delta, dst_in, dst_out);
+                               nt, rb, P, split, (const float*)a.delta, dst_in, dst_out);
         else if (d == 128)
             hipLaunchKernelGGL(bf16_apply_kernel<128>, agrid, dim3(256), 0, c.stream, skey, stouch,
-                               nt, rb, (const float*)a.delta, dst_in, dst_out);
+                               nt, rb, P, split, (const float*)a.delta, dst_in, dst_out);
         else
             hipLaunchKernelGGL(bf16_apply_kernel<256>, agrid, dim3(256), 0, c.stream, skey, stouch,
-                               nt, rb, (const float*)a.delta, dst_in, dst_out);
+                               nt, rb, P, split, (const float*)a.delta, dst_in, dst_out);
         FELOG_HIP(hipGetLastError());
         pairs_done += np;
     }

@@ -201,7 +201,7 @@ struct Model {
     DevBuf sm_tinfo, sm_segs, sm_spair, sm_meta, sm_gpos, sm_dinp, sm_ctxc;
     // shared-negative (BF16) minibatch scratch
     uint32_t bf_P = 0, bf_M = 0;
-    DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_G, bf_Gt, bf_g0;
+    DevBuf bf_ids, bf_C, bf_O, bf_N, bf_Ct, bf_Nt, bf_g0;
     // per-touch update terms and the touches sorted by (table, row): plans of
     // a launch group (small minibatches) or one minibatch with its sort input
     // and radix-sort storage (large ones)
