@@ -132,8 +132,10 @@ def cpu_baseline(g, cfg, n_walks: int, n_mb: int, cores: int, model: str):
 
 
 # --------------------------------------------------------------- side legs
-def c2_algorithm1(felog, max_rounds: int):
-    """Algorithm 1 end to end on R-MAT 2^20 (the feedback-loop workload)."""
+def c2_algorithm1(felog, max_rounds: int, per_round: bool = True):
+    """Algorithm 1 end to end on R-MAT 2^20 (the feedback-loop workload) through
+    felog_run, timed; with per_round, the same rounds again through the
+    separate calls for the per-round AUC and hub-row norms."""
     import synth
     pre = synth.CONFIGS["rmat20"]
     t = time.perf_counter()
@@ -176,12 +178,125 @@ def c2_algorithm1(felog, max_rounds: int):
            "link_pred_auc": auc}
     log("c2: %d rounds, active %s, %.2f s, %.3g pair-updates/s, AUC %.4f"
         % (st.rounds, [r["active"] for r in rounds], wall, pairs / wall, auc))
+    if per_round:
+        # the same rounds through the separate calls, with the AUC and the
+        # hub-row norms after each round; their active sets equal felog_run's
+        pr = feest_rounds(felog, G, split, pre, mu=pre["mu"], mode="monotone",
+                          rounds=max_rounds)
+        out["per_round"] = pr["rounds"]
+        out["per_round_matches_felog_run"] = \
+            [r["active"] for r in pr["rounds"]] == [r["active"] for r in rounds]
     W = felog.Walks.generate(G, r=pre["r"], L=pre["L"], seed=1)
     out_codec = codec_sample(felog, W)
     W.close()
     M.close()
     G.close()
     return out, out_codec
+
+
+def hub_norms(emb: np.ndarray, deg: np.ndarray, top: int = 100):
+    """Row norms of the in-table: the top-degree nodes (the rows that take the
+    most summed terms per minibatch) against the median non-isolated node."""
+    norms = np.linalg.norm(emb, axis=1)
+    hubs = np.argsort(deg)[::-1][:top]
+    live = deg > 0
+    return {"hub_top%d_mean_norm" % top: float(norms[hubs].mean()),
+            "median_norm": float(np.median(norms[live])), "max_norm": float(norms[live].max())}
+
+
+def feest_rounds(felog, G, split, cfg, *, mu, mode, rounds, lr_span=False, seed_psi=4):
+    """Algorithm 1 round by round through the separate calls (walks from the
+    active set, one training call, feedback): per round the active set, pairs,
+    walk steps, times, link-prediction AUC, hub-row norms and, in
+    RECOMPUTE_ALL mode, the reactivated nodes.  lr_span: one learning-rate
+    decay over all rounds (round r decays from lr(r / R) to lr((r + 1) / R))
+    instead of a restart per round."""
+    g = split.train
+    deg = g.degrees()
+    M = felog.Model.create(G, dim=cfg["dim"], neg_dist=felog.NEG_UNIGRAM, seed=2)
+    fmode = felog.FEEDBACK_MONOTONE if mode == "monotone" else felog.FEEDBACK_RECOMPUTE_ALL
+    active, prev = None, None
+    id_base = 0
+    out = []
+    t_all = time.perf_counter()
+    for rnd in range(rounds):
+        n_act = g.n if active is None else active.count()
+        if n_act == 0:
+            break
+        lr0, lr1 = cfg["lr0"], cfg["lr_end"]
+        if lr_span:
+            span = lr0 - lr1
+            lr0, lr1 = cfg["lr0"] - span * rnd / rounds, cfg["lr0"] - span * (rnd + 1) / rounds
+        prm = felog.train_params(window=cfg["window"], negatives=cfg["K"], lr_start=lr0,
+                                 lr_end=lr1, minibatch_pairs=cfg["minibatch"], seed=3)
+        t0 = time.perf_counter()
+        W = felog.Walks.generate(G, r=cfg["r"], L=cfg["L"], seed=1, id_base=id_base,
+                                 starts=active)
+        walks, _ = W.info()
+        t1 = time.perf_counter()
+        if rnd == 0:
+            M.set_unigram(W)
+        st = M.train_epoch(W, prm)
+        t2 = time.perf_counter()
+        id_base += walks
+        W.close()
+        # a walk from a node with neighbours takes L - 1 transitions, one from
+        # an isolated node none
+        starts_live = int((deg > 0).sum()) if active is None else int((deg[active.read()] > 0).sum())
+        steps = cfg["r"] * (cfg["L"] - 1) * starts_live
+        nxt = M.feedback(mu=mu, k_s=cfg["k_s"], seed=seed_psi, round=rnd, mode=fmode,
+                         active=active)
+        t3 = time.perf_counter()
+        auc = auc_score(M.read(felog.TABLE_IN), split.test_pos, split.test_neg)
+        r = {"round": rnd + 1, "active": int(n_act), "walks": int(walks), "pairs": int(st.pairs),
+             "walk_steps": steps, "s_walk": t1 - t0, "s_train": t2 - t1, "s_feedback": t3 - t2,
+             "pair_updates_per_s": st.pairs / max(1e-9, t2 - t1), "auc": auc,
+             "next_active": int(nxt.count())}
+        r.update(hub_norms(M.read(felog.TABLE_IN), deg))
+        if fmode == felog.FEEDBACK_RECOMPUTE_ALL and active is not None:
+            cur = set(active.read().tolist())
+            new = nxt.read()
+            r["reactivated"] = int(sum(1 for v in new.tolist() if v not in cur))
+            r["reactivated_frac"] = r["reactivated"] / max(1, new.shape[0])
+        if prev is not None:
+            prev.close()
+        prev = active
+        active = nxt
+        out.append(r)
+        log("  mu %.2f %s round %d: active %d, pairs %.4g, AUC %.4f, hub norm %.3f, median %.3f"
+            % (mu, mode, rnd + 1, n_act, st.pairs, auc, r["hub_top100_mean_norm"],
+               r["median_norm"]))
+    for a in (prev, active):
+        if a is not None:
+            a.close()
+    M.close()
+    return {"mu": mu, "mode": mode, "lr": "one decay over the rounds" if lr_span else
+            "restart per round", "rounds": out, "pairs": int(sum(r["pairs"] for r in out)),
+            "wall_s": time.perf_counter() - t_all, "final_auc": out[-1]["auc"] if out else None}
+
+
+def ablation(felog, mus, rounds):
+    """FeeST ablation on R-MAT 2^20 (the Algorithm 1 workload): MONOTONE at each
+    mu (mu = 2 keeps every node with neighbours active: training without
+    FeeST), RECOMPUTE_ALL at mu = 0.65 with the reactivated share of each new
+    active set, and mu = 0.65 with one learning-rate decay over the rounds."""
+    import synth
+    pre = synth.CONFIGS["rmat20"]
+    split = synth.build_graph("rmat20")
+    ctx = felog.Context(0)
+    G = felog.Graph.from_csr(ctx, split.train.indptr, split.train.indices)
+    runs = []
+    for mu in mus:
+        runs.append(feest_rounds(felog, G, split, pre, mu=mu, mode="monotone", rounds=rounds))
+    runs.append(feest_rounds(felog, G, split, pre, mu=0.65, mode="recompute_all",
+                             rounds=rounds))
+    runs.append(feest_rounds(felog, G, split, pre, mu=0.65, mode="monotone", rounds=rounds,
+                             lr_span=True))
+    G.close()
+    ctx.close()
+    return {"workload": "R-MAT scale 20, 2^24 undirected edges, 10% held out; uniform walks "
+                        "r=10 L=80; SGNS d=128 w=10 K=5 unigram^0.75 P=65536; k_s=10",
+            "runs": runs}
 
 
 def codec_sample(felog, W, reps: int = 3):
@@ -333,21 +448,28 @@ def c3_forms(felog, n_mb: int):
     return out
 
 
-def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
-    """p50/p99 job latency of the serving loop on a bounded sample of the serving
-    mix: capacity = 1 / mean service time of the jobs run alone, then the same
-    jobs arrive as a seeded Poisson process at 0.5, 0.8 and 0.95 x capacity."""
+def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4, n_max: int = 200_000,
+                   minibatch: int = 65536, persistent: bool = False):
+    """p50/p99 job latency of the serving loop on a sample of the serving mix
+    (job sizes log-uniform in [200, n_max]): capacity = 1 / mean service time
+    of the jobs run alone, then the same jobs arrive as a seeded Poisson
+    process at 0.5, 0.8 and 0.95 x capacity."""
     import synth
     t0 = time.perf_counter()
-    mix = synth.job_mix(n_jobs, seed=seed)
+    mix = synth.job_mix(n_jobs, seed=seed, n_max=n_max)
     graphs = [synth.job_graph(j) for j in mix]
-    log("serving: %d jobs (graphs %.1f s)" % (n_jobs, time.perf_counter() - t0))
+    log("serving: %d jobs, n in [200, %d] (graphs %.1f s)" % (n_jobs, n_max,
+                                                             time.perf_counter() - t0))
 
     def submit(S, j, g, at=0.0):
         return S.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
                         window=j["window"], seed=j["seed"], arrival_time=at)
 
-    S = felog.Server(0, 0, slots=1, minibatch_pairs=65536, negatives=5)
+    def server(n_slots):
+        return felog.Server(0, 0, slots=n_slots, minibatch_pairs=minibatch, negatives=5,
+                            persistent=persistent)
+
+    S = server(1)
     service, pairs = [], []
     for j, g in zip(mix, graphs):
         st = S.wait(submit(S, j, g), -1.0)
@@ -355,13 +477,17 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4):
         pairs.append(st.pairs)
     S.close()
     capacity = 1.0 / float(np.mean(service))
-    out = {"jobs": n_jobs, "slots": slots, "capacity_jobs_per_s": capacity,
-           "mean_service_s": 1.0 / capacity, "pairs_per_job": float(np.mean(pairs)), "rates": []}
+    out = {"jobs": n_jobs, "slots": slots, "n_max": n_max, "minibatch_cap": minibatch,
+           "update_path": "persistent" if persistent else "per-minibatch launches",
+           "capacity_jobs_per_s": capacity, "mean_service_s": 1.0 / capacity,
+           "pairs_per_job": float(np.mean(pairs)), "rates": []}
+    log("serving: alone %.3f s per job on average, %.4g pairs per job" % (1.0 / capacity,
+                                                                         np.mean(pairs)))
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     for frac in (0.5, 0.8, 0.95):
         lam = frac * capacity
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_jobs))
-        S = felog.Server(0, 0, slots=slots, minibatch_pairs=65536, negatives=5)
+        S = server(slots)
         base = S.stats()[0] + 0.05
         ids = []
         for (j, g), at in zip(zip(mix, graphs), arrivals):
@@ -563,6 +689,20 @@ def main():
     ap.add_argument("--c3-minibatches", type=int, default=20000, help="0 skips the C3 leg")
     ap.add_argument("--serving-jobs", type=int, default=8, help="0 skips the serving sample")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--no-c2-per-round", action="store_true",
+                    help="skip the per-round AUC / hub-norm rerun of the Algorithm 1 leg")
+    ap.add_argument("--ablation", action="store_true",
+                    help="run the FeeST ablation and mu sweep instead of the benchmark")
+    ap.add_argument("--ablation-mus", default="0.5,0.6,0.65,0.7,1.0,2.0")
+    ap.add_argument("--ablation-rounds", type=int, default=4)
+    ap.add_argument("--serving-nmax", type=int, default=20_000,
+                    help="largest job of the serving sample (log-uniform sizes from 200)")
+    ap.add_argument("--serving-minibatch", type=int, default=65536,
+                    help="serving jobs' largest minibatch")
+    ap.add_argument("--serving-persistent", action="store_true",
+                    help="serving jobs take the persistent update where it applies")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving sample and print it")
     ap.add_argument("--counters", action="store_true",
                     help="run the short single-stream workload for counter passes instead")
     ap.add_argument("--graph-cache", default=None, help="--counters: graph cache file (.npz)")
@@ -573,6 +713,20 @@ def main():
         sys.exit(2)
     if args.counters:
         counter_workload(args)
+        return
+    if args.ablation or args.serving_only:
+        from paper_2606_22180_amd import build as hipbuild
+        if not os.path.exists(hipbuild.LIB):
+            hipbuild.build()
+        from paper_2606_22180_amd import felog
+        if args.ablation:
+            mus = [float(x) for x in args.ablation_mus.split(",") if x]
+            print(json.dumps({"ablation": ablation(felog, mus, args.ablation_rounds)}), flush=True)
+        else:
+            print(json.dumps({"serving": serving_sample(
+                felog, args.serving_jobs, args.serving_slots, n_max=args.serving_nmax,
+                minibatch=args.serving_minibatch, persistent=args.serving_persistent)}),
+                flush=True)
         return
 
     import synth
@@ -678,11 +832,15 @@ def main():
     for a in offsets.values():
         a.close()
     if args.c2_rounds > 0:
-        out["c2_algorithm1"], out["walk_codec"] = c2_algorithm1(felog, args.c2_rounds)
+        out["c2_algorithm1"], out["walk_codec"] = c2_algorithm1(felog, args.c2_rounds,
+                                                                not args.no_c2_per_round)
     if args.c3_minibatches > 0:
         out["c3_forms"] = c3_forms(felog, args.c3_minibatches)
     if args.serving_jobs > 0:
-        out["serving"] = serving_sample(felog, args.serving_jobs, args.serving_slots)
+        out["serving"] = serving_sample(felog, args.serving_jobs, args.serving_slots,
+                                        n_max=args.serving_nmax,
+                                        minibatch=args.serving_minibatch,
+                                        persistent=args.serving_persistent)
         out["p99_job_latency_s"] = out["serving"]["rates"][1]["p99_latency_s"]
     if cpu is not None:
         out["cpu_baseline"] = cpu

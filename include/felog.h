@@ -494,6 +494,14 @@ typedef struct felog_server_params {
                               /* next to n (rows touched hundreds of times per step)  */
     int32_t negatives;        /* K for every job                                       */
     float lr_start, lr_end;   /* learning-rate decay over each job's epoch             */
+    int32_t persistent;       /* 0 (default): jobs take the per-minibatch launches.    */
+                              /* 1: jobs with P (K + 2) <= 8192 take the persistent    */
+                              /* update on 1 / slots of the compute units each, so all */
+                              /* running jobs' launches are resident together.  The    */
+                              /* results are the same; cooperative launches of         */
+                              /* different streams do not overlap on the device, so    */
+                              /* the per-minibatch launches serve concurrent jobs      */
+                              /* faster                                                */
 } felog_server_params;
 
 typedef struct felog_job_desc {

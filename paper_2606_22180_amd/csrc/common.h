@@ -295,6 +295,8 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
                              int64_t end, felog_train_stats* stats);
 void launch_loss_reduce(const double* part, int64_t n, double* out, hipStream_t s);
 int64_t small_minibatches_per_launch();
+// touches per minibatch, P (K + 2), up to which the persistent update applies
+constexpr int kSmallMaxTouches = 8192;
 uint64_t small_path_bytes(int64_t P, int K, int d, int64_t B, int num_cus);
 void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
               double* psi_host, int64_t psi_cap);

@@ -5,11 +5,21 @@
 // a job is admitted when one of the worker slots is free and its estimated
 // device footprint fits the remaining budget.  The head of the queue is never
 // bypassed, so every job is admitted after finitely many earlier jobs finish
-// (no starvation).  An admitted job runs on its worker's own HIP stream, so
-// the kernels of the jobs in flight overlap on the GPU's hardware queues;
+// (no starvation).  An admitted job runs on its worker's own HIP stream (one
+// stream per job: the id launches of its minibatches go to the same stream),
+// so the kernels of the jobs in flight overlap on the GPU's hardware queues;
 // its in-table is copied to host memory at the end and its device memory is
-// released for the next admission.  A job's results depend only on its own
-// inputs: its RNG counters and minibatch sequence are job-local.
+// released for the next admission.  Jobs take the per-minibatch launches by
+// default.  The persistent cooperative update serves one job well and
+// concurrent jobs poorly: measured on MI355X with four slots, a 219-node job
+// that takes 0.19 s alone finished only with the three larger jobs beside it,
+// after 2.4 s (its launches waited behind theirs).  With `persistent` set,
+// jobs whose minibatches fit the persistent update use it with 1 / slots of
+// the compute units each, so the launches of all running jobs can be
+// resident at once and none waits at a grid barrier for workgroups that
+// another job's launch keeps from starting.  A job's results depend only on
+// its own inputs: its RNG counters and minibatch sequence are job-local, and
+// both update paths give bit-identical tables.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -98,6 +108,12 @@ static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_param
     b += 8 * P * (K + 1) + 4 * T + 4 * P * dim + 8 * sc * dim;   // outputs, keys, split sums
     b += 8 * (P + 4) + 4 * L * 2 * (uint64_t)d.window;           // loss slots, slices
     b += 64 * 16;                                                // small allocations of 16 B
+    if (p.persistent && P * (K + 2) <= (uint64_t)kSmallMaxTouches) {
+        // persistent update: plans, per-pair rows, descriptors (B minibatches
+        // at most W (L - 1) 2 w / P + one per walk chunk), control words
+        const uint64_t B = W * L * 2 * (uint64_t)d.window / P + W / (1u << 20) + 2;
+        b += small_path_bytes((int64_t)P, (int)K, (int)dim, (int64_t)B, 256);
+    }
     return b + b / 16;                                           // headroom
 }
 
@@ -111,11 +127,13 @@ static void run_job(Server& s, Job& job)
     hipDeviceProp_t prop;
     FELOG_HIP(hipGetDeviceProperties(&prop, s.device));
     ctx.num_cus = prop.multiProcessorCount;
-    // Jobs run side by side on their own streams.  Two persistent cooperative
-    // launches that are each only partly resident would wait for each other
-    // (until their bounded barrier waits gave up), so jobs take the
-    // per-minibatch launches.
-    ctx.sgns_path = 1;
+    // One stream per job.  The persistent update's workgroups: 1 / slots of
+    // the compute units (at most 64), so that every running job's launch can
+    // be resident at once (two launches that were each only partly resident
+    // would wait for each other at their grid barriers).
+    ctx.single_stream = true;
+    ctx.sgns_path = s.params.persistent ? 0 : 1;
+    ctx.sgns_blocks = std::max(1, std::min(64, ctx.num_cus / std::max(1, s.params.slots)));
     FELOG_HIP(hipEventCreate(&ctx.ev0));
     FELOG_HIP(hipEventCreate(&ctx.ev1));
     struct StreamGuard {
@@ -290,6 +308,8 @@ felog_status felog_server_create(int device, uint64_t hbm_budget_bytes,
                       "minibatch_pairs must be in [1, 2^24]");
         FELOG_REQUIRE(params->negatives >= 1 && params->negatives <= 20,
                       "negatives must be in [1, 20]");
+        FELOG_REQUIRE(params->persistent == 0 || params->persistent == 1,
+                      "persistent must be 0 or 1");
         auto s = std::make_unique<felog_server>();
         s->device = device;
         s->budget = hbm_budget_bytes;

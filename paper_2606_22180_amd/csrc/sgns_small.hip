@@ -57,7 +57,7 @@ struct MbDesc {
 static_assert(sizeof(MbDesc) == 32, "descriptor layout shared by host and device");
 
 constexpr int kPlanThreads = 512;
-constexpr int kPlanMaxTouches = 8192;   // touches a plan sorts in LDS (64 KB of keys)
+constexpr int kPlanMaxTouches = kSmallMaxTouches;   // touches a plan sorts in LDS (64 KB of keys)
 constexpr int32_t kPosMask = (1 << 30) - 1;
 constexpr int32_t kSingleBit = 1 << 30;  // out row touched once: the forward updates it
 constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a barrier wait gives up (seconds)

@@ -123,3 +123,32 @@ def test_serving_budget_and_fifo(fl):
         big = fl.Server(0, 1 << 20, slots=1, minibatch_pairs=4096, negatives=5)
         big.submit(g.indptr, g.indices, dim=256, r=10, L=80, window=5, seed=1)
     S.close()
+
+
+def test_serving_persistent_jobs_concurrent(fl):
+    """Four slots of jobs on the persistent update (minibatches of at most
+    1,024 pairs, each job's launch on a quarter of the compute units) give the
+    same embeddings and losses as the jobs alone on the per-minibatch
+    launches."""
+    jobs = _jobs()[:8]
+    alone = {}
+    S1 = fl.Server(0, 0, slots=1, minibatch_pairs=1024, negatives=5, persistent=False)
+    for j, g in jobs:
+        jid = S1.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                        window=j["window"], seed=j["seed"])
+        st = S1.wait(jid, 300.0)
+        alone[j["job"]] = (S1.fetch(jid), st.loss, st.t_done - st.t_admit)
+    S1.close()
+    S4 = fl.Server(0, 0, slots=4, minibatch_pairs=1024, negatives=5, persistent=True)
+    ids = [(j, S4.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                         window=j["window"], seed=j["seed"])) for j, g in jobs]
+    for j, jid in ids:
+        st = S4.wait(jid, 300.0)
+        emb, loss, t_alone = alone[j["job"]]
+        same = np.array_equal(S4.fetch(jid), emb)
+        _say("job %d n=%d P=%d: persistent in a mix equal to per-minibatch alone: %s, "
+             "service %.3f s (alone, per-minibatch %.3f s)" % (
+                 j["job"], j["n"], st.minibatch_pairs, same, st.t_done - st.t_admit, t_alone))
+        # the two paths sum the loss terms in different orders
+        assert st.state == fl.JOB_DONE and same and abs(st.loss - loss) <= 1e-12 * abs(loss)
+    S4.close()
