@@ -232,7 +232,7 @@ def feest_rounds(felog, G, split, cfg, *, mu, mode, rounds, lr_span=False, seed_
         t0 = time.perf_counter()
         W = felog.Walks.generate(G, r=cfg["r"], L=cfg["L"], seed=1, id_base=id_base,
                                  starts=active)
-        walks, _ = W.info()
+        walks = W.info()[0]
         t1 = time.perf_counter()
         if rnd == 0:
             M.set_unigram(W)
@@ -247,16 +247,17 @@ def feest_rounds(felog, G, split, cfg, *, mu, mode, rounds, lr_span=False, seed_
         nxt = M.feedback(mu=mu, k_s=cfg["k_s"], seed=seed_psi, round=rnd, mode=fmode,
                          active=active)
         t3 = time.perf_counter()
-        auc = auc_score(M.read(felog.TABLE_IN), split.test_pos, split.test_neg)
+        emb = M.read(felog.TABLE_IN)
+        auc = auc_score(emb, split.test_pos, split.test_neg)
         r = {"round": rnd + 1, "active": int(n_act), "walks": int(walks), "pairs": int(st.pairs),
              "walk_steps": steps, "s_walk": t1 - t0, "s_train": t2 - t1, "s_feedback": t3 - t2,
              "pair_updates_per_s": st.pairs / max(1e-9, t2 - t1), "auc": auc,
              "next_active": int(nxt.count())}
-        r.update(hub_norms(M.read(felog.TABLE_IN), deg))
+        r.update(hub_norms(emb, deg))
+        del emb
         if fmode == felog.FEEDBACK_RECOMPUTE_ALL and active is not None:
-            cur = set(active.read().tolist())
             new = nxt.read()
-            r["reactivated"] = int(sum(1 for v in new.tolist() if v not in cur))
+            r["reactivated"] = int(np.isin(new, active.read(), invert=True).sum())
             r["reactivated_frac"] = r["reactivated"] / max(1, new.shape[0])
         if prev is not None:
             prev.close()
@@ -275,7 +276,7 @@ def feest_rounds(felog, G, split, cfg, *, mu, mode, rounds, lr_span=False, seed_
             "wall_s": time.perf_counter() - t_all, "final_auc": out[-1]["auc"] if out else None}
 
 
-def ablation(felog, mus, rounds):
+def ablation(felog, mus, rounds, extra=True):
     """FeeST ablation on R-MAT 2^20 (the Algorithm 1 workload): MONOTONE at each
     mu (mu = 2 keeps every node with neighbours active: training without
     FeeST), RECOMPUTE_ALL at mu = 0.65 with the reactivated share of each new
@@ -288,10 +289,11 @@ def ablation(felog, mus, rounds):
     runs = []
     for mu in mus:
         runs.append(feest_rounds(felog, G, split, pre, mu=mu, mode="monotone", rounds=rounds))
-    runs.append(feest_rounds(felog, G, split, pre, mu=0.65, mode="recompute_all",
-                             rounds=rounds))
-    runs.append(feest_rounds(felog, G, split, pre, mu=0.65, mode="monotone", rounds=rounds,
-                             lr_span=True))
+    if extra:
+        runs.append(feest_rounds(felog, G, split, pre, mu=0.65, mode="recompute_all",
+                                 rounds=rounds))
+        runs.append(feest_rounds(felog, G, split, pre, mu=0.65, mode="monotone", rounds=rounds,
+                                 lr_span=True))
     G.close()
     ctx.close()
     return {"workload": "R-MAT scale 20, 2^24 undirected edges, 10% held out; uniform walks "
@@ -695,6 +697,8 @@ def main():
                     help="run the FeeST ablation and mu sweep instead of the benchmark")
     ap.add_argument("--ablation-mus", default="0.5,0.6,0.65,0.7,1.0,2.0")
     ap.add_argument("--ablation-rounds", type=int, default=4)
+    ap.add_argument("--ablation-no-extra", action="store_true",
+                    help="only the mu sweep (no RECOMPUTE_ALL and learning-rate runs)")
     ap.add_argument("--serving-nmax", type=int, default=20_000,
                     help="largest job of the serving sample (log-uniform sizes from 200)")
     ap.add_argument("--serving-minibatch", type=int, default=65536,
@@ -721,7 +725,8 @@ def main():
         from paper_2606_22180_amd import felog
         if args.ablation:
             mus = [float(x) for x in args.ablation_mus.split(",") if x]
-            print(json.dumps({"ablation": ablation(felog, mus, args.ablation_rounds)}), flush=True)
+            print(json.dumps({"ablation": ablation(felog, mus, args.ablation_rounds,
+                                                   not args.ablation_no_extra)}), flush=True)
         else:
             print(json.dumps({"serving": serving_sample(
                 felog, args.serving_jobs, args.serving_slots, n_max=args.serving_nmax,
