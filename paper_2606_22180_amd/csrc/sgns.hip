@@ -388,8 +388,8 @@ struct FwdArgs {
 };
 
 // One pair per group of LPP lanes, 64 / LPP pairs at a time.  With FP64
-// dots and coefficients the kernel needs about 220 registers at d = 128,
-// K = 5 (two waves per SIMD); capping it at 128 for four waves spills.
+// dots and coefficients the kernel needs 164 registers at d = 128, K = 5
+// (three waves per SIMD).
 template <int D, int K>
 __global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
 {

@@ -102,11 +102,12 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
-// Lanes per pair in the forward: up to K = 5 at d <= 128, 16 lanes per pair
-// (four pairs' rows in flight per wave); more negatives or d = 256 take 32
-// lanes, where 16 would not fit the registers.
+// Lanes per pair in the forward: 16 at d = 64, 32 from d = 128.  With FP64
+// dots and coefficients, 16 lanes at d = 128 needed 228 registers (two waves
+// per SIMD); 32 lanes need 164 (three), and the forward at P = 65,536 on
+// R-MAT 2^20 went from 103.9 to 91.9 us.
 template <int D, int K>
-constexpr int fwd_lanes_per_pair() { return (D <= 64 || (D == 128 && K <= 5)) ? 16 : 32; }
+constexpr int fwd_lanes_per_pair() { return D <= 64 ? 16 : 32; }
 
 template <int L>
 __device__ __forceinline__ double group_sum_d(double x);

@@ -283,3 +283,78 @@ def test_rmat23w_node2vec(fl, orc):
     # a constant learning rate keeps lr independent of the corpus' minibatch count
     _step(fl, orc, M, W, ow, cdf, tin, tout, P=1024, K=5, window=10, b=777, seed=3,
           what="rmat23w fp32 mb 777", lr0=0.025, lr1=0.025)
+
+
+def test_rmat23w_persistent_update(fl, orc):
+    """The headline launch configuration on weighted R-MAT 2^23: the
+    persistent update (64 workgroups, P = 1,024, d = 128, K = 5, w = 10) runs
+    minibatches 777-780 of the first 2^20-walk chunk in one call from the
+    oracle's tables; the oracle runs the same four minibatches in order.
+
+    Every row the minibatches touch must change by the oracle's change within
+    1e-5 of its norm plus 1e-12, or else every entry of the row must lie
+    within m FP32 spacings of the oracle's entry, m the number of the four
+    minibatches that stored the row: both sides store each entry as the FP32
+    rounding of an FP64 value, and where the two FP64 values straddle a
+    rounding boundary the stored entries differ by exactly one spacing (the
+    per-step delta tests compare unrounded deltas and need no such case).
+    The rows of the second kind are counted and printed."""
+    sp = synth.build_graph("rmat23w")
+    g = sp.train
+    _say("rmat23w persistent update, minibatches 777-780")
+    ctx = fl.Context(0)
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices, g.weights)
+    starts = fl.Active.from_host(G, np.arange(1 << 20, dtype=np.int32))
+    W = fl.Walks.generate(G, r=1, L=80, seed=1, kind=fl.WALK_NODE2VEC, p=0.5, q=2.0,
+                          starts=starts)
+    ow = orc.walks_node2vec(g, np.arange(1 << 20, dtype=np.int32), 1, 80, 0.5, 2.0, 1, 0)[0]
+    assert np.array_equal(W.read(), ow)
+    cdf = orc.neg_cdf(g.degrees().astype(np.uint64))
+    M = fl.Model.create(G, dim=128, neg_dist=fl.NEG_DEGREE, seed=2)
+    tin, tout = orc.init_tables(g.n, 128, 2)
+    # a state away from the initial one (out = 0 would zero every in-row delta)
+    tout += np.float32(0.05) * np.random.default_rng(4).standard_normal(tout.shape,
+                                                                         dtype=np.float32)
+    M.write(fl.TABLE_IN, tin)
+    M.write(fl.TABLE_OUT, tout)
+    prm = fl.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=3,
+                          lr_start=0.0125, lr_end=0.0125)
+    st = M.train_steps(W, prm, 777, 4)
+    assert st.path == 1 and st.update_blocks == 64 and st.minibatches == 4
+    # rows touched, with the number of minibatches that touch each
+    m_in, m_out = {}, {}
+    for b in range(777, 781):
+        mb = orc.minibatch_pairs(ow, 10, 1024, b)
+        ng = orc.draw_negatives(mb, 0, 5, 3, cdf)
+        for r in set(mb.ctx.tolist()):
+            m_in[r] = m_in.get(r, 0) + 1
+        for r in set(mb.ctr.tolist()) | set(int(x) for x in ng.ravel().tolist() if x >= 0):
+            m_out[r] = m_out.get(r, 0) + 1
+    ref_in, ref_out = tin.copy(), tout.copy()
+    res = orc.train_epoch(ref_in, ref_out, ow, window=10, K=5, lr0=0.0125, lr_end=0.0125,
+                          P=1024, seed=3, cdf=cdf, mb_begin=777, mb_end=781)
+    assert st.pairs == res.pairs
+    assert abs(st.loss - res.loss) <= 1e-5 * abs(res.loss)
+    for what, which, ref, before, touched in (("in", fl.TABLE_IN, ref_in, tin, m_in),
+                                              ("out", fl.TABLE_OUT, ref_out, tout, m_out)):
+        r = np.array(sorted(touched), dtype=np.int64)
+        m = np.array([touched[x] for x in r.tolist()], dtype=np.float64)
+        got = M.read(which)[r].astype(np.float64)
+        dr = ref[r].astype(np.float64) - before[r]
+        dg = got - before[r]
+        num = np.linalg.norm(dg - dr, axis=1)
+        nref = np.linalg.norm(dr, axis=1)
+        out = np.nonzero(num > 1e-5 * nref + 1e-12)[0]
+        ok = True
+        for i in out.tolist():
+            sp_ = np.spacing(np.abs(ref[r[i]])).astype(np.float64)
+            steps = np.abs(got[i] - ref[r[i]].astype(np.float64)) / sp_
+            _say("  %s row %d (stored by %d minibatches): rel %.2e, %d entries differ, by at "
+                 "most %.3g FP32 spacings" % (what, r[i], m[i], num[i] / nref[i],
+                                             int((steps > 0).sum()), steps.max()))
+            ok = ok and steps.max() <= m[i]
+        _say("%s: %d touched rows, max rel %.2e, outside the plain bar %d" % (
+            what, r.shape[0], (num / np.maximum(nref, 1e-30)).max(), out.shape[0]))
+        assert ok, what
+    for o in (M, W, starts, G, ctx):
+        o.close()
