@@ -451,7 +451,7 @@ def c3_forms(felog, n_mb: int):
 
 
 def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4, n_max: int = 200_000,
-                   minibatch: int = 65536, persistent: bool = False):
+                   minibatch: int = 65536, update_mode: int = 0):
     """p50/p99 job latency of the serving loop on a sample of the serving mix
     (job sizes log-uniform in [200, n_max]): capacity = 1 / mean service time
     of the jobs run alone, then the same jobs arrive as a seeded Poisson
@@ -469,7 +469,7 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4, n_max: int = 2
 
     def server(n_slots):
         return felog.Server(0, 0, slots=n_slots, minibatch_pairs=minibatch, negatives=5,
-                            persistent=persistent)
+                            update_mode=update_mode)
 
     S = server(1)
     service, pairs = [], []
@@ -480,7 +480,8 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4, n_max: int = 2
     S.close()
     capacity = 1.0 / float(np.mean(service))
     out = {"jobs": n_jobs, "slots": slots, "n_max": n_max, "minibatch_cap": minibatch,
-           "update_path": "persistent" if persistent else "per-minibatch launches",
+           "update_mode": ["per-minibatch launches", "persistent per job",
+                           "shared persistent launches"][update_mode],
            "capacity_jobs_per_s": capacity, "mean_service_s": 1.0 / capacity,
            "pairs_per_job": float(np.mean(pairs)), "rates": []}
     log("serving: alone %.3f s per job on average, %.4g pairs per job" % (1.0 / capacity,
@@ -703,8 +704,9 @@ def main():
                     help="largest job of the serving sample (log-uniform sizes from 200)")
     ap.add_argument("--serving-minibatch", type=int, default=65536,
                     help="serving jobs' largest minibatch")
-    ap.add_argument("--serving-persistent", action="store_true",
-                    help="serving jobs take the persistent update where it applies")
+    ap.add_argument("--serving-mode", type=int, default=0,
+                    help="serving update mode: 0 per-minibatch launches, 1 persistent per job, "
+                         "2 shared persistent launches")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving sample and print it")
     ap.add_argument("--counters", action="store_true",
@@ -730,7 +732,7 @@ def main():
         else:
             print(json.dumps({"serving": serving_sample(
                 felog, args.serving_jobs, args.serving_slots, n_max=args.serving_nmax,
-                minibatch=args.serving_minibatch, persistent=args.serving_persistent)}),
+                minibatch=args.serving_minibatch, update_mode=args.serving_mode)}),
                 flush=True)
         return
 
@@ -845,7 +847,7 @@ def main():
         out["serving"] = serving_sample(felog, args.serving_jobs, args.serving_slots,
                                         n_max=args.serving_nmax,
                                         minibatch=args.serving_minibatch,
-                                        persistent=args.serving_persistent)
+                                        update_mode=args.serving_mode)
         out["p99_job_latency_s"] = out["serving"]["rates"][1]["p99_latency_s"]
     if cpu is not None:
         out["cpu_baseline"] = cpu

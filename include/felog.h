@@ -487,22 +487,29 @@ felog_status felog_run(felog_model* m, const felog_run_params* params, felog_run
 typedef struct felog_server felog_server;
 
 typedef struct felog_server_params {
-    int32_t slots;            /* jobs on the device at once (1..16), one HIP stream each */
+    int32_t slots;            /* jobs on the device at once (1..4; 1..3 when shared)  */
     int64_t minibatch_pairs;  /* largest P of a job; a job on n nodes uses            */
                               /* min(minibatch_pairs, the next power of two >= n):    */
                               /* summed minibatch updates diverge once P is large     */
                               /* next to n (rows touched hundreds of times per step)  */
     int32_t negatives;        /* K for every job                                       */
     float lr_start, lr_end;   /* learning-rate decay over each job's epoch             */
-    int32_t persistent;       /* 0 (default): jobs take the per-minibatch launches.    */
-                              /* 1: jobs with P (K + 2) <= 8192 take the persistent    */
-                              /* update on 1 / slots of the compute units each, so all */
-                              /* running jobs' launches are resident together.  The    */
-                              /* results are the same; cooperative launches of         */
-                              /* different streams do not overlap on the device, so    */
-                              /* the per-minibatch launches serve concurrent jobs      */
-                              /* faster                                                */
+    int32_t update_mode;      /* FELOG_SERVE_*: how the jobs' SGNS minibatches run     */
 } felog_server_params;
+
+/* Update modes of a server (the tables are the same in every mode):
+ *   FELOG_SERVE_LAUNCHES (0, the default): each job's per-minibatch launches on
+ *     its own stream;
+ *   FELOG_SERVE_PERSISTENT: jobs with P (K + 2) <= 8192 take the persistent
+ *     update, each on its own stream with 1 / slots of the compute units (so
+ *     the running jobs' cooperative launches are resident together);
+ *   FELOG_SERVE_SHARED: jobs with P (K + 2) <= 8192 train in persistent
+ *     launches shared by up to 8 running jobs of equal d: each launch plans
+ *     and updates the next 64 minibatches of every job in it, phase by phase
+ *     together, on one more stream of the server; other jobs as LAUNCHES.
+ * Streams: one per slot, plus one in FELOG_SERVE_SHARED; slots is at most 4
+ * (3 in FELOG_SERVE_SHARED), the device's hardware queues per process. */
+enum { FELOG_SERVE_LAUNCHES = 0, FELOG_SERVE_PERSISTENT = 1, FELOG_SERVE_SHARED = 2 };
 
 typedef struct felog_job_desc {
     int32_t n_nodes;

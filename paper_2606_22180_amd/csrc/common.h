@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "felog.h"
@@ -297,6 +298,38 @@ void launch_loss_reduce(const double* part, int64_t n, double* out, hipStream_t 
 int64_t small_minibatches_per_launch();
 // touches per minibatch, P (K + 2), up to which the persistent update applies
 constexpr int kSmallMaxTouches = 8192;
+// jobs whose minibatches one shared persistent launch can carry
+constexpr int kMaxBatchJobs = 8;
+
+// The schedule and pair slices of a training call over a corpus.
+TrainSchedule train_schedule(Walks& w, const felog_train_params& p);
+std::vector<int32_t> train_slices(int32_t L, int32_t window);
+
+// Training calls of several models in shared persistent launches (serving):
+// each launch plans and updates the next launch group of up to
+// kMaxBatchJobs jobs of equal d and K, phase by phase together.
+struct SmallJob;
+struct SmallJobDeleter {
+    void operator()(SmallJob* j) const;
+};
+using SmallJobPtr = std::unique_ptr<SmallJob, SmallJobDeleter>;
+struct SmallBatchCtl {
+    DevBuf words;        // barrier flags and the abort flag of the shared launches
+    uint32_t epoch = 0;  // barriers passed so far
+    int nblocks = 0;
+};
+bool small_job_fits(const Model& m, const felog_train_params& p);
+// Prepares the model's buffers and the call's descriptors (on the model's
+// stream, then waits for it); nblocks is the grid of the shared launches.
+SmallJobPtr small_job_begin(Model& m, Walks& w, const felog_train_params& p, int nblocks);
+int small_job_dim(const SmallJob& j);
+int small_job_negatives(const SmallJob& j);
+bool small_job_done(const SmallJob& j);
+int small_update_blocks(const Ctx& c, int D, int K);
+void small_batch_init(SmallBatchCtl& ctl, Ctx& c, int nblocks);
+void small_jobs_step(const std::vector<SmallJob*>& jobs, SmallBatchCtl& ctl, hipStream_t s);
+bool small_batch_aborted(SmallBatchCtl& ctl, hipStream_t s);   // waits for the stream
+void small_job_end(SmallJob& j, hipStream_t s, felog_train_stats* stats);   // waits too
 uint64_t small_path_bytes(int64_t P, int K, int d, int64_t B, int num_cus);
 void feedback(Model& m, const felog_feedback_params& p, const Active* in, Active& out,
               double* psi_host, int64_t psi_cap);

@@ -9,17 +9,24 @@
 // stream per job: the id launches of its minibatches go to the same stream),
 // so the kernels of the jobs in flight overlap on the GPU's hardware queues;
 // its in-table is copied to host memory at the end and its device memory is
-// released for the next admission.  Jobs take the per-minibatch launches by
-// default.  The persistent cooperative update serves one job well and
-// concurrent jobs poorly: measured on MI355X with four slots, a 219-node job
-// that takes 0.19 s alone finished only with the three larger jobs beside it,
-// after 2.4 s (its launches waited behind theirs).  With `persistent` set,
-// jobs whose minibatches fit the persistent update use it with 1 / slots of
-// the compute units each, so the launches of all running jobs can be
-// resident at once and none waits at a grid barrier for workgroups that
-// another job's launch keeps from starting.  A job's results depend only on
-// its own inputs: its RNG counters and minibatch sequence are job-local, and
-// both update paths give bit-identical tables.
+// released for the next admission.  Update modes:
+//   launches    (default) each job's per-minibatch launches on its stream;
+//   persistent  jobs whose minibatches fit the persistent update run it on
+//               their own streams with 1 / slots of the compute units each,
+//               so the launches of all running jobs can be resident at once
+//               and none waits at a grid barrier for workgroups that another
+//               job's launch keeps from starting.  Measured on MI355X with
+//               four slots, a 219-node job that takes 0.19 s alone finished
+//               only with the three larger jobs beside it, after 2.4 s (its
+//               launches waited behind theirs);
+//   shared      a batcher thread runs the persistent update of up to
+//               kMaxBatchJobs running jobs of equal d in shared launches:
+//               each plans and updates the next launch group of every job in
+//               it, phase by phase together (one grid barrier per phase for
+//               all of them).  A job joins at the next launch after its walks
+//               and tables are ready and leaves when its minibatches are done.
+// A job's results depend only on its own inputs: its RNG counters and
+// minibatch sequence are job-local, and every mode gives bit-identical tables.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -66,6 +73,19 @@ struct Server {
     uint64_t peak_reserved = 0;
     bool stopping = false;
     std::vector<std::thread> workers;
+    // shared persistent launches (update_mode FELOG_SERVE_SHARED)
+    struct BatchEntry {
+        SmallJob* job = nullptr;
+        bool done = false;
+        std::string err;
+        felog_train_stats st{};
+    };
+    std::thread batcher;
+    std::mutex bmu;
+    std::condition_variable bcv;
+    std::deque<BatchEntry*> bq;          // jobs in training, in arrival order
+    bool bstop = false;
+    int bblocks = 0;                     // grid of the shared launches
 
     double now() const
     {
@@ -108,11 +128,12 @@ static uint64_t estimate_bytes(const felog_job_desc& d, const felog_server_param
     b += 8 * P * (K + 1) + 4 * T + 4 * P * dim + 8 * sc * dim;   // outputs, keys, split sums
     b += 8 * (P + 4) + 4 * L * 2 * (uint64_t)d.window;           // loss slots, slices
     b += 64 * 16;                                                // small allocations of 16 B
-    if (p.persistent && P * (K + 2) <= (uint64_t)kSmallMaxTouches) {
+    if (p.update_mode != FELOG_SERVE_LAUNCHES && P * (K + 2) <= (uint64_t)kSmallMaxTouches) {
         // persistent update: plans, per-pair rows, descriptors (B minibatches
         // at most W (L - 1) 2 w / P + one per walk chunk), control words
         const uint64_t B = W * L * 2 * (uint64_t)d.window / P + W / (1u << 20) + 2;
-        b += small_path_bytes((int64_t)P, (int)K, (int)dim, (int64_t)B, 256);
+        b += small_path_bytes((int64_t)P, (int)K, (int)dim, (int64_t)B, 256) +
+             4 * L * 2 * (uint64_t)d.window;                       // its slices
     }
     return b + b / 16;                                           // headroom
 }
@@ -132,7 +153,7 @@ static void run_job(Server& s, Job& job)
     // be resident at once (two launches that were each only partly resident
     // would wait for each other at their grid barriers).
     ctx.single_stream = true;
-    ctx.sgns_path = s.params.persistent ? 0 : 1;
+    ctx.sgns_path = s.params.update_mode == FELOG_SERVE_PERSISTENT ? 0 : 1;
     ctx.sgns_blocks = std::max(1, std::min(64, ctx.num_cus / std::max(1, s.params.slots)));
     FELOG_HIP(hipEventCreate(&ctx.ev0));
     FELOG_HIP(hipEventCreate(&ctx.ev1));
@@ -208,8 +229,23 @@ static void run_job(Server& s, Job& job)
         tp.chunk_walks = 0;
         tp.seed = d.seed;
         felog_train_stats st{};
-        train_minibatches(m, w, tp, 0, -1, true, &st, nullptr, nullptr, 0, nullptr, nullptr,
-                          nullptr, 0, nullptr);
+        if (s.params.update_mode == FELOG_SERVE_SHARED && small_job_fits(m, tp)) {
+            // training in the batcher's shared launches
+            SmallJobPtr sj = small_job_begin(m, w, tp, s.bblocks);
+            Server::BatchEntry e;
+            e.job = sj.get();
+            {
+                std::unique_lock<std::mutex> lk(s.bmu);
+                s.bq.push_back(&e);
+                s.bcv.notify_all();
+                s.bcv.wait(lk, [&] { return e.done; });
+            }
+            FELOG_REQUIRE(e.err.empty(), "%s", e.err.c_str());
+            st = e.st;
+        } else {
+            train_minibatches(m, w, tp, 0, -1, true, &st, nullptr, nullptr, 0, nullptr, nullptr,
+                              nullptr, 0, nullptr);
+        }
         job.result.resize((size_t)g.n * d.dim);
         FELOG_HIP(hipMemcpyAsync(job.result.data(), m.tin.ptr, tb, hipMemcpyDeviceToHost,
                                  ctx.stream));
@@ -217,6 +253,83 @@ static void run_job(Server& s, Job& job)
         job.pairs = st.pairs;
         job.loss = st.loss;
         job.peak_bytes = ctx.peak;
+    }
+}
+
+// The shared launches: each round takes the jobs in training whose d and K
+// equal those of the oldest one (up to kMaxBatchJobs), launches their next
+// launch group together, waits for it, and hands finished jobs back to their
+// workers.  A launch that aborts (a barrier wait exceeded its bound) fails its
+// jobs; the barrier words are then reset.
+static void batcher_loop(Server* s)
+{
+    Ctx c;
+    c.device = s->device;
+    c.make_current();
+    hipDeviceProp_t prop;
+    std::string setup_err;
+    SmallBatchCtl ctl;
+    try {
+        FELOG_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+        FELOG_HIP(hipGetDeviceProperties(&prop, s->device));
+        c.num_cus = prop.multiProcessorCount;
+        small_batch_init(ctl, c, s->bblocks);
+    } catch (const Error&) {
+        setup_err = felog_last_error();
+        if (setup_err.empty()) setup_err = "shared launches could not start";
+    }
+    for (;;) {
+        std::vector<Server::BatchEntry*> batch;
+        {
+            std::unique_lock<std::mutex> lk(s->bmu);
+            s->bcv.wait(lk, [&] { return s->bstop || !s->bq.empty(); });
+            if (s->bq.empty()) break;   // stopping and nothing in training
+            const SmallJob& head = *s->bq.front()->job;
+            for (Server::BatchEntry* e : s->bq)
+                if ((int)batch.size() < kMaxBatchJobs && small_job_dim(*e->job) == small_job_dim(head) &&
+                    small_job_negatives(*e->job) == small_job_negatives(head))
+                    batch.push_back(e);
+        }
+        std::string err = setup_err;
+        std::vector<bool> finished(batch.size(), false);
+        if (err.empty()) {
+            try {
+                std::vector<SmallJob*> jobs;
+                for (Server::BatchEntry* e : batch) jobs.push_back(e->job);
+                small_jobs_step(jobs, ctl, c.stream);
+                if (small_batch_aborted(ctl, c.stream)) {
+                    err = "shared persistent update: a grid barrier wait exceeded its bound";
+                    small_batch_init(ctl, c, s->bblocks);
+                } else {
+                    for (size_t i = 0; i < batch.size(); ++i)
+                        if (small_job_done(*batch[i]->job)) {
+                            small_job_end(*batch[i]->job, c.stream, &batch[i]->st);
+                            finished[i] = true;
+                        }
+                }
+            } catch (const Error&) {
+                err = felog_last_error();
+                if (err.empty()) err = "shared persistent update failed";
+            } catch (...) {
+                err = "shared persistent update failed with an unexpected internal error";
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->bmu);
+            for (size_t i = 0; i < batch.size(); ++i) {
+                if (!err.empty()) batch[i]->err = err;
+                if (!err.empty() || finished[i]) {
+                    batch[i]->done = true;
+                    s->bq.erase(std::find(s->bq.begin(), s->bq.end(), batch[i]));
+                }
+            }
+        }
+        s->bcv.notify_all();
+    }
+    if (c.stream) {
+        (void)hipStreamSynchronize(c.stream);
+        ctl.words.release();
+        (void)hipStreamDestroy(c.stream);
     }
 }
 
@@ -303,18 +416,37 @@ felog_status felog_server_create(int device, uint64_t hbm_budget_bytes,
         int n = 0;
         FELOG_HIP(hipGetDeviceCount(&n));
         FELOG_REQUIRE(device >= 0 && device < n, "device %d out of range", device);
-        FELOG_REQUIRE(params->slots >= 1 && params->slots <= 16, "slots must be in [1, 16]");
+        FELOG_REQUIRE(params->update_mode == FELOG_SERVE_LAUNCHES ||
+                          params->update_mode == FELOG_SERVE_PERSISTENT ||
+                          params->update_mode == FELOG_SERVE_SHARED,
+                      "unknown update_mode %d", params->update_mode);
+        const int max_slots = params->update_mode == FELOG_SERVE_SHARED ? 3 : 4;
+        FELOG_REQUIRE(params->slots >= 1 && params->slots <= max_slots,
+                      "slots must be in [1, %d] (one stream each%s; the device has 4 hardware "
+                      "queues per process)", max_slots,
+                      params->update_mode == FELOG_SERVE_SHARED ? ", plus the shared launches'" : "");
         FELOG_REQUIRE(params->minibatch_pairs >= 1 && params->minibatch_pairs <= (1 << 24),
                       "minibatch_pairs must be in [1, 2^24]");
         FELOG_REQUIRE(params->negatives >= 1 && params->negatives <= 20,
                       "negatives must be in [1, 20]");
-        FELOG_REQUIRE(params->persistent == 0 || params->persistent == 1,
-                      "persistent must be 0 or 1");
         auto s = std::make_unique<felog_server>();
         s->device = device;
         s->budget = hbm_budget_bytes;
         s->params = *params;
         s->t0 = std::chrono::steady_clock::now();
+        if (params->update_mode == FELOG_SERVE_SHARED) {
+            // one grid for every shared launch: resident for each d
+            Ctx probe;
+            probe.device = device;
+            hipDeviceProp_t prop;
+            FELOG_HIP(hipGetDeviceProperties(&prop, device));
+            probe.num_cus = prop.multiProcessorCount;
+            int blocks = 1 << 30;
+            for (int d : {64, 128, 256})
+                blocks = std::min(blocks, small_update_blocks(probe, d, params->negatives));
+            s->bblocks = blocks;
+            s->batcher = std::thread(batcher_loop, s.get());
+        }
         for (int i = 0; i < params->slots; ++i) s->workers.emplace_back(worker_loop, s.get());
         *out = s.release();
     });
@@ -452,7 +584,15 @@ void felog_server_destroy(felog_server* s)
         s->stopping = true;
     }
     s->cv.notify_all();
-    for (auto& t : s->workers) t.join();
+    for (auto& t : s->workers) t.join();   // running jobs finish (with the batcher's help)
+    if (s->batcher.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->bmu);
+            s->bstop = true;
+        }
+        s->bcv.notify_all();
+        s->batcher.join();
+    }
     delete s;
 }
 

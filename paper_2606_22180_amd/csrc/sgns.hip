@@ -804,6 +804,10 @@ static TrainSchedule make_schedule(Walks& w, const felog_train_params& p)
     return s;
 }
 
+TrainSchedule train_schedule(Walks& w, const felog_train_params& p) { return make_schedule(w, p); }
+
+std::vector<int32_t> train_slices(int32_t L, int32_t window) { return make_slices(L, window); }
+
 int64_t count_minibatches(Walks& w, const felog_train_params& p, int64_t* total_pairs)
 {
     TrainSchedule s = make_schedule(w, p);

@@ -85,6 +85,14 @@ struct PlanArgs {
     unsigned long long* row_totals;// [3]: in rows, out rows, out rows touched once
 };
 
+// Plans of one launch: workgroups [start[j], start[j + 1]) plan the
+// minibatches of job j (one model and corpus per job).
+struct PlanBatch {
+    PlanArgs job[kMaxBatchJobs];
+    int32_t start[kMaxBatchJobs + 1];
+    int32_t njobs;
+};
+
 // Exclusive scan of one value per thread over the workgroup; *total gets the sum.
 __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32_t* total)
 {
@@ -115,21 +123,25 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* tmp, uint32
 }
 
 template <int K>
-__global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
+__global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanBatch pb)
 {
     constexpr int T = K + 2;
+    int jb = 0;
+    while (jb + 1 < pb.njobs && (int32_t)blockIdx.x >= pb.start[jb + 1]) ++jb;
+    const PlanArgs& a = pb.job[jb];
+    const uint32_t lb = blockIdx.x - (uint32_t)pb.start[jb];   // minibatch within the job's group
     __shared__ unsigned long long keys[kPlanMaxTouches];
     // segment starts (step 3); before that, the pairs' centres (step 1)
     __shared__ __align__(16) uint16_t seg_first[kPlanMaxTouches + 1];
     __shared__ uint32_t tmp[kPlanThreads / 64 + 1];
     __shared__ uint32_t counts[3];
-    const MbDesc d = a.desc[blockIdx.x];
+    const MbDesc d = a.desc[lb];
     const uint32_t nt = d.npairs * T;
     uint32_t N = 64;
     while (N < nt) N <<= 1;                 // nt <= kPlanMaxTouches (checked on the host)
-    int2* tinfo = a.tinfo + (int64_t)blockIdx.x * a.tmax;
-    int4* segs = a.segs + (int64_t)blockIdx.x * a.tmax;
-    int32_t* spair = a.spair + (int64_t)blockIdx.x * a.tmax;
+    int2* tinfo = a.tinfo + (int64_t)lb * a.tmax;
+    int4* segs = a.segs + (int64_t)lb * a.tmax;
+    int32_t* spair = a.spair + (int64_t)lb * a.tmax;
     const int32_t* vcols = a.vcols + d.vcol_base;
     if (threadIdx.x < 3) counts[threadIdx.x] = 0;
 
@@ -247,7 +259,7 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t* m = a.meta + (int64_t)blockIdx.x * 4;
+        uint32_t* m = a.meta + (int64_t)lb * 4;
         m[0] = n_apply;
         m[1] = counts[0];
         m[2] = nseg - counts[0];
@@ -259,20 +271,31 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanArgs a)
 }
 
 // ----------------------------------------------------------------- update
-struct UpdArgs {
+// One job's part of an update launch.
+struct UpdJob {
     float* tin;
     float* tout;
     const MbDesc* desc;            // [nmb]
     const int2* tinfo;             // [nmb][tmax]
     const int4* segs;              // [nmb][tmax]
     const uint32_t* meta;          // [nmb][4]
-    int32_t tmax;
-    int32_t nmb;
     const int32_t* spair;          // [nmb][tmax]: pair of each sorted position
     double* gpos;                  // [tmax]: FP64 coefficient of each out-touch, by position
     float* dinp;                   // [P][D]: each pair's in-row delta, by sorted position
     float* ctxc;                   // [P][D]: each pair's context row at the minibatch start
     double* loss_part;             // [waves]
+    int32_t tmax;
+    int32_t nmb;
+};
+
+// An update launch over the minibatches of up to kMaxBatchJobs jobs (equal d
+// and K): phase by phase, minibatch m of every job that has one.  The jobs'
+// tables are distinct, so their minibatches share each phase and its
+// barriers.
+struct UpdArgs {
+    UpdJob job[kMaxBatchJobs];
+    int32_t njobs;
+    int32_t nmb_max;               // largest nmb of the jobs
     uint32_t* flags;               // go flag at [0], workgroup b's at [kFlagStride (1 + b)];
                                    // zero at the call's start
     uint32_t epoch0;               // barriers passed by earlier launches of the call
@@ -345,202 +368,228 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
     const uint32_t gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     uint32_t epoch = a.epoch0;
     double lacc = 0.0;
-    // plan data of the next phase, loaded a phase ahead: this lane's touch of
-    // the wave's first pair group (forward) and the group's first segment with
-    // the pair of each of its first 16 positions (apply)
+    // plan data of job 0's next phase, loaded a phase ahead: this lane's touch
+    // of the wave's first pair group (forward) and the group's first segment
+    // with the pair of each of its first 16 positions (apply)
+    const UpdJob& J0 = a.job[0];
     auto first_touch = [&](int mm) -> int2 {
-        const uint32_t npm = a.desc[mm].npairs, q0 = gw * G;
+        const uint32_t npm = J0.desc[mm].npairs, q0 = gw * G;
         if (q0 < npm && lane < (int)min((uint32_t)G, npm - q0) * T)
-            return a.tinfo[(int64_t)mm * a.tmax + (int64_t)q0 * T + lane];
+            return J0.tinfo[(int64_t)mm * J0.tmax + (int64_t)q0 * T + lane];
         return make_int2(-1, -1);
     };
-    int2 pf_touch = a.nmb > 0 ? first_touch(0) : make_int2(-1, -1);
+    int2 pf_touch = J0.nmb > 0 ? first_touch(0) : make_int2(-1, -1);
+    const uint32_t sidx0 = gw * 4 + (uint32_t)g16;
 
-    for (int m = 0; m < a.nmb; ++m) {
-        const MbDesc dsc = a.desc[m];
-        const int2* ti = a.tinfo + (int64_t)m * a.tmax;
-        const int32_t* sp = a.spair + (int64_t)m * a.tmax;
-        const uint32_t np = dsc.npairs;
-        const double lr = (double)dsc.lr;
-        const uint32_t nseg = a.meta[(int64_t)m * 4], nin = a.meta[(int64_t)m * 4 + 1];
-        const int4* sg = a.segs + (int64_t)m * a.tmax;
-        const uint32_t sidx0 = gw * 4 + (uint32_t)g16;
-        const int4 pf_seg = sidx0 < nseg ? sg[sidx0] : make_int4(0, 0, 0, 0);
+    for (int m = 0; m < a.nmb_max; ++m) {
+        int4 pf_seg = make_int4(0, 0, 0, 0);
+        int32_t pf_pair = 0;
+        if (m < J0.nmb) {
+            const uint32_t nseg0 = J0.meta[(int64_t)m * 4];
+            if (sidx0 < nseg0) pf_seg = J0.segs[(int64_t)m * J0.tmax + sidx0];
+        }
 
-        // ---- forward: G pairs per wave at a time
-        for (uint32_t q0 = gw * G; q0 < np; q0 += nw * G) {
-            const int npw = (int)min((uint32_t)G, np - q0);
-            int32_t m_row = -1, m_code = -1;
-            if (q0 == gw * G) {
-                m_row = pf_touch.x;
-                m_code = pf_touch.y;
-            } else if (lane < npw * T) {
-                const int2 x = ti[(int64_t)q0 * T + lane];
-                m_row = x.x;
-                m_code = x.y;
-            }
-            const unsigned long long single = __ballot(m_code >= 0 && (m_code & kSingleBit));
-            const int p = grp;
-            const bool live = p < npw;
-            const uint32_t q = q0 + (uint32_t)p;
-            const int src = (live ? p : 0) * T;
-            const int32_t ctx = __shfl(m_row, src);
-            const int32_t pos_in = __shfl(m_code, src) & kPosMask;
-            int32_t t[K + 1];
-#pragma unroll
-            for (int k = 0; k <= K; ++k) t[k] = __shfl(m_row, src + 1 + k);
-            const int32_t my_code = __shfl(m_code, src + 1 + (gl <= K ? gl : 0));
-            int32_t my_code_hi = 0;
-            if (LPP == 16 && K >= 16) my_code_hi = __shfl(m_code, src + 1 + (gl + 16 <= K ? gl + 16 : 0));
-
-            float4 vin[V4];
-            float4 vo[K + 1][V4];
-            const float4* ri = reinterpret_cast<const float4*>(a.tin + (int64_t)(live ? ctx : 0) * D);
-#pragma unroll
-            for (int i = 0; i < V4; ++i) vin[i] = ri[i * LPP + gl];
-#pragma unroll
-            for (int k = 0; k <= K; ++k) {
-                const bool ok = live && t[k] >= 0;
-                const float4* ro = reinterpret_cast<const float4*>(a.tout + (int64_t)(ok ? t[k] : 0) * D);
-#pragma unroll
-                for (int i = 0; i < V4; ++i)
-                    vo[k][i] = ok ? ro[i * LPP + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
-            double g[K + 1];
-            coefficients<K, LPP, V4>(vin, vo, t, lr, live, gl, grp, g, lacc);
-            // entries of the out-touches (not the rows touched once)
-#pragma unroll
-            for (int h = 0; h < (K + LPP) / LPP; ++h) {
-                const int k = gl + h * LPP;
-                double gk = g[0];
-                int32_t tk = t[0];
-#pragma unroll
-                for (int jj = 1; jj <= K; ++jj)
-                    if (k == jj) {
-                        gk = g[jj];
-                        tk = t[jj];
-                    }
-                if (k <= K && live && tk >= 0 && !((single >> (src + 1 + k)) & 1ull)) {
-                    const int32_t code = h == 0 ? my_code : my_code_hi;
-                    a.gpos[code & kPosMask] = gk;
+        // ---- forward of every job's minibatch m: G pairs per wave at a time
+        for (int j = 0; j < a.njobs; ++j) {
+            const UpdJob& J = a.job[j];
+            if (m >= J.nmb) continue;
+            const MbDesc dsc = J.desc[m];
+            const int2* ti = J.tinfo + (int64_t)m * J.tmax;
+            const uint32_t np = dsc.npairs;
+            const double lr = (double)dsc.lr;
+            for (uint32_t q0 = gw * G; q0 < np; q0 += nw * G) {
+                const int npw = (int)min((uint32_t)G, np - q0);
+                int32_t m_row = -1, m_code = -1;
+                if (j == 0 && q0 == gw * G) {
+                    m_row = pf_touch.x;
+                    m_code = pf_touch.y;
+                } else if (lane < npw * T) {
+                    const int2 x = ti[(int64_t)q0 * T + lane];
+                    m_row = x.x;
+                    m_code = x.y;
                 }
-            }
-            // out rows touched once: row + g in[ctx] in FP64, rounded once
+                const unsigned long long single = __ballot(m_code >= 0 && (m_code & kSingleBit));
+                const int p = grp;
+                const bool live = p < npw;
+                const uint32_t q = q0 + (uint32_t)p;
+                const int src = (live ? p : 0) * T;
+                const int32_t ctx = __shfl(m_row, src);
+                const int32_t pos_in = __shfl(m_code, src) & kPosMask;
+                int32_t t[K + 1];
 #pragma unroll
-            for (int k = 0; k <= K; ++k) {
-                if (live && t[k] >= 0 && ((single >> (src + 1 + k)) & 1ull)) {
-                    float4* dst = reinterpret_cast<float4*>(a.tout + (int64_t)t[k] * D);
+                for (int k = 0; k <= K; ++k) t[k] = __shfl(m_row, src + 1 + k);
+                const int32_t my_code = __shfl(m_code, src + 1 + (gl <= K ? gl : 0));
+                int32_t my_code_hi = 0;
+                if (LPP == 16 && K >= 16) my_code_hi = __shfl(m_code, src + 1 + (gl + 16 <= K ? gl + 16 : 0));
+
+                float4 vin[V4];
+                float4 vo[K + 1][V4];
+                const float4* ri = reinterpret_cast<const float4*>(J.tin + (int64_t)(live ? ctx : 0) * D);
+#pragma unroll
+                for (int i = 0; i < V4; ++i) vin[i] = ri[i * LPP + gl];
+#pragma unroll
+                for (int k = 0; k <= K; ++k) {
+                    const bool ok = live && t[k] >= 0;
+                    const float4* ro = reinterpret_cast<const float4*>(J.tout + (int64_t)(ok ? t[k] : 0) * D);
+#pragma unroll
+                    for (int i = 0; i < V4; ++i)
+                        vo[k][i] = ok ? ro[i * LPP + gl] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+                double g[K + 1];
+                coefficients<K, LPP, V4>(vin, vo, t, lr, live, gl, grp, g, lacc);
+                // entries of the out-touches (not the rows touched once)
+#pragma unroll
+                for (int h = 0; h < (K + LPP) / LPP; ++h) {
+                    const int k = gl + h * LPP;
+                    double gk = g[0];
+                    int32_t tk = t[0];
+#pragma unroll
+                    for (int jj = 1; jj <= K; ++jj)
+                        if (k == jj) {
+                            gk = g[jj];
+                            tk = t[jj];
+                        }
+                    if (k <= K && live && tk >= 0 && !((single >> (src + 1 + k)) & 1ull)) {
+                        const int32_t code = h == 0 ? my_code : my_code_hi;
+                        J.gpos[code & kPosMask] = gk;
+                    }
+                }
+                // out rows touched once: row + g in[ctx] in FP64, rounded once
+#pragma unroll
+                for (int k = 0; k <= K; ++k) {
+                    if (live && t[k] >= 0 && ((single >> (src + 1 + k)) & 1ull)) {
+                        float4* dst = reinterpret_cast<float4*>(J.tout + (int64_t)t[k] * D);
+#pragma unroll
+                        for (int i = 0; i < V4; ++i) {
+                            const float4 b = vo[k][i];
+                            dst[i * LPP + gl] = make_float4((float)fma(g[k], (double)vin[i].x, (double)b.x),
+                                                            (float)fma(g[k], (double)vin[i].y, (double)b.y),
+                                                            (float)fma(g[k], (double)vin[i].z, (double)b.z),
+                                                            (float)fma(g[k], (double)vin[i].w, (double)b.w));
+                        }
+                    }
+                }
+                if (live) {
+                    float4* cc = reinterpret_cast<float4*>(J.ctxc + (int64_t)q * D);
+                    float4* dp = reinterpret_cast<float4*>(J.dinp + (int64_t)pos_in * D);
 #pragma unroll
                     for (int i = 0; i < V4; ++i) {
-                        const float4 b = vo[k][i];
-                        dst[i * LPP + gl] = make_float4((float)fma(g[k], (double)vin[i].x, (double)b.x),
-                                                        (float)fma(g[k], (double)vin[i].y, (double)b.y),
-                                                        (float)fma(g[k], (double)vin[i].z, (double)b.z),
-                                                        (float)fma(g[k], (double)vin[i].w, (double)b.w));
+                        cc[i * LPP + gl] = vin[i];
+                        double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
+#pragma unroll
+                        for (int k = 0; k <= K; ++k) {
+                            ax = fma(g[k], (double)vo[k][i].x, ax);
+                            ay = fma(g[k], (double)vo[k][i].y, ay);
+                            az = fma(g[k], (double)vo[k][i].z, az);
+                            aw = fma(g[k], (double)vo[k][i].w, aw);
+                        }
+                        dp[i * LPP + gl] = make_float4((float)ax, (float)ay, (float)az, (float)aw);
                     }
                 }
             }
-            if (live) {
-                float4* cc = reinterpret_cast<float4*>(a.ctxc + (int64_t)q * D);
-                float4* dp = reinterpret_cast<float4*>(a.dinp + (int64_t)pos_in * D);
-#pragma unroll
-                for (int i = 0; i < V4; ++i) {
-                    cc[i * LPP + gl] = vin[i];
-                    double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
-#pragma unroll
-                    for (int k = 0; k <= K; ++k) {
-                        ax = fma(g[k], (double)vo[k][i].x, ax);
-                        ay = fma(g[k], (double)vo[k][i].y, ay);
-                        az = fma(g[k], (double)vo[k][i].z, az);
-                        aw = fma(g[k], (double)vo[k][i].w, aw);
-                    }
-                    dp[i * LPP + gl] = make_float4((float)ax, (float)ay, (float)az, (float)aw);
-                }
+            if (a.njobs > 1) {
+                // each job's loss terms to its own partials
+                const double l = wave_sum_f64(lacc);
+                if (lane == 0) J.loss_part[gw] += l;
+                lacc = 0.0;
             }
         }
-        const int32_t pf_pair = (sidx0 < nseg && l16 < pf_seg.z) ? sp[pf_seg.y + l16] : 0;
+        if (m < J0.nmb) {
+            const uint32_t nseg0 = J0.meta[(int64_t)m * 4];
+            if (sidx0 < nseg0 && l16 < pf_seg.z) pf_pair = J0.spair[(int64_t)m * J0.tmax + pf_seg.y + l16];
+        }
         if (!grid_sync(a, epoch)) break;
 
         // ---- apply: one 16-lane group per segment, in and out rows together
-        if (m + 1 < a.nmb) pf_touch = first_touch(m + 1);
-        const double gc = dsc.grid_c;
-        for (uint32_t sidx = sidx0; sidx < nseg; sidx += nw * 4) {
-            const bool first_seg = sidx == sidx0;
-            const int4 sd = first_seg ? pf_seg : sg[sidx];
-            const bool out = sidx >= nin;
-            const int32_t row = sd.x, start = sd.y, len = sd.z;
-            float* table = out ? a.tout : a.tin;
-            const float* srcb = out ? a.ctxc : a.dinp;
-            float4 cur[AV4];
-            const float4* r4 = reinterpret_cast<const float4*>(table + (int64_t)row * D);
+        if (m + 1 < J0.nmb) pf_touch = first_touch(m + 1);
+        for (int j = 0; j < a.njobs; ++j) {
+            const UpdJob& J = a.job[j];
+            if (m >= J.nmb) continue;
+            const MbDesc dsc = J.desc[m];
+            const int32_t* sp = J.spair + (int64_t)m * J.tmax;
+            const uint32_t nseg = J.meta[(int64_t)m * 4], nin = J.meta[(int64_t)m * 4 + 1];
+            const int4* sg = J.segs + (int64_t)m * J.tmax;
+            const double gc = dsc.grid_c;
+            for (uint32_t sidx = sidx0; sidx < nseg; sidx += nw * 4) {
+                const bool first_seg = j == 0 && sidx == sidx0;
+                const int4 sd = first_seg ? pf_seg : sg[sidx];
+                const bool out = sidx >= nin;
+                const int32_t row = sd.x, start = sd.y, len = sd.z;
+                float* table = out ? J.tout : J.tin;
+                const float* srcb = out ? J.ctxc : J.dinp;
+                float4 cur[AV4];
+                const float4* r4 = reinterpret_cast<const float4*>(table + (int64_t)row * D);
 #pragma unroll
-            for (int i = 0; i < AV4; ++i) cur[i] = r4[i * 16 + l16];
-            double acc[D / 16];
+                for (int i = 0; i < AV4; ++i) cur[i] = r4[i * 16 + l16];
+                double acc[D / 16];
 #pragma unroll
-            for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
-            const bool exact = len > kChunk;
-            // touches in batches of 16, one descriptor per lane
-            for (int32_t b0 = 0; b0 < len; b0 += 16) {
-                const int32_t nb = min(16, len - b0);
-                // out rows: the touch's coefficient and its pair's context
-                // copy; in rows: the pair's delta at the touch's position
-                double my_g = 1.0;
-                int32_t my_src = start + b0 + l16;
-                if (out && l16 < nb) {
-                    my_g = a.gpos[start + b0 + l16];
-                    my_src = (first_seg && b0 == 0) ? pf_pair : sp[start + b0 + l16];
-                }
-                for (int32_t i0 = 0; i0 < nb; i0 += kRows) {
-                    double gg[kRows];
-                    float4 x[kRows][AV4];
-#pragma unroll
-                    for (int u = 0; u < kRows; ++u) {
-                        const bool ok = i0 + u < nb;
-                        const int32_t idx = min(i0 + u, 15);
-                        gg[u] = __shfl(my_g, (g16 << 4) + idx);
-                        const int32_t rr = __shfl(my_src, (g16 << 4) + idx);
-                        const float4* rp = reinterpret_cast<const float4*>(srcb + (int64_t)(ok ? rr : 0) * D);
-#pragma unroll
-                        for (int i = 0; i < AV4; ++i)
-                            x[u][i] = ok ? rp[i * 16 + l16] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                        if (!ok) gg[u] = 0.0;
+                for (int e = 0; e < D / 16; ++e) acc[e] = 0.0;
+                const bool exact = len > kChunk;
+                // touches in batches of 16, one descriptor per lane
+                for (int32_t b0 = 0; b0 < len; b0 += 16) {
+                    const int32_t nb = min(16, len - b0);
+                    // out rows: the touch's coefficient and its pair's context
+                    // copy; in rows: the pair's delta at the touch's position
+                    double my_g = 1.0;
+                    int32_t my_src = start + b0 + l16;
+                    if (out && l16 < nb) {
+                        my_g = J.gpos[start + b0 + l16];
+                        my_src = (first_seg && b0 == 0) ? pf_pair : sp[start + b0 + l16];
                     }
+                    for (int32_t i0 = 0; i0 < nb; i0 += kRows) {
+                        double gg[kRows];
+                        float4 x[kRows][AV4];
 #pragma unroll
-                    for (int u = 0; u < kRows; ++u) {
-                        if (i0 + u >= nb) break;
+                        for (int u = 0; u < kRows; ++u) {
+                            const bool ok = i0 + u < nb;
+                            const int32_t idx = min(i0 + u, 15);
+                            gg[u] = __shfl(my_g, (g16 << 4) + idx);
+                            const int32_t rr = __shfl(my_src, (g16 << 4) + idx);
+                            const float4* rp = reinterpret_cast<const float4*>(srcb + (int64_t)(ok ? rr : 0) * D);
 #pragma unroll
-                        for (int i = 0; i < AV4; ++i) {
-                            if (exact) {
-                                // order-free: each term rounded onto the grid, sums exact
-                                acc[4 * i + 0] += on_grid(gg[u] * (double)x[u][i].x, gc);
-                                acc[4 * i + 1] += on_grid(gg[u] * (double)x[u][i].y, gc);
-                                acc[4 * i + 2] += on_grid(gg[u] * (double)x[u][i].z, gc);
-                                acc[4 * i + 3] += on_grid(gg[u] * (double)x[u][i].w, gc);
-                            } else {
-                                // in rows: g = 1, and 1 * x + acc is exactly x + acc
-                                acc[4 * i + 0] = fma(gg[u], (double)x[u][i].x, acc[4 * i + 0]);
-                                acc[4 * i + 1] = fma(gg[u], (double)x[u][i].y, acc[4 * i + 1]);
-                                acc[4 * i + 2] = fma(gg[u], (double)x[u][i].z, acc[4 * i + 2]);
-                                acc[4 * i + 3] = fma(gg[u], (double)x[u][i].w, acc[4 * i + 3]);
+                            for (int i = 0; i < AV4; ++i)
+                                x[u][i] = ok ? rp[i * 16 + l16] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                            if (!ok) gg[u] = 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kRows; ++u) {
+                            if (i0 + u >= nb) break;
+#pragma unroll
+                            for (int i = 0; i < AV4; ++i) {
+                                if (exact) {
+                                    // order-free: each term rounded onto the grid, sums exact
+                                    acc[4 * i + 0] += on_grid(gg[u] * (double)x[u][i].x, gc);
+                                    acc[4 * i + 1] += on_grid(gg[u] * (double)x[u][i].y, gc);
+                                    acc[4 * i + 2] += on_grid(gg[u] * (double)x[u][i].z, gc);
+                                    acc[4 * i + 3] += on_grid(gg[u] * (double)x[u][i].w, gc);
+                                } else {
+                                    // in rows: g = 1, and 1 * x + acc is exactly x + acc
+                                    acc[4 * i + 0] = fma(gg[u], (double)x[u][i].x, acc[4 * i + 0]);
+                                    acc[4 * i + 1] = fma(gg[u], (double)x[u][i].y, acc[4 * i + 1]);
+                                    acc[4 * i + 2] = fma(gg[u], (double)x[u][i].z, acc[4 * i + 2]);
+                                    acc[4 * i + 3] = fma(gg[u], (double)x[u][i].w, acc[4 * i + 3]);
+                                }
                             }
                         }
                     }
                 }
-            }
-            float4* d4 = reinterpret_cast<float4*>(table + (int64_t)row * D);
+                float4* d4 = reinterpret_cast<float4*>(table + (int64_t)row * D);
 #pragma unroll
-            for (int i = 0; i < AV4; ++i) {
-                const float4 c = cur[i];
-                d4[i * 16 + l16] = make_float4((float)((double)c.x + acc[4 * i + 0]),
-                                               (float)((double)c.y + acc[4 * i + 1]),
-                                               (float)((double)c.z + acc[4 * i + 2]),
-                                               (float)((double)c.w + acc[4 * i + 3]));
+                for (int i = 0; i < AV4; ++i) {
+                    const float4 c = cur[i];
+                    d4[i * 16 + l16] = make_float4((float)((double)c.x + acc[4 * i + 0]),
+                                                   (float)((double)c.y + acc[4 * i + 1]),
+                                                   (float)((double)c.z + acc[4 * i + 2]),
+                                                   (float)((double)c.w + acc[4 * i + 3]));
+                }
             }
         }
         if (!grid_sync(a, epoch)) break;
     }
-    lacc = wave_sum_f64(lacc);
-    if (lane == 0) a.loss_part[gw] += lacc;
+    if (a.njobs == 1) {
+        lacc = wave_sum_f64(lacc);
+        if (lane == 0) J0.loss_part[gw] += lacc;
+    }
 }
 
 __global__ void zero_words_kernel(uint32_t* p, int32_t n)
@@ -600,12 +649,12 @@ static void* update_kernel(int D, int K)
     return update_kernel_d<256>(K);
 }
 
-static void launch_plan(int K, int nmb, const PlanArgs& pa, hipStream_t s)
+static void launch_plan(int K, int nblocks, const PlanBatch& pb, hipStream_t s)
 {
     switch (K) {
-#define FELOG_CASE(k)                                                                      \
-    case k:                                                                                \
-        hipLaunchKernelGGL((sgns_plan_kernel<k>), dim3(nmb), dim3(kPlanThreads), 0, s, pa); \
+#define FELOG_CASE(k)                                                                          \
+    case k:                                                                                    \
+        hipLaunchKernelGGL((sgns_plan_kernel<k>), dim3(nblocks), dim3(kPlanThreads), 0, s, pb); \
         break;
         FELOG_CASE(1) FELOG_CASE(2) FELOG_CASE(3) FELOG_CASE(4) FELOG_CASE(5) FELOG_CASE(6)
         FELOG_CASE(7) FELOG_CASE(8) FELOG_CASE(9) FELOG_CASE(10) FELOG_CASE(11) FELOG_CASE(12)
@@ -617,33 +666,15 @@ static void launch_plan(int K, int nmb, const PlanArgs& pa, hipStream_t s)
     FELOG_HIP(hipGetLastError());
 }
 
-void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
-                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
-                             int64_t end, felog_train_stats* stats)
+// Model-owned buffers of the persistent path, grown on demand: two sets of
+// plan buffers for 64 minibatches (the plans of launch group i + 1 are
+// written while the update of group i reads set i mod 2), the out-touch
+// coefficients, and each pair's in-row delta and context copy.
+static void small_buffers(Model& m, int64_t P, int32_t tmax)
 {
     Ctx& c = *m.ctx;
-    const int K = p.negatives;
-    const int D = m.dim;
-    const int64_t P = p.minibatch_pairs;
-    const int32_t tmax = (int32_t)(P * (K + 2));
-    FELOG_REQUIRE(tmax <= kPlanMaxTouches, "minibatch of %lld pairs is too large for the "
-                  "small-minibatch update", (long long)P);
-    FELOG_REQUIRE(D == 64 || D == 128 || D == 256, "dim %d not supported", D);
     const int64_t G = small_minibatches_per_launch();
-    void* kern = update_kernel(D, K);
-
-    // workgroups of the persistent launch: all co-resident (cooperative)
-    int per_cu = 0;
-    FELOG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kUpdThreads, 0));
-    FELOG_REQUIRE(per_cu >= 1, "the update kernel does not fit a compute unit");
-    const int64_t max_blocks = (int64_t)per_cu * c.num_cus;
-    const int64_t want = c.sgns_blocks > 0 ? c.sgns_blocks : kDefaultUpdBlocks;
-    const int nblocks = (int)std::max<int64_t>(1, std::min(want, max_blocks));
-    const int nwaves = nblocks * (kUpdThreads / 64);
-
-    // buffers (model-owned, grown on demand)
-    // two sets of plan buffers: the plans of launch group i + 1 are written
-    // (on the second stream) while the update of group i reads set i mod 2
+    const int D = m.dim;
     if (m.sm_tmax < tmax || m.sm_G < 2 * G) {
         m.sm_tmax = std::max<int64_t>(m.sm_tmax, tmax);
         m.sm_G = std::max<int64_t>(m.sm_G, 2 * G);
@@ -654,25 +685,17 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
         m.sm_gpos.alloc(&c, sizeof(double) * m.sm_tmax);
     }
     if (m.sm_pairs < P || m.sm_dim != D) {
-        // each pair's in-row delta and context copy: P rows of d floats
         m.sm_pairs = std::max<int64_t>(m.sm_pairs, P);
         m.sm_dim = D;
         m.sm_dinp.alloc(&c, sizeof(float) * m.sm_pairs * D);
         m.sm_ctxc.alloc(&c, sizeof(float) * m.sm_pairs * D);
     }
-    // control words: barrier flags (go, then one per workgroup, each on its
-    // own 128-byte line), the abort flag on the next line, then the loss
-    // partials, one per wave
-    const int64_t ctl_words = (int64_t)kFlagStride * (nblocks + 2);
-    DevBuf ctl;
-    ctl.alloc(&c, sizeof(uint32_t) * ctl_words + sizeof(double) * nwaves);
-    uint32_t* flags = ctl.as<uint32_t>();
-    int32_t* abort = reinterpret_cast<int32_t*>(flags + (int64_t)kFlagStride * (nblocks + 1));
-    double* loss_part = reinterpret_cast<double*>(flags + ctl_words);
-    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, c.stream, flags,
-                       (int32_t)(ctl.bytes / sizeof(uint32_t)));
-    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
+}
 
+// Plan arguments of a training call (plan set 0; the caller offsets them).
+static PlanArgs plan_args(Model& m, Walks& w, const felog_train_params& p,
+                          const int32_t* d_slices, int32_t tmax)
+{
     PlanArgs pa{};
     pa.walks = w.data.as<int32_t>();
     pa.W = w.W;
@@ -689,49 +712,260 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     pa.spair = m.sm_spair.as<int32_t>();
     pa.meta = m.sm_meta.as<uint32_t>();
     pa.row_totals = m.row_totals.as<unsigned long long>();
+    return pa;
+}
 
-    // every minibatch's descriptor, uploaded once for the call
+// Descriptors of minibatches [first_mb, end); *last_chunk gets the chunk of
+// the last minibatch of each launch group of G, *pairs the pair count.
+static std::vector<MbDesc> mb_descs(const Walks& w, const felog_train_params& p,
+                                    const TrainSchedule& sch, int64_t first_mb, int64_t end,
+                                    int64_t G, std::vector<size_t>* last_chunk, int64_t* pairs)
+{
+    const int64_t P = p.minibatch_pairs;
     const double lr0 = (double)p.lr_start, lr1 = (double)p.lr_end;
     std::vector<MbDesc> desc((size_t)std::max<int64_t>(1, end - first_mb));
+    size_t chunk = 0;
+    *pairs = 0;
+    for (int64_t b = first_mb; b < end; ++b) {
+        while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b) ++chunk;
+        const int64_t first = (b - sch.chunk_first_mb[chunk]) * P;
+        const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
+        MbDesc& d = desc[(size_t)(b - first_mb)];
+        d.vcol_base = sch.chunk_valid_base[chunk];
+        d.Wv = (uint32_t)w.chunk_valid[chunk];
+        d.first_pair = (uint32_t)first;
+        d.npairs = (uint32_t)np;
+        const double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
+        d.lr = (float)lr;
+        d.grid_c = d.lr > 0.0f ? std::ldexp(1.5, std::ilogb(d.lr) + 17) : 1.5;
+        *pairs += np;
+        if (last_chunk && ((b - first_mb) % G == G - 1 || b == end - 1)) last_chunk->push_back(chunk);
+    }
+    return desc;
+}
+
+// Workgroups of a persistent update launch: the context's choice (default 64),
+// capped at what is resident at once (the launch is cooperative).
+int small_update_blocks(const Ctx& c, int D, int K)
+{
+    int per_cu = 0;
+    FELOG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, update_kernel(D, K),
+                                                           kUpdThreads, 0));
+    FELOG_REQUIRE(per_cu >= 1, "the update kernel does not fit a compute unit");
+    const int64_t max_blocks = (int64_t)per_cu * c.num_cus;
+    const int64_t want = c.sgns_blocks > 0 ? c.sgns_blocks : kDefaultUpdBlocks;
+    return (int)std::max<int64_t>(1, std::min(want, max_blocks));
+}
+
+// ------------------------------------------------------- shared launches
+// A training call of one model (one job) run inside launches shared with
+// other jobs: plans and updates of the jobs' next launch groups together.
+struct SmallJob {
+    Model* m = nullptr;
+    Walks* w = nullptr;
+    felog_train_params p{};
+    TrainSchedule sch;
+    DevBuf slices, ddesc, loss;
+    int K = 0, D = 0;
+    int32_t tmax = 0;
+    int64_t next = 0, end = 0, pairs = 0;
+    int nwaves = 0;
+    PlanArgs pa{};
+    UpdJob uj{};
+};
+
+void SmallJobDeleter::operator()(SmallJob* j) const { delete j; }
+
+bool small_job_fits(const Model& m, const felog_train_params& p)
+{
+    return m.precision == FELOG_PREC_FP32 && p.negatives <= 20 &&
+           p.minibatch_pairs * (p.negatives + 2) <= kPlanMaxTouches &&
+           (m.dim == 64 || m.dim == 128 || m.dim == 256);
+}
+
+SmallJobPtr small_job_begin(Model& m, Walks& w, const felog_train_params& p, int nblocks)
+{
+    Ctx& c = *m.ctx;
+    FELOG_REQUIRE(small_job_fits(m, p), "the job does not fit the shared persistent update");
+    SmallJobPtr j(new SmallJob);
+    j->m = &m;
+    j->w = &w;
+    j->p = p;
+    j->sch = train_schedule(w, p);
+    j->K = p.negatives;
+    j->D = m.dim;
+    j->tmax = (int32_t)(p.minibatch_pairs * (p.negatives + 2));
+    j->end = j->sch.B;
+    j->nwaves = nblocks * (kUpdThreads / 64);
+    small_buffers(m, p.minibatch_pairs, j->tmax);
+    const std::vector<int32_t> sl = train_slices(w.L, p.window);
+    j->slices.alloc(&c, sizeof(int32_t) * std::max<size_t>(sl.size(), 1));
+    if (!sl.empty())
+        FELOG_HIP(hipMemcpyAsync(j->slices.ptr, sl.data(), sizeof(int32_t) * sl.size(),
+                                 hipMemcpyHostToDevice, c.stream));
+    const std::vector<MbDesc> desc =
+        mb_descs(w, p, j->sch, 0, j->end, small_minibatches_per_launch(), nullptr, &j->pairs);
+    j->ddesc.alloc(&c, sizeof(MbDesc) * desc.size());
+    FELOG_HIP(hipMemcpyAsync(j->ddesc.ptr, desc.data(), sizeof(MbDesc) * desc.size(),
+                             hipMemcpyHostToDevice, c.stream));
+    j->loss.alloc(&c, sizeof(double) * j->nwaves);
+    FELOG_HIP(hipMemsetAsync(j->loss.ptr, 0, j->loss.bytes, c.stream));
+    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
+    j->pa = plan_args(m, w, p, j->slices.as<int32_t>(), j->tmax);
+    j->uj.tin = m.tin.as<float>();
+    j->uj.tout = m.tout.as<float>();
+    j->uj.tmax = j->tmax;
+    j->uj.gpos = m.sm_gpos.as<double>();
+    j->uj.dinp = m.sm_dinp.as<float>();
+    j->uj.ctxc = m.sm_ctxc.as<float>();
+    j->uj.loss_part = j->loss.as<double>();
+    c.sync();   // the buffers are ready before another stream uses them
+    return j;
+}
+
+int small_job_dim(const SmallJob& j) { return j.D; }
+int small_job_negatives(const SmallJob& j) { return j.K; }
+bool small_job_done(const SmallJob& j) { return j.next >= j.end; }
+
+void small_batch_init(SmallBatchCtl& ctl, Ctx& c, int nblocks)
+{
+    ctl.nblocks = nblocks;
+    ctl.epoch = 0;
+    ctl.words.alloc(&c, sizeof(uint32_t) * kFlagStride * (nblocks + 2));
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, c.stream,
+                       ctl.words.as<uint32_t>(), (int32_t)(ctl.words.bytes / sizeof(uint32_t)));
+    FELOG_HIP(hipGetLastError());
+    c.sync();
+}
+
+void small_jobs_step(const std::vector<SmallJob*>& jobs, SmallBatchCtl& ctl, hipStream_t s)
+{
+    FELOG_REQUIRE(!jobs.empty() && jobs.size() <= (size_t)kMaxBatchJobs,
+                  "a shared launch takes 1 to %d jobs", kMaxBatchJobs);
+    const int K = jobs[0]->K, D = jobs[0]->D;
+    const int64_t G = small_minibatches_per_launch();
+    PlanBatch pb{};
+    UpdArgs u{};
+    int nb = 0, nmb_max = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        SmallJob& j = *jobs[i];
+        FELOG_REQUIRE(j.K == K && j.D == D && !small_job_done(j),
+                      "jobs of a shared launch need equal d and K and minibatches left");
+        FELOG_REQUIRE(j.nwaves == ctl.nblocks * (kUpdThreads / 64),
+                      "job prepared for another grid size");
+        const int nmb = (int)std::min<int64_t>(G, j.end - j.next);
+        PlanArgs pl = j.pa;
+        pl.desc = j.ddesc.as<MbDesc>() + j.next;
+        pb.job[i] = pl;
+        pb.start[i] = nb;
+        nb += nmb;
+        UpdJob uj = j.uj;
+        uj.desc = pl.desc;
+        uj.tinfo = pl.tinfo;
+        uj.segs = pl.segs;
+        uj.spair = pl.spair;
+        uj.meta = pl.meta;
+        uj.nmb = nmb;
+        u.job[i] = uj;
+        nmb_max = std::max(nmb_max, nmb);
+        j.next += nmb;
+    }
+    pb.start[jobs.size()] = nb;
+    pb.njobs = (int32_t)jobs.size();
+    launch_plan(K, nb, pb, s);
+    u.njobs = (int32_t)jobs.size();
+    u.nmb_max = nmb_max;
+    u.flags = ctl.words.as<uint32_t>();
+    u.abort = reinterpret_cast<int32_t*>(u.flags + (int64_t)kFlagStride * (ctl.nblocks + 1));
+    u.epoch0 = ctl.epoch;
+    void* args[] = {&u};
+    FELOG_HIP(hipLaunchCooperativeKernel(update_kernel(D, K), dim3(ctl.nblocks), dim3(kUpdThreads),
+                                         args, 0, s));
+    ctl.epoch += 2u * (uint32_t)nmb_max;
+}
+
+bool small_batch_aborted(SmallBatchCtl& ctl, hipStream_t s)
+{
+    int32_t aborted = 0;
+    const int32_t* abort =
+        reinterpret_cast<const int32_t*>(ctl.words.as<uint32_t>() + (int64_t)kFlagStride * (ctl.nblocks + 1));
+    FELOG_HIP(hipMemcpyAsync(&aborted, abort, sizeof aborted, hipMemcpyDeviceToHost, s));
+    FELOG_HIP(hipStreamSynchronize(s));
+    return aborted != 0;
+}
+
+void small_job_end(SmallJob& j, hipStream_t s, felog_train_stats* stats)
+{
+    Model& m = *j.m;
+    launch_loss_reduce(j.loss.as<double>(), j.nwaves, m.loss_out.as<double>(), s);
+    double loss = 0.0;
+    unsigned long long rows[3] = {0, 0, 0};
+    FELOG_HIP(hipMemcpyAsync(&loss, m.loss_out.ptr, sizeof loss, hipMemcpyDeviceToHost, s));
+    FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost, s));
+    FELOG_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        *stats = felog_train_stats{};
+        stats->minibatches = j.end;
+        stats->pairs = j.pairs;
+        stats->minibatches_total = j.sch.B;
+        stats->loss = loss;
+        stats->rows_in = (int64_t)rows[0];
+        stats->rows_out = (int64_t)rows[1];
+        stats->rows_out_single = (int64_t)rows[2];
+        stats->path = 1;
+    }
+}
+
+void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
+                             const TrainSchedule& sch, const int32_t* d_slices, int64_t first_mb,
+                             int64_t end, felog_train_stats* stats)
+{
+    Ctx& c = *m.ctx;
+    const int K = p.negatives;
+    const int D = m.dim;
+    const int64_t P = p.minibatch_pairs;
+    const int32_t tmax = (int32_t)(P * (K + 2));
+    FELOG_REQUIRE(tmax <= kPlanMaxTouches, "minibatch of %lld pairs is too large for the "
+                  "small-minibatch update", (long long)P);
+    FELOG_REQUIRE(D == 64 || D == 128 || D == 256, "dim %d not supported", D);
+    const int64_t G = small_minibatches_per_launch();
+    void* kern = update_kernel(D, K);
+    const int nblocks = small_update_blocks(c, D, K);
+    const int nwaves = nblocks * (kUpdThreads / 64);
+
+    small_buffers(m, P, tmax);
+    // control words: barrier flags (go, then one per workgroup, each on its
+    // own 128-byte line), the abort flag on the next line, then the loss
+    // partials, one per wave
+    const int64_t ctl_words = (int64_t)kFlagStride * (nblocks + 2);
+    DevBuf ctl;
+    ctl.alloc(&c, sizeof(uint32_t) * ctl_words + sizeof(double) * nwaves);
+    uint32_t* flags = ctl.as<uint32_t>();
+    int32_t* abort = reinterpret_cast<int32_t*>(flags + (int64_t)kFlagStride * (nblocks + 1));
+    double* loss_part = reinterpret_cast<double*>(flags + ctl_words);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, c.stream, flags,
+                       (int32_t)(ctl.bytes / sizeof(uint32_t)));
+    FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
+
+    const PlanArgs pa = plan_args(m, w, p, d_slices, tmax);
+
+    // every minibatch's descriptor, uploaded once for the call
     std::vector<size_t> last_chunk;   // chunk of the last minibatch of each launch
     int64_t pairs = 0;
-    {
-        size_t chunk = 0;
-        for (int64_t b = first_mb; b < end; ++b) {
-            while (chunk + 1 < sch.chunk_first_mb.size() && sch.chunk_first_mb[chunk + 1] <= b)
-                ++chunk;
-            const int64_t first = (b - sch.chunk_first_mb[chunk]) * P;
-            const int64_t np = std::min<int64_t>(P, sch.chunk_pairs[chunk] - first);
-            MbDesc& d = desc[(size_t)(b - first_mb)];
-            d.vcol_base = sch.chunk_valid_base[chunk];
-            d.Wv = (uint32_t)w.chunk_valid[chunk];
-            d.first_pair = (uint32_t)first;
-            d.npairs = (uint32_t)np;
-            const double lr = lr0 - (lr0 - lr1) * (double)b / (double)std::max<int64_t>(1, sch.B - 1);
-            d.lr = (float)lr;
-            d.grid_c = d.lr > 0.0f ? std::ldexp(1.5, std::ilogb(d.lr) + 17) : 1.5;
-            pairs += np;
-            if ((b - first_mb) % G == G - 1 || b == end - 1) last_chunk.push_back(chunk);
-        }
-    }
+    const std::vector<MbDesc> desc = mb_descs(w, p, sch, first_mb, end, G, &last_chunk, &pairs);
     DevBuf ddesc;
     ddesc.alloc(&c, sizeof(MbDesc) * desc.size());
     FELOG_HIP(hipMemcpyAsync(ddesc.ptr, desc.data(), sizeof(MbDesc) * desc.size(),
                              hipMemcpyHostToDevice, c.stream));
 
-    UpdArgs ua{};
-    ua.tin = m.tin.as<float>();
-    ua.tout = m.tout.as<float>();
-    ua.tinfo = pa.tinfo;
-    ua.segs = pa.segs;
-    ua.meta = pa.meta;
-    ua.tmax = tmax;
-    ua.gpos = m.sm_gpos.as<double>();
-    ua.dinp = m.sm_dinp.as<float>();
-    ua.ctxc = m.sm_ctxc.as<float>();
-    ua.loss_part = loss_part;
-    ua.flags = flags;
-    ua.abort = abort;
+    UpdJob uj{};
+    uj.tin = m.tin.as<float>();
+    uj.tout = m.tout.as<float>();
+    uj.tmax = tmax;
+    uj.gpos = m.sm_gpos.as<double>();
+    uj.dinp = m.sm_dinp.as<float>();
+    uj.ctxc = m.sm_ctxc.as<float>();
+    uj.loss_part = loss_part;
 
     // Plans run on the context's second stream one launch group ahead of the
     // updates: plan(i) waits for update(i - 2) (its buffer set), update(i)
@@ -783,19 +1017,29 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
         pl.segs = pa.segs + (int64_t)set * G * tmax;
         pl.spair = pa.spair + (int64_t)set * G * tmax;
         pl.meta = pa.meta + (int64_t)set * G * 4;
+        PlanBatch pb{};
+        pb.job[0] = pl;
+        pb.start[0] = 0;
+        pb.start[1] = nmb;
+        pb.njobs = 1;
         if (e) FELOG_HIP(hipEventRecord(e[0], ps));
-        launch_plan(K, nmb, pl, ps);
+        launch_plan(K, nmb, pb, ps);
         if (e) FELOG_HIP(hipEventRecord(e[1], ps));
         FELOG_HIP(hipEventRecord(c.pipe_ev[1 + set], ps));
         // update of group li, on the context's stream
         FELOG_HIP(hipStreamWaitEvent(c.stream, c.pipe_ev[1 + set], 0));
-        UpdArgs u = ua;
-        u.desc = pl.desc;
-        u.tinfo = pl.tinfo;
-        u.segs = pl.segs;
-        u.spair = pl.spair;
-        u.meta = pl.meta;
-        u.nmb = nmb;
+        UpdArgs u{};
+        u.job[0] = uj;
+        u.job[0].desc = pl.desc;
+        u.job[0].tinfo = pl.tinfo;
+        u.job[0].segs = pl.segs;
+        u.job[0].spair = pl.spair;
+        u.job[0].meta = pl.meta;
+        u.job[0].nmb = nmb;
+        u.njobs = 1;
+        u.nmb_max = nmb;
+        u.flags = flags;
+        u.abort = abort;
         u.epoch0 = epoch;
         void* args[] = {&u};
         if (e) FELOG_HIP(hipEventRecord(e[2], c.stream));

@@ -92,7 +92,7 @@ class felog_run_stats(C.Structure):
 
 class felog_server_params(C.Structure):
     _fields_ = [("slots", C.c_int32), ("minibatch_pairs", C.c_int64), ("negatives", C.c_int32),
-                ("lr_start", C.c_float), ("lr_end", C.c_float), ("persistent", C.c_int32)]
+                ("lr_start", C.c_float), ("lr_end", C.c_float), ("update_mode", C.c_int32)]
 
 
 class felog_job_desc(C.Structure):
@@ -110,6 +110,7 @@ class felog_job_state(C.Structure):
 
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+SERVE_LAUNCHES, SERVE_PERSISTENT, SERVE_SHARED = 0, 1, 2
 
 _p = C.c_void_p
 _pp = C.POINTER(C.c_void_p)
@@ -567,9 +568,9 @@ class Server:
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, *, slots: int = 4,
                  minibatch_pairs: int = 65536, negatives: int = 5, lr_start: float = 0.025,
-                 lr_end: float = 1e-4, persistent: bool = False):
+                 lr_end: float = 1e-4, update_mode: int = 0):
         prm = felog_server_params(slots, minibatch_pairs, negatives, lr_start, lr_end,
-                                  1 if persistent else 0)
+                                  update_mode)
         h = C.c_void_p()
         _check(load().felog_server_create(device, hbm_budget, C.byref(prm), C.byref(h)))
         self.handle = h

@@ -132,14 +132,16 @@ def test_serving_persistent_jobs_concurrent(fl):
     launches."""
     jobs = _jobs()[:8]
     alone = {}
-    S1 = fl.Server(0, 0, slots=1, minibatch_pairs=1024, negatives=5, persistent=False)
+    S1 = fl.Server(0, 0, slots=1, minibatch_pairs=1024, negatives=5,
+                   update_mode=fl.SERVE_LAUNCHES)
     for j, g in jobs:
         jid = S1.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
                         window=j["window"], seed=j["seed"])
         st = S1.wait(jid, 300.0)
         alone[j["job"]] = (S1.fetch(jid), st.loss, st.t_done - st.t_admit)
     S1.close()
-    S4 = fl.Server(0, 0, slots=4, minibatch_pairs=1024, negatives=5, persistent=True)
+    S4 = fl.Server(0, 0, slots=4, minibatch_pairs=1024, negatives=5,
+                   update_mode=fl.SERVE_PERSISTENT)
     ids = [(j, S4.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
                          window=j["window"], seed=j["seed"])) for j, g in jobs]
     for j, jid in ids:
@@ -152,3 +154,42 @@ def test_serving_persistent_jobs_concurrent(fl):
         # the two paths sum the loss terms in different orders
         assert st.state == fl.JOB_DONE and same and abs(st.loss - loss) <= 1e-12 * abs(loss)
     S4.close()
+
+
+def test_serving_shared_launches(fl):
+    """Jobs training in shared persistent launches (up to 8 running jobs of
+    equal d per launch; here 3 slots, jobs of d = 64 and 128, minibatches of
+    at most 1,024 pairs, and one job whose P is 2,048, which keeps its
+    per-minibatch launches) give the same embeddings as each job alone on the
+    per-minibatch launches, and every job's loss within 1e-12."""
+    jobs = [jg for jg in _jobs() if jg[0]["n"] <= 1024][:6]
+    extra = synth.job_mix(1, seed=5, n_min=1500, n_max=1800)[0]
+    jobs.append((extra, synth.job_graph(extra)))
+    _say("shared launches: jobs n = %s, d = %s" % ([j["n"] for j, _ in jobs],
+                                                     [j["dim"] for j, _ in jobs]))
+    alone = {}
+    S1 = fl.Server(0, 0, slots=1, minibatch_pairs=2048, negatives=5,
+                   update_mode=fl.SERVE_LAUNCHES)
+    for j, g in jobs:
+        jid = S1.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                        window=j["window"], seed=j["seed"])
+        st = S1.wait(jid, 300.0)
+        alone[j["job"], j["n"]] = (S1.fetch(jid), st.loss, st.t_done - st.t_admit,
+                                   st.minibatch_pairs)
+    S1.close()
+    S3 = fl.Server(0, 0, slots=3, minibatch_pairs=2048, negatives=5,
+                   update_mode=fl.SERVE_SHARED)
+    ids = [(j, S3.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                         window=j["window"], seed=j["seed"])) for j, g in jobs]
+    for j, jid in ids:
+        st = S3.wait(jid, 300.0)
+        emb, loss, t_alone, P = alone[j["job"], j["n"]]
+        same = np.array_equal(S3.fetch(jid), emb)
+        _say("job %d n=%d d=%d P=%d: shared launches equal to alone: %s, service %.3f s "
+             "(alone %.3f s)" % (j["job"], j["n"], j["dim"], st.minibatch_pairs, same,
+                                 st.t_done - st.t_admit, t_alone))
+        assert st.state == fl.JOB_DONE and same and st.minibatch_pairs == P
+        assert abs(st.loss - loss) <= 1e-12 * abs(loss)
+    S3.close()
+    with pytest.raises(fl.FelogError):
+        fl.Server(0, 0, slots=4, minibatch_pairs=1024, negatives=5, update_mode=fl.SERVE_SHARED)
