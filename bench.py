@@ -692,6 +692,9 @@ def main():
     ap.add_argument("--c3-minibatches", type=int, default=20000, help="0 skips the C3 leg")
     ap.add_argument("--serving-jobs", type=int, default=8, help="0 skips the serving sample")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--large-minibatches", type=int, default=256,
+                    help="minibatches of 65,536 pairs on the headline graph after the timed "
+                         "steps (0 skips)")
     ap.add_argument("--no-c2-per-round", action="store_true",
                     help="skip the per-round AUC / hub-norm rerun of the Algorithm 1 leg")
     ap.add_argument("--ablation", action="store_true",
@@ -775,16 +778,24 @@ def main():
                              lr_end=cfg["lr_end"], minibatch_pairs=cfg["minibatch"],
                              seed=cfg["seed_train"])
 
-    def step(s):
-        c = s % n_chunks
-        first = c * CHUNK
+    def chunk_starts(s):
+        """Walk id base and start list of corpus chunk s mod 80."""
+        first = (s % n_chunks) * CHUNK
         off = first % g.n
         if off not in offsets:
             offsets[off] = felog.Active.from_host(G, np.arange(off, off + CHUNK, dtype=np.int32))
+        return first, off
+
+    def chunk_walks(first, off):
+        """The chunk's walks: the corpus's own walk ids and start nodes."""
+        return felog.Walks.generate(G, r=1, L=cfg["L"], seed=cfg["seed_walk"], id_base=first,
+                                    kind=felog.WALK_NODE2VEC, p=cfg["p"], q=cfg["q"],
+                                    starts=offsets[off])
+
+    def step(s):
+        first, off = chunk_starts(s)
         t0 = time.perf_counter()
-        W = felog.Walks.generate(G, r=1, L=cfg["L"], seed=cfg["seed_walk"], id_base=first,
-                                 kind=felog.WALK_NODE2VEC, p=cfg["p"], q=cfg["q"],
-                                 starts=offsets[off])
+        W = chunk_walks(first, off)
         t1 = time.perf_counter()
         st = M.train_steps(W, prm, 0, args.mb_per_step)
         W.close()
@@ -834,6 +845,29 @@ def main():
         "pairs_per_step": pairs / args.steps, "node2vec_capped": int(capped),
         "roofline": roof,
     }
+    if args.large_minibatches > 0:
+        # the same graph, walks and model at the plain FP32 configuration's
+        # minibatch of 65,536 pairs (per-minibatch launches), outside the
+        # timed steps: the rate at which the C4 graph trains in large minibatches
+        W = chunk_walks(*chunk_starts(args.steps + args.warmup))
+        prm_l = felog.train_params(window=cfg["window"], negatives=cfg["K"], lr_start=cfg["lr0"],
+                                   lr_end=cfg["lr_end"], minibatch_pairs=65536,
+                                   seed=cfg["seed_train"])
+        M.train_steps(W, prm_l, 0, 4)
+        ctx.set_timing(4)
+        st = M.train_steps(W, prm_l, 4, args.large_minibatches)
+        ctx.set_timing(0)
+        W.close()
+        lr_roof = sgns_roofline([st], cfg["dim"], cfg["K"], st.pairs)
+        out["c4_minibatch_65536"] = {
+            "minibatches": int(st.minibatches), "pairs": int(st.pairs),
+            "pair_updates_per_s": st.pairs / (st.ms / 1e3),
+            "us_per_minibatch": st.ms / st.minibatches * 1e3,
+            "dominant_kernel": lr_roof["kernel"], "achieved_gbs": lr_roof["achieved"],
+            "frac": lr_roof["frac"], "sgns_update": lr_roof["sgns_update"]}
+        log("c4 at P = 65536: %.4g pair-updates/s, %.1f us per minibatch, %s at %.3f of HBM"
+            % (st.pairs / (st.ms / 1e3), st.ms / st.minibatches * 1e3, lr_roof["kernel"],
+               lr_roof["frac"]))
     G.close()
     M.close()
     for a in offsets.values():

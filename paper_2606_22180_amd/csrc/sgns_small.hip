@@ -760,6 +760,10 @@ int small_update_blocks(const Ctx& c, int D, int K)
 // ------------------------------------------------------- shared launches
 // A training call of one model (one job) run inside launches shared with
 // other jobs: plans and updates of the jobs' next launch groups together.
+// Its plans run on the model's own stream one launch group ahead of the
+// shared updates, in two buffer sets (group g uses set g mod 2): the plan of
+// group g waits for the update of group g - 2, the update of group g for the
+// plan of group g.
 struct SmallJob {
     Model* m = nullptr;
     Walks* w = nullptr;
@@ -768,13 +772,56 @@ struct SmallJob {
     DevBuf slices, ddesc, loss;
     int K = 0, D = 0;
     int32_t tmax = 0;
-    int64_t next = 0, end = 0, pairs = 0;
+    int64_t next = 0;        // first minibatch not yet updated
+    int64_t planned = 0;     // first minibatch whose plan is not launched
+    int64_t end = 0, pairs = 0;
     int nwaves = 0;
     PlanArgs pa{};
     UpdJob uj{};
+    hipEvent_t plan_done[2] = {nullptr, nullptr};
+    hipEvent_t upd_done[2] = {nullptr, nullptr};
+    ~SmallJob()
+    {
+        for (hipEvent_t e : {plan_done[0], plan_done[1], upd_done[0], upd_done[1]})
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 void SmallJobDeleter::operator()(SmallJob* j) const { delete j; }
+
+// Plan arguments of a job's launch group starting at minibatch b (set b / G mod 2).
+static PlanArgs group_plan(const SmallJob& j, int64_t b)
+{
+    const int64_t G = small_minibatches_per_launch();
+    const int64_t set = (b / G) & 1;
+    PlanArgs pl = j.pa;
+    pl.desc = j.ddesc.as<MbDesc>() + b;
+    pl.tinfo = j.pa.tinfo + set * G * j.tmax;
+    pl.segs = j.pa.segs + set * G * j.tmax;
+    pl.spair = j.pa.spair + set * G * j.tmax;
+    pl.meta = j.pa.meta + set * G * 4;
+    return pl;
+}
+
+// Launches the plan of the job's next unplanned launch group on its model's stream.
+static void plan_next_group(SmallJob& j)
+{
+    const int64_t G = small_minibatches_per_launch();
+    if (j.planned >= j.end) return;
+    const int64_t g = j.planned / G;
+    const int set = (int)(g & 1);
+    hipStream_t js = j.m->ctx->stream;
+    if (g >= 2) FELOG_HIP(hipStreamWaitEvent(js, j.upd_done[set], 0));
+    const int nmb = (int)std::min<int64_t>(G, j.end - j.planned);
+    PlanBatch pb{};
+    pb.job[0] = group_plan(j, j.planned);
+    pb.start[0] = 0;
+    pb.start[1] = nmb;
+    pb.njobs = 1;
+    launch_plan(j.K, nmb, pb, js);
+    FELOG_HIP(hipEventRecord(j.plan_done[set], js));
+    j.planned += nmb;
+}
 
 bool small_job_fits(const Model& m, const felog_train_params& p)
 {
@@ -819,7 +866,10 @@ SmallJobPtr small_job_begin(Model& m, Walks& w, const felog_train_params& p, int
     j->uj.dinp = m.sm_dinp.as<float>();
     j->uj.ctxc = m.sm_ctxc.as<float>();
     j->uj.loss_part = j->loss.as<double>();
+    for (hipEvent_t* e : {&j->plan_done[0], &j->plan_done[1], &j->upd_done[0], &j->upd_done[1]})
+        FELOG_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     c.sync();   // the buffers are ready before another stream uses them
+    plan_next_group(*j);
     return j;
 }
 
@@ -844,21 +894,19 @@ void small_jobs_step(const std::vector<SmallJob*>& jobs, SmallBatchCtl& ctl, hip
                   "a shared launch takes 1 to %d jobs", kMaxBatchJobs);
     const int K = jobs[0]->K, D = jobs[0]->D;
     const int64_t G = small_minibatches_per_launch();
-    PlanBatch pb{};
     UpdArgs u{};
-    int nb = 0, nmb_max = 0;
+    int nmb_max = 0;
     for (size_t i = 0; i < jobs.size(); ++i) {
         SmallJob& j = *jobs[i];
         FELOG_REQUIRE(j.K == K && j.D == D && !small_job_done(j),
                       "jobs of a shared launch need equal d and K and minibatches left");
         FELOG_REQUIRE(j.nwaves == ctl.nblocks * (kUpdThreads / 64),
                       "job prepared for another grid size");
+        if (j.planned == j.next) plan_next_group(j);
+        const int set = (int)((j.next / G) & 1);
+        FELOG_HIP(hipStreamWaitEvent(s, j.plan_done[set], 0));
         const int nmb = (int)std::min<int64_t>(G, j.end - j.next);
-        PlanArgs pl = j.pa;
-        pl.desc = j.ddesc.as<MbDesc>() + j.next;
-        pb.job[i] = pl;
-        pb.start[i] = nb;
-        nb += nmb;
+        const PlanArgs pl = group_plan(j, j.next);
         UpdJob uj = j.uj;
         uj.desc = pl.desc;
         uj.tinfo = pl.tinfo;
@@ -868,11 +916,7 @@ void small_jobs_step(const std::vector<SmallJob*>& jobs, SmallBatchCtl& ctl, hip
         uj.nmb = nmb;
         u.job[i] = uj;
         nmb_max = std::max(nmb_max, nmb);
-        j.next += nmb;
     }
-    pb.start[jobs.size()] = nb;
-    pb.njobs = (int32_t)jobs.size();
-    launch_plan(K, nb, pb, s);
     u.njobs = (int32_t)jobs.size();
     u.nmb_max = nmb_max;
     u.flags = ctl.words.as<uint32_t>();
@@ -882,6 +926,14 @@ void small_jobs_step(const std::vector<SmallJob*>& jobs, SmallBatchCtl& ctl, hip
     FELOG_HIP(hipLaunchCooperativeKernel(update_kernel(D, K), dim3(ctl.nblocks), dim3(kUpdThreads),
                                          args, 0, s));
     ctl.epoch += 2u * (uint32_t)nmb_max;
+    for (SmallJob* jp : jobs) {
+        SmallJob& j = *jp;
+        const int set = (int)((j.next / G) & 1);
+        FELOG_HIP(hipEventRecord(j.upd_done[set], s));
+        j.next += std::min<int64_t>(G, j.end - j.next);
+        // the next group's plan beside this update, on the job's stream
+        if (j.planned == j.next) plan_next_group(j);
+    }
 }
 
 bool small_batch_aborted(SmallBatchCtl& ctl, hipStream_t s)

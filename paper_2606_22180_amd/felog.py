@@ -612,9 +612,16 @@ class Server:
         return c.value, pk.value, q.value
 
     def close(self):
-        if self.handle:
+        """Finish the running jobs and stop the server's threads."""
+        if getattr(self, "handle", None):
             load().felog_server_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __del__(self):
         try:

@@ -118,10 +118,13 @@ def test_serving_budget_and_fifo(fl):
     for a in states:
         live = [b.device_bytes for b in states if b.t_admit <= a.t_admit < b.t_done]
         assert sum(live) <= budget
-    with pytest.raises(fl.FelogError):
-        g = jobs[0][1]
-        big = fl.Server(0, 1 << 20, slots=1, minibatch_pairs=4096, negatives=5)
-        big.submit(g.indptr, g.indices, dim=256, r=10, L=80, window=5, seed=1)
+    g = jobs[0][1]
+    big = fl.Server(0, 1 << 20, slots=1, minibatch_pairs=4096, negatives=5)
+    try:
+        with pytest.raises(fl.FelogError):
+            big.submit(g.indptr, g.indices, dim=256, r=10, L=80, window=5, seed=1)
+    finally:
+        big.close()
     S.close()
 
 
