@@ -692,7 +692,7 @@ def main():
     ap.add_argument("--c3-minibatches", type=int, default=20000, help="0 skips the C3 leg")
     ap.add_argument("--serving-jobs", type=int, default=8, help="0 skips the serving sample")
     ap.add_argument("--serving-slots", type=int, default=4)
-    ap.add_argument("--large-minibatches", type=int, default=256,
+    ap.add_argument("--large-minibatches", type=int, default=1024,
                     help="minibatches of 65,536 pairs on the headline graph after the timed "
                          "steps (0 skips)")
     ap.add_argument("--no-c2-per-round", action="store_true",
