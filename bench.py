@@ -457,6 +457,8 @@ def serving_sample(felog, n_jobs: int, slots: int, seed: int = 4, n_max: int = 2
     of the jobs run alone, then the same jobs arrive as a seeded Poisson
     process at 0.5, 0.8 and 0.95 x capacity."""
     import synth
+    if update_mode == 1:
+        slots = 1   # the persistent mode runs one job at a time
     t0 = time.perf_counter()
     mix = synth.job_mix(n_jobs, seed=seed, n_max=n_max)
     graphs = [synth.job_graph(j) for j in mix]

@@ -501,14 +501,15 @@ typedef struct felog_server_params {
  *   FELOG_SERVE_LAUNCHES (0, the default): each job's per-minibatch launches on
  *     its own stream;
  *   FELOG_SERVE_PERSISTENT: jobs with P (K + 2) <= 8192 take the persistent
- *     update, each on its own stream with 1 / slots of the compute units (so
- *     the running jobs' cooperative launches are resident together);
+ *     update; one slot only (slots > 1 is FELOG_EINVAL), so that one
+ *     cooperative launch is in flight at a time;
  *   FELOG_SERVE_SHARED: jobs with P (K + 2) <= 8192 train in persistent
  *     launches shared by up to 8 running jobs of equal d: each launch plans
  *     and updates the next 64 minibatches of every job in it, phase by phase
  *     together, on one more stream of the server; other jobs as LAUNCHES.
  * Streams: one per slot, plus one in FELOG_SERVE_SHARED; slots is at most 4
- * (3 in FELOG_SERVE_SHARED), the device's hardware queues per process. */
+ * (3 in FELOG_SERVE_SHARED, 1 in FELOG_SERVE_PERSISTENT), the device's
+ * hardware queues per process. */
 enum { FELOG_SERVE_LAUNCHES = 0, FELOG_SERVE_PERSISTENT = 1, FELOG_SERVE_SHARED = 2 };
 
 typedef struct felog_job_desc {

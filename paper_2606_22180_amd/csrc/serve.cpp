@@ -148,10 +148,9 @@ static void run_job(Server& s, Job& job)
     hipDeviceProp_t prop;
     FELOG_HIP(hipGetDeviceProperties(&prop, s.device));
     ctx.num_cus = prop.multiProcessorCount;
-    // One stream per job.  The persistent update's workgroups: 1 / slots of
-    // the compute units (at most 64), so that every running job's launch can
-    // be resident at once (two launches that were each only partly resident
-    // would wait for each other at their grid barriers).
+    // One stream per job.  The persistent mode has one slot, so the job's
+    // cooperative launch is the only one in flight; it takes the default
+    // grid (64 workgroups).
     ctx.single_stream = true;
     ctx.sgns_path = s.params.update_mode == FELOG_SERVE_PERSISTENT ? 0 : 1;
     ctx.sgns_blocks = std::max(1, std::min(64, ctx.num_cus / std::max(1, s.params.slots)));
@@ -420,11 +419,22 @@ felog_status felog_server_create(int device, uint64_t hbm_budget_bytes,
                           params->update_mode == FELOG_SERVE_PERSISTENT ||
                           params->update_mode == FELOG_SERVE_SHARED,
                       "unknown update_mode %d", params->update_mode);
-        const int max_slots = params->update_mode == FELOG_SERVE_SHARED ? 3 : 4;
+        // The persistent mode runs one job at a time: with several slots, the
+        // jobs' cooperative launches would be in flight together on separate
+        // streams, and whether they are all resident at once is up to the
+        // runtime and the dispatcher, not to this library (the shared mode
+        // puts the jobs into one cooperative launch instead).
+        const int max_slots = params->update_mode == FELOG_SERVE_SHARED       ? 3
+                              : params->update_mode == FELOG_SERVE_PERSISTENT ? 1
+                                                                              : 4;
         FELOG_REQUIRE(params->slots >= 1 && params->slots <= max_slots,
-                      "slots must be in [1, %d] (one stream each%s; the device has 4 hardware "
-                      "queues per process)", max_slots,
-                      params->update_mode == FELOG_SERVE_SHARED ? ", plus the shared launches'" : "");
+                      "slots must be in [1, %d] (%s; the device has 4 hardware queues per "
+                      "process)", max_slots,
+                      params->update_mode == FELOG_SERVE_SHARED
+                          ? "one stream each, plus the shared launches'"
+                          : params->update_mode == FELOG_SERVE_PERSISTENT
+                                ? "one cooperative launch in flight at a time"
+                                : "one stream each");
         FELOG_REQUIRE(params->minibatch_pairs >= 1 && params->minibatch_pairs <= (1 << 24),
                       "minibatch_pairs must be in [1, 2^24]");
         FELOG_REQUIRE(params->negatives >= 1 && params->negatives <= 20,

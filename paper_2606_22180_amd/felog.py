@@ -622,9 +622,3 @@ class Server:
             self.close()
         except Exception:
             pass
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass

@@ -128,6 +128,10 @@ def test_serving_budget_and_fifo(fl):
     S.close()
 
 
+@pytest.mark.skip(reason="several jobs' cooperative launches in flight at once on separate "
+                         "streams: the test ran for more than 180 s without output once in a "
+                         "full-suite run (it had passed three times); the cause was not found, "
+                         "and the persistent serving mode now takes one slot only")
 def test_serving_persistent_jobs_concurrent(fl):
     """Four slots of jobs on the persistent update (minibatches of at most
     1,024 pairs, each job's launch on a quarter of the compute units) give the
@@ -157,6 +161,43 @@ def test_serving_persistent_jobs_concurrent(fl):
         # the two paths sum the loss terms in different orders
         assert st.state == fl.JOB_DONE and same and abs(st.loss - loss) <= 1e-12 * abs(loss)
     S4.close()
+
+
+def test_serving_persistent_one_slot(fl):
+    """The persistent mode takes one slot (one cooperative launch in flight);
+    its jobs give the same embeddings and losses as the jobs alone on the
+    per-minibatch launches.  More slots are refused."""
+    with pytest.raises(fl.FelogError):
+        fl.Server(0, 0, slots=2, minibatch_pairs=1024, negatives=5,
+                  update_mode=fl.SERVE_PERSISTENT)
+    jobs = _jobs()[:4]
+    alone = {}
+    S1 = fl.Server(0, 0, slots=1, minibatch_pairs=1024, negatives=5,
+                   update_mode=fl.SERVE_LAUNCHES)
+    try:
+        for j, g in jobs:
+            jid = S1.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                            window=j["window"], seed=j["seed"])
+            st = S1.wait(jid, 120.0)
+            alone[j["job"]] = (S1.fetch(jid), st.loss, st.t_done - st.t_admit)
+    finally:
+        S1.close()
+    SP = fl.Server(0, 0, slots=1, minibatch_pairs=1024, negatives=5,
+                   update_mode=fl.SERVE_PERSISTENT)
+    try:
+        ids = [(j, SP.submit(g.indptr, g.indices, dim=j["dim"], r=j["r"], L=j["L"],
+                             window=j["window"], seed=j["seed"])) for j, g in jobs]
+        for j, jid in ids:
+            st = SP.wait(jid, 120.0)
+            emb, loss, t_alone = alone[j["job"]]
+            same = np.array_equal(SP.fetch(jid), emb)
+            _say("job %d n=%d P=%d: persistent (one slot) equal to per-minibatch alone: %s, "
+                 "service %.3f s (per-minibatch %.3f s)" % (
+                     j["job"], j["n"], st.minibatch_pairs, same, st.t_done - st.t_admit,
+                     t_alone))
+            assert st.state == fl.JOB_DONE and same and abs(st.loss - loss) <= 1e-12 * abs(loss)
+    finally:
+        SP.close()
 
 
 def test_serving_shared_launches(fl):
