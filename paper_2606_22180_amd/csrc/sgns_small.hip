@@ -27,14 +27,16 @@
 // terms rounded onto the exact-sum grid, every stored value is rounded once.
 // The two paths therefore give bit-identical tables.
 //
-// The grid barrier gathers flags: each workgroup stores its barrier count to
-// a flag on its own 128-byte line, workgroup 0 waits for all of them (one
-// thread per flag) and then raises a go flag that every workgroup waits for.
-// On MI355X this measured 2.2 us at 32 workgroups, 2.8 at 64, 3.7 at 128 and
-// 5.6 at 256, against 3.4 / 3.4 / 4.9 / 8.1 us for one shared atomic
-// counter, whose same-address atomics serialise.  Every wait is bounded: one
-// that exceeds kSpinLimit polls raises an abort flag that every workgroup
-// checks, so every wave leaves the kernel, and the host reports the failure.
+// The grid barrier is a flag per workgroup: each workgroup stores its barrier
+// count to a flag on its own 128-byte line, and the first wave of every
+// workgroup watches all the flags (one lane per flag).  On MI355X (512
+// threads per workgroup) this measured 1.7 us at 32 workgroups, 2.2 at 64 and
+// 3.4 at 128; workgroup 0 gathering the flags and raising a go flag that the
+// others wait for took 2.0-3.1 / 2.5 / 3.5 us, and one shared atomic counter,
+// whose same-address atomics serialise, 3.4 / 3.4 / 4.9 us.  Every wait is
+// bounded: one that exceeds kSpinLimit polls raises an abort flag that every
+// workgroup checks, so every wave leaves the kernel, and the host reports the
+// failure.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -296,8 +298,8 @@ struct UpdArgs {
     UpdJob job[kMaxBatchJobs];
     int32_t njobs;
     int32_t nmb_max;               // largest nmb of the jobs
-    uint32_t* flags;               // go flag at [0], workgroup b's at [kFlagStride (1 + b)];
-                                   // zero at the call's start
+    uint32_t* flags;               // workgroup b's at [kFlagStride (1 + b)] (the first line is
+                                   // unused); zero at the call's start
     uint32_t epoch0;               // barriers passed by earlier launches of the call
     int32_t* abort;
 };
@@ -331,19 +333,17 @@ __device__ __forceinline__ bool grid_sync(const UpdArgs& a, uint32_t& epoch)
         __hip_atomic_store(&a.flags[kFlagStride * (1 + blockIdx.x)], epoch, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    bool ok = true;
-    if (blockIdx.x == 0) {
-        for (uint32_t b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+    // every workgroup's first wave watches every flag (lane l the flags of
+    // workgroups l, l + 64, ...), then acquires for the workgroup
+    if (threadIdx.x < 64) {
+        bool ok = true;
+        for (uint32_t b = threadIdx.x; b < gridDim.x; b += 64)
             ok = ok && wait_at_least(&a.flags[kFlagStride * (1 + b)], epoch, a.abort);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&a.flags[0], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x == 0) {
-        ok = wait_at_least(&a.flags[0], epoch, a.abort) && ok;
+        const bool all_ok = __all(ok);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s_ok = ok &&
-               !__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0)
+            s_ok = all_ok &&
+                   !__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     return s_ok != 0;
@@ -986,9 +986,9 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     const int nwaves = nblocks * (kUpdThreads / 64);
 
     small_buffers(m, P, tmax);
-    // control words: barrier flags (go, then one per workgroup, each on its
-    // own 128-byte line), the abort flag on the next line, then the loss
-    // partials, one per wave
+    // control words: barrier flags (an unused line, then one per workgroup,
+    // each on its own 128-byte line), the abort flag on the next line, then
+    // the loss partials, one per wave
     const int64_t ctl_words = (int64_t)kFlagStride * (nblocks + 2);
     DevBuf ctl;
     ctl.alloc(&c, sizeof(uint32_t) * ctl_words + sizeof(double) * nwaves);
