@@ -44,6 +44,8 @@ enum {
     FELOG_ESTATE = -4,        /* handle in the wrong state for this call           */
     FELOG_EUNSUPPORTED = -5,  /* valid request this build does not implement        */
     FELOG_EIO = -6,           /* a file could not be opened, read or written        */
+    FELOG_EFAULT_INJECTED = -7, /* the training call stopped where the debug hook
+                                   FELOG_DEBUG_FAIL_AFTER_MINIBATCHES asked it to    */
 };
 
 typedef struct felog_ctx felog_ctx;
@@ -365,6 +367,13 @@ typedef struct felog_train_stats {
  * Negative k of a pair uses words 2(k mod 2), 2(k mod 2)+1 (low, high) of
  * Philox(key = seed, counter = (walk id low, walk id high, j << 8 | slot,
  * 3 << 24 | k / 2)); a negative equal to the centre is skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1). */
+/* Failure hook (the library's only environment variable): when
+ * FELOG_DEBUG_FAIL_AFTER_MINIBATCHES=N (N >= 0) is set, felog_train_epoch and
+ * felog_train_steps train at most the first N minibatches of their range and,
+ * if the range holds more, return FELOG_EFAULT_INJECTED with the tables as
+ * those N minibatches left them (stats, when given, describe those N).  It
+ * stands in for a failure in the middle of a round, so that recovery from a
+ * checkpoint (felog_model_save / felog_model_load) can be tested. */
 felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
                                const felog_train_params* params, felog_train_stats* stats);
 /* BF16 models (shared negatives, not in the paper; a systems form of Eq. (2)):

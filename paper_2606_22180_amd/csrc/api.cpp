@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -945,13 +946,44 @@ static void check_train_params(const felog_model* m, const felog_walks* w,
     }
 }
 
+// FELOG_DEBUG_FAIL_AFTER_MINIBATCHES=N: -1 when unset (or not a number >= 0).
+static int64_t fail_after_minibatches()
+{
+    const char* v = std::getenv("FELOG_DEBUG_FAIL_AFTER_MINIBATCHES");
+    if (!v || !*v) return -1;
+    char* end = nullptr;
+    const long long n = std::strtoll(v, &end, 10);
+    return (end && *end == '\0' && n >= 0) ? (int64_t)n : -1;
+}
+
+// Trains minibatches [first_mb, first_mb + n_mb) (n_mb < 0: to the end of
+// the epoch), stopping after the failure hook's count if it is set.
+static void train_range(felog_model* m, const felog_walks* corpus,
+                        const felog_train_params* params, int64_t first_mb, int64_t n_mb,
+                        felog_train_stats* stats)
+{
+    const int64_t cut = fail_after_minibatches();
+    felog_train_stats st{};
+    int64_t n = n_mb;
+    if (cut >= 0) n = n_mb < 0 ? cut : std::min(n_mb, cut);
+    train_minibatches(*m, *const_cast<felog_walks*>(corpus), *params, first_mb, n, true, &st,
+                      nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr);
+    if (stats) *stats = st;
+    if (cut < 0) return;
+    const int64_t left = std::max<int64_t>(0, st.minibatches_total - first_mb);
+    const int64_t want = n_mb < 0 ? left : std::min(n_mb, left);
+    if (want > cut)
+        fail(FELOG_EFAULT_INJECTED, "FELOG_DEBUG_FAIL_AFTER_MINIBATCHES=%lld: stopped after "
+             "%lld of %lld minibatches", (long long)cut, (long long)st.minibatches,
+             (long long)want);
+}
+
 felog_status felog_train_epoch(felog_model* m, const felog_walks* corpus,
                                const felog_train_params* params, felog_train_stats* stats)
 {
     return guarded([&] {
         check_train_params(m, corpus, params);
-        train_minibatches(*m, *const_cast<felog_walks*>(corpus), *params, 0, -1, true, stats,
-                          nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr);
+        train_range(m, corpus, params, 0, -1, stats);
     });
 }
 
@@ -962,8 +994,7 @@ felog_status felog_train_steps(felog_model* m, const felog_walks* corpus,
     return guarded([&] {
         check_train_params(m, corpus, params);
         FELOG_REQUIRE(first_mb >= 0 && n_mb >= 0, "minibatch range must be non-negative");
-        train_minibatches(*m, *const_cast<felog_walks*>(corpus), *params, first_mb, n_mb, true,
-                          stats, nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr);
+        train_range(m, corpus, params, first_mb, n_mb, stats);
     });
 }
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libfelog.so")
 FELOG_OK, FELOG_EINVAL, FELOG_ENOMEM, FELOG_EDEVICE, FELOG_ESTATE, FELOG_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 FELOG_EIO = -6
+FELOG_EFAULT_INJECTED = -7
 WALK_UNIFORM, WALK_NODE2VEC = 0, 1
 NEG_DEGREE, NEG_UNIGRAM = 0, 1
 TABLE_IN, TABLE_OUT = 0, 1
@@ -29,7 +30,8 @@ FABC_MAX_SYMBOLS = 16
 MAX_ROUNDS = 64
 
 _STATUS = {0: "FELOG_OK", -1: "FELOG_EINVAL", -2: "FELOG_ENOMEM", -3: "FELOG_EDEVICE",
-           -4: "FELOG_ESTATE", -5: "FELOG_EUNSUPPORTED", -6: "FELOG_EIO"}
+           -4: "FELOG_ESTATE", -5: "FELOG_EUNSUPPORTED", -6: "FELOG_EIO",
+           -7: "FELOG_EFAULT_INJECTED"}
 
 
 class FelogError(RuntimeError):

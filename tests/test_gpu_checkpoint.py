@@ -131,6 +131,52 @@ def test_resume_equals_uninterrupted(fl, ctx, rmat12, tmp_path):
         assert np.array_equal(C.read(t), A.read(t))
 
 
+@pytest.mark.parametrize("P", [1024, 4096])
+def test_injected_failure_then_resume(fl, ctx, rmat12, tmp_path, monkeypatch, P):
+    """FELOG_DEBUG_FAIL_AFTER_MINIBATCHES=N stops an epoch after N minibatches
+    with FELOG_EFAULT_INJECTED; the tables then hold exactly those N
+    minibatches, and both recoveries (the rest of the epoch from minibatch N,
+    or the whole epoch again from the checkpoint taken before it) equal the
+    uninterrupted epoch bit for bit.  P = 1,024 takes the persistent update,
+    P = 4,096 the per-minibatch launches."""
+    g, G = rmat12
+    W = fl.Walks.generate(G, r=2, L=20, seed=21)
+    prm = fl.train_params(window=4, negatives=5, minibatch_pairs=P, seed=22)
+
+    def fresh():
+        M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_UNIGRAM, seed=23)
+        M.set_unigram(W)
+        return M
+
+    A = fresh()
+    st_a = A.train_epoch(W, prm)
+    B_total = st_a.minibatches_total
+    cut = B_total // 3
+    _say("injected failure rmat12 P=%d: %d minibatches, fail after %d" % (P, B_total, cut))
+    assert 0 < cut < B_total
+    B = fresh()
+    path = str(tmp_path / "before.felog")
+    B.save(path, round=0, walk_id_base=0)
+    monkeypatch.setenv("FELOG_DEBUG_FAIL_AFTER_MINIBATCHES", str(cut))
+    with pytest.raises(fl.FelogError) as err:
+        B.train_epoch(W, prm)
+    assert err.value.status == fl.FELOG_EFAULT_INJECTED
+    # a range the count covers is not cut short
+    Cm = fresh()
+    Cm.train_steps(W, prm, 0, cut)
+    monkeypatch.delenv("FELOG_DEBUG_FAIL_AFTER_MINIBATCHES")
+    for t in (fl.TABLE_IN, fl.TABLE_OUT):
+        assert np.array_equal(B.read(t), Cm.read(t))
+    B.train_steps(W, prm, cut, B_total - cut)
+    L, _, rnd, _ = fl.Model.load(G, path)
+    assert rnd == 0
+    L.train_epoch(W, prm)
+    for t in (fl.TABLE_IN, fl.TABLE_OUT):
+        a = A.read(t)
+        assert np.array_equal(B.read(t), a)
+        assert np.array_equal(L.read(t), a)
+
+
 def test_bad_checkpoints_rejected(fl, ctx, rmat12, tmp_path):
     g, G = rmat12
     M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=1)
