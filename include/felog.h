@@ -78,7 +78,7 @@ felog_status felog_ctx_bytes_in_use(const felog_ctx* ctx, uint64_t* bytes);
 felog_status felog_ctx_set_timing(felog_ctx* ctx, int32_t every);
 
 /* SGNS update path of the FP32 form.  path 0 (the default): minibatches of
- * P (K + 2) <= 8192 touches run as plan launches (ids and a sort of each
+ * P (K + 2) <= 8192 touches (and K <= 14 at d = 64) run as plan launches (ids and a sort of each
  * minibatch's touches by row, many minibatches per launch) and one persistent
  * cooperative update launch per group of minibatches; larger ones run
  * per-minibatch launches.  path 1: per-minibatch launches always.  Both give

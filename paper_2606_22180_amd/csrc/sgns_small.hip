@@ -15,12 +15,13 @@
 //           the noise table, never on the embeddings.
 //   update  one persistent cooperative launch for those minibatches.  Per
 //           minibatch: the forward (gathers, FP64 dots, sigma, coefficients;
-//           each out-touch's coefficient at its sorted position; each pair's
-//           context row copied; out rows touched once updated in place),
-//           a grid barrier, the apply (one 16-lane group per segment sums
-//           the row's terms and adds them once), and a grid barrier.  The
-//           apply reads the context copies, not the in-table, so in and out
-//           rows are applied together.
+//           each out-touch's coefficient at its sorted position; the context
+//           row copied for pairs with an out row touched more than once; rows
+//           touched once in either table updated in place), a grid barrier,
+//           the apply (one 16-lane group per segment of two or more touches
+//           sums the row's terms and adds them once), and a grid barrier.
+//           The apply reads the context copies, not the in-table, so in and
+//           out rows are applied together.
 //
 // The arithmetic is that of sgns.hip term for term: rows of at most kChunk
 // touches sum their FP64 terms sequentially in pair order, longer rows sum
@@ -61,7 +62,7 @@ static_assert(sizeof(MbDesc) == 32, "descriptor layout shared by host and device
 constexpr int kPlanThreads = 512;
 constexpr int kPlanMaxTouches = kSmallMaxTouches;   // touches a plan sorts in LDS (64 KB of keys)
 constexpr int32_t kPosMask = (1 << 30) - 1;
-constexpr int32_t kSingleBit = 1 << 30;  // out row touched once: the forward updates it
+constexpr int32_t kSingleBit = 1 << 30;  // row touched once in the minibatch: the forward updates it
 constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a barrier wait gives up (seconds)
 constexpr int kUpdThreads = 512;         // one workgroup per CU at two waves per SIMD
 constexpr int kFlagStride = 32;          // 32-bit words between barrier flags (128 bytes)
@@ -82,8 +83,8 @@ struct PlanArgs {
     int2* tinfo;                   // [mb][tmax]: (row, sorted position | kSingleBit), -1 skipped
     int4* segs;                    // [mb][tmax]: (row, first position, touches, table)
     int32_t* spair;                // [mb][tmax]: pair of each sorted position
-    uint32_t* meta;                // [mb][4]: applied segments, in segments, out rows,
-                                   // out rows touched once
+    uint32_t* meta;                // [mb][4]: applied segments, applied in segments,
+                                   // out rows, out rows touched once
     unsigned long long* row_totals;// [3]: in rows, out rows, out rows touched once
 };
 
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanBatch pb)
     // segment starts (step 3); before that, the pairs' centres (step 1)
     __shared__ __align__(16) uint16_t seg_first[kPlanMaxTouches + 1];
     __shared__ uint32_t tmp[kPlanThreads / 64 + 1];
-    __shared__ uint32_t counts[3];
+    __shared__ uint32_t counts[3];     // in rows, out rows touched once, applied in segments
     const MbDesc d = a.desc[lb];
     const uint32_t nt = d.npairs * T;
     uint32_t N = 64;
@@ -229,29 +230,31 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanBatch pb)
     if (threadIdx.x == 0) seg_first[nseg] = (uint16_t)nv;
     __syncthreads();
 
-    // 4. per segment: length; in segments and out segments of two or more
-    //    touches go to the apply list (in segments first: they sort first);
-    //    every touch's sorted position
+    // 4. per segment: length; segments of two or more touches go to the
+    //    apply list (in segments first: they sort first), rows touched once
+    //    are updated by the forward; every touch's sorted position
     const uint32_t sper = (nseg + kPlanThreads - 1) / kPlanThreads;
     const uint32_t s_lo = min(nseg, threadIdx.x * sper), s_hi = min(nseg, s_lo + sper);
-    uint32_t napply = 0, nin = 0, nsingle = 0;
+    uint32_t napply = 0, nin = 0, nin_apply = 0, nsingle = 0;
     for (uint32_t q = s_lo; q < s_hi; ++q) {
         const uint32_t f = seg_first[q], len = seg_first[q + 1] - f;
         const bool out = (keys[f] >> 62) != 0;
-        napply += (!out || len > 1) ? 1u : 0u;
+        napply += len > 1 ? 1u : 0u;
         nin += out ? 0u : 1u;
+        nin_apply += (!out && len > 1) ? 1u : 0u;
         nsingle += (out && len == 1) ? 1u : 0u;
     }
     uint32_t n_apply;
     uint32_t slot = block_scan(napply, tmp, &n_apply);
     atomicAdd(&counts[0], nin);
     atomicAdd(&counts[1], nsingle);
+    atomicAdd(&counts[2], nin_apply);
     for (uint32_t q = s_lo; q < s_hi; ++q) {
         const uint32_t f = seg_first[q], len = seg_first[q + 1] - f;
         const unsigned long long x = keys[f];
         const int32_t out = (int32_t)(x >> 62);
         const int32_t row = (int32_t)((x >> 16) & 0x7FFFFFFFull);
-        const bool single = out && len == 1;
+        const bool single = len == 1;
         if (!single) segs[slot++] = make_int4(row, (int32_t)f, (int32_t)len, out);
         for (uint32_t i = f; i < f + len; ++i) {
             const uint32_t t = (uint32_t)(keys[i] & 0xFFFF);
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(kPlanThreads) void sgns_plan_kernel(PlanBatch pb)
     if (threadIdx.x == 0) {
         uint32_t* m = a.meta + (int64_t)lb * 4;
         m[0] = n_apply;
-        m[1] = counts[0];
+        m[1] = counts[2];
         m[2] = nseg - counts[0];
         m[3] = counts[1];
         atomicAdd(&a.row_totals[0], (unsigned long long)counts[0]);
@@ -470,11 +473,21 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                     }
                 }
                 if (live) {
+                    // the context copy is read by the apply of the pair's out
+                    // rows touched more than once; an in row touched once is
+                    // updated here (its delta rounded to FP32 first, as the
+                    // apply rounds the stored delta), others store the delta
+                    bool need_ctx = false;
+#pragma unroll
+                    for (int k = 0; k <= K; ++k)
+                        need_ctx = need_ctx || (t[k] >= 0 && !((single >> (src + 1 + k)) & 1ull));
+                    const bool in_single = (single >> src) & 1ull;
                     float4* cc = reinterpret_cast<float4*>(J.ctxc + (int64_t)q * D);
-                    float4* dp = reinterpret_cast<float4*>(J.dinp + (int64_t)pos_in * D);
+                    float4* dp = in_single ? reinterpret_cast<float4*>(J.tin + (int64_t)ctx * D)
+                                           : reinterpret_cast<float4*>(J.dinp + (int64_t)pos_in * D);
 #pragma unroll
                     for (int i = 0; i < V4; ++i) {
-                        cc[i * LPP + gl] = vin[i];
+                        if (need_ctx) cc[i * LPP + gl] = vin[i];
                         double ax = 0.0, ay = 0.0, az = 0.0, aw = 0.0;
 #pragma unroll
                         for (int k = 0; k <= K; ++k) {
@@ -483,7 +496,13 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                             az = fma(g[k], (double)vo[k][i].z, az);
                             aw = fma(g[k], (double)vo[k][i].w, aw);
                         }
-                        dp[i * LPP + gl] = make_float4((float)ax, (float)ay, (float)az, (float)aw);
+                        float4 dv = make_float4((float)ax, (float)ay, (float)az, (float)aw);
+                        if (in_single)
+                            dv = make_float4((float)((double)vin[i].x + (double)dv.x),
+                                             (float)((double)vin[i].y + (double)dv.y),
+                                             (float)((double)vin[i].z + (double)dv.z),
+                                             (float)((double)vin[i].w + (double)dv.w));
+                        dp[i * LPP + gl] = dv;
                     }
                 }
             }
@@ -600,10 +619,20 @@ __global__ void zero_words_kernel(uint32_t* p, int32_t n)
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// The forward of the update kernel holds the touches of a wave's pairs in one
+// lane each: (64 / lanes per pair) pairs of K + 2 touches must fit 64 lanes
+// (K <= 14 at d = 64, where 16 lanes take a pair).
+static bool small_touches_fit_wave(int d, int K)
+{
+    const int pairs_per_wave = d >= 128 ? 2 : 4;
+    return pairs_per_wave * (K + 2) <= 64;
+}
+
 bool small_path_applies(const Model& m, const felog_train_params& p)
 {
     return m.precision == FELOG_PREC_FP32 && m.ctx->sgns_path == 0 &&
-           p.minibatch_pairs * (p.negatives + 2) <= kPlanMaxTouches && p.negatives <= 20;
+           p.minibatch_pairs * (p.negatives + 2) <= kPlanMaxTouches && p.negatives <= 20 &&
+           small_touches_fit_wave(m.dim, p.negatives);
 }
 
 // Minibatches per plan / update launch pair: the launches' fixed costs spread
@@ -827,7 +856,7 @@ bool small_job_fits(const Model& m, const felog_train_params& p)
 {
     return m.precision == FELOG_PREC_FP32 && p.negatives <= 20 &&
            p.minibatch_pairs * (p.negatives + 2) <= kPlanMaxTouches &&
-           (m.dim == 64 || m.dim == 128 || m.dim == 256);
+           (m.dim == 64 || m.dim == 128 || m.dim == 256) && small_touches_fit_wave(m.dim, p.negatives);
 }
 
 SmallJobPtr small_job_begin(Model& m, Walks& w, const felog_train_params& p, int nblocks)

@@ -176,3 +176,14 @@ def test_single_stream_identical(fl, sbm):
              % (path, np.array_equal(i0, i1) and np.array_equal(o0, o1), l0, l1))
         assert np.array_equal(i0, i1) and np.array_equal(o0, o1)
         assert l0 == l1
+
+
+def test_small_update_wide_k_at_d64_uses_launches(fl, sbm):
+    """d = 64 with K = 15: four pairs of 17 touches do not fit the 64 lanes the
+    persistent forward gives a wave's pairs, so the per-minibatch launches
+    serve the call on path 0 too, with the same tables."""
+    (i1, o1, s1), (i0, o0, s0) = _both_paths(fl, sbm.train, dim=64, K=15, P=256, window=5,
+                                             L=40, r=10, first=0, n=40)
+    _say("d=64 K=15 P=256: paths %d and %d" % (s1.path, s0.path))
+    assert s1.path == 0 and s0.path == 0
+    assert np.array_equal(i1, i0) and np.array_equal(o1, o0)
