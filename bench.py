@@ -554,6 +554,11 @@ def sgns_roofline(sts, d: int, K: int, pairs: int):
                           "us_per_minibatch": avg * 1e6 / max(1e-30, per_launch_mb),
                           "achieved_gbs": ach, "frac": ach / HBM_PEAK_GBS if ach else None}
         blocks = sts[0].update_blocks
+        # device wall-clock phases of the update (per minibatch and workgroup)
+        ph = [sum(s.us_phase[i] * s.timed_minibatches for s in sts) / max(1, tmb)
+              for i in range(4)]
+        kern["sgns_small_update_kernel<%d, %d>" % (d, K)]["phases_us_per_minibatch"] = {
+            "forward": ph[0], "barrier_1": ph[1], "apply": ph[2], "barrier_2": ph[3]}
     else:
         multi_out = rows_out - single
         out_touches = pairs * (K + 1)

@@ -355,6 +355,12 @@ typedef struct felog_train_stats {
     int64_t timed_minibatches;/* path 1: minibatches covered by the timed launches   */
     double ms_update;         /* path 1: summed duration of the timed persistent
                                  update launches (ms_prep: their plan launches)      */
+    double us_phase[4];       /* path 1 with timing on: mean time per minibatch and
+                                 workgroup of the update's forward phase, its first
+                                 grid barrier, the apply phase and the second barrier
+                                 (us, device wall clock; a phase ends when every wave
+                                 of the workgroup reaches the barrier, a barrier when
+                                 the workgroup leaves it)                            */
 } felog_train_stats;
 
 /* One Train() call: every minibatch of the corpus in order.  Pairs: within each

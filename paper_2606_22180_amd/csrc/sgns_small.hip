@@ -305,6 +305,9 @@ struct UpdArgs {
                                    // unused); zero at the call's start
     uint32_t epoch0;               // barriers passed by earlier launches of the call
     int32_t* abort;
+    unsigned long long* clocks;    // null, or [4]: device wall-clock ticks of the forward,
+                                   // the first barrier, the apply and the second barrier,
+                                   // summed over workgroups and minibatches
 };
 
 // Bounded wait until *p >= target; false (and the abort flag raised) when
@@ -326,10 +329,12 @@ __device__ __forceinline__ bool wait_at_least(const uint32_t* p, uint32_t target
 
 // Grid barrier with release/acquire at agent scope.  Returns false when the
 // launch is aborting (a wait exceeded its bound somewhere).
-__device__ __forceinline__ bool grid_sync(const UpdArgs& a, uint32_t& epoch)
+__device__ __forceinline__ bool grid_sync(const UpdArgs& a, uint32_t& epoch,
+                                          unsigned long long* arrive)
 {
     __shared__ int s_ok;
     __syncthreads();
+    if (arrive) *arrive = wall_clock64();   // every wave of the workgroup is here
     ++epoch;
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -384,7 +389,16 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
     int2 pf_touch = J0.nmb > 0 ? first_touch(0) : make_int2(-1, -1);
     const uint32_t sidx0 = gw * 4 + (uint32_t)g16;
 
+    // phase clocks (thread 0 of each workgroup, when asked for), kept in LDS:
+    // [0..3] ticks of the phases summed over the launch's minibatches (added
+    // to the totals once at the end), [4] phase start, [5] barrier arrival,
+    // [6] first barrier's exit
+    __shared__ unsigned long long s_clk[7];
+    const bool clk = a.clocks != nullptr && threadIdx.x == 0;
+    if (clk)
+        for (int i = 0; i < 4; ++i) s_clk[i] = 0;
     for (int m = 0; m < a.nmb_max; ++m) {
+        if (clk) s_clk[4] = wall_clock64();
         int4 pf_seg = make_int4(0, 0, 0, 0);
         int32_t pf_pair = 0;
         if (m < J0.nmb) {
@@ -517,7 +531,12 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
             const uint32_t nseg0 = J0.meta[(int64_t)m * 4];
             if (sidx0 < nseg0 && l16 < pf_seg.z) pf_pair = J0.spair[(int64_t)m * J0.tmax + pf_seg.y + l16];
         }
-        if (!grid_sync(a, epoch)) break;
+        if (!grid_sync(a, epoch, clk ? &s_clk[5] : nullptr)) break;
+        if (clk) {
+            s_clk[6] = wall_clock64();
+            s_clk[0] += s_clk[5] - s_clk[4];
+            s_clk[1] += s_clk[6] - s_clk[5];
+        }
 
         // ---- apply: one 16-lane group per segment, in and out rows together
         if (m + 1 < J0.nmb) pf_touch = first_touch(m + 1);
@@ -603,8 +622,14 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                 }
             }
         }
-        if (!grid_sync(a, epoch)) break;
+        if (!grid_sync(a, epoch, clk ? &s_clk[5] : nullptr)) break;
+        if (clk) {
+            s_clk[2] += s_clk[5] - s_clk[6];
+            s_clk[3] += wall_clock64() - s_clk[5];
+        }
     }
+    if (clk)
+        for (int i = 0; i < 4; ++i) atomicAdd(&a.clocks[i], s_clk[i]);
     if (a.njobs == 1) {
         lacc = wave_sum_f64(lacc);
         if (lane == 0) J0.loss_part[gw] += lacc;
@@ -1017,13 +1042,15 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     small_buffers(m, P, tmax);
     // control words: barrier flags (an unused line, then one per workgroup,
     // each on its own 128-byte line), the abort flag on the next line, then
-    // the loss partials, one per wave
+    // the loss partials, one per wave, and the four phase-clock sums
     const int64_t ctl_words = (int64_t)kFlagStride * (nblocks + 2);
     DevBuf ctl;
-    ctl.alloc(&c, sizeof(uint32_t) * ctl_words + sizeof(double) * nwaves);
+    ctl.alloc(&c, sizeof(uint32_t) * ctl_words + sizeof(double) * nwaves +
+                      sizeof(unsigned long long) * 4);
     uint32_t* flags = ctl.as<uint32_t>();
     int32_t* abort = reinterpret_cast<int32_t*>(flags + (int64_t)kFlagStride * (nblocks + 1));
     double* loss_part = reinterpret_cast<double*>(flags + ctl_words);
+    unsigned long long* clocks = reinterpret_cast<unsigned long long*>(loss_part + nwaves);
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(256), 0, c.stream, flags,
                        (int32_t)(ctl.bytes / sizeof(uint32_t)));
     FELOG_HIP(hipMemsetAsync(m.row_totals.ptr, 0, sizeof(uint64_t) * 3, c.stream));
@@ -1122,6 +1149,7 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
         u.flags = flags;
         u.abort = abort;
         u.epoch0 = epoch;
+        u.clocks = timing ? clocks : nullptr;
         void* args[] = {&u};
         if (e) FELOG_HIP(hipEventRecord(e[2], c.stream));
         FELOG_HIP(hipLaunchCooperativeKernel(kern, dim3(nblocks), dim3(kUpdThreads), args, 0,
@@ -1138,9 +1166,12 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
     double loss = 0.0;
     unsigned long long rows[3] = {0, 0, 0};
     int32_t aborted = 0;
+    unsigned long long ticks[4] = {0, 0, 0, 0};
     FELOG_HIP(hipMemcpyAsync(&loss, m.loss_out.ptr, sizeof loss, hipMemcpyDeviceToHost, c.stream));
     FELOG_HIP(hipMemcpyAsync(rows, m.row_totals.ptr, sizeof rows, hipMemcpyDeviceToHost, c.stream));
     FELOG_HIP(hipMemcpyAsync(&aborted, abort, sizeof aborted, hipMemcpyDeviceToHost, c.stream));
+    if (timing)
+        FELOG_HIP(hipMemcpyAsync(ticks, clocks, sizeof ticks, hipMemcpyDeviceToHost, c.stream));
     c.sync();
     FELOG_HIP(hipStreamSynchronize(ps));
     FELOG_REQUIRE(!aborted, "small-minibatch update: a grid barrier wait exceeded its bound");
@@ -1162,6 +1193,13 @@ void train_minibatches_small(Model& m, Walks& w, const felog_train_params& p,
         stats->ms_prep = ms_plan;
         stats->ms_update = ms_update;
         stats->update_blocks = nblocks;
+        if (timing && end > first_mb) {
+            int khz = 0;   // device wall-clock rate
+            FELOG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device));
+            const double per = (double)nblocks * (double)(end - first_mb) * (double)khz / 1e3;
+            for (int i = 0; i < 4; ++i)
+                stats->us_phase[i] = khz > 0 ? (double)ticks[i] / per : 0.0;
+        }
     }
 }
 

@@ -67,7 +67,8 @@ class felog_train_stats(C.Structure):
                 ("ms_apply", C.c_double), ("ms_prep", C.c_double),
                 ("ms_apply_first", C.c_double), ("rows_out_single", C.c_int64),
                 ("path", C.c_int32), ("update_blocks", C.c_int32),
-                ("timed_minibatches", C.c_int64), ("ms_update", C.c_double)]
+                ("timed_minibatches", C.c_int64), ("ms_update", C.c_double),
+                ("us_phase", C.c_double * 4)]
 
 
 class felog_feedback_params(C.Structure):

@@ -60,6 +60,35 @@ def test_serving_job_matches_oracle(fl, orc):
     assert abs(st.loss - ref.loss) <= 1e-4 * ref.loss
 
 
+@pytest.mark.parametrize("mode", [0, 2])
+def test_serving_job_equals_direct_path(fl, mode):
+    """A serving job's embeddings equal, bit for bit, those of the same job run
+    through the library's own calls (uniform walks, degree^0.75 noise, one
+    epoch, the job's seed for walks, tables and negatives), whose minibatch
+    steps the parity tests hold to the oracle row by row: per-minibatch
+    launches (mode 0) and shared persistent launches (mode 2)."""
+    sp = synth.build_graph("sbm1k")
+    g = sp.train
+    S = fl.Server(0, 0, slots=2, minibatch_pairs=65536, negatives=5, update_mode=mode)
+    jid = S.submit(g.indptr, g.indices, dim=64, r=10, L=40, window=5, seed=21)
+    st = S.wait(jid, 120.0)
+    emb = S.fetch(jid)
+    S.close()
+    assert st.state == fl.JOB_DONE and st.minibatch_pairs == 1024
+    ctx = fl.Context(0)
+    G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+    W = fl.Walks.generate(G, r=10, L=40, seed=21)
+    M = fl.Model.create(G, dim=64, neg_dist=fl.NEG_DEGREE, seed=21)
+    ds = M.train_epoch(W, fl.train_params(window=5, negatives=5, minibatch_pairs=1024, seed=21))
+    ref = M.read(fl.TABLE_IN)
+    for o in (M, W, G, ctx):
+        o.close()
+    diff = int((emb.view(np.uint32) != ref.view(np.uint32)).sum())
+    _say("mode %d: serving job vs direct calls: pairs %d/%d, differing words %d of %d"
+         % (mode, st.pairs, ds.pairs, diff, ref.size))
+    assert st.pairs == ds.pairs and diff == 0
+
+
 def test_serving_alone_equals_mix(fl):
     jobs = _jobs()
     _say("serving alone vs mix: %d jobs, n = %s" % (len(jobs), [j["n"] for j, _ in jobs]))

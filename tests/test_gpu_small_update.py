@@ -187,3 +187,32 @@ def test_small_update_wide_k_at_d64_uses_launches(fl, sbm):
     _say("d=64 K=15 P=256: paths %d and %d" % (s1.path, s0.path))
     assert s1.path == 0 and s0.path == 0
     assert np.array_equal(i1, i0) and np.array_equal(o1, o0)
+
+
+def test_phase_clocks(fl, sbm):
+    """With timing on, the persistent update reports its four phases (forward,
+    barrier, apply, barrier) per minibatch from the device wall clock; they add
+    up to the launches' HIP-event time per minibatch, and timing leaves the
+    tables unchanged."""
+    g = sbm.train
+    res = []
+    for timing in (0, 1):
+        ctx = fl.Context(0)
+        ctx.set_timing(timing)
+        G = fl.Graph.from_csr(ctx, g.indptr, g.indices)
+        W = fl.Walks.generate(G, r=10, L=40, seed=11)
+        M = fl.Model.create(G, dim=128, neg_dist=fl.NEG_DEGREE, seed=5)
+        prm = fl.train_params(window=5, negatives=5, minibatch_pairs=1024, seed=3)
+        st = M.train_steps(W, prm, 0, 300)
+        res.append((M.read(fl.TABLE_IN), M.read(fl.TABLE_OUT), st))
+        for o in (M, W, G, ctx):
+            o.close()
+    (i0, o0, s0), (i1, o1, s1) = res
+    assert np.array_equal(i0, i1) and np.array_equal(o0, o1)
+    ph = list(s1.us_phase)
+    ev = 1e3 * s1.ms_update / s1.timed_minibatches
+    _say("phases per minibatch: forward %.2f barrier %.2f apply %.2f barrier %.2f us "
+         "(sum %.2f); events %.2f us" % (*ph, sum(ph), ev))
+    assert s1.path == 1 and s1.timed_minibatches == 300
+    assert all(p > 0 for p in ph) and list(s0.us_phase) == [0.0] * 4
+    assert 0.7 * ev <= sum(ph) <= 1.1 * ev
