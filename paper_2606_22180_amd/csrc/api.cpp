@@ -335,6 +335,7 @@ felog_status felog_graph_load_csr(felog_ctx* ctx, int32_t n_nodes, int64_t nnz,
             fail(FELOG_EINVAL, "graph is not a valid symmetric CSR: row %d has %s", h_bad[0],
                  what[h_bad[1] >= 0 && h_bad[1] < 7 ? h_bad[1] : 0]);
         launch_row_wmax(*g);
+        build_edge_records(*g);
         ctx->sync();
         *out = g.release();
     });

@@ -101,7 +101,9 @@ struct Graph {
     bool weighted = false;
     DevBuf indptr;    // int64 [n+1]
     DevBuf indices;   // int32 [nnz]
-    DevBuf weights;   // float [nnz]   (weighted only)
+    DevBuf weights;   // float [nnz]   (weighted only; freed once `edges` is built)
+    DevBuf edges;     // int2 [nnz]: (index, weight bits) of each entry (weighted only), so
+                      // that a node2vec proposal reads one 8-byte record, not two arrays
     DevBuf wmax;      // float [n]     (max weight of each row; 1 when unweighted)
     int64_t isolated = 0;                // nodes without neighbours
 };
@@ -260,6 +262,7 @@ __device__ __forceinline__ uint32_t scale32(uint32_t x, uint32_t m) { return __u
 // ---------------------------------------------------------------------------
 void launch_validate_graph(Graph& g, unsigned long long* d_bad);
 void launch_row_wmax(Graph& g);
+void build_edge_records(Graph& g);
 void launch_walks(Walks& w, const felog_walk_params& p, const Active* starts, int64_t n_starts);
 // columns [col0, col0 + ncols) of the corpus on stream s; node2vec adds its
 // capped proposals to *d_capped

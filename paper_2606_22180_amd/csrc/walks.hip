@@ -101,6 +101,33 @@ void launch_row_wmax(Graph& g)
     FELOG_HIP(hipGetLastError());
 }
 
+// (index, weight) records of a weighted graph's entries.  A node2vec attempt
+// reads the proposal's index and weight; from two arrays that is two random
+// cache lines, from one record one.  The walk kernel is bound by its random
+// line fetches (about 2.7 KB per step on weighted R-MAT 2^23 with p = 0.5,
+// q = 2, where most proposals are rejected).
+__global__ void edge_records_kernel(const int32_t* __restrict__ indices,
+                                    const float* __restrict__ weights, int64_t nnz,
+                                    int2* __restrict__ edges)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) edges[e] = make_int2(indices[e], __float_as_int(weights[e]));
+}
+
+void build_edge_records(Graph& g)
+{
+    Ctx& c = *g.ctx;
+    if (!g.weighted) return;
+    g.edges.alloc(&c, sizeof(int2) * std::max<int64_t>(g.nnz, 1));
+    if (g.nnz)
+        hipLaunchKernelGGL(edge_records_kernel, dim3((g.nnz + 255) / 256), dim3(256), 0,
+                           c.stream, g.indices.as<int32_t>(), g.weights.as<float>(), g.nnz,
+                           g.edges.as<int2>());
+    FELOG_HIP(hipGetLastError());
+    c.sync();
+    g.weights.release();
+}
+
 // --------------------------------------------------------------------------
 // Uniform walks.  Transition t of walk `wid` moves from v to its neighbour
 // number floor(x0 * deg(v) / 2^32), x0 = word 0 of Philox(wid, t, WALK).
@@ -135,12 +162,13 @@ __global__ __launch_bounds__(256) void walk_uniform_kernel(
 //   u * (wmax(v) * alpha_max) < w(v, x) * alpha(prev, x)
 // in FP32, alpha = 1/p (x == prev), 1 (x adjacent to prev), 1/q (otherwise).
 // The first transition uses alpha = 1 and the bound wmax(v).  The adjacency
-// test is a binary search in prev's sorted row, and it is skipped when the
-// proposal is decided by the extreme alpha values alone (same result).
+// test is a binary search in the shorter of the sorted rows of prev and x,
+// and it is skipped when the proposal is decided by the extreme alpha values
+// alone (same result).
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void walk_node2vec_kernel(
     const int64_t* __restrict__ indptr, const int32_t* __restrict__ indices,
-    const float* __restrict__ weights, const float* __restrict__ wmax,
+    const int2* __restrict__ edges, const float* __restrict__ wmax,
     const int32_t* __restrict__ starts, int64_t n_starts, int64_t W, int64_t col0,
     int64_t col_end, int32_t L, float inv_p, float inv_q, float amax, uint32_t max_attempts,
     uint64_t seed, int64_t id_base, int32_t* __restrict__ walks,
@@ -165,8 +193,14 @@ __global__ __launch_bounds__(256) void walk_node2vec_kernel(
             Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)t, kTagN2V | a,
                                  seed);
             int64_t e = lo + scale32(r.v[0], (uint32_t)deg);
-            x = indices[e];
-            float w = weights ? weights[e] : 1.0f;
+            float w = 1.0f;
+            if (edges) {
+                const int2 rec = edges[e];
+                x = rec.x;
+                w = __int_as_float(rec.y);
+            } else {
+                x = indices[e];
+            }
             float u = (float)(r.v[1] >> 8) * (1.0f / 16777216.0f);
             float lhs = __fmul_rn(u, bound);
             bool accept;
@@ -179,13 +213,21 @@ __global__ __launch_bounds__(256) void walk_node2vec_kernel(
             } else if (lhs < __fmul_rn(w, fminf(1.0f, inv_q))) {
                 accept = true;         // accepted even by the smaller of alpha in {1, 1/q}
             } else {
-                // decided by adjacency of x to prev: binary search in prev's row
-                int64_t lo2 = indptr[prev], hi2 = indptr[prev + 1];
+                // decided by adjacency of x to prev.  The graph is symmetric, so
+                // the shorter of the two rows is searched for the other node:
+                // walk positions favour hubs, whose long rows would cost a
+                // cache line per step of the search
+                const int64_t plo = indptr[prev], phi = indptr[prev + 1];
+                const int64_t xlo = indptr[x], xhi = indptr[x + 1];
+                const bool in_x = xhi - xlo < phi - plo;
+                const int32_t target = in_x ? prev : x;
+                int64_t lo2 = in_x ? xlo : plo, hi2 = in_x ? xhi : phi;
+                const int64_t end = hi2;
                 while (lo2 < hi2) {
                     int64_t mid = lo2 + ((hi2 - lo2) >> 1);
-                    if (indices[mid] < x) lo2 = mid + 1; else hi2 = mid;
+                    if (indices[mid] < target) lo2 = mid + 1; else hi2 = mid;
                 }
-                bool adj = lo2 < indptr[prev + 1] && indices[lo2] == x;
+                bool adj = lo2 < end && indices[lo2] == target;
                 accept = lhs < __fmul_rn(w, adj ? 1.0f : inv_q);
             }
             if (accept) break;
@@ -218,7 +260,7 @@ void launch_walk_columns(Walks& w, const felog_walk_params& p, const Active* sta
         float amax = fmaxf(1.0f, fmaxf(inv_p, inv_q));
         hipLaunchKernelGGL(walk_node2vec_kernel, dim3(blocks), dim3(256), 0, s,
                            g.indptr.as<int64_t>(), g.indices.as<int32_t>(),
-                           g.weighted ? g.weights.as<float>() : nullptr, g.wmax.as<float>(), st,
+                           g.weighted ? g.edges.as<int2>() : nullptr, g.wmax.as<float>(), st,
                            n_starts, w.W, col0, col0 + ncols, w.L, inv_p, inv_q, amax, 1u << 16,
                            p.seed, w.id_base, w.data.as<int32_t>(), d_capped);
     }
