@@ -162,10 +162,23 @@ __global__ __launch_bounds__(256) void walk_uniform_kernel(
 //   u * (wmax(v) * alpha_max) < w(v, x) * alpha(prev, x)
 // in FP32, alpha = 1/p (x == prev), 1 (x adjacent to prev), 1/q (otherwise).
 // The first transition uses alpha = 1 and the bound wmax(v).  The adjacency
-// test is a binary search in the shorter of the sorted rows of prev and x,
-// and it is skipped when the proposal is decided by the extreme alpha values
-// alone (same result).
+// test is a binary search in the shorter of the sorted rows of prev and x
+// (the graph is symmetric), and it is skipped when the proposal is decided
+// by the extreme alpha values alone (same result).
+//
+// The transition takes the first accepted attempt in attempt order, or after
+// max_attempts rejections the last proposal.  Attempts are evaluated S at a
+// time: their record reads are issued together, the searches of the
+// undecided ones run in lockstep, and the first accepted attempt of the group
+// (in order) is taken.  Every attempt keeps its own counter, so the walk is
+// the one that evaluating attempt by attempt gives; with most proposals
+// rejected (p = 0.5, q = 2, weights in (0, 1]), pairs of attempts save round
+// trips to memory (S = 2 keeps 8 waves per SIMD; S = 4 drops to 5 and was
+// slower).
 // --------------------------------------------------------------------------
+constexpr int kN2vAttempts = 2;   // attempts evaluated per round trip
+
+template <int S>
 __global__ __launch_bounds__(256) void walk_node2vec_kernel(
     const int64_t* __restrict__ indptr, const int32_t* __restrict__ indices,
     const int2* __restrict__ edges, const float* __restrict__ wmax,
@@ -182,57 +195,102 @@ __global__ __launch_bounds__(256) void walk_node2vec_kernel(
     int64_t wid = id_base + col;
     walks[col] = v;
     uint32_t my_capped = 0;
+    const float a_hi = fmaxf(1.0f, inv_q), a_lo = fminf(1.0f, inv_q);
     int32_t t = 0;
     for (; t + 1 < L; ++t) {
-        int64_t lo = indptr[v];
-        int64_t deg = indptr[v + 1] - lo;
+        const int64_t lo = indptr[v];
+        const int64_t deg = indptr[v + 1] - lo;
         if (deg == 0) break;
         const float bound = t == 0 ? wmax[v] : __fmul_rn(wmax[v], amax);
-        int32_t x = -1;
-        for (uint32_t a = 0; a < max_attempts; ++a) {
-            Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)t, kTagN2V | a,
-                                 seed);
-            int64_t e = lo + scale32(r.v[0], (uint32_t)deg);
-            float w = 1.0f;
-            if (edges) {
-                const int2 rec = edges[e];
-                x = rec.x;
-                w = __int_as_float(rec.y);
-            } else {
-                x = indices[e];
-            }
-            float u = (float)(r.v[1] >> 8) * (1.0f / 16777216.0f);
-            float lhs = __fmul_rn(u, bound);
-            bool accept;
-            if (t == 0) {
-                accept = lhs < w;
-            } else if (x == prev) {
-                accept = lhs < __fmul_rn(w, inv_p);
-            } else if (!(lhs < __fmul_rn(w, fmaxf(1.0f, inv_q)))) {
-                accept = false;        // rejected even by the larger of alpha in {1, 1/q}
-            } else if (lhs < __fmul_rn(w, fminf(1.0f, inv_q))) {
-                accept = true;         // accepted even by the smaller of alpha in {1, 1/q}
-            } else {
-                // decided by adjacency of x to prev.  The graph is symmetric, so
-                // the shorter of the two rows is searched for the other node:
-                // walk positions favour hubs, whose long rows would cost a
-                // cache line per step of the search
-                const int64_t plo = indptr[prev], phi = indptr[prev + 1];
-                const int64_t xlo = indptr[x], xhi = indptr[x + 1];
-                const bool in_x = xhi - xlo < phi - plo;
-                const int32_t target = in_x ? prev : x;
-                int64_t lo2 = in_x ? xlo : plo, hi2 = in_x ? xhi : phi;
-                const int64_t end = hi2;
-                while (lo2 < hi2) {
-                    int64_t mid = lo2 + ((hi2 - lo2) >> 1);
-                    if (indices[mid] < target) lo2 = mid + 1; else hi2 = mid;
-                }
-                bool adj = lo2 < end && indices[lo2] == target;
-                accept = lhs < __fmul_rn(w, adj ? 1.0f : inv_q);
-            }
-            if (accept) break;
-            if (a + 1 == max_attempts) ++my_capped;
+        int64_t plo = 0, phi = 0;
+        if (t > 0) {
+            plo = indptr[prev];
+            phi = indptr[prev + 1];
         }
+        int32_t x = -1;
+        bool done = false;
+        for (uint32_t a0 = 0; a0 < max_attempts && !done; a0 += S) {
+            int32_t xs[S];
+            float ws[S], lhs[S];
+            int st[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)t,
+                                           kTagN2V | (a0 + (uint32_t)k), seed);
+                const int64_t e = lo + scale32(r.v[0], (uint32_t)deg);
+                if (edges) {
+                    const int2 rec = edges[e];
+                    xs[k] = rec.x;
+                    ws[k] = __int_as_float(rec.y);
+                } else {
+                    xs[k] = indices[e];
+                    ws[k] = 1.0f;
+                }
+                lhs[k] = __fmul_rn((float)(r.v[1] >> 8) * (1.0f / 16777216.0f), bound);
+            }
+            bool any_adj = false;
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                if (t == 0) st[k] = lhs[k] < ws[k] ? 1 : 0;
+                else if (xs[k] == prev) st[k] = lhs[k] < __fmul_rn(ws[k], inv_p) ? 1 : 0;
+                else if (!(lhs[k] < __fmul_rn(ws[k], a_hi))) st[k] = 0;
+                else if (lhs[k] < __fmul_rn(ws[k], a_lo)) st[k] = 1;
+                else st[k] = 2;
+                any_adj = any_adj || st[k] == 2;
+            }
+            if (any_adj) {
+                int64_t l[S], h[S], en[S];
+                int32_t tg[S];
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    l[k] = plo;
+                    h[k] = plo;
+                    tg[k] = 0;
+                    if (st[k] == 2) {
+                        const int64_t xlo = indptr[xs[k]], xhi = indptr[xs[k] + 1];
+                        const bool in_x = xhi - xlo < phi - plo;
+                        l[k] = in_x ? xlo : plo;
+                        h[k] = in_x ? xhi : phi;
+                        tg[k] = in_x ? prev : xs[k];
+                    }
+                    en[k] = h[k];
+                }
+                for (;;) {
+                    bool active = false;
+                    int32_t val[S];
+                    int64_t mid[S];
+#pragma unroll
+                    for (int k = 0; k < S; ++k) {
+                        mid[k] = l[k] + ((h[k] - l[k]) >> 1);
+                        val[k] = indices[l[k] < h[k] ? mid[k] : plo];
+                    }
+#pragma unroll
+                    for (int k = 0; k < S; ++k) {
+                        if (l[k] < h[k]) {
+                            active = true;
+                            if (val[k] < tg[k]) l[k] = mid[k] + 1;
+                            else h[k] = mid[k];
+                        }
+                    }
+                    if (!active) break;
+                }
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    if (st[k] == 2) {
+                        const bool adj = l[k] < en[k] && indices[l[k] < en[k] ? l[k] : plo] == tg[k];
+                        st[k] = lhs[k] < __fmul_rn(ws[k], adj ? 1.0f : inv_q) ? 1 : 0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                if (!done && a0 + (uint32_t)k < max_attempts) {
+                    x = xs[k];
+                    done = st[k] == 1;
+                }
+            }
+        }
+        if (!done) ++my_capped;
         prev = v;
         v = x;
         walks[(int64_t)(t + 1) * W + col] = v;
@@ -258,7 +316,7 @@ void launch_walk_columns(Walks& w, const felog_walk_params& p, const Active* sta
         FELOG_REQUIRE(d_capped, "node2vec walks need a device counter for capped proposals");
         float inv_p = 1.0f / p.p, inv_q = 1.0f / p.q;
         float amax = fmaxf(1.0f, fmaxf(inv_p, inv_q));
-        hipLaunchKernelGGL(walk_node2vec_kernel, dim3(blocks), dim3(256), 0, s,
+        hipLaunchKernelGGL(walk_node2vec_kernel<kN2vAttempts>, dim3(blocks), dim3(256), 0, s,
                            g.indptr.as<int64_t>(), g.indices.as<int32_t>(),
                            g.weighted ? g.edges.as<int2>() : nullptr, g.wmax.as<float>(), st,
                            n_starts, w.W, col0, col0 + ncols, w.L, inv_p, inv_q, amax, 1u << 16,
