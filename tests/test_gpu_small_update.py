@@ -93,13 +93,15 @@ def test_small_update_equals_launches_sbm(fl, sbm, dim, K, P):
     _check_identical(res, "sbm1k d=%d K=%d P=%d" % (dim, K, P))
 
 
-def test_small_update_equals_launches_rmat(fl):
+@pytest.mark.parametrize("n", [777, 1500])
+def test_small_update_equals_launches_rmat(fl, n):
     """R-MAT 2^14, d = 128, K = 5, P = 1,024, unigram noise: a ragged range of
-    minibatches that crosses launch groups, from a trained state."""
+    minibatches that crosses launch groups of 64, from a trained state (777
+    and 1,500 minibatches)."""
     g = _rmat(14, 1 << 18, seed=4)
-    res = _both_paths(fl, g, dim=128, K=5, P=1024, window=10, L=80, r=2, first=300, n=777,
+    res = _both_paths(fl, g, dim=128, K=5, P=1024, window=10, L=80, r=2, first=300, n=n,
                       neg=fl.NEG_UNIGRAM)
-    _check_identical(res, "rmat14 d=128 K=5 P=1024")
+    _check_identical(res, "rmat14 d=128 K=5 P=1024 n=%d" % n)
 
 
 def test_small_update_block_counts(fl, sbm):
