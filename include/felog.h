@@ -109,7 +109,10 @@ const char* felog_last_error(void);
  * increasing within each row, no self loops), weights[nnz] (float32 > 0, or
  * NULL for an unweighted graph).  The graph must be symmetric (v in N(u) iff
  * u in N(v)) with equal weights on both directions; a graph that is not gives
- * FELOG_EINVAL with a message naming the first offending row. */
+ * FELOG_EINVAL with a message naming the first offending row.  The caller's
+ * arrays are copied; the call returns after the upload and the checks.  On the
+ * device a weighted graph keeps 8 bytes per entry (index and weight side by
+ * side, for node2vec proposals) besides the indices; an unweighted one 4. */
 felog_status felog_graph_load_csr(felog_ctx* ctx, int32_t n_nodes, int64_t nnz,
                                   const int64_t* indptr, const int32_t* indices,
                                   const float* weights, felog_graph** out);
