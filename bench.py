@@ -22,6 +22,10 @@ After the timed steps the JSON line also carries, measured outside them:
   - c2_algorithm1: Algorithm 1 end to end on R-MAT 2^20 (uniform walks,
     P = 65,536, FeeST mu = 0.65, at most 4 rounds): per-round active set,
     pairs, walk steps/s, and link-prediction AUC;
+  - c4_minibatch_65536, c4_bf16_shared_negative: the headline graph and
+    corpus trained at 65,536 pairs per minibatch, and in the BF16
+    shared-negative form (P = M = 1,024) against the FP32 form's time per
+    minibatch;
   - c3_forms: FP32 per-pair against BF16 shared-negative minibatches
     (P = M = 1,024) on R-MAT 2^22, their error against the FP64 oracle on one
     minibatch, and the AUC of both forms after one epoch on the small SBM;
@@ -697,6 +701,8 @@ def main():
     ap.add_argument("--cpu-minibatches", type=int, default=12)
     ap.add_argument("--c2-rounds", type=int, default=4, help="0 skips the Algorithm 1 leg")
     ap.add_argument("--c3-minibatches", type=int, default=20000, help="0 skips the C3 leg")
+    ap.add_argument("--c4-bf16-minibatches", type=int, default=2048,
+                    help="BF16 shared-negative minibatches on the headline graph (0 skips)")
     ap.add_argument("--serving-jobs", type=int, default=8, help="0 skips the serving sample")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--large-minibatches", type=int, default=1024,
@@ -775,6 +781,12 @@ def main():
     full_s = time.perf_counter() - t
     capped = Wf.capped()
     M.set_unigram(Wf)
+    Mb = None
+    if args.c4_bf16_minibatches > 0:
+        # the BF16 shared-negative form on the same graph and noise table
+        Mb = felog.Model.create(G, dim=cfg["dim"], neg_dist=felog.NEG_UNIGRAM,
+                                seed=cfg["seed_model"], precision=felog.PREC_BF16)
+        Mb.set_unigram(Wf)
     Wf.close()
     full_steps = cfg["r"] * (cfg["L"] - 1) * int((deg > 0).sum())
     log("full node2vec corpus: %d walks, %d steps in %.3f s, capped %d; unigram table set"
@@ -875,6 +887,29 @@ def main():
         log("c4 at P = 65536: %.4g pair-updates/s, %.1f us per minibatch, %s at %.3f of HBM"
             % (st.pairs / (st.ms / 1e3), st.ms / st.minibatches * 1e3, lr_roof["kernel"],
                lr_roof["frac"]))
+    if Mb is not None:
+        # BF16 shared-negative minibatches (P = M = 1,024) on one chunk of the
+        # same corpus, outside the timed steps, against the FP32 form's rate
+        W = chunk_walks(*chunk_starts(args.steps + args.warmup + 1))
+        prm16 = felog.train_params(window=cfg["window"], negatives=cfg["K"],
+                                   lr_start=cfg["lr0"], lr_end=cfg["lr_end"],
+                                   minibatch_pairs=cfg["minibatch"], seed=cfg["seed_train"],
+                                   shared_negatives=1024)
+        Mb.train_steps(W, prm16, 0, 64)
+        st = Mb.train_steps(W, prm16, 64, args.c4_bf16_minibatches)
+        W.close()
+        us = st.ms / st.minibatches * 1e3
+        flop = 2.0 * 3 * cfg["minibatch"] * 1024 * cfg["dim"]   # S = C N^T, dC = G N, dN = G^T C
+        fp32_us = roof["sgns_update"]["us_per_minibatch"]   # device time per minibatch, FP32 form
+        out["c4_bf16_shared_negative"] = {
+            "minibatches": int(st.minibatches), "us_per_minibatch": us,
+            "pair_updates_per_s": st.pairs / (st.ms / 1e3),
+            "mfma_tflops": flop / (us * 1e-6) / 1e12,
+            "mfma_frac": flop / (us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS,
+            "fp32_us_per_minibatch": fp32_us, "bf16_speedup": fp32_us / us}
+        log("c4 bf16 shared-negative: %.1f us per minibatch (fp32 %.1f), %.3g pair-updates/s"
+            % (us, fp32_us, st.pairs / (st.ms / 1e3)))
+        Mb.close()
     G.close()
     M.close()
     for a in offsets.values():

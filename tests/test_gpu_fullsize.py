@@ -189,6 +189,56 @@ def test_rmat20_unigram_table(fl, orc):
     _say("all walks and the unigram table bit-exact")
 
 
+def _bf16_step(fl, orc, G, W, chunk, cdf, tin, tout, b, what):
+    """One BF16 shared-negative minibatch (P = M = 1,024, d = 128, K = 5, w =
+    10) from the tables (tin, tout) against the oracle's BF16 emulation:
+    every row's delta within 2^-8 of its |term| mass (one BF16 rounding of G
+    per entry) plus 1e-5 of its norm; the loss within 1e-3."""
+    B = 1
+    Mb = fl.Model.create(G, dim=128, neg_dist=fl.NEG_DEGREE, seed=2, precision=fl.PREC_BF16)
+    Mb.write(fl.TABLE_IN, tin)
+    Mb.write(fl.TABLE_OUT, tout)
+    prm = fl.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=3,
+                          shared_negatives=1024, lr_start=0.0125, lr_end=0.0125)
+    _say("bf16 shared-negative step, minibatch %d" % b)
+    ri, di, ro, do, loss = Mb.train_delta(W, prm, b)
+    Mb.close()
+    mb = orc.minibatch_pairs(chunk, 10, 1024, b)
+    neg = orc.shared_negatives(b, 0, 1024, 3, cdf)
+    lr = orc.lr_at(b, B, prm.lr_start, prm.lr_end)
+    dctx, dneg, dctr, oloss = orc.shared_neg_step(tin, tout, mb.ctx, mb.ctr, neg, 5, lr,
+                                                  bf16=True)
+    # reference sums and |term| mass per row (BF16-rounded operands, FP64 sums)
+    rows_in, inv_in = np.unique(mb.ctx, return_inverse=True)
+    outs = np.concatenate([neg, mb.ctr])
+    rows_out, inv_out = np.unique(outs, return_inverse=True)
+    ref_in = np.zeros((rows_in.shape[0], 128))
+    np.add.at(ref_in, inv_in, dctx)
+    ref_out = np.zeros((rows_out.shape[0], 128))
+    np.add.at(ref_out, inv_out, np.concatenate([dneg, dctr]))
+    Cm = orc.bf16_round(tin[mb.ctx]).astype(np.float64)
+    Om = orc.bf16_round(tout[mb.ctr]).astype(np.float64)
+    Nm = orc.bf16_round(tout[neg]).astype(np.float64)
+    S = Cm @ Nm.T
+    Gm = lr * 5 / 1024 / (1 + np.exp(-S)) * (neg[None, :] != mb.ctr[:, None])
+    g0 = lr / (1 + np.exp((Cm * Om).sum(1)))
+    m_in = np.zeros_like(ref_in)
+    np.add.at(m_in, inv_in, Gm @ np.abs(Nm) + g0[:, None] * np.abs(Om))
+    m_out = np.zeros_like(ref_out)
+    np.add.at(m_out, inv_out, np.concatenate([Gm.T @ np.abs(Cm), g0[:, None] * np.abs(Cm)]))
+    for side, gr, gd, rr, rd, mm in (("in", ri, di, rows_in, ref_in, m_in),
+                                     ("out", ro, do, rows_out, ref_out, m_out)):
+        assert np.array_equal(np.sort(gr), rr)
+        gv = gd[np.argsort(gr)].astype(np.float64)
+        err = np.linalg.norm(gv - rd, axis=1)
+        tol = 2.0 ** -8 * np.linalg.norm(mm, axis=1) + 1e-5 * np.linalg.norm(rd, axis=1)
+        rel = err / np.maximum(np.linalg.norm(rd, axis=1), 1e-30)
+        _say("%s bf16 mb %d %s: rows %d, max rel %.3e, bad %d" % (
+            what, b, side, rr.shape[0], rel.max(), int((err > tol + 1e-30).sum())))
+        assert (err <= tol + 1e-30).all()
+    assert abs(loss - oloss) <= 1e-3 * abs(oloss)
+
+
 def test_rmat22_fp32_and_bf16_forms(fl, orc):
     """R-MAT 2^22: the FP32 per-pair and BF16 shared-negative forms on one
     minibatch of the first chunk (degree^0.75 noise: the oracle's corpus of
@@ -214,52 +264,13 @@ def test_rmat22_fp32_and_bf16_forms(fl, orc):
     _say("fp32 step, minibatch %d" % b)
     _step(fl, orc, M, W, chunk, cdf, tin, tout, P=1024, K=5, window=10, b=b, seed=3,
           what="rmat22 fp32 mb %d" % b, lr0=0.0125, lr1=0.0125)
-    B = 1
-    # BF16 shared-negative form on the same state and minibatch
-    Mb = fl.Model.create(G, dim=128, neg_dist=fl.NEG_DEGREE, seed=2, precision=fl.PREC_BF16)
-    Mb.write(fl.TABLE_IN, tin)
-    Mb.write(fl.TABLE_OUT, tout)
-    prm = fl.train_params(window=10, negatives=5, minibatch_pairs=1024, seed=3,
-                          shared_negatives=1024, lr_start=0.0125, lr_end=0.0125)
-    _say("bf16 shared-negative step, minibatch %d" % b)
-    ri, di, ro, do, loss = Mb.train_delta(W, prm, b)
-    mb = orc.minibatch_pairs(chunk, 10, 1024, b)
-    neg = orc.shared_negatives(b, 0, 1024, 3, cdf)
-    lr = orc.lr_at(b, B, prm.lr_start, prm.lr_end)
-    dctx, dneg, dctr, oloss = orc.shared_neg_step(tin, tout, mb.ctx, mb.ctr, neg, 5, lr,
-                                                  bf16=True)
-    # reference sums and |term| mass per row (BF16-rounded operands, FP64 sums)
-    rows_in, inv_in = np.unique(mb.ctx, return_inverse=True)
-    outs = np.concatenate([neg, mb.ctr])
-    rows_out, inv_out = np.unique(outs, return_inverse=True)
-    ref_in = np.zeros((rows_in.shape[0], 128))
-    np.add.at(ref_in, inv_in, dctx)
-    ref_out = np.zeros((rows_out.shape[0], 128))
-    np.add.at(ref_out, inv_out, np.concatenate([dneg, dctr]))
-    Cm = orc.bf16_round(tin[mb.ctx]).astype(np.float64)
-    Om = orc.bf16_round(tout[mb.ctr]).astype(np.float64)
-    Nm = orc.bf16_round(tout[neg]).astype(np.float64)
-    S = Cm @ Nm.T
-    Gm = lr * 5 / 1024 / (1 + np.exp(-S)) * (neg[None, :] != mb.ctr[:, None])
-    g0 = lr / (1 + np.exp((Cm * Om).sum(1)))
-    m_in = np.zeros_like(ref_in)
-    np.add.at(m_in, inv_in, Gm @ np.abs(Nm) + g0[:, None] * np.abs(Om))
-    m_out = np.zeros_like(ref_out)
-    np.add.at(m_out, inv_out, np.concatenate([Gm.T @ np.abs(Cm), g0[:, None] * np.abs(Cm)]))
-    for what, gr, gd, rr, rd, mm in (("in", ri, di, rows_in, ref_in, m_in),
-                                     ("out", ro, do, rows_out, ref_out, m_out)):
-        assert np.array_equal(np.sort(gr), rr)
-        gv = gd[np.argsort(gr)].astype(np.float64)
-        err = np.linalg.norm(gv - rd, axis=1)
-        tol = 2.0 ** -8 * np.linalg.norm(mm, axis=1) + 1e-5 * np.linalg.norm(rd, axis=1)
-        rel = err / np.maximum(np.linalg.norm(rd, axis=1), 1e-30)
-        _say("rmat22 bf16 mb %d %s: rows %d, max rel %.3e, bad %d" % (
-            b, what, rr.shape[0], rel.max(), int((err > tol + 1e-30).sum())))
-        assert (err <= tol + 1e-30).all()
-    assert abs(loss - oloss) <= 1e-3 * abs(oloss)
+    _bf16_step(fl, orc, G, W, chunk, cdf, tin, tout, b, "rmat22")
 
 
 def test_rmat23w_node2vec(fl, orc):
+    """Weighted R-MAT 2^23, node2vec p = 0.5, q = 2: sampled walks and the
+    first 2^20-walk chunk bit-exact, then one FP32 step and one BF16
+    shared-negative step on that chunk's pairs against the oracle."""
     sp = synth.build_graph("rmat23w")
     g = sp.train
     _say("rmat23w n=%d nnz=%d: node2vec p=0.5 q=2, r=10 L=80" % (g.n, g.nnz))
@@ -283,6 +294,11 @@ def test_rmat23w_node2vec(fl, orc):
     # a constant learning rate keeps lr independent of the corpus' minibatch count
     _step(fl, orc, M, W, ow, cdf, tin, tout, P=1024, K=5, window=10, b=777, seed=3,
           what="rmat23w fp32 mb 777", lr0=0.025, lr1=0.025)
+    M.close()
+    # the BF16 shared-negative form on the same walks, from the oracle's
+    # initial tables with out rows moved off zero
+    tout += np.random.default_rng(4).normal(0, 0.05, tout.shape).astype(np.float32)
+    _bf16_step(fl, orc, G, W, ow, cdf, tin, tout, 777, "rmat23w")
 
 
 def test_rmat23w_persistent_update(fl, orc):
