@@ -103,9 +103,9 @@ void launch_row_wmax(Graph& g)
 
 // (index, weight) records of a weighted graph's entries.  A node2vec attempt
 // reads the proposal's index and weight; from two arrays that is two random
-// cache lines, from one record one.  The walk kernel is bound by its random
-// line fetches (about 2.7 KB per step on weighted R-MAT 2^23 with p = 0.5,
-// q = 2, where most proposals are rejected).
+// cache lines, from one record one.  The walk kernel is bound by such random
+// line fetches: with p = 0.5, q = 2 and weights in (0, 1] most proposals are
+// rejected, so a step takes several attempts.
 __global__ void edge_records_kernel(const int32_t* __restrict__ indices,
                                     const float* __restrict__ weights, int64_t nnz,
                                     int2* __restrict__ edges)
@@ -210,9 +210,9 @@ __global__ __launch_bounds__(256) void walk_node2vec_kernel(
         int32_t x = -1;
         bool done = false;
         for (uint32_t a0 = 0; a0 < max_attempts && !done; a0 += S) {
-            int32_t xs[S];
+            int32_t xs[S];     // proposals
             float ws[S], lhs[S];
-            int st[S];
+            int st[S];         // 0 rejected, 1 accepted, 2 decided by adjacency to prev
 #pragma unroll
             for (int k = 0; k < S; ++k) {
                 const Rand4 r = philox4x32((uint32_t)wid, (uint32_t)(wid >> 32), (uint32_t)t,
@@ -239,6 +239,10 @@ __global__ __launch_bounds__(256) void walk_node2vec_kernel(
                 any_adj = any_adj || st[k] == 2;
             }
             if (any_adj) {
+                // lower-bound searches of the undecided proposals, each in the
+                // shorter of the rows of prev and x for the other node, in
+                // lockstep: every round reads one index per search (inactive
+                // searches re-read prev's first entry)
                 int64_t l[S], h[S], en[S];
                 int32_t tg[S];
 #pragma unroll
