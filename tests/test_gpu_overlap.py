@@ -5,8 +5,8 @@ so the run must equal, bit for bit, the same rounds driven through the
 separate calls (walk the whole corpus, then train, then feedback).  Runs cover
 ragged chunks, chunks without a single walk that yields pairs, both stream
 modes of the FP32 path, node2vec with unigram noise (round 1 walks first, the
-later rounds overlap) and the BF16 form (one round; its atomic adds to the
-masters make it equal up to their order)."""
+later rounds overlap) and the BF16 form (one round; its per-row sums in
+touch order make it bit-reproducible too)."""
 import numpy as np
 import pytest
 
@@ -71,9 +71,10 @@ def _sequential(fl, G, M, rp, neg):
 
 
 def _compare(fl, G, rp, neg, dim, prec=None):
-    """Bit for bit for the FP32 path.  The BF16 form adds its gradient tiles to
-    the masters with FP32 atomics, whose order varies from run to run: there
-    the schedule must be equal and the results close."""
+    """Bit for bit, in both forms: the FP32 path and the BF16 form (whose
+    apply sums each row's terms in touch order, without atomics) give the
+    same rounds, losses and tables whether the walks overlap training or
+    not."""
     kw = dict(dim=dim, neg_dist=neg, seed=7)
     if prec is not None:
         kw["precision"] = prec
@@ -86,14 +87,6 @@ def _compare(fl, G, rp, neg, dim, prec=None):
     _say("rounds", got)
     for r in range(st.rounds):
         assert st.ms_walk[r] > 0.0
-    if prec == fl.PREC_BF16:
-        assert [x[:4] for x in got] == [x[:4] for x in rounds]
-        for a, b in zip(got, rounds):
-            assert abs(a[4] - b[4]) <= 1e-6 * abs(b[4])
-        for t in (fl.TABLE_IN, fl.TABLE_OUT):
-            A, B = Ma.read(t), Mb.read(t)
-            assert np.linalg.norm(A - B) <= 1e-3 * np.linalg.norm(B)
-        return st
     assert got == rounds
     assert st.final_active == final
     for t in (fl.TABLE_IN, fl.TABLE_OUT):
