@@ -15,11 +15,12 @@
 // weighs K/M, so the expected update equals Eq. (2) with K negatives per pair.
 //
 // Kernels per minibatch: gather (rows, transposed copies, positive terms),
-// scores (S and G on 32x32 tiles, 4 waves of 16x16), grads (dC and dN on
-// 32x32 tiles, the shared dimension M or P split over a block's 8 waves; each
-// touch's FP32 term stored as a row of a delta buffer), apply (one wave per
-// touched row sums its touches' terms in FP64, in touch order, and adds the
-// sum to the master with one rounding).  A row repeats when a node is the
+// fused (S, G, dC and dN in one launch: a block takes a 16-row panel of one
+// side and streams the other side in 32-row chunks, G passing from the score
+// MFMAs to the output MFMAs in registers; each touch's FP32 term stored as a
+// row of a delta buffer, in up to four parts), apply (one wave per touched
+// row sums its touches' terms in FP64, in touch order, and adds the sum to
+// the master with one rounding).  A row repeats when a node is the
 // context of several pairs, the centre of several, a negative drawn twice, or
 // both a centre and a negative; summing its terms in a fixed order instead of
 // with atomics makes the tables bit-reproducible.  The touches' order comes
