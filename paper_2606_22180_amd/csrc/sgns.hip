@@ -22,17 +22,18 @@
 //            touches and one per kChunk touches of the rows with more.  No
 //            atomics: same-address device atomics serialise at about one per
 //            12 ns on this part.
-//   forward  one 16-lane group per pair: gather in[ctx], out[ctr],
-//            out[neg_1..K]; K+1 dots, sigma, coefficients g; writes
-//            (g_k, ctx) and the touch's pair-order key at the out-row's
-//            segment position, sum_k g_k out[t_k] and the pair at the
-//            in-row's.
+//   forward  one group of 16 lanes (d = 64) or 32 (d >= 128) per pair: gather
+//            in[ctx], out[ctr], out[neg_1..K]; K+1 dots, sigma and the
+//            coefficients g in FP64 over the FP32 entries; writes (g_k, ctx)
+//            and the touch's pair-order key at the out-row's segment
+//            position, sum_k g_k out[t_k] (rounded to FP32 once) and the pair
+//            at the in-row's; out rows touched once are updated in place.
 //   split    chunks of the rows with more than kChunk touches: exact sums
 //            (below), stored per chunk.
 //   reduce   rows of at most kChunk touches, out rows first (they read the
 //            in-table as of the minibatch start), then in rows: the touches
-//            are sorted by key inside a 16-lane group and summed in FP32 in
-//            pair order.
+//            are sorted by key inside a 16-lane group and their terms summed
+//            in FP64 in pair order, added to the row with one rounding.
 //   merge    each split row adds its chunks' sums in chunk order.
 // prep and scan read only the walks and the noise table, so with two sets
 // of their buffers the next minibatch's run on a second stream while this
@@ -523,8 +524,8 @@ __global__ __launch_bounds__(256) void sgns_forward_kernel(FwdArgs a)
 // In rows:  delta in[c]  = sum over touches of the pair's in-row delta.
 // Rows of at most kChunk touches: one 16-lane group per row sorts the
 // touches by their pair-order key (a bitonic network over the group) and
-// sums them in FP32 in that order, so the result is the sequential sum in
-// pair order whatever the atomics did.  Chunks of the rows with more
+// sums their FP64 terms in that order, so the result is the sequential sum
+// in pair order whatever the atomics did.  Chunks of the rows with more
 // touches (their membership follows the atomics' order) get exact sums
 // instead, which a merge adds in chunk order.
 // Sort (key, a, b) ascending over the 16 lanes of a group.
