@@ -375,7 +375,13 @@ typedef struct felog_train_stats {
  *   delta in[c] += sum_k gk out[tk],   delta out[tk] += gk in[c].
  * Negative k of a pair uses words 2(k mod 2), 2(k mod 2)+1 (low, high) of
  * Philox(key = seed, counter = (walk id low, walk id high, j << 8 | slot,
- * 3 << 24 | k / 2)); a negative equal to the centre is skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1). */
+ * 3 << 24 | k / 2)); a negative equal to the centre is skipped.  lr for minibatch b of B: lr_start - (lr_start - lr_end) b / (B-1).
+ * Arithmetic: dots, sigma and the coefficients in FP64 over the FP32 entries;
+ * a row's terms summed in FP64 (in pair order for rows of at most 16 touches,
+ * rounded onto a grid on which FP64 addition is exact for longer rows) and
+ * added to the FP32 entry with one rounding; a row touched once takes its one
+ * term the same way.  The tables are identical on both update paths and from
+ * run to run. */
 /* Failure hook (the library's only environment variable): when
  * FELOG_DEBUG_FAIL_AFTER_MINIBATCHES=N (N >= 0) is set, felog_train_epoch and
  * felog_train_steps train at most the first N minibatches of their range and,
