@@ -218,3 +218,14 @@ def test_phase_clocks(fl, sbm):
     assert s1.path == 1 and s1.timed_minibatches == 300
     assert all(p > 0 for p in ph) and list(s0.us_phase) == [0.0] * 4
     assert 0.7 * ev <= sum(ph) <= 1.1 * ev
+
+
+@pytest.mark.parametrize("dim,K,P", [(128, 12, 512), (64, 13, 512), (256, 10, 512),
+                                     (256, 20, 256)])
+def test_small_update_register_spilling_instantiations(fl, sbm, dim, K, P):
+    """Instantiations of the persistent update whose registers spill to
+    scratch (K >= 11 at d = 64 and 128, every K at d = 256) against the
+    per-minibatch launches, which do not spill at these sizes: bit-identical
+    tables over 200 minibatches."""
+    res = _both_paths(fl, sbm.train, dim=dim, K=K, P=P, window=5, L=40, r=10, first=0, n=200)
+    _check_identical(res, "spilling instantiation d=%d K=%d P=%d" % (dim, K, P))
