@@ -387,9 +387,14 @@ __global__ __launch_bounds__(256) void fabc_unpack_kernel(UnpackArgs a)
 #pragma unroll
         for (int i = 0; i < kWalksPerLane; ++i)
             if (sum[i] != (uint32_t)__popc(any[i]) || (any[i] >> valid) != 0u) bad |= 1u;
+        // the group's eight positions: slots and reads first (the residual
+        // offsets follow from the bitmaps alone, so all reads are in flight
+        // together), then the checks and the stores
+        int32_t v[8][kWalksPerLane];
+        uint32_t from_res = 0;   // bit 4 t + i: v[t][i] was read from the residuals
+#pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const int32_t j = 8 * j8 + t;
-            if (j >= a.L) break;
+            if (t >= valid) break;
             int hit[kWalksPerLane];
             bool f[kWalksPerLane];
 #pragma unroll
@@ -399,32 +404,38 @@ __global__ __launch_bounds__(256) void fabc_unpack_kernel(UnpackArgs a)
             }
             uint32_t slot[kWalksPerLane], total;
             wave_slots(f, slot, &total);
-            int32_t v[kWalksPerLane];
 #pragma unroll
             for (int i = 0; i < kWalksPerLane; ++i) {
-                v[i] = -1;
+                v[t][i] = -1;
                 if (hit[i] >= 0 && hit[i] < a.k) {
-                    v[i] = a.symbols[hit[i]];
+                    v[t][i] = a.symbols[hit[i]];
                 } else if (f[i]) {
                     if (at + slot[i] < a.R) {
-                        v[i] = a.residuals[at + slot[i]];
-                        if (v[i] < -1 || v[i] >= a.n) {
-                            bad |= 8u;
-                            v[i] = -1;
-                        }
+                        v[t][i] = a.residuals[at + slot[i]];
+                        from_res |= 1u << (4 * t + i);
                     } else {
                         bad |= 4u;
                     }
                 }
             }
             at += total;
-            int32_t* row = a.data + (int64_t)j * a.W;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t >= valid) break;
+#pragma unroll
+            for (int i = 0; i < kWalksPerLane; ++i)
+                if (((from_res >> (4 * t + i)) & 1u) && (v[t][i] < -1 || v[t][i] >= a.n)) {
+                    bad |= 8u;
+                    v[t][i] = -1;
+                }
+            int32_t* row = a.data + (int64_t)(8 * j8 + t) * a.W;
             if (vec && full) {
-                store_nt4(row + w0, v[0], v[1], v[2], v[3]);
+                store_nt4(row + w0, v[t][0], v[t][1], v[t][2], v[t][3]);
             } else {
 #pragma unroll
                 for (int i = 0; i < kWalksPerLane; ++i)
-                    if (w0 + i < a.W) row[w0 + i] = v[i];
+                    if (w0 + i < a.W) row[w0 + i] = v[t][i];
             }
         }
     }
