@@ -82,6 +82,23 @@ __device__ __forceinline__ const float4* row4(const float* base, int64_t row)
     return reinterpret_cast<const float4*>(base + row * D);
 }
 
+// The apply's row slots past a segment's end: zeros, with no load issued.
+// Pointing those loads at row 0 instead made every short segment of the
+// minibatch read the same line, which queued in one L2 channel (about 1 us
+// per minibatch of the persistent update on R-MAT 2^20).
+template <int D, int NV>
+__device__ __forceinline__ void load_row_if(float4 (&x)[NV], const float* base, int32_t row,
+                                            bool ok, int lane16)
+{
+#pragma unroll
+    for (int i = 0; i < NV; ++i) x[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (ok) {
+        const float4* r = row4<D>(base, row);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) x[i] = r[i * 16 + lane16];
+    }
+}
+
 __device__ __forceinline__ float dot4(float4 a, float4 b, float acc)
 {
     acc = fmaf(a.x, b.x, acc);

@@ -583,10 +583,7 @@ __global__ __launch_bounds__(kUpdThreads) void sgns_small_update_kernel(UpdArgs 
                             const int32_t idx = min(i0 + u, 15);
                             gg[u] = __shfl(my_g, (g16 << 4) + idx);
                             const int32_t rr = __shfl(my_src, (g16 << 4) + idx);
-                            const float4* rp = reinterpret_cast<const float4*>(srcb + (int64_t)(ok ? rr : 0) * D);
-#pragma unroll
-                            for (int i = 0; i < AV4; ++i)
-                                x[u][i] = ok ? rp[i * 16 + l16] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                            load_row_if<D, AV4>(x[u], srcb, rr, ok, l16);
                             if (!ok) gg[u] = 0.0;
                         }
 #pragma unroll
