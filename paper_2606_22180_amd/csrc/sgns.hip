@@ -584,7 +584,11 @@ template <int D, int PHASE>
 __global__ __launch_bounds__(256) void sgns_apply_kernel(ApplyArgs a)
 {
     constexpr int V4 = D / 64;
-    constexpr int kRows = 4;    // rows in flight per group, rows of one chunk
+    // rows in flight per group, rows of one chunk: fewer registers and more
+    // waves beat more loads per wave here (65,536 pairs on R-MAT 2^20, us per
+    // minibatch with 4 / 2 / 1 rows: d = 64 128.4 / 124.7 / 125.9, d = 128
+    // 193.9 / 184.6 / 180.2, d = 256 400.8 / 346.3 / 319.1)
+    constexpr int kRows = D >= 128 ? 1 : 2;
     constexpr int kRowsS = 2;   // rows in flight per group, chunks of split rows
     const int lane = threadIdx.x & 63;
     const int grp = lane >> 4, gl = lane & 15;
